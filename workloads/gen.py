@@ -1,0 +1,289 @@
+"""Seeded synthetic initial states shaped like the paper's workloads.
+
+The paper uses no public data set: all of its systems are Lennard-Jones
+particles placed on surfaces.  These generators stand in for them.  They hold
+geometry only (sampling points area-uniformly on a surface and drawing
+Maxwell-Boltzmann momenta tangent to it); none of the integration method is
+here.  Both the oracle tests and the GPU path take their inputs from this
+module, so that both sides see identical arrays.
+
+Recipe (every system):
+  * positions: candidates drawn area-uniformly on the surface with numpy's
+    PCG64 seeded by `seed`, then random sequential adsorption with a minimum
+    pair distance `dmin` (0.9 sigma by default);
+  * momenta: N(0, m kT) per Cartesian component from the same generator,
+    then the component along the unit surface normal removed.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_RSA_SRC = os.path.join(HERE, "rsa.c")
+_RSA_LIB = os.path.join(HERE, "librsa.so")
+_rsa = None
+
+
+def build(force: bool = False) -> str:
+    if force or not os.path.exists(_RSA_LIB) or os.path.getmtime(_RSA_LIB) < os.path.getmtime(_RSA_SRC):
+        tmp = _RSA_LIB + ".tmp"
+        subprocess.check_call(["gcc", "-std=c11", "-O2", "-fPIC", "-shared", "-o", tmp, _RSA_SRC, "-lm"])
+        os.replace(tmp, _RSA_LIB)
+    return _RSA_LIB
+
+
+def _lib():
+    global _rsa
+    if _rsa is None:
+        build()
+        L = C.CDLL(_RSA_LIB)
+        dp = C.POINTER(C.c_double)
+        L.rsa_filter.argtypes = [dp, C.c_int64, C.c_double, dp, dp, C.POINTER(C.c_int), C.c_int64, dp]
+        L.rsa_filter.restype = C.c_int64
+        _rsa = L
+    return _rsa
+
+
+@dataclass
+class System:
+    """A synthetic initial state.  Arrays are float64, shape (n, 3)."""
+    x: np.ndarray
+    p: np.ndarray
+    surface: str
+    surf: tuple
+    box_lo: tuple = (0.0, 0.0, 0.0)
+    box_hi: tuple = (0.0, 0.0, 0.0)
+    periodic: tuple = (0, 0, 0)
+    cons: np.ndarray | None = None
+    mass: np.ndarray | None = None
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return int(self.x.shape[0])
+
+
+def rsa(candidates: np.ndarray, n: int, dmin: float, lo=(0, 0, 0), hi=(0, 0, 0), periodic=(0, 0, 0)):
+    cand = np.ascontiguousarray(candidates, dtype=np.float64).reshape(-1, 3)
+    out = np.zeros((n, 3))
+    lo_ = np.ascontiguousarray(lo, dtype=np.float64)
+    hi_ = np.ascontiguousarray(hi, dtype=np.float64)
+    per = (C.c_int * 3)(*[int(v) for v in periodic])
+    dp = C.POINTER(C.c_double)
+    got = _lib().rsa_filter(cand.ctypes.data_as(dp), cand.shape[0], dmin, lo_.ctypes.data_as(dp),
+                            hi_.ctypes.data_as(dp), per, n, out.ctypes.data_as(dp))
+    if got < 0:
+        raise MemoryError("rsa_filter")
+    return out[:got]
+
+
+def _fill(sampler, n, dmin, rng, lo=(0, 0, 0), hi=(0, 0, 0), periodic=(0, 0, 0), prefix=None):
+    """Draw candidates in growing batches until RSA accepts n points."""
+    pts = np.zeros((0, 3)) if prefix is None else prefix
+    mult = 3.0
+    for _ in range(12):
+        need = n - (0 if prefix is None else 0)
+        cand = sampler(rng, int(mult * n) + 64)
+        allc = np.concatenate([pts, cand]) if pts.shape[0] else cand
+        acc = rsa(allc, n, dmin, lo, hi, periodic)
+        if acc.shape[0] >= need:
+            return acc
+        pts = acc
+        mult *= 2.0
+    raise RuntimeError(f"RSA could not place {n} points at dmin={dmin}")
+
+
+def _tangent_momenta(rng, nhat, kT, mass):
+    n = nhat.shape[0]
+    m = np.ones(n) if mass is None else np.asarray(mass, dtype=np.float64)
+    p = rng.standard_normal((n, 3)) * np.sqrt(m * kT)[:, None]
+    p -= np.sum(p * nhat, axis=1, keepdims=True) * nhat
+    return p
+
+
+def _unit(v):
+    return v / np.linalg.norm(v, axis=1, keepdims=True)
+
+
+# ----------------------------------------------------------------------------- surfaces
+
+
+def sphere(n: int, R: float, seed: int, dmin: float = 0.9, kT: float = 1.0) -> System:
+    """Sphere of radius R centred at 0: directions from normalised 3-D Gaussians."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+
+    def sampler(rng, m):
+        return R * _unit(rng.standard_normal((m, 3)))
+
+    x = _fill(sampler, n, dmin, rng)
+    p = _tangent_momenta(rng, _unit(x), kT, None)
+    return System(x, p, "sphere", (0.0, 0.0, 0.0, R), meta=dict(R=R))
+
+
+def torus(n: int, Rt: float, r: float, seed: int, dmin: float = 0.9, kT: float = 1.0) -> System:
+    """Torus about the z axis: tube angle accepted with probability (Rt + r cos t)/(Rt + r)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+
+    def sampler(rng, m):
+        t = rng.uniform(0.0, 2.0 * np.pi, size=m)
+        keep = rng.uniform(0.0, 1.0, size=m) < (Rt + r * np.cos(t)) / (Rt + r)
+        t = t[keep]
+        ph = rng.uniform(0.0, 2.0 * np.pi, size=t.shape[0])
+        rho = Rt + r * np.cos(t)
+        return np.stack([rho * np.cos(ph), rho * np.sin(ph), r * np.sin(t)], axis=1)
+
+    x = _fill(sampler, n, dmin, rng)
+    rho = np.hypot(x[:, 0], x[:, 1])
+    nh = np.stack([(rho - Rt) * x[:, 0] / rho, (rho - Rt) * x[:, 1] / rho, x[:, 2]], axis=1)
+    p = _tangent_momenta(rng, _unit(nh), kT, None)
+    return System(x, p, "torus", (0.0, 0.0, 0.0, Rt, r), meta=dict(Rt=Rt, r=r))
+
+
+def ellipsoid(n: int, a: float, b: float, c: float, seed: int, dmin: float = 0.9, kT: float = 1.0) -> System:
+    """Ellipsoid with semi-axes a, b, c: a point u on the unit sphere maps to (a u0, b u1, c u2),
+    accepted with probability proportional to the area stretch abc |(u0/a, u1/b, u2/c)|."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    mn = min(a, b, c)
+
+    def sampler(rng, m):
+        u = _unit(rng.standard_normal((m, 3)))
+        w = mn * np.sqrt((u[:, 0] / a) ** 2 + (u[:, 1] / b) ** 2 + (u[:, 2] / c) ** 2)
+        u = u[rng.uniform(0.0, 1.0, size=m) < w]
+        return u * np.array([a, b, c])
+
+    x = _fill(sampler, n, dmin, rng)
+    nh = x / np.array([a * a, b * b, c * c])
+    p = _tangent_momenta(rng, _unit(nh), kT, None)
+    return System(x, p, "ellipsoid", (0.0, 0.0, 0.0, a, b, c), meta=dict(a=a, b=b, c=c))
+
+
+def _height(x, y, A, L):
+    k = 2.0 * np.pi / L
+    return A * np.sin(k * x) * np.sin(k * y)
+
+
+def plane(n: int, L: float, seed: int, dmin: float = 0.9, kT: float = 1.0, z0: float = 0.0) -> System:
+    """Plane z = z0 in a box periodic along x and y (side L)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    lo, hi, per = (0.0, 0.0, z0 - 0.5 * L), (L, L, z0 + 0.5 * L), (1, 1, 0)
+
+    def sampler(rng, m):
+        xy = rng.uniform(0.0, L, size=(m, 2))
+        return np.column_stack([xy, np.full(m, z0)])
+
+    x = _fill(sampler, n, dmin, rng, lo, hi, per)
+    nh = np.tile([0.0, 0.0, 1.0], (n, 1))
+    p = _tangent_momenta(rng, nh, kT, None)
+    return System(x, p, "plane", (0.0, 0.0, z0, 0.0, 0.0, 1.0), lo, hi, per, meta=dict(L=L))
+
+
+def cylinder(n: int, R: float, L: float, seed: int, dmin: float = 0.9, kT: float = 1.0) -> System:
+    """Cylinder of radius R about the z axis, periodic along z with length L."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    lo, hi, per = (-R - 1.0, -R - 1.0, 0.0), (R + 1.0, R + 1.0, L), (0, 0, 1)
+
+    def sampler(rng, m):
+        t = rng.uniform(0.0, 2.0 * np.pi, size=m)
+        z = rng.uniform(0.0, L, size=m)
+        return np.column_stack([R * np.cos(t), R * np.sin(t), z])
+
+    x = _fill(sampler, n, dmin, rng, lo, hi, per)
+    nh = np.column_stack([x[:, 0], x[:, 1], np.zeros(n)])
+    p = _tangent_momenta(rng, _unit(nh), kT, None)
+    return System(x, p, "cylinder", (0.0, 0.0, 0.0, 1.0, 1.0, 0.0, R), lo, hi, per, meta=dict(R=R, L=L))
+
+
+def height_membrane(n_c: int, n_b: int, Lx: float, Ly: float, Lz: float, A: float, Lw: float, seed: int,
+                    dmin: float = 0.9, kT: float = 1.0, slab: float = 1.0) -> System:
+    """Height-field membrane z = A sin(2 pi x/Lw) sin(2 pi y/Lw) in a periodic box
+    [0,Lx) x [0,Ly) x [-Lz/2, Lz/2), carrying n_c constrained particles, plus n_b
+    free particles in the volume with |z - h(x, y)| >= slab.  Constrained
+    particles come first; cons marks them."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    lo, hi, per = (0.0, 0.0, -0.5 * Lz), (Lx, Ly, 0.5 * Lz), (1, 1, 1)
+    k = 2.0 * np.pi / Lw
+    smax = math.sqrt(1.0 + (A * k) ** 2)
+
+    def surf_sampler(rng, m):
+        xy = rng.uniform(0.0, 1.0, size=(m, 2)) * np.array([Lx, Ly])
+        hx = A * k * np.cos(k * xy[:, 0]) * np.sin(k * xy[:, 1])
+        hy = A * k * np.sin(k * xy[:, 0]) * np.cos(k * xy[:, 1])
+        keep = rng.uniform(0.0, 1.0, size=m) < np.sqrt(1.0 + hx * hx + hy * hy) / smax
+        xy = xy[keep]
+        return np.column_stack([xy, _height(xy[:, 0], xy[:, 1], A, Lw)])
+
+    xs = _fill(surf_sampler, n_c, dmin, rng, lo, hi, per)
+
+    def bulk_sampler(rng, m):
+        q = rng.uniform(0.0, 1.0, size=(m, 3)) * np.array([Lx, Ly, Lz]) + np.array(lo)
+        h = _height(q[:, 0], q[:, 1], A, Lw)
+        dz = q[:, 2] - h
+        dz -= Lz * np.rint(dz / Lz)
+        return q[np.abs(dz) >= slab]
+
+    allx = _fill(bulk_sampler, n_c + n_b, dmin, rng, lo, hi, per, prefix=xs) if n_b > 0 else xs
+    x = allx
+    hx = A * k * np.cos(k * x[:n_c, 0]) * np.sin(k * x[:n_c, 1])
+    hy = A * k * np.sin(k * x[:n_c, 0]) * np.cos(k * x[:n_c, 1])
+    nh = _unit(np.column_stack([-hx, -hy, np.ones(n_c)]))
+    ps = _tangent_momenta(rng, nh, kT, None)
+    pb = rng.standard_normal((n_b, 3)) * math.sqrt(kT)
+    p = np.concatenate([ps, pb])
+    cons = np.concatenate([np.ones(n_c, np.uint8), np.zeros(n_b, np.uint8)])
+    return System(x, p, "height", (0.0, A, Lw, Lw), lo, hi, per, cons=cons,
+                  meta=dict(A=A, L=Lw, n_c=n_c, n_b=n_b))
+
+
+# ----------------------------------------------------------------------------- sizes
+
+
+def sphere_radius_for(n: int, phi: float, d: float = 1.0) -> float:
+    """Radius giving area fraction phi for n disks of diameter d."""
+    return math.sqrt(n * math.pi * d * d / 4.0 / phi / (4.0 * math.pi))
+
+
+def torus_radii_for(n: int, phi: float, ratio: float = 1.0 / 3.0, d: float = 1.0):
+    """(Rt, r) with r = ratio*Rt giving area fraction phi (area 4 pi^2 Rt r)."""
+    area = n * math.pi * d * d / 4.0 / phi
+    Rt = math.sqrt(area / (4.0 * math.pi ** 2 * ratio))
+    return Rt, ratio * Rt
+
+
+def prolate_axes_for(n: int, phi: float, d: float = 1.0):
+    """(a, a, 1.5 a) with area fraction phi; prolate spheroid area
+    2 pi a^2 (1 + (c / (a e)) asin e), e = sqrt(1 - a^2/c^2)."""
+    e = math.sqrt(1.0 - 1.0 / 2.25)
+    fac = 2.0 * math.pi * (1.0 + (1.5 / e) * math.asin(e))
+    area = n * math.pi * d * d / 4.0 / phi
+    a = math.sqrt(area / fac)
+    return a, a, 1.5 * a
+
+
+# ----------------------------------------------------------------------------- named workloads
+
+WCA_RC = 2.0 ** (1.0 / 6.0)
+
+
+def sphere_wca_1000(seed: int = 42) -> tuple[System, dict]:
+    """1000 WCA particles on a sphere R = 14.4 (area fraction 0.30), gamma 1, kT 1,
+    dt 0.001, FP64 forces, Philox seed 42."""
+    s = sphere(1000, 14.4, seed)
+    run = dict(dt=0.001, kT=1.0, gamma=1.0, eps=1.0, sigma=1.0, rc=WCA_RC, pair="lj", seed=42,
+               force_fp64=1, steps=1000)
+    return s, run
+
+
+def torus_lj_2m(n: int = 2_000_000, seed: int = 7, phi: float = 0.4) -> tuple[System, dict]:
+    """n LJ particles (cut-off 2.5) on a torus with r = Rt/3 at area fraction 0.4,
+    gamma 1, kT 1, dt 0.002, FP32 pair forces, Philox seed 7."""
+    Rt, r = torus_radii_for(n, phi)
+    s = torus(n, Rt, r, seed)
+    run = dict(dt=0.002, kT=1.0, gamma=1.0, eps=1.0, sigma=1.0, rc=2.5, pair="lj", seed=7,
+               force_fp64=0, steps=10000)
+    return s, run
