@@ -1,0 +1,186 @@
+#!/usr/bin/env python3
+"""Throughput of the RATTLE + Langevin time step on one MI355X.
+
+Workload (default): 2,000,000 Lennard-Jones particles (cut-off 2.5 sigma) on a
+torus with r = Rt/3 at area fraction 0.4 (Rt = 546.27, r = 182.09), kT = 1,
+gamma = 1, dt = 0.002, FP32 pair forces with FP64 positions, momenta and
+constraint solves; Philox seed 7; initial state from the seeded generator
+(area-uniform positions with a 0.9 sigma exclusion, tangent Maxwell-Boltzmann
+momenta).  One "step" is one full time step of all particles (pair forces,
+Langevin combination, both RATTLE stages, and the amortised neighbour-list
+rebuilds).  Inputs are resident on the device before timing starts.
+
+Prints one JSON line:
+  value       particle-steps/s over the timed steps (wall clock around md_step)
+  roofline    the fused step kernel: algorithmic bytes per launch / mean launch
+              time from HIP events on the library's stream, against 8 TB/s
+  cpu_baseline the FP64 oracle on the host cores, one full step of the same
+              2M-particle system (kind "oracle")
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "particle-steps/s (2M on torus, % HBM roof); batched-job p50/p99 latency vs plain"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_torus2m_traffic.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("device.hpp", "kernels.hpp"):
+        with open(os.path.join(ROOT, "paper_1411_3019_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def device_sync():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            torch.cuda.synchronize()
+    except Exception:
+        pass
+
+
+def step_kernel_bytes(nl_mean: float) -> float:
+    """Algorithmic bytes per particle-step of the fused step kernel:
+    x^m read + x^{m+1} write (48), p read + write (48), particle index (4),
+    constraint flag (1), neighbour count (4), neighbour indices (4 per entry).
+    Neighbour positions are re-reads of x^m served by the caches (counted 0)."""
+    return 48.0 + 48.0 + 4.0 + 1.0 + 4.0 + 4.0 * nl_mean
+
+
+def traffic_for(n: int, launches_key: str):
+    """HBM bytes per step launch from the committed rocprofv3 counter summary,
+    if it was taken on the current kernel source; else None."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha") != kernel_source_hash() or t.get("n") != n:
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(s, run, budget_s: float = 12.0):
+    from oracle import oracle as o
+    P = o.Params(dt=run["dt"], kT=run["kT"], gamma=run["gamma"], eps=run["eps"], sigma=run["sigma"],
+                 rc=run["rc"], pair=run["pair"], surface=s.surface, surf=s.surf, seed=run["seed"], use_cells=1)
+    st = o.State(P, s.x, s.p)
+    steps, t = 0, 0.0
+    while steps < 5 and t < budget_s:
+        t0 = time.perf_counter()
+        st.run(1)
+        t += time.perf_counter() - t0
+        steps += 1
+    cores = int(os.environ.get("OMP_NUM_THREADS") or len(os.sched_getaffinity(0)))
+    return {"value": s.n * steps / t, "unit": "particle-steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"{steps} full time step(s) of the same {s.n}-particle torus system, FP64, "
+                      f"linked cells, OpenMP; {t:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10000)
+    ap.add_argument("--warmup", type=int, default=300)
+    ap.add_argument("--n", type=int, default=2_000_000)
+    ap.add_argument("--skin", type=float, default=0.3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-graph", action="store_true", help="launch steps one by one instead of hipGraph chunks")
+    args = ap.parse_args()
+    if args.no_graph:
+        os.environ["MD_NO_GRAPH"] = "1"
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the single-system step would shard as described in DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+
+    from paper_1411_3019_amd import md
+    from workloads import gen
+
+    t0 = time.perf_counter()
+    s, run = gen.torus_lj_2m(args.n)
+    log(f"[bench] generated {s.n} particles on the torus in {time.perf_counter() - t0:.1f} s")
+    prm = md.Params(dt=run["dt"], kT=run["kT"], gamma=run["gamma"], eps=run["eps"], sigma=run["sigma"],
+                    rc=run["rc"], pair=run["pair"], force_fp64=run["force_fp64"], skin=args.skin, seed=run["seed"])
+    sysm = md.System(prm, s.surface, s.surf)
+    sysm.set_particles(s.x, s.p)
+    sysm.step(args.warmup)
+    device_sync()
+    st0 = sysm.stats()
+    t0 = time.perf_counter()
+    sysm.step(args.steps)
+    device_sync()
+    wall = time.perf_counter() - t0
+    st1 = sysm.stats()
+    state = sysm.get_state(want_force=False)
+    sysm.close()
+    d = state["diag"]
+    log(f"[bench] {args.steps} steps in {wall:.3f} s; kT={d['kT']:.4f} gdist={d['gdist_max']:.2e} "
+        f"nv={d['nv_max']:.2e} newton_max={d['newton_iter_max']} nl_max={d['nlist_max']}")
+
+    launches = st1["step_launches"] - st0["step_launches"]
+    kern_ms = st1["step_kernel_ms"] - st0["step_kernel_ms"]
+    builds = st1["builds"] - st0["builds"]
+    rebuild_ms = st1["rebuild_ms"] - st0["rebuild_ms"]
+    per_launch_s = kern_ms * 1e-3 / max(1, launches)
+    bytes_launch = s.n * step_kernel_bytes(st1["nl_mean"])
+    achieved = bytes_launch / per_launch_s / 1e9
+    traffic = traffic_for(s.n, "step")
+    value = s.n * args.steps / wall
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64/f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "torus_lj_2m",
+            "n": s.n,
+            "surface": f"torus Rt={s.meta['Rt']:.3f} r={s.meta['r']:.3f} (area fraction 0.4)",
+            "pair": "LJ truncated-shifted, rc=2.5", "dt": run["dt"], "gamma": run["gamma"], "kT": run["kT"],
+            "forces": "fp32", "state": "fp64", "skin": args.skin, "parallelism": "1 GPU",
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "kernel": "k_step<fp32 forces>", "mean_launch_us": per_launch_s * 1e6,
+            "alg_bytes_per_particle_step": step_kernel_bytes(st1["nl_mean"]), "nl_mean": st1["nl_mean"],
+        },
+        "breakdown": {
+            "step_kernel_ms": kern_ms, "launches": launches, "builds": builds, "build_ms": rebuild_ms,
+            "wall_ms": wall * 1e3,
+        },
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] timing the FP64 oracle on the host (bounded sample)")
+        out["cpu_baseline"] = cpu_baseline(s, run)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

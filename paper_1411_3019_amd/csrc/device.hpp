@@ -1,0 +1,404 @@
+// device.hpp -- per-particle device math for the RATTLE + Langevin step.
+//
+// Everything here is FP64 except the optional FP32 pair-force path.  The
+// constants of the Philox4x32-10 generator are those published by Salmon et
+// al. (SC'11).  The RATTLE position stage is the scalar form of the Newton
+// iteration of Algorithm 1: because the first three rows of its Jacobian are
+// -I, J^{-1} r reduces to one scalar update of lambda per iteration, which is
+// the analytic solve the paper reports as fastest (SI Section S2).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+namespace mdk {
+
+constexpr int kTile = 256;          // particles per workgroup in per-particle kernels
+constexpr int kNlistBlock = 64;     // one wavefront per workgroup in the list build
+
+enum : int { kSurfNone = 0, kSurfPlane = 1, kSurfSphere = 2, kSurfEllipsoid = 3, kSurfTorus = 4,
+             kSurfCylinder = 5, kSurfHeight = 6 };
+enum : int { kPairNone = 0, kPairLJ = 1, kPairLJSmooth = 2 };
+enum : int { kModeSteady = 0, kModeStart = 1, kModeStartGiven = 2 };
+enum : int { kFlagStale = 1, kFlagError = 2 };
+enum : int { kErrNewton = 1, kErrNaN = 2 };
+
+// Per-job constants, written by the host before each launch set.
+struct JobDev {
+  double dt, half_dt, gamma, b;     // b = 1 / (1 + dt gamma / 2)        (Algorithm S1)
+  double noise_k;                   // sqrt(2 kT gamma / dt); times sqrt(m) per particle
+  double mass, inv_mass;            // used when uniform_mass
+  double eps, sig2, rc2, rlist2;    // pair parameters; rlist = rc + skin
+  double phic, dphic;               // phi(rc) and phi'(rc)              (Eq. S1)
+  double half_skin;
+  double newton_tol;
+  double surf[8];
+  double box_len[3], inv_box_len[3];
+  double glo[3], inv_cs[3];
+  int nc[3];
+  int periodic[3];
+  int surf_kind, pair_kind, force_fp64, uniform_mass;
+  int newton_cap, mode, xcur, pcur;
+  int scur, pad0;
+  uint64_t seed;
+  int64_t off, n, bm_off;
+  int64_t step0, remaining;
+};
+
+// Per-job bookkeeping written by the device.
+struct JobBook {
+  double acc[2];                    // accumulated max displacement, by step parity
+  unsigned long long dmax[3];       // per-step max displacement (bit pattern of a double >= 0)
+  int flags;                        // kFlagStale | kFlagError
+  int err_code;
+  int err_id;
+  int newton_max;
+  int nl_max;
+  int pad1;
+  long long stale_step;
+  unsigned long long nl_sum;        // neighbours summed over the job's particles at the last build
+};
+
+// Device buffers, passed by value to every kernel.
+struct DevBufs {
+  double* X[2];        // positions, SoA [3][C]; parity flips every step
+  double* P[2];        // momenta, SoA [3][C]; parity flips at rebuilds
+  uint32_t* ID[2];     // particle index within its job; parity flips at rebuilds
+  uint8_t* FLG[2];     // 1 = constrained
+  double* MASS[2];     // per-particle mass (jobs with non-uniform mass)
+  double* FC;          // combined force handed in by the caller, SoA [3][C], by job offset + id
+  double* OX;          // outputs of the finish kernel, by job offset + id
+  double* OP;
+  double* OF;
+  double* OD;          // [4][C]: kinetic energy, potential energy share, |g|/|n|, |n.v|/|n|
+  uint32_t* NL;        // neighbour slots, column-major [kmax][C]
+  uint32_t* NCNT;      // neighbour count per slot
+  uint32_t* BM;        // occupied-cell bitmap words (per job segment)
+  uint32_t* WOFF;      // exclusive popcount prefix per bitmap word (job-local)
+  uint32_t* CCNT;      // particles per occupied cell, at job offset + compact cell
+  uint32_t* CSTART;    // exclusive prefix of CCNT (job-local)
+  uint32_t* RASTER;    // raster cell index per slot
+  uint32_t* CID;       // compact cell index per slot
+  uint32_t* RANK;      // rank within the cell per slot
+  JobDev* jobs;
+  JobBook* book;
+  int64_t C;           // slot capacity (SoA stride)
+  int kmax;
+  int pad2;
+};
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 and Box-Muller normals.
+// Counter (id, step lo, step hi, 0), key (seed lo, seed hi);
+// u = (w + 1/2) 2^-32; z0, z1 from (w0, w1), z2 from (w2, w3).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32_t& c2, uint32_t& c3,
+                                              uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
+    const uint32_t lo0 = 0xD2511F53u * c0;
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
+    const uint32_t lo1 = 0xCD9E8D57u * c2;
+    const uint32_t n0 = hi1 ^ c1 ^ k0;
+    const uint32_t n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+}
+
+__device__ __forceinline__ void normals3(uint64_t seed, uint32_t id, long long step, double& z0, double& z1,
+                                         double& z2) {
+  uint32_t c0 = id, c1 = (uint32_t)(unsigned long long)step, c2 = (uint32_t)((unsigned long long)step >> 32),
+           c3 = 0u;
+  philox4x32_10(c0, c1, c2, c3, (uint32_t)seed, (uint32_t)(seed >> 32));
+  const double inv32 = 2.3283064365386963e-10;  // 2^-32
+  const double u0 = ((double)c0 + 0.5) * inv32;
+  const double u1 = ((double)c1 + 0.5) * inv32;
+  const double u2 = ((double)c2 + 0.5) * inv32;
+  const double u3 = ((double)c3 + 0.5) * inv32;
+  const double r0 = sqrt(-2.0 * log(u0));
+  const double r1 = sqrt(-2.0 * log(u2));
+  double s1, co1;
+  sincospi(2.0 * u1, &s1, &co1);
+  z0 = r0 * co1;
+  z1 = r0 * s1;
+  z2 = r1 * cospi(2.0 * u3);
+}
+
+// The same normals with the Box-Muller transform in FP32 on the hardware
+// transcendental units (v_log_f32; v_sin_f32 / v_cos_f32 take their argument in
+// revolutions, so sin(2 pi u) is one instruction).  Used with FP32 pair forces;
+// the normals differ from the FP64 transform by ~1e-6 relative.
+__device__ __forceinline__ void normals3_fast(uint64_t seed, uint32_t id, long long step, double& z0, double& z1,
+                                              double& z2) {
+  uint32_t c0 = id, c1 = (uint32_t)(unsigned long long)step, c2 = (uint32_t)((unsigned long long)step >> 32),
+           c3 = 0u;
+  philox4x32_10(c0, c1, c2, c3, (uint32_t)seed, (uint32_t)(seed >> 32));
+  const double inv32 = 2.3283064365386963e-10;  // 2^-32
+  const float u0 = (float)(((double)c0 + 0.5) * inv32);
+  const float u1 = (float)(((double)c1 + 0.5) * inv32);
+  const float u2 = (float)(((double)c2 + 0.5) * inv32);
+  const float u3 = (float)(((double)c3 + 0.5) * inv32);
+  const float r0 = sqrtf(-2.0f * __logf(u0));
+  const float r1 = sqrtf(-2.0f * __logf(u2));
+  z0 = (double)(r0 * __builtin_amdgcn_cosf(u1));
+  z1 = (double)(r0 * __builtin_amdgcn_sinf(u1));
+  z2 = (double)(r1 * __builtin_amdgcn_cosf(u3));
+}
+
+template <bool kF64>
+__device__ __forceinline__ void langevin_normals(uint64_t seed, uint32_t id, long long step, double& z0, double& z1,
+                                                 double& z2) {
+  if (kF64)
+    normals3(seed, id, step, z0, z1, z2);
+  else
+    normals3_fast(seed, id, step, z0, z1, z2);
+}
+
+// ---------------------------------------------------------------------------
+// Surfaces: g(x) and n = dg/dx (un-normalised, Eq. 4).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double surf_eval(const JobDev& J, double x, double y, double z, double& nx, double& ny,
+                                            double& nz) {
+  const double* q = J.surf;
+  switch (J.surf_kind) {
+    case kSurfPlane:
+      nx = q[3];
+      ny = q[4];
+      nz = q[5];
+      return q[3] * (x - q[0]) + q[4] * (y - q[1]) + q[5] * (z - q[2]);
+    case kSurfSphere: {
+      const double d0 = x - q[0], d1 = y - q[1], d2 = z - q[2];
+      nx = 2.0 * d0;
+      ny = 2.0 * d1;
+      nz = 2.0 * d2;
+      return d0 * d0 + d1 * d1 + d2 * d2 - q[3] * q[3];
+    }
+    case kSurfEllipsoid: {
+      // q[3..5] hold 1/a^2, 1/b^2, 1/c^2 on the device
+      const double d0 = x - q[0], d1 = y - q[1], d2 = z - q[2];
+      nx = 2.0 * d0 * q[3];
+      ny = 2.0 * d1 * q[4];
+      nz = 2.0 * d2 * q[5];
+      return d0 * d0 * q[3] + d1 * d1 * q[4] + d2 * d2 * q[5] - 1.0;
+    }
+    case kSurfTorus: {
+      const double d0 = x - q[0], d1 = y - q[1], d2 = z - q[2];
+      const double rho = sqrt(d0 * d0 + d1 * d1);
+      const double e = rho - q[3];
+      const double s = 2.0 * (1.0 - q[3] / rho);
+      nx = s * d0;
+      ny = s * d1;
+      nz = 2.0 * d2;
+      return e * e + d2 * d2 - q[4] * q[4];
+    }
+    case kSurfCylinder: {
+      const double d0 = x - q[0], d1 = y - q[1], d2 = z - q[2];
+      nx = 2.0 * q[3] * d0;
+      ny = 2.0 * q[4] * d1;
+      nz = 2.0 * q[5] * d2;
+      return q[3] * d0 * d0 + q[4] * d1 * d1 + q[5] * d2 * d2 - q[6] * q[6];
+    }
+    case kSurfHeight: {
+      // q[2], q[3] hold 2/Lx, 2/Ly on the device (sinpi/cospi arguments)
+      double sx, cx, sy, cy;
+      sincospi(q[2] * x, &sx, &cx);
+      sincospi(q[3] * y, &sy, &cy);
+      const double kx = M_PI * q[2], ky = M_PI * q[3];
+      nx = -q[1] * kx * cx * sy;
+      ny = -q[1] * ky * sx * cy;
+      nz = 1.0;
+      return z - q[0] - q[1] * sx * sy;
+    }
+    default:
+      nx = ny = nz = 0.0;
+      return 0.0;
+  }
+}
+
+__device__ __forceinline__ double maxabs3(double a, double b, double c) {
+  return fmax(fabs(a), fmax(fabs(b), fabs(c)));
+}
+
+// ---------------------------------------------------------------------------
+// RATTLE position stage (Algorithm 1, first loop) for one particle.
+// Input: x^m, the half-kicked momentum pt = p^m + dt/2 f^m, n^m = n(x^m) and
+// g(x^m).  Output: x^{m+1} = x~ - c lambda n^m and p^{m+1/2} = pt - dt/2 lambda n^m
+// with x~ = x^m + dt/m pt and c = dt^2/(2m).
+// Newton iterates (identical to Algorithm 1's 4x4 iteration):
+//   first:  lambda = [g(x^m) + n^m.(x~ - x^m)] / (c n^m.n^m)
+//   then:   lambda += g(x') / (c n(x').n^m),  x' = x~ - c lambda n^m
+// Stop: eta > 0: max(|g(x')|, |r_x|_inf) < eta (residual before the update);
+//       eta = 0: position update within 16 ulp of max(1, |x'|_inf).
+// Returns the iteration count, or -count when the cap was hit.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int rattle_position(const JobDev& J, double m, double x0, double y0, double z0,
+                                               double g0, double nx, double ny, double nz, double& px,
+                                               double& py, double& pz, double& x1, double& y1, double& z1) {
+  const double dtm = J.dt / m;
+  const double c = J.dt * dtm * 0.5;
+  const double xt = x0 + dtm * px, yt = y0 + dtm * py, zt = z0 + dtm * pz;
+  const double eps16 = 16.0 * 2.220446049250313e-16;
+  // iteration 1: linearisation at x^m (the start x' = x^m, lambda = 0 of Algorithm 1)
+  const double rx = xt - x0, ry = yt - y0, rz = zt - z0;
+  const double nn = nx * nx + ny * ny + nz * nz;
+  double lam = (g0 + nx * rx + ny * ry + nz * rz) / (c * nn);
+  double xc = xt - c * lam * nx, yc = yt - c * lam * ny, zc = zt - c * lam * nz;
+  bool done;
+  if (J.newton_tol > 0.0) {
+    done = fmax(fabs(g0), maxabs3(rx, ry, rz)) < J.newton_tol;
+  } else {
+    const double upd = maxabs3(xc - x0, yc - y0, zc - z0);
+    done = upd <= eps16 * fmax(1.0, maxabs3(xc, yc, zc));
+  }
+  int it = 1;
+  while (!done && it < J.newton_cap) {
+    ++it;
+    double mx, my, mz;
+    const double g = surf_eval(J, xc, yc, zc, mx, my, mz);
+    const double dl = g / (c * (mx * nx + my * ny + mz * nz));
+    lam += dl;
+    const double xn = xt - c * lam * nx, yn = yt - c * lam * ny, zn = zt - c * lam * nz;
+    if (J.newton_tol > 0.0) {
+      done = fabs(g) < J.newton_tol;
+    } else {
+      done = maxabs3(xn - xc, yn - yc, zn - zc) <= eps16 * fmax(1.0, maxabs3(xn, yn, zn));
+    }
+    xc = xn;
+    yc = yn;
+    zc = zn;
+  }
+  x1 = xc;
+  y1 = yc;
+  z1 = zc;
+  const double hl = J.half_dt * lam;
+  px -= hl * nx;
+  py -= hl * ny;
+  pz -= hl * nz;
+  return done ? it : -it;
+}
+
+// Minimum image along periodic dimensions.
+__device__ __forceinline__ void min_image(const JobDev& J, double& dx, double& dy, double& dz) {
+  if (J.periodic[0]) dx -= J.box_len[0] * rint(dx * J.inv_box_len[0]);
+  if (J.periodic[1]) dy -= J.box_len[1] * rint(dy * J.inv_box_len[1]);
+  if (J.periodic[2]) dz -= J.box_len[2] * rint(dz * J.inv_box_len[2]);
+}
+
+// Force coefficient c of one pair, F_i += c (x_i - x_j), for r^2 < rc^2
+// (Eq. S1: -dV/dr / r); zero beyond the cut-off.
+template <typename real>
+__device__ __forceinline__ real pair_coef(const JobDev& J, double r2, real eps24, real sig2, real dphic, bool smooth) {
+  if (!(r2 < J.rc2)) return (real)0;
+  const real r2r = (real)r2;
+  const real inv = (real)1 / r2r;
+  const real s2 = sig2 * inv;
+  const real s6 = s2 * s2 * s2;
+  real coef = eps24 * inv * s6 * ((real)2 * s6 - (real)1);
+  if (smooth) {
+    const real rinv = sizeof(real) == 8 ? (real)(1.0 / sqrt((double)r2r)) : (real)rsqrtf((float)r2r);
+    coef += dphic * rinv;
+  }
+  return coef;
+}
+
+// Pair forces on slot i from its neighbour list, summed in list order (the
+// list is sorted by particle index).  FP32 variant: separations and the
+// cut-off test in FP64, the force in FP32 with FP32 accumulation.  The loop
+// issues the gathers of four neighbours before using them; the additions
+// still happen one neighbour at a time in list order.
+template <bool kF64>
+__device__ __forceinline__ void pair_forces(const JobDev& J, const DevBufs& B, const double* __restrict__ X,
+                                            int64_t i, double xi, double yi, double zi, double& Fx, double& Fy,
+                                            double& Fz) {
+  using real = typename std::conditional<kF64, double, float>::type;
+  const int64_t C = B.C;
+  const int cnt = (int)B.NCNT[i];
+  const uint32_t* __restrict__ nl = B.NL + i;
+  real fx = 0, fy = 0, fz = 0;
+  const real eps24 = (real)(24.0 * J.eps);
+  const real sig2 = (real)J.sig2;
+  const real dphic = (real)J.dphic;
+  const bool smooth = J.pair_kind == kPairLJSmooth;
+  const bool anyper = J.periodic[0] | J.periodic[1] | J.periodic[2];
+  int k = 0;
+  for (; k + 4 <= cnt; k += 4) {
+    int64_t j[4];
+    double ax[4], ay[4], az[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) j[u] = nl[(int64_t)(k + u) * C];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      ax[u] = X[j[u]];
+      ay[u] = X[C + j[u]];
+      az[u] = X[2 * C + j[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      double dx = xi - ax[u], dy = yi - ay[u], dz = zi - az[u];
+      if (anyper) min_image(J, dx, dy, dz);
+      const double r2 = dx * dx + dy * dy + dz * dz;
+      const real c = pair_coef<real>(J, r2, eps24, sig2, dphic, smooth);
+      fx += c * (real)dx;
+      fy += c * (real)dy;
+      fz += c * (real)dz;
+    }
+  }
+  for (; k < cnt; ++k) {
+    const int64_t j = nl[(int64_t)k * C];
+    double dx = xi - X[j], dy = yi - X[C + j], dz = zi - X[2 * C + j];
+    if (anyper) min_image(J, dx, dy, dz);
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    const real c = pair_coef<real>(J, r2, eps24, sig2, dphic, smooth);
+    fx += c * (real)dx;
+    fy += c * (real)dy;
+    fz += c * (real)dz;
+  }
+  Fx = (double)fx;
+  Fy = (double)fy;
+  Fz = (double)fz;
+}
+
+// Energy share U_i = 1/2 sum_j V_ij (Eq. S1), FP64, for diagnostics.
+__device__ __forceinline__ double pair_energy(const JobDev& J, const DevBufs& B, const double* __restrict__ X,
+                                              int64_t i, double xi, double yi, double zi) {
+  const int64_t C = B.C;
+  const int cnt = (int)B.NCNT[i];
+  const bool smooth = J.pair_kind == kPairLJSmooth;
+  const bool anyper = J.periodic[0] | J.periodic[1] | J.periodic[2];
+  const double rc = sqrt(J.rc2);
+  double u = 0.0;
+  for (int k = 0; k < cnt; ++k) {
+    const int64_t j = B.NL[(int64_t)k * C + i];
+    double dx = xi - X[j], dy = yi - X[C + j], dz = zi - X[2 * C + j];
+    if (anyper) min_image(J, dx, dy, dz);
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    if (!(r2 < J.rc2)) continue;
+    const double s2 = J.sig2 / r2;
+    const double s6 = s2 * s2 * s2;
+    double v = 4.0 * J.eps * s6 * (s6 - 1.0) - J.phic;
+    if (smooth) v -= (sqrt(r2) - rc) * J.dphic;
+    u += 0.5 * v;
+  }
+  return u;
+}
+
+// XCD-aware workgroup order: the dispatcher deals workgroups round-robin over
+// the 8 XCDs; remap so that each XCD walks one contiguous range of tiles
+// (neighbouring tiles share neighbour data in that XCD's L2).
+__device__ __forceinline__ int xcd_remap(int b, int G) {
+  const int xcd = b & 7;
+  const int local = b >> 3;
+  const int per = G >> 3;
+  const int rem = G & 7;
+  return xcd * per + (xcd < rem ? xcd : rem) + local;
+}
+
+}  // namespace mdk

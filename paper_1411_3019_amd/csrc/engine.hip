@@ -1,0 +1,1303 @@
+// engine.hip -- host engine and C ABI (include/md.h) of the RATTLE + Langevin
+// hot path on MI355X.
+//
+// An Engine holds the device state of one or more jobs (systems) in
+// concatenated SoA arrays, a job table, and the tile lists that let one
+// launch cover every resident job.  md_ctx is an Engine with one job; md_pool
+// is an Engine with many.
+//
+// Time stepping: chunks of k step launches are captured once into a hipGraph
+// and replayed; the device flags a job whose neighbour list would go stale
+// (accumulated maximum displacement above skin/2) and skips its remaining
+// launches; after each chunk the host reads the per-job bookkeeping, rebuilds
+// the lists of the jobs that need it and chooses the next chunk length from
+// the observed displacement rate.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <new>
+#include <vector>
+
+#include "../../include/md.h"
+#include "kernels.hpp"
+
+using namespace mdk;
+
+namespace {
+
+constexpr int kDefaultKmax = 16;
+constexpr int kMaxChunk = 64;
+constexpr int kPoolChunk = 32;
+
+#define HIPCHK(expr)                   \
+  do {                                 \
+    hipError_t e_ = (expr);            \
+    if (e_ != hipSuccess) {            \
+      (void)hipGetLastError();         \
+      return MD_EHIP;                  \
+    }                                  \
+  } while (0)
+
+#define MDCHK(expr)        \
+  do {                     \
+    int r_ = (expr);       \
+    if (r_ != MD_OK) return r_; \
+  } while (0)
+
+int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+// ---------------------------------------------------------------------------
+// First-fit allocator over an index range (particle slots, bitmap words).
+// ---------------------------------------------------------------------------
+class FirstFit {
+ public:
+  void reset(int64_t cap) {
+    free_.clear();
+    if (cap > 0) free_[0] = cap;
+    cap_ = cap;
+  }
+  int64_t alloc(int64_t len, int64_t align) {
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      const int64_t start = round_up(it->first, align);
+      const int64_t end = it->first + it->second;
+      if (start + len <= end) {
+        const int64_t f0 = it->first;
+        free_.erase(it);
+        if (start > f0) free_[f0] = start - f0;
+        if (start + len < end) free_[start + len] = end - (start + len);
+        return start;
+      }
+    }
+    return -1;
+  }
+  void release(int64_t off, int64_t len) {
+    if (len <= 0) return;
+    auto next = free_.lower_bound(off);
+    if (next != free_.end() && off + len == next->first) {
+      len += next->second;
+      free_.erase(next);
+    }
+    auto it = free_.lower_bound(off);
+    if (it != free_.begin()) {
+      auto prev = std::prev(it);
+      if (prev->first + prev->second == off) {
+        prev->second += len;
+        return;
+      }
+    }
+    free_[off] = len;
+  }
+  int64_t cap() const { return cap_; }
+
+ private:
+  std::map<int64_t, int64_t> free_;
+  int64_t cap_ = 0;
+};
+
+// ---------------------------------------------------------------------------
+// Host-side surface evaluation (input validation only).
+// ---------------------------------------------------------------------------
+int surf_nprm(int kind) {
+  switch (kind) {
+    case MD_SURF_NONE: return 0;
+    case MD_SURF_PLANE: return 6;
+    case MD_SURF_SPHERE: return 4;
+    case MD_SURF_ELLIPSOID: return 6;
+    case MD_SURF_TORUS: return 5;
+    case MD_SURF_CYLINDER: return 7;
+    case MD_SURF_HEIGHT: return 4;
+    default: return -1;
+  }
+}
+
+double host_g(int kind, const double* q, const double* x, double* n) {
+  const double d0 = x[0] - q[0], d1 = x[1] - q[1], d2 = x[2] - q[2];
+  switch (kind) {
+    case MD_SURF_PLANE:
+      n[0] = q[3], n[1] = q[4], n[2] = q[5];
+      return q[3] * d0 + q[4] * d1 + q[5] * d2;
+    case MD_SURF_SPHERE:
+      n[0] = 2 * d0, n[1] = 2 * d1, n[2] = 2 * d2;
+      return d0 * d0 + d1 * d1 + d2 * d2 - q[3] * q[3];
+    case MD_SURF_ELLIPSOID: {
+      const double a = 1.0 / (q[3] * q[3]), b = 1.0 / (q[4] * q[4]), c = 1.0 / (q[5] * q[5]);
+      n[0] = 2 * d0 * a, n[1] = 2 * d1 * b, n[2] = 2 * d2 * c;
+      return d0 * d0 * a + d1 * d1 * b + d2 * d2 * c - 1.0;
+    }
+    case MD_SURF_TORUS: {
+      const double rho = std::sqrt(d0 * d0 + d1 * d1);
+      const double s = 2.0 * (1.0 - q[3] / rho);
+      n[0] = s * d0, n[1] = s * d1, n[2] = 2 * d2;
+      return (rho - q[3]) * (rho - q[3]) + d2 * d2 - q[4] * q[4];
+    }
+    case MD_SURF_CYLINDER:
+      n[0] = 2 * q[3] * d0, n[1] = 2 * q[4] * d1, n[2] = 2 * q[5] * d2;
+      return q[3] * d0 * d0 + q[4] * d1 * d1 + q[5] * d2 * d2 - q[6] * q[6];
+    case MD_SURF_HEIGHT: {
+      const double kx = 2 * M_PI / q[2], ky = 2 * M_PI / q[3];
+      n[0] = -q[1] * kx * std::cos(kx * x[0]) * std::sin(ky * x[1]);
+      n[1] = -q[1] * ky * std::sin(kx * x[0]) * std::cos(ky * x[1]);
+      n[2] = 1.0;
+      return x[2] - q[0] - q[1] * std::sin(kx * x[0]) * std::sin(ky * x[1]);
+    }
+    default:
+      n[0] = n[1] = n[2] = 0;
+      return 0;
+  }
+}
+
+double lj_phi(double eps, double sigma, double r, double* dphi) {
+  const double sr = sigma / r;
+  const double s6 = sr * sr * sr * sr * sr * sr;
+  *dphi = -24.0 * eps * (2.0 * s6 * s6 - s6) / r;
+  return 4.0 * eps * (s6 * s6 - s6);
+}
+
+int validate_params(const md_params& p) {
+  if (!(p.dt > 0.0) || !(p.kT >= 0.0) || !(p.gamma >= 0.0)) return MD_EINVAL;
+  if (p.pair_kind < MD_PAIR_NONE || p.pair_kind > MD_PAIR_LJ_SMOOTH) return MD_EINVAL;
+  if (p.pair_kind != MD_PAIR_NONE && (!(p.eps >= 0.0) || !(p.sigma > 0.0) || !(p.rc > 0.0))) return MD_EINVAL;
+  if (p.skin < 0.0 || p.newton_tol < 0.0 || p.newton_max_iter < 0) return MD_EINVAL;
+  for (int k = 0; k < 3; ++k)
+    if (p.periodic[k] && !(p.box_hi[k] > p.box_lo[k])) return MD_EINVAL;
+  return MD_OK;
+}
+
+// Bytes of device state per particle slot (excluding the neighbour list).
+constexpr int64_t kSlotBytes = 2 * 24 /*X*/ + 2 * 24 /*P*/ + 2 * 4 /*ID*/ + 2 * 1 /*FLG*/ + 2 * 8 /*MASS*/ +
+                               24 /*FC*/ + 3 * 24 /*OX,OP,OF*/ + 32 /*OD*/ + 4 /*NCNT*/ + 4 * 5 /*rebuild*/;
+
+struct HostJob {
+  bool used = false;
+  md_params prm{};
+  int surf_kind = MD_SURF_NONE;
+  double surf[MD_SURF_MAXPRM] = {0};
+  int64_t n = 0, off = 0, seg = 0, bm_off = 0, bm_words = 0;
+  JobDev dev{};
+  int64_t step = 0, target = 0;
+  int64_t last_build = 0, rebuilds = 0;
+  bool built = false, done = false, reported = false;
+  int status = MD_OK;
+  int newton_max = 0, nl_max = 0, err_id = -1;
+  double A_now = 0.0;
+  double rate_prev = 0.0;  // displacement per step while the previous list was in use
+  double ndof = 0.0;
+};
+
+// Per-job cell grid over the region the particles can occupy.
+int make_grid(HostJob& h, const double* x) {
+  JobDev& d = h.dev;
+  const double rlist = std::sqrt(d.rlist2);
+  double lo[3], hi[3];
+  bool have[3] = {false, false, false};
+  const double* q = h.surf;
+  switch (h.surf_kind) {
+    case MD_SURF_SPHERE:
+      for (int k = 0; k < 3; ++k) lo[k] = q[k] - q[3], hi[k] = q[k] + q[3], have[k] = true;
+      break;
+    case MD_SURF_ELLIPSOID:
+      for (int k = 0; k < 3; ++k) lo[k] = q[k] - q[3 + k], hi[k] = q[k] + q[3 + k], have[k] = true;
+      break;
+    case MD_SURF_TORUS:
+      for (int k = 0; k < 2; ++k) lo[k] = q[k] - q[3] - q[4], hi[k] = q[k] + q[3] + q[4], have[k] = true;
+      lo[2] = q[2] - q[4], hi[2] = q[2] + q[4], have[2] = true;
+      break;
+    case MD_SURF_CYLINDER:
+      for (int k = 0; k < 3; ++k)
+        if (q[3 + k] != 0.0) lo[k] = q[k] - q[6], hi[k] = q[k] + q[6], have[k] = true;
+      break;
+    case MD_SURF_HEIGHT:
+      lo[2] = q[0] - std::fabs(q[1]), hi[2] = q[0] + std::fabs(q[1]), have[2] = true;
+      break;
+    default:
+      break;
+  }
+  const bool free_particles = h.surf_kind == MD_SURF_NONE;
+  int64_t total = 1;
+  for (int k = 0; k < 3; ++k) {
+    double a, b;
+    if (h.prm.periodic[k]) {
+      a = h.prm.box_lo[k];
+      b = h.prm.box_hi[k];
+      const double L = b - a;
+      if (L < 2.0 * rlist) return MD_EINVAL;
+      int nc = (int)std::floor(L / rlist);
+      nc = std::max(1, std::min(nc, 1 << 20));
+      d.nc[k] = nc;
+      d.glo[k] = a;
+      d.inv_cs[k] = nc / L;
+      d.box_len[k] = L;
+      d.inv_box_len[k] = 1.0 / L;
+      d.periodic[k] = 1;
+    } else {
+      if (h.prm.box_hi[k] > h.prm.box_lo[k]) {
+        a = h.prm.box_lo[k];
+        b = h.prm.box_hi[k];
+      } else if (have[k] && !free_particles) {
+        a = lo[k] - rlist;
+        b = hi[k] + rlist;
+      } else {
+        a = b = h.n > 0 ? x[k] : 0.0;
+        for (int64_t i = 1; i < h.n; ++i) a = std::min(a, x[3 * i + k]), b = std::max(b, x[3 * i + k]);
+        a -= rlist;
+        b += rlist;
+      }
+      const double L = b - a;
+      int nc = (int)std::floor(L / rlist);
+      nc = std::max(1, std::min(nc, 1 << 20));
+      d.nc[k] = nc;
+      d.glo[k] = a;
+      d.inv_cs[k] = nc / L;
+      d.box_len[k] = L;
+      d.inv_box_len[k] = 1.0 / L;
+      d.periodic[k] = 0;
+    }
+    total *= d.nc[k];
+  }
+  // keep raster indices within 32 bits by coarsening the grid if needed
+  while (total > 0xF0000000LL) {
+    total = 1;
+    for (int k = 0; k < 3; ++k) {
+      if (d.nc[k] > 3) {
+        const int nc = d.nc[k] / 2;
+        d.inv_cs[k] = d.inv_cs[k] * nc / d.nc[k];
+        d.nc[k] = nc;
+      }
+      total *= d.nc[k];
+    }
+  }
+  h.bm_words = total / 32 + 1;  // one spare word: the end of the last z-run is addressable
+  return MD_OK;
+}
+
+struct GraphKey {
+  int k;
+  bool operator<(const GraphKey& o) const { return k < o.k; }
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Engine
+// ---------------------------------------------------------------------------
+struct Engine {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int64_t C = 0;        // slot capacity
+  int64_t BMW = 0;      // bitmap word capacity
+  int max_jobs = 0;
+  int kmax = kDefaultKmax;
+  DevBufs B{};
+  std::vector<HostJob> jobs;
+  FirstFit slots, words;
+  // device scratch for launch descriptors
+  int* step_tiles_job = nullptr;       // [2][tile_cap]: fp64-force tiles, then fp32-force tiles
+  int64_t* step_tiles_first = nullptr;
+  int* step_counts = nullptr;          // [2]: tiles in each list (read by the step kernel)
+  int grid64 = 0, grid32 = 0;          // grid sizes baked into the cached graphs
+  int* aux_tiles_job = nullptr;        // rebuild / finish lists
+  int64_t* aux_tiles_first = nullptr;
+  int64_t tile_cap = 0;
+  Chunk* chunks_d = nullptr;
+  uint32_t* chunk_sums = nullptr;
+  int64_t chunk_cap = 0;
+  Range* ranges_d = nullptr;
+  int64_t range_cap = 0;
+  // pinned host staging
+  JobBook* book_h = nullptr;
+  char* stage = nullptr;
+  size_t stage_cap = 0;
+  // step graphs
+  std::map<GraphKey, hipGraphExec_t> graphs;
+  bool step_tiles_valid = false;
+  md_stats stats{};
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  std::vector<int> last_tj[2];
+  std::vector<int64_t> last_tf[2];
+  size_t nl_bytes = 0;
+
+  ~Engine() { release(); }
+
+  void drop_graphs() {
+    for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    graphs.clear();
+  }
+
+  void release() {
+    if (device >= 0) (void)hipSetDevice(device);
+    drop_graphs();
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e), e = nullptr;
+    void* ptrs[] = {B.X[0], B.X[1], B.P[0], B.P[1], B.ID[0], B.ID[1], B.FLG[0], B.FLG[1], B.MASS[0], B.MASS[1],
+                    B.FC, B.OX, B.OP, B.OF, B.OD, B.NL, B.NCNT, B.BM, B.WOFF, B.CCNT, B.CSTART, B.RASTER,
+                    B.CID, B.RANK, B.jobs, B.book, step_tiles_job, step_tiles_first, step_counts, aux_tiles_job,
+                    aux_tiles_first, chunks_d, chunk_sums, ranges_d};
+    for (void* p : ptrs)
+      if (p) (void)hipFree(p);
+    std::memset(&B, 0, sizeof(B));
+    step_tiles_job = nullptr;
+    step_counts = nullptr;
+    step_tiles_first = aux_tiles_first = nullptr;
+    aux_tiles_job = nullptr;
+    chunks_d = nullptr;
+    chunk_sums = nullptr;
+    ranges_d = nullptr;
+    if (book_h) (void)hipHostFree(book_h);
+    if (stage) (void)hipHostFree(stage);
+    book_h = nullptr;
+    stage = nullptr;
+    stage_cap = 0;
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
+    stream = nullptr;
+    own_stream = false;
+  }
+
+  template <class T>
+  int dalloc(T** p, size_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    if (hipMalloc((void**)p, count * sizeof(T)) != hipSuccess) {
+      (void)hipGetLastError();
+      *p = nullptr;
+      return MD_ENOMEM;
+    }
+    return MD_OK;
+  }
+
+  int init(int dev, void* user_stream, int64_t slot_cap, int64_t word_cap, int njobs) {
+    device = dev;
+    HIPCHK(hipSetDevice(dev));
+    if (user_stream) {
+      stream = (hipStream_t)user_stream;
+      own_stream = false;
+    } else {
+      HIPCHK(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
+      own_stream = true;
+    }
+    C = round_up(std::max<int64_t>(slot_cap, kTile), kTile);
+    BMW = std::max<int64_t>(word_cap, 64);
+    max_jobs = std::max(1, njobs);
+    jobs.assign(max_jobs, HostJob());
+    slots.reset(C);
+    words.reset(BMW);
+    B.C = C;
+    B.kmax = kmax;
+    for (int q = 0; q < 2; ++q) {
+      MDCHK(dalloc(&B.X[q], 3 * C));
+      MDCHK(dalloc(&B.P[q], 3 * C));
+      MDCHK(dalloc(&B.ID[q], C));
+      MDCHK(dalloc(&B.FLG[q], C));
+      MDCHK(dalloc(&B.MASS[q], C));
+    }
+    MDCHK(dalloc(&B.FC, 3 * C));
+    MDCHK(dalloc(&B.OX, 3 * C));
+    MDCHK(dalloc(&B.OP, 3 * C));
+    MDCHK(dalloc(&B.OF, 3 * C));
+    MDCHK(dalloc(&B.OD, 4 * C));
+    nl_bytes = (size_t)kmax * C * 4;
+    MDCHK(dalloc(&B.NL, (size_t)kmax * C));
+    MDCHK(dalloc(&B.NCNT, C));
+    MDCHK(dalloc(&B.BM, BMW));
+    MDCHK(dalloc(&B.WOFF, BMW));
+    MDCHK(dalloc(&B.CCNT, C));
+    MDCHK(dalloc(&B.CSTART, C));
+    MDCHK(dalloc(&B.RASTER, C));
+    MDCHK(dalloc(&B.CID, C));
+    MDCHK(dalloc(&B.RANK, C));
+    MDCHK(dalloc(&B.jobs, max_jobs));
+    MDCHK(dalloc(&B.book, max_jobs));
+    HIPCHK(hipMemsetAsync(B.book, 0, sizeof(JobBook) * max_jobs, stream));
+    HIPCHK(hipMemsetAsync(B.NCNT, 0, sizeof(uint32_t) * C, stream));
+    tile_cap = C / kTile + max_jobs + 8;
+    MDCHK(dalloc(&step_tiles_job, 2 * tile_cap));
+    MDCHK(dalloc(&step_tiles_first, 2 * tile_cap));
+    MDCHK(dalloc(&step_counts, 2));
+    HIPCHK(hipMemsetAsync(step_counts, 0, 2 * sizeof(int), stream));
+    MDCHK(dalloc(&aux_tiles_job, tile_cap));
+    MDCHK(dalloc(&aux_tiles_first, tile_cap));
+    chunk_cap = (C + max_jobs) / kScanChunk + BMW / kScanChunk + 4 * max_jobs + 16;
+    MDCHK(dalloc(&chunks_d, chunk_cap));
+    MDCHK(dalloc(&chunk_sums, chunk_cap));
+    range_cap = 2 * max_jobs + 4;
+    MDCHK(dalloc(&ranges_d, range_cap));
+    HIPCHK(hipHostMalloc((void**)&book_h, sizeof(JobBook) * max_jobs, hipHostMallocDefault));
+    for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+    HIPCHK(hipStreamSynchronize(stream));
+    return MD_OK;
+  }
+
+  // GPU time between two events recorded on the stream (both complete).
+  double elapsed_ms(hipEvent_t a, hipEvent_t b) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+      (void)hipGetLastError();
+      return 0.0;
+    }
+    return (double)ms;
+  }
+
+  // Stage host bytes in pinned memory and copy them to the device, in order on
+  // the stream.  The stream is drained first so the staging area is free.
+  int upload(void* dst, const void* src, size_t bytes) {
+    if (bytes == 0) return MD_OK;
+    HIPCHK(hipStreamSynchronize(stream));
+    if (bytes > stage_cap) {
+      if (stage) (void)hipHostFree(stage);
+      stage = nullptr;
+      stage_cap = 0;
+      HIPCHK(hipHostMalloc((void**)&stage, bytes, hipHostMallocDefault));
+      stage_cap = bytes;
+    }
+    std::memcpy(stage, src, bytes);
+    HIPCHK(hipMemcpyAsync(dst, stage, bytes, hipMemcpyHostToDevice, stream));
+    return MD_OK;
+  }
+
+  int ensure_stage(size_t bytes) {
+    HIPCHK(hipStreamSynchronize(stream));
+    if (bytes > stage_cap) {
+      if (stage) (void)hipHostFree(stage);
+      stage = nullptr;
+      stage_cap = 0;
+      HIPCHK(hipHostMalloc((void**)&stage, bytes, hipHostMallocDefault));
+      stage_cap = bytes;
+    }
+    return MD_OK;
+  }
+
+  int upload_jobs() {
+    std::vector<JobDev> tab(max_jobs);
+    for (int j = 0; j < max_jobs; ++j) tab[j] = jobs[j].dev;
+    return upload(B.jobs, tab.data(), sizeof(JobDev) * max_jobs);
+  }
+
+  int read_book() {
+    HIPCHK(hipMemcpyAsync(book_h, B.book, sizeof(JobBook) * max_jobs, hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    return MD_OK;
+  }
+
+  static void tiles_of(const HostJob& h, int j, std::vector<int>& tj, std::vector<int64_t>& tf) {
+    for (int64_t t = 0; t < h.n; t += kTile) {
+      tj.push_back(j);
+      tf.push_back(h.off + t);
+    }
+  }
+
+  // ------------------------------------------------------------------ admission
+  static void fill_constants(HostJob& h) {
+    const md_params& p = h.prm;
+    JobDev& d = h.dev;
+    d.dt = p.dt;
+    d.half_dt = 0.5 * p.dt;
+    d.gamma = p.gamma;
+    d.b = 1.0 / (1.0 + 0.5 * p.dt * p.gamma);
+    d.noise_k = p.gamma > 0.0 ? std::sqrt(2.0 * p.kT * p.gamma / p.dt) : 0.0;
+    d.eps = p.eps;
+    d.sig2 = p.sigma * p.sigma;
+    d.pair_kind = p.pair_kind;
+    const double rc = p.pair_kind != MD_PAIR_NONE ? p.rc : 0.0;
+    const double skin = p.skin > 0.0 ? p.skin : 0.3;
+    d.rc2 = rc * rc;
+    const double rl = (rc > 0.0 ? rc : 1.0) + skin;
+    d.rlist2 = rl * rl;
+    d.half_skin = 0.5 * skin;
+    if (p.pair_kind != MD_PAIR_NONE) {
+      double dphic;
+      d.phic = lj_phi(p.eps, p.sigma, p.rc, &dphic);
+      d.dphic = dphic;
+    }
+    d.force_fp64 = p.force_fp64 ? 1 : 0;
+    d.newton_tol = p.newton_tol;
+    d.newton_cap = p.newton_max_iter > 0 ? p.newton_max_iter : 32;
+    d.seed = p.seed;
+    d.surf_kind = h.surf_kind;
+    for (int k = 0; k < MD_SURF_MAXPRM; ++k) d.surf[k] = h.surf[k];
+    if (h.surf_kind == MD_SURF_ELLIPSOID)
+      for (int k = 0; k < 3; ++k) d.surf[3 + k] = 1.0 / (h.surf[3 + k] * h.surf[3 + k]);
+    if (h.surf_kind == MD_SURF_HEIGHT) {
+      d.surf[2] = 2.0 / h.surf[2];
+      d.surf[3] = 2.0 / h.surf[3];
+    }
+  }
+
+  static int validate_particles(const HostJob& h, const double* x, const double* p, const double* mass,
+                                const uint8_t* cons) {
+    for (int64_t i = 0; i < h.n; ++i) {
+      for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(x[3 * i + k]) || !std::isfinite(p[3 * i + k])) return MD_EINVAL;
+      if (mass && !(mass[i] > 0.0)) return MD_EINVAL;
+      const bool c = h.surf_kind != MD_SURF_NONE && (cons ? cons[i] != 0 : true);
+      if (!c) continue;
+      double n[3];
+      const double g = host_g(h.surf_kind, h.surf, &x[3 * i], n);
+      const double nn = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+      if (!(nn > 0.0)) return MD_EOFFSURF;
+      const double xs = std::max({1.0, std::fabs(x[3 * i]), std::fabs(x[3 * i + 1]), std::fabs(x[3 * i + 2])});
+      const double ps =
+          std::max({1.0, std::fabs(p[3 * i]), std::fabs(p[3 * i + 1]), std::fabs(p[3 * i + 2])});
+      if (std::fabs(g) / nn > 1e-9 * xs) return MD_EOFFSURF;
+      const double np = n[0] * p[3 * i] + n[1] * p[3 * i + 1] + n[2] * p[3 * i + 2];
+      if (std::fabs(np) / nn > 1e-9 * ps) return MD_EOFFSURF;
+    }
+    return MD_OK;
+  }
+
+  static int64_t seg_slots(int64_t n) { return round_up(n + 1, kTile); }
+
+  // Place a job: allocate its slots and bitmap words, upload its state.
+  int admit(const md_params& prm, int surf_kind, const double* surf, int64_t n, const double* x,
+            const double* p, const double* mass, const uint8_t* cons, const double* fcomb, int64_t step0,
+            int64_t target, int* job_id) {
+    MDCHK(validate_params(prm));
+    if (n < 0 || (n > 0 && (!x || !p)) || n > 0xFFFFFFF0LL) return MD_EINVAL;
+    int j = -1;
+    for (int q = 0; q < max_jobs; ++q)
+      if (!jobs[q].used) {
+        j = q;
+        break;
+      }
+    if (j < 0) return MD_EAGAIN;
+    HostJob h;
+    h.used = true;
+    h.prm = prm;
+    h.surf_kind = surf_kind;
+    for (int k = 0; k < MD_SURF_MAXPRM; ++k) h.surf[k] = surf ? surf[k] : 0.0;
+    h.n = n;
+    fill_constants(h);
+    MDCHK(validate_particles(h, x, p, mass, cons));
+    MDCHK(make_grid(h, x));
+    h.seg = seg_slots(n);
+    h.off = slots.alloc(h.seg, kTile);
+    if (h.off < 0) return MD_EAGAIN;
+    h.bm_off = words.alloc(h.bm_words, 1);
+    if (h.bm_off < 0) {
+      slots.release(h.off, h.seg);
+      return MD_EAGAIN;
+    }
+    JobDev& d = h.dev;
+    d.off = h.off;
+    d.n = n;
+    d.bm_off = h.bm_off;
+    d.xcur = d.pcur = d.scur = 0;
+    d.step0 = step0;
+    d.remaining = 0;
+    d.mode = fcomb ? kModeStartGiven : kModeStart;
+    bool uniform = true;
+    double m0 = mass && n > 0 ? mass[0] : 1.0;
+    if (mass)
+      for (int64_t i = 1; i < n; ++i)
+        if (mass[i] != m0) uniform = false;
+    d.uniform_mass = uniform ? 1 : 0;
+    d.mass = m0;
+    d.inv_mass = 1.0 / m0;
+    h.step = step0;
+    h.target = target;
+    h.last_build = step0;
+    // upload: SoA positions, momenta, forces; ids in order; flags; masses
+    if (n > 0) {
+      MDCHK(ensure_stage(sizeof(double) * 3 * n));
+      double* st = (double*)stage;
+      auto put_soa = [&](double* dst, const double* src) -> int {
+        HIPCHK(hipStreamSynchronize(stream));
+        for (int k = 0; k < 3; ++k)
+          for (int64_t i = 0; i < n; ++i) st[k * n + i] = src[3 * i + k];
+        for (int k = 0; k < 3; ++k)
+          HIPCHK(hipMemcpyAsync(dst + k * C + h.off, st + k * n, sizeof(double) * n, hipMemcpyHostToDevice,
+                                stream));
+        return MD_OK;
+      };
+      MDCHK(put_soa(B.X[0], x));
+      MDCHK(put_soa(B.P[0], p));
+      if (fcomb) MDCHK(put_soa(B.FC, fcomb));
+      std::vector<uint32_t> ids(n);
+      for (int64_t i = 0; i < n; ++i) ids[i] = (uint32_t)i;
+      MDCHK(upload(B.ID[0] + h.off, ids.data(), sizeof(uint32_t) * n));
+      std::vector<uint8_t> fl(n);
+      for (int64_t i = 0; i < n; ++i) fl[i] = (surf_kind != MD_SURF_NONE && (cons ? cons[i] != 0 : true)) ? 1 : 0;
+      MDCHK(upload(B.FLG[0] + h.off, fl.data(), n));
+      for (int64_t i = 0; i < n; ++i) h.ndof += fl[i] ? 2.0 : 3.0;
+      if (!uniform) MDCHK(upload(B.MASS[0] + h.off, mass, sizeof(double) * n));
+    }
+    jobs[j] = h;
+    step_tiles_valid = false;
+    *job_id = j;
+    return MD_OK;
+  }
+
+  void drop(int j) {
+    HostJob& h = jobs[j];
+    if (!h.used) return;
+    slots.release(h.off, h.seg);
+    words.release(h.bm_off, h.bm_words);
+    h = HostJob();
+    step_tiles_valid = false;
+  }
+
+  // ------------------------------------------------------------------ rebuild
+  int grow_kmax(int need) {
+    int nk = kmax;
+    while (nk < need) nk = nk + nk / 2 + 4;
+    uint32_t* nl = nullptr;
+    MDCHK(dalloc(&nl, (size_t)nk * C));
+    HIPCHK(hipMemcpyAsync(nl, B.NL, sizeof(uint32_t) * (size_t)kmax * C, hipMemcpyDeviceToDevice, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    (void)hipFree(B.NL);
+    B.NL = nl;
+    kmax = nk;
+    B.kmax = nk;
+    nl_bytes = (size_t)nk * C * 4;
+    drop_graphs();
+    return MD_OK;
+  }
+
+  int rebuild(const std::vector<int>& set) {
+    if (set.empty()) return MD_OK;
+    std::vector<int> tj;
+    std::vector<int64_t> tf;
+    std::vector<Chunk> cb, cc;
+    std::vector<Range> rb, rcnt;
+    for (int j : set) {
+      HostJob& h = jobs[j];
+      h.dev.remaining = 0;
+      tiles_of(h, j, tj, tf);
+      rb.push_back({h.bm_off, h.bm_words});
+      rcnt.push_back({h.off, h.n + 1});
+      int first = (int)cb.size();
+      for (int64_t s = 0; s < h.bm_words; s += kScanChunk)
+        cb.push_back({h.bm_off + s, (int)std::min<int64_t>(kScanChunk, h.bm_words - s), first});
+      first = (int)cc.size();
+      for (int64_t s = 0; s < h.n + 1; s += kScanChunk)
+        cc.push_back({h.off + s, (int)std::min<int64_t>(kScanChunk, h.n + 1 - s), first});
+    }
+    if (tj.empty()) {
+      for (int j : set) {
+        jobs[j].built = true;
+        jobs[j].A_now = 0.0;
+      }
+      return MD_OK;
+    }
+    if ((int64_t)(cb.size() + cc.size()) > chunk_cap || (int64_t)tj.size() > tile_cap ||
+        (int64_t)(rb.size() + rcnt.size()) > range_cap)
+      return MD_ENOMEM;
+    MDCHK(upload_jobs());
+    MDCHK(upload(aux_tiles_job, tj.data(), sizeof(int) * tj.size()));
+    MDCHK(upload(aux_tiles_first, tf.data(), sizeof(int64_t) * tf.size()));
+    std::vector<Chunk> call(cb);
+    call.insert(call.end(), cc.begin(), cc.end());
+    // seg_first stays relative to each sub-list: the two scans get separate base pointers
+    MDCHK(upload(chunks_d, call.data(), sizeof(Chunk) * call.size()));
+    std::vector<Range> rall(rb);
+    rall.insert(rall.end(), rcnt.begin(), rcnt.end());
+    MDCHK(upload(ranges_d, rall.data(), sizeof(Range) * rall.size()));
+    const int ntiles = (int)tj.size();
+    HIPCHK(hipEventRecord(ev[2], stream));
+    // zero bitmaps and cell counters
+    hipLaunchKernelGGL(k_zero_ranges, dim3(64, (unsigned)rb.size()), dim3(256), 0, stream, B.BM, ranges_d,
+                       (int)rb.size());
+    hipLaunchKernelGGL(k_zero_ranges, dim3(64, (unsigned)rcnt.size()), dim3(256), 0, stream, B.CCNT,
+                       ranges_d + rb.size(), (int)rcnt.size());
+    for (int j : set) {
+      std::memset(&book_h[j], 0, sizeof(JobBook));
+    }
+    // reset bookkeeping of the rebuilt jobs (small copies, pinned source)
+    for (int j : set) HIPCHK(hipMemcpyAsync(&B.book[j], &book_h[j], sizeof(JobBook), hipMemcpyHostToDevice, stream));
+    hipLaunchKernelGGL(k_mark, dim3(ntiles), dim3(kTile), 0, stream, B, aux_tiles_job, aux_tiles_first);
+    // bitmap popcount prefix (segmented by job)
+    const int nb = (int)cb.size(), nc = (int)cc.size();
+    hipLaunchKernelGGL(k_scan_a<true>, dim3(nb), dim3(kScanThreads), 0, stream, B.BM, B.WOFF, chunks_d, chunk_sums);
+    hipLaunchKernelGGL(k_scan_b, dim3(1), dim3(kScanB), 0, stream, chunk_sums, chunks_d, nb);
+    hipLaunchKernelGGL(k_scan_c, dim3(nb), dim3(kScanThreads), 0, stream, B.WOFF, chunks_d, chunk_sums);
+    hipLaunchKernelGGL(k_count, dim3(ntiles), dim3(kTile), 0, stream, B, aux_tiles_job, aux_tiles_first);
+    // cell starts (segmented by job)
+    hipLaunchKernelGGL(k_scan_a<false>, dim3(nc), dim3(kScanThreads), 0, stream, B.CCNT, B.CSTART, chunks_d + nb,
+                       chunk_sums + nb);
+    hipLaunchKernelGGL(k_scan_b, dim3(1), dim3(kScanB), 0, stream, chunk_sums + nb, chunks_d + nb, nc);
+    hipLaunchKernelGGL(k_scan_c, dim3(nc), dim3(kScanThreads), 0, stream, B.CSTART, chunks_d + nb, chunk_sums + nb);
+    hipLaunchKernelGGL(k_scatter, dim3(ntiles), dim3(kTile), 0, stream, B, aux_tiles_job, aux_tiles_first);
+    for (int attempt = 0; attempt < 3; ++attempt) {
+      const size_t lds = (size_t)kmax * kNlistBlock * 2 * sizeof(uint32_t);
+      if (lds > 160 * 1024) return MD_ENOMEM;
+      hipLaunchKernelGGL(k_nlist, dim3(4 * ntiles), dim3(kNlistBlock), lds, stream, B, aux_tiles_job,
+                         aux_tiles_first);
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipEventRecord(ev[3], stream));
+      MDCHK(read_book());
+      stats.rebuild_ms += elapsed_ms(ev[2], ev[3]);
+      stats.builds += 1;
+      int need = 0;
+      for (int j : set) need = std::max(need, book_h[j].nl_max);
+      if (need <= kmax) break;
+      MDCHK(grow_kmax(need + need / 8 + 2));
+      for (int j : set) {
+        book_h[j].nl_sum = 0ull;
+        HIPCHK(hipMemcpyAsync(&B.book[j].nl_sum, &book_h[j].nl_sum, sizeof(unsigned long long),
+                              hipMemcpyHostToDevice, stream));
+      }
+    }
+    for (int j : set) {
+      HostJob& h = jobs[j];
+      h.dev.xcur ^= 1;
+      h.dev.pcur ^= 1;
+      h.dev.scur ^= 1;
+      h.built = true;
+      if (h.step > h.last_build && h.A_now > 0.0) h.rate_prev = h.A_now / (double)(h.step - h.last_build);
+      h.A_now = 0.0;
+      h.last_build = h.step;
+      h.rebuilds += 1;
+      h.nl_max = book_h[j].nl_max;
+      nl_sum_all += (double)book_h[j].nl_sum;
+      nl_n_all += (double)h.n;
+    }
+    if (nl_n_all > 0) stats.nl_mean = nl_sum_all / nl_n_all;
+    nl_sum_all = nl_n_all = 0.0;
+    return MD_OK;
+  }
+  double nl_sum_all = 0.0, nl_n_all = 0.0;
+
+  // ------------------------------------------------------------------ stepping
+  bool steppable(const HostJob& h) const { return h.used && h.status == MD_OK && !h.done && h.step < h.target; }
+
+  static int grid_for(int count) {
+    if (count <= 0) return 0;
+    int g = 64;
+    while (g < count) g *= 2;
+    return g;
+  }
+
+  // Upload the tile lists of the steppable jobs.  Graphs bake the grid size,
+  // not the lists: they stay valid while each list fits its grid and is not
+  // much smaller than it.
+  int prepare_step_tiles() {
+    if (step_tiles_valid) return MD_OK;
+    std::vector<int> tj[2];
+    std::vector<int64_t> tf[2];
+    for (int j = 0; j < max_jobs; ++j) {
+      const HostJob& h = jobs[j];
+      if (!h.used || h.done || h.status != MD_OK) continue;
+      const int c = h.dev.force_fp64 ? 0 : 1;
+      tiles_of(h, j, tj[c], tf[c]);
+    }
+    for (int c = 0; c < 2; ++c)
+      if ((int64_t)tj[c].size() > tile_cap) return MD_ENOMEM;
+    step_tiles_valid = true;
+    if (tj[0] == last_tj[0] && tf[0] == last_tf[0] && tj[1] == last_tj[1] && tf[1] == last_tf[1]) return MD_OK;
+    int counts[2];
+    for (int c = 0; c < 2; ++c) {
+      counts[c] = (int)tj[c].size();
+      if (!tj[c].empty()) {
+        MDCHK(upload(step_tiles_job + c * tile_cap, tj[c].data(), sizeof(int) * tj[c].size()));
+        MDCHK(upload(step_tiles_first + c * tile_cap, tf[c].data(), sizeof(int64_t) * tf[c].size()));
+      }
+      last_tj[c].swap(tj[c]);
+      last_tf[c].swap(tf[c]);
+    }
+    MDCHK(upload(step_counts, counts, sizeof(counts)));
+    const int want64 = grid_for(counts[0]), want32 = grid_for(counts[1]);
+    auto fits = [](int grid, int count, int want) {
+      if (count == 0) return grid == 0;
+      return grid >= count && grid <= 4 * want;
+    };
+    if (!fits(grid64, counts[0], want64) || !fits(grid32, counts[1], want32)) {
+      grid64 = want64;
+      grid32 = want32;
+      drop_graphs();
+    }
+    return MD_OK;
+  }
+
+  void enqueue_steps(int t0, int k) {
+    for (int t = t0; t < t0 + k; ++t) {
+      if (grid64 > 0)
+        hipLaunchKernelGGL(k_step<true>, dim3(grid64), dim3(kTile), 0, stream, B, step_tiles_job, step_tiles_first,
+                           step_counts, t);
+      if (grid32 > 0)
+        hipLaunchKernelGGL(k_step<false>, dim3(grid32), dim3(kTile), 0, stream, B, step_tiles_job + tile_cap,
+                           step_tiles_first + tile_cap, step_counts + 1, t);
+    }
+  }
+
+  int launch_chunk(int k, bool use_graph) {
+    if (!use_graph) {
+      enqueue_steps(0, k);
+      HIPCHK(hipGetLastError());
+      return MD_OK;
+    }
+    auto it = graphs.find(GraphKey{k});
+    if (it == graphs.end()) {
+      hipGraph_t g = nullptr;
+      HIPCHK(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+      enqueue_steps(0, k);
+      HIPCHK(hipStreamEndCapture(stream, &g));
+      hipGraphExec_t ex = nullptr;
+      const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      HIPCHK(e);
+      it = graphs.emplace(GraphKey{k}, ex).first;
+    }
+    HIPCHK(hipGraphLaunch(it->second, stream));
+    return MD_OK;
+  }
+
+  // Steps a job can take before its list goes stale: the remaining half skin
+  // over the larger of the displacement rates of this and the previous list.
+  static int predict_chunk(const HostJob& h) {
+    const int64_t since = h.step - h.last_build;
+    double rate = h.rate_prev;
+    if (since > 0 && h.A_now > 0.0) rate = std::max(rate, h.A_now / (double)since);
+    if (!(rate > 0.0)) return 16;
+    const double left = (h.dev.half_skin - h.A_now) / rate;
+    return (int)std::max(0.0, std::min(1e6, std::floor(0.8 * left)));
+  }
+
+  // One chunk of at most kcap steps for every steppable job; rebuilds first
+  // where a list is missing or would go stale within the chunk.
+  // eager = true (pools): rebuild every job whose list would go stale within
+  // the chunk, and run the full chunk; eager = false (one system): rebuild only
+  // when the list is (nearly) stale and shorten the chunk to the prediction.
+  int run_chunk(int kcap, bool use_graph, int64_t* advanced, bool eager = false) {
+    std::vector<int> need;
+    int k = std::min(kcap, kMaxChunk);
+    for (int j = 0; j < max_jobs; ++j) {
+      HostJob& h = jobs[j];
+      if (!steppable(h)) continue;
+      if (!h.built) {
+        need.push_back(j);
+        continue;
+      }
+      const int pk = predict_chunk(h);
+      if (pk < (eager ? std::min<int64_t>(k, h.target - h.step) : 2)) need.push_back(j);
+    }
+    MDCHK(rebuild(need));
+    int kk = k;
+    bool any = false;
+    for (int j = 0; j < max_jobs; ++j) {
+      HostJob& h = jobs[j];
+      if (!steppable(h)) continue;
+      any = true;
+      if (!eager) kk = std::min<int64_t>(kk, std::max(1, predict_chunk(h)));
+    }
+    if (!any) {
+      *advanced = 0;
+      return MD_OK;
+    }
+    // a power of two keeps the number of distinct graphs small
+    int kq = 1;
+    while (kq * 2 <= kk) kq *= 2;
+    for (int j = 0; j < max_jobs; ++j) {
+      HostJob& h = jobs[j];
+      h.dev.step0 = h.step;
+      h.dev.remaining = steppable(h) ? std::min<int64_t>(h.target - h.step, kq) : 0;
+    }
+    MDCHK(prepare_step_tiles());
+    MDCHK(upload_jobs());
+    HIPCHK(hipEventRecord(ev[0], stream));
+    MDCHK(launch_chunk(kq, use_graph));
+    HIPCHK(hipEventRecord(ev[1], stream));
+    MDCHK(read_book());
+    stats.step_kernel_ms += elapsed_ms(ev[0], ev[1]);
+    stats.chunks += 1;
+    stats.step_launches += (int64_t)kq * ((grid64 > 0) + (grid32 > 0));
+    int64_t adv = 0;
+    for (int j = 0; j < max_jobs; ++j) {
+      HostJob& h = jobs[j];
+      if (!h.used || h.dev.remaining == 0) continue;
+      const JobBook& K = book_h[j];
+      int64_t done = h.dev.remaining;
+      if (K.flags & kFlagError) {
+        h.status = K.err_code == kErrNewton ? MD_ENEWTON : MD_ENAN;
+        h.err_id = K.err_id;
+        h.done = true;
+        step_tiles_valid = false;
+        continue;
+      }
+      if (K.flags & kFlagStale) {
+        done = K.stale_step - h.step;
+        h.built = false;
+      }
+      h.step += done;
+      if (done & 1) h.dev.xcur ^= 1;
+      if (done > 0) h.dev.mode = kModeSteady;
+      h.newton_max = std::max(h.newton_max, K.newton_max);
+      const long long s = h.step;
+      h.A_now = K.acc[(s + 1) & 1] + [&] {
+        double v;
+        unsigned long long u = K.dmax[(s + 2) % 3];
+        std::memcpy(&v, &u, sizeof(v));
+        return v;
+      }();
+      if (h.A_now > h.dev.half_skin) h.built = false;
+      if (h.step >= h.target) {
+        h.done = true;
+        step_tiles_valid = false;
+      }
+      adv = std::max<int64_t>(adv, done);
+      stats.steps += done;
+      stats.particle_steps += done * h.n;
+    }
+    *advanced = adv;
+    return MD_OK;
+  }
+
+  // ------------------------------------------------------------------ finish
+  int finish(int j, double* x, double* p, double* f, md_diag* diag) {
+    HostJob& h = jobs[j];
+    if (!h.used) return MD_ENOTFOUND;
+    if (h.n == 0) {
+      if (diag) {
+        std::memset(diag, 0, sizeof(*diag));
+        diag->step = h.step;
+        diag->error_index = -1;
+      }
+      return h.status;
+    }
+    if (h.status == MD_OK && (!h.built || h.A_now > h.dev.half_skin)) MDCHK(rebuild({j}));
+    h.dev.step0 = h.step;
+    h.dev.remaining = 0;
+    MDCHK(upload_jobs());
+    std::vector<int> tj;
+    std::vector<int64_t> tf;
+    tiles_of(h, j, tj, tf);
+    MDCHK(upload(aux_tiles_job, tj.data(), sizeof(int) * tj.size()));
+    MDCHK(upload(aux_tiles_first, tf.data(), sizeof(int64_t) * tf.size()));
+    if (h.dev.force_fp64)
+      hipLaunchKernelGGL(k_finish<true>, dim3((unsigned)tj.size()), dim3(kTile), 0, stream, B, aux_tiles_job,
+                         aux_tiles_first);
+    else
+      hipLaunchKernelGGL(k_finish<false>, dim3((unsigned)tj.size()), dim3(kTile), 0, stream, B, aux_tiles_job,
+                         aux_tiles_first);
+    HIPCHK(hipGetLastError());
+    const int64_t n = h.n;
+    MDCHK(ensure_stage(sizeof(double) * 13 * n));
+    double* st = (double*)stage;
+    auto get_rows = [&](const double* src, int rows, double* dst) -> int {
+      for (int k = 0; k < rows; ++k)
+        HIPCHK(hipMemcpyAsync(dst + k * n, src + k * C + h.off, sizeof(double) * n, hipMemcpyDeviceToHost, stream));
+      return MD_OK;
+    };
+    MDCHK(get_rows(B.OX, 3, st));
+    MDCHK(get_rows(B.OP, 3, st + 3 * n));
+    MDCHK(get_rows(B.OF, 3, st + 6 * n));
+    MDCHK(get_rows(B.OD, 4, st + 9 * n));
+    HIPCHK(hipStreamSynchronize(stream));
+    for (int64_t i = 0; i < n; ++i)
+      for (int k = 0; k < 3; ++k) {
+        if (x) x[3 * i + k] = st[k * n + i];
+        if (p) p[3 * i + k] = st[(3 + k) * n + i];
+        if (f) f[3 * i + k] = st[(6 + k) * n + i];
+      }
+    if (diag) {
+      double K = 0.0, U = 0.0, gd = 0.0, nv = 0.0, ndof = 0.0;
+      for (int64_t i = 0; i < n; ++i) {
+        K += st[9 * n + i];
+        U += st[10 * n + i];
+        gd = std::max(gd, st[11 * n + i]);
+        nv = std::max(nv, st[12 * n + i]);
+      }
+      ndof = h.ndof;
+      std::memset(diag, 0, sizeof(*diag));
+      diag->K = K;
+      diag->U = U;
+      diag->ndof = ndof;
+      diag->kT = ndof > 0 ? 2.0 * K / ndof : 0.0;
+      diag->gdist_max = gd;
+      diag->nv_max = nv;
+      diag->step = h.step;
+      diag->rebuilds = h.rebuilds;
+      diag->newton_iter_max = h.newton_max;
+      diag->nlist_max = h.nl_max;
+      diag->error_index = h.err_id;
+    }
+    return h.status;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+namespace {
+
+bool use_graphs() {
+  const char* e = std::getenv("MD_NO_GRAPH");
+  return !(e && e[0] == '1');
+}
+
+// Slots and bitmap words one job needs.
+int plan_job(const md_params& prm, int kind, const double* surf, int64_t n, const double* x, int64_t* nslots,
+             int64_t* nwords) {
+  HostJob h;
+  h.prm = prm;
+  h.surf_kind = kind;
+  for (int k = 0; k < MD_SURF_MAXPRM; ++k) h.surf[k] = surf ? surf[k] : 0.0;
+  h.n = n;
+  Engine::fill_constants(h);
+  MDCHK(make_grid(h, x));
+  *nslots = Engine::seg_slots(n);
+  *nwords = h.bm_words;
+  return MD_OK;
+}
+
+int check_device(int dev) {
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess) {
+    (void)hipGetLastError();
+    return MD_EHIP;
+  }
+  if (dev < 0 || dev >= count) return MD_EINVAL;
+  return MD_OK;
+}
+
+}  // namespace
+
+struct md_ctx {
+  md_params prm{};
+  int surf_kind = MD_SURF_NONE;
+  double surf[MD_SURF_MAXPRM] = {0};
+  bool have_particles = false;
+  Engine* eng = nullptr;
+  int job = -1;
+};
+
+struct md_pool {
+  Engine eng;
+};
+
+extern "C" {
+
+const char* md_strerror(int code) {
+  switch (code) {
+    case MD_OK: return "ok";
+    case MD_EINVAL: return "invalid argument";
+    case MD_ESTATE: return "call out of order";
+    case MD_EOFFSURF: return "particle off the surface or with a normal momentum component";
+    case MD_ENEWTON: return "RATTLE Newton iteration did not converge";
+    case MD_ENAN: return "non-finite state";
+    case MD_ENOMEM: return "out of memory";
+    case MD_EAGAIN: return "no room in the pool";
+    case MD_EHIP: return "HIP runtime error";
+    case MD_ENOTFOUND: return "unknown job";
+    default: return "unknown status";
+  }
+}
+
+int md_create(const md_params* params, md_ctx** out) {
+  if (!params || !out) return MD_EINVAL;
+  *out = nullptr;
+  MDCHK(validate_params(*params));
+  MDCHK(check_device(params->device));
+  md_ctx* c = new (std::nothrow) md_ctx();
+  if (!c) return MD_ENOMEM;
+  c->prm = *params;
+  *out = c;
+  return MD_OK;
+}
+
+int md_set_surface(md_ctx* ctx, int kind, const double* prm, int nprm) {
+  if (!ctx) return MD_EINVAL;
+  const int need = surf_nprm(kind);
+  if (need < 0 || nprm < need || (need > 0 && !prm)) return MD_EINVAL;
+  for (int k = 0; k < need; ++k)
+    if (!std::isfinite(prm[k])) return MD_EINVAL;
+  if (kind == MD_SURF_SPHERE && !(prm[3] > 0)) return MD_EINVAL;
+  if (kind == MD_SURF_ELLIPSOID && !(prm[3] > 0 && prm[4] > 0 && prm[5] > 0)) return MD_EINVAL;
+  if (kind == MD_SURF_TORUS && !(prm[3] > prm[4] && prm[4] > 0)) return MD_EINVAL;
+  if (kind == MD_SURF_HEIGHT && (!(prm[2] > 0 && prm[3] > 0) || !ctx->prm.periodic[0] || !ctx->prm.periodic[1]))
+    return MD_EINVAL;
+  ctx->surf_kind = kind;
+  for (int k = 0; k < MD_SURF_MAXPRM; ++k) ctx->surf[k] = k < need ? prm[k] : 0.0;
+  return MD_OK;
+}
+
+int md_set_particles(md_ctx* ctx, int64_t n, const double* x, const double* p, const double* mass,
+                     const uint8_t* constrained, const double* fcomb, int64_t step0) {
+  if (!ctx || n < 0 || step0 < 0) return MD_EINVAL;
+  if (n > 0 && (!x || !p)) return MD_EINVAL;
+  int64_t nslots = 0, nwords = 0;
+  MDCHK(plan_job(ctx->prm, ctx->surf_kind, ctx->surf, n, x, &nslots, &nwords));
+  Engine* e = ctx->eng;
+  if (e && ctx->job >= 0) e->drop(ctx->job);
+  ctx->job = -1;
+  ctx->have_particles = false;
+  if (e && (e->C < nslots || e->BMW < nwords)) {
+    delete e;
+    e = ctx->eng = nullptr;
+  }
+  if (!e) {
+    e = new (std::nothrow) Engine();
+    if (!e) return MD_ENOMEM;
+    const int r = e->init(ctx->prm.device, ctx->prm.stream, nslots, nwords, 1);
+    if (r != MD_OK) {
+      delete e;
+      return r;
+    }
+    ctx->eng = e;
+  }
+  int j = -1;
+  MDCHK(e->admit(ctx->prm, ctx->surf_kind, ctx->surf, n, x, p, mass, constrained, fcomb, step0, step0, &j));
+  ctx->job = j;
+  ctx->have_particles = true;
+  return MD_OK;
+}
+
+int md_step(md_ctx* ctx, int64_t nsteps) {
+  if (!ctx || nsteps < 0) return MD_EINVAL;
+  if (!ctx->have_particles) return MD_ESTATE;
+  Engine* e = ctx->eng;
+  HostJob& h = e->jobs[ctx->job];
+  if (h.status != MD_OK) return h.status;
+  if (nsteps == 0 || h.n == 0) {
+    h.step += (h.n == 0) ? nsteps : 0;
+    return MD_OK;
+  }
+  h.target = h.step + nsteps;
+  h.done = false;
+  e->step_tiles_valid = false;
+  const bool graph = use_graphs();
+  while (h.step < h.target && h.status == MD_OK) {
+    int64_t adv = 0;
+    MDCHK(e->run_chunk((int)std::min<int64_t>(h.target - h.step, kMaxChunk), graph, &adv));
+  }
+  return h.status;
+}
+
+int md_get_state(md_ctx* ctx, double* x, double* p, double* fcomb, int64_t* step, md_diag* diag) {
+  if (!ctx) return MD_EINVAL;
+  if (!ctx->have_particles) return MD_ESTATE;
+  Engine* e = ctx->eng;
+  if (step) *step = e->jobs[ctx->job].step;
+  return e->finish(ctx->job, x, p, fcomb, diag);
+}
+
+int md_get_stats(md_ctx* ctx, md_stats* stats) {
+  if (!ctx || !stats) return MD_EINVAL;
+  std::memset(stats, 0, sizeof(*stats));
+  if (ctx->eng) *stats = ctx->eng->stats;
+  return MD_OK;
+}
+
+void md_destroy(md_ctx* ctx) {
+  if (!ctx) return;
+  delete ctx->eng;
+  delete ctx;
+}
+
+size_t md_job_footprint(int64_t n, int surface_kind, const double* surface_prm, const md_params* params) {
+  if (!params || n < 0) return 0;
+  // the grid of a surface-less job depends on the particles; size it as a cube
+  // holding them at unit density
+  int64_t nslots = 0, nwords = 0;
+  if (surface_kind == MD_SURF_NONE) {
+    nslots = Engine::seg_slots(n);
+    nwords = n / 8 + 64;
+  } else if (plan_job(*params, surface_kind, surface_prm, n, nullptr, &nslots, &nwords) != MD_OK) {
+    return 0;
+  }
+  return (size_t)nslots * (size_t)(kSlotBytes + 4 * (kDefaultKmax + kDefaultKmax / 2)) + (size_t)nwords * 8;
+}
+
+int md_pool_create(size_t hbm_budget_bytes, int max_jobs, int device, void* stream, md_pool** out) {
+  if (!out || max_jobs <= 0 || hbm_budget_bytes < (1u << 20)) return MD_EINVAL;
+  *out = nullptr;
+  MDCHK(check_device(device));
+  md_pool* pl = new (std::nothrow) md_pool();
+  if (!pl) return MD_ENOMEM;
+  const double per_slot = (double)(kSlotBytes + 4 * (kDefaultKmax + kDefaultKmax / 2));
+  const int64_t slots = (int64_t)(0.75 * (double)hbm_budget_bytes / per_slot);
+  const int64_t words = (int64_t)(0.25 * (double)hbm_budget_bytes / 8.0);
+  const int r = pl->eng.init(device, stream, slots, words, max_jobs);
+  if (r != MD_OK) {
+    delete pl;
+    return r;
+  }
+  *out = pl;
+  return MD_OK;
+}
+
+int md_pool_admit(md_pool* pool, const md_job_desc* job, int* job_id) {
+  if (!pool || !job || !job_id) return MD_EINVAL;
+  const int need = surf_nprm(job->surface_kind);
+  if (need < 0 || job->nsteps < 0 || job->step0 < 0) return MD_EINVAL;
+  return pool->eng.admit(job->params, job->surface_kind, job->surface_prm, job->n, job->x, job->p, job->mass,
+                         job->constrained, nullptr, job->step0, job->step0 + job->nsteps, job_id);
+}
+
+int md_pool_run(md_pool* pool, int steps_chunk) {
+  if (!pool || steps_chunk < 0) return MD_EINVAL;
+  Engine& e = pool->eng;
+  const bool graph = use_graphs();
+  int64_t left = steps_chunk;
+  while (left > 0) {
+    int64_t adv = 0;
+    MDCHK(e.run_chunk((int)std::min<int64_t>(left, kPoolChunk), graph, &adv, true));
+    if (adv <= 0) {
+      bool any = false;
+      for (int j = 0; j < e.max_jobs; ++j) any = any || e.steppable(e.jobs[j]);
+      if (!any) break;
+      continue;
+    }
+    left -= adv;
+  }
+  return MD_OK;
+}
+
+int md_pool_poll(md_pool* pool, int* done_ids, int cap, int* ndone) {
+  if (!pool || !ndone || (cap > 0 && !done_ids)) return MD_EINVAL;
+  Engine& e = pool->eng;
+  int c = 0;
+  for (int j = 0; j < e.max_jobs && c < cap; ++j) {
+    HostJob& h = e.jobs[j];
+    if (!h.used || h.reported) continue;
+    if (h.done || h.status != MD_OK || h.step >= h.target) {
+      h.reported = true;
+      done_ids[c++] = j;
+    }
+  }
+  *ndone = c;
+  return MD_OK;
+}
+
+int md_pool_fetch(md_pool* pool, int job_id, double* x, double* p, md_diag* diag) {
+  if (!pool || job_id < 0 || job_id >= pool->eng.max_jobs) return MD_ENOTFOUND;
+  if (!pool->eng.jobs[job_id].used) return MD_ENOTFOUND;
+  return pool->eng.finish(job_id, x, p, nullptr, diag);
+}
+
+int md_pool_release(md_pool* pool, int job_id) {
+  if (!pool || job_id < 0 || job_id >= pool->eng.max_jobs) return MD_ENOTFOUND;
+  if (!pool->eng.jobs[job_id].used) return MD_ENOTFOUND;
+  pool->eng.drop(job_id);
+  return MD_OK;
+}
+
+int md_pool_usage(md_pool* pool, int* jobs, int64_t* particles, size_t* bytes) {
+  if (!pool) return MD_EINVAL;
+  int nj = 0;
+  int64_t np = 0, slots = 0, words = 0;
+  for (const HostJob& h : pool->eng.jobs)
+    if (h.used) {
+      ++nj;
+      np += h.n;
+      slots += h.seg;
+      words += h.bm_words;
+    }
+  if (jobs) *jobs = nj;
+  if (particles) *particles = np;
+  if (bytes) *bytes = (size_t)slots * (size_t)(kSlotBytes + 4 * pool->eng.kmax) + (size_t)words * 8;
+  return MD_OK;
+}
+
+int md_pool_get_stats(md_pool* pool, md_stats* stats) {
+  if (!pool || !stats) return MD_EINVAL;
+  *stats = pool->eng.stats;
+  return MD_OK;
+}
+
+void md_pool_destroy(md_pool* pool) { delete pool; }
+
+}  // extern "C"

@@ -1,0 +1,207 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 oracle on
+identical seeded inputs.
+
+Tolerances (one-step map): positions 1e-6 relative, as
+max_i |dx_i| / max(1, |x_i|).  The FP64-force path is expected to agree to
+round-off (~1e-13); the FP32-force path to the FP32 force error times
+dt^2/2m in positions.  Momenta and forces are reported beside positions.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as o
+from workloads import gen
+
+from _common import WCA, gpu_params, gpu_system, oracle_params, rel_err, rel_pos_err, report
+
+pytestmark = pytest.mark.gpu
+
+POS_TOL = 1e-6
+
+
+def _one_step(s, steps=1, **kw):
+    P = oracle_params(s, **kw)
+    ref = o.State(P, s.x, s.p, mass=s.mass, cons=s.cons, step0=kw.get("step0", 0))
+    f0 = ref.f.copy()
+    ref.run(steps)
+    g = gpu_system(s, **kw)
+    st0 = g.get_state()
+    g.step(steps)
+    st = g.get_state()
+    g.close()
+    return ref, f0, st0, st
+
+
+CASES = {
+    "sphere_wca_fp64": lambda: (gen.sphere_wca_1000()[0], dict(dt=0.001, rc=WCA, seed=42, force_fp64=1)),
+    "sphere_wca_fp32": lambda: (gen.sphere(1000, 14.4, 3), dict(dt=0.001, rc=WCA, seed=5, force_fp64=0)),
+    "torus_lj_fp32": lambda: (gen.torus(3000, 26.1, 8.7, 7), dict(dt=0.002, rc=2.5, seed=7, force_fp64=0)),
+    "torus_lj_fp64": lambda: (gen.torus(3000, 26.1, 8.7, 8), dict(dt=0.002, rc=2.5, seed=9, force_fp64=1)),
+    "ellipsoid_wca": lambda: (gen.ellipsoid(2000, 16.0, 16.0, 24.0, 4), dict(dt=0.001, rc=WCA, seed=3)),
+    "height_mixed": lambda: (gen.height_membrane(800, 1500, 40.0, 40.0, 24.0, 4.0, 40.0, 5),
+                             dict(dt=0.002, rc=WCA, seed=11, force_fp64=0)),
+    "plane_lj_smooth": lambda: (gen.plane(1500, 50.0, 6), dict(dt=0.002, rc=2.5, pair="lj_smooth", seed=1)),
+    "cylinder_lj": lambda: (gen.cylinder(1500, 8.0, 60.0, 7), dict(dt=0.002, rc=2.5, seed=2, force_fp64=0)),
+    "sphere_nve": lambda: (gen.sphere(800, 12.0, 9), dict(dt=0.001, rc=WCA, gamma=0.0)),
+    "sphere_eta": lambda: (gen.sphere(800, 12.0, 10), dict(dt=0.002, rc=WCA, seed=4, newton_tol=1e-6)),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_one_step_map(case):
+    s, kw = CASES[case]()
+    print(f"[gpu] one-step map {case} n={s.n}", flush=True)
+    ref, f0, st0, st = _one_step(s, 1, **kw)
+    # state as set: x, p unchanged, f^0 from the starting formula
+    assert np.array_equal(st0["x"], s.x)
+    e_f0 = rel_err(st0["f"], f0)
+    ex, ep, ef = rel_pos_err(st["x"], ref.x), rel_err(st["p"], ref.p), rel_err(st["f"], ref.f)
+    report(case + " 1-step", x=ex, p=ep, f=ef, f0=e_f0)
+    assert st["step"] == 1
+    assert ex < POS_TOL
+    fp32 = kw.get("force_fp64", 1) == 0
+    assert ep < (1e-6 if fp32 else 1e-10)
+    assert ef < (1e-4 if fp32 else 1e-9)
+    assert e_f0 < (1e-4 if fp32 else 1e-9)
+
+
+@pytest.mark.parametrize("case", ["sphere_wca_fp64", "torus_lj_fp32", "height_mixed", "ellipsoid_wca",
+                                  "sphere_eta"])
+def test_short_trajectory(case):
+    """50 steps: trajectories still agree point-wise (chaos has not amplified the
+    round-off yet); constraint residuals at round-off on both sides."""
+    s, kw = CASES[case]()
+    print(f"[gpu] 50-step trajectory {case} n={s.n}", flush=True)
+    ref, _, _, st = _one_step(s, 50, **kw)
+    ex, ep = rel_pos_err(st["x"], ref.x), rel_err(st["p"], ref.p)
+    report(case + " 50-step", x=ex, p=ep, gdist=st["diag"]["gdist_max"], nv=st["diag"]["nv_max"])
+    assert ex < POS_TOL
+    assert st["diag"]["gdist_max"] < 1e-13 * max(1.0, np.abs(st["x"]).max())
+    assert st["diag"]["nv_max"] < 1e-11
+    d = ref.diag()
+    assert abs(st["diag"]["K"] - d["K"]) <= 1e-6 * abs(d["K"])
+    assert abs(st["diag"]["U"] - d["U"]) <= 1e-5 * max(1.0, abs(d["U"]))
+
+
+def test_sphere_1000_steps():
+    """The 1000-particle sphere run end to end (1000 steps = 1 tau)."""
+    s, run = gen.sphere_wca_1000()
+    kw = dict(dt=run["dt"], rc=WCA, seed=42, force_fp64=1)
+    print("[gpu] sphere 1000 x 1000 steps", flush=True)
+    ref, _, _, st = _one_step(s, 1000, **kw)
+    ex = rel_pos_err(st["x"], ref.x)
+    d = ref.diag()
+    report("sphere1000 1000-step", x=ex, kT_gpu=st["diag"]["kT"], kT_ref=d["kT"])
+    assert ex < 1e-6
+    assert abs(st["diag"]["kT"] / d["kT"] - 1) < 1e-6
+    assert st["diag"]["newton_iter_max"] <= 4
+
+
+def test_deterministic_rerun_and_schedule_independence():
+    """Bitwise: the same run twice; and a different skin (so different rebuild
+    steps and list contents) gives the same bits, because neighbours are summed
+    in particle-index order."""
+    s = gen.torus(4000, 30.0, 10.0, 12)
+    kw = dict(dt=0.002, rc=2.5, seed=3, force_fp64=0)
+    print("[gpu] determinism torus 4000", flush=True)
+    outs = []
+    for skin in (0.3, 0.3, 0.7):
+        g = gpu_system(s, skin=skin, **kw)
+        g.step(300)
+        outs.append(g.get_state())
+        g.close()
+    assert np.array_equal(outs[0]["x"], outs[1]["x"]) and np.array_equal(outs[0]["p"], outs[1]["p"])
+    assert outs[2]["diag"]["rebuilds"] != outs[0]["diag"]["rebuilds"]
+    assert np.array_equal(outs[0]["x"], outs[2]["x"]) and np.array_equal(outs[0]["p"], outs[2]["p"])
+
+
+def test_resume_is_exact():
+    s = gen.sphere(1500, 16.0, 13)
+    kw = dict(dt=0.001, rc=WCA, seed=8, force_fp64=0)
+    print("[gpu] resume sphere 1500", flush=True)
+    g = gpu_system(s, **kw)
+    g.step(200)
+    full = g.get_state()
+    g.close()
+    g = gpu_system(s, **kw)
+    g.step(120)
+    mid = g.get_state()
+    g.set_particles(mid["x"], mid["p"], fcomb=mid["f"], step0=mid["step"])
+    g.step(80)
+    part = g.get_state()
+    g.close()
+    assert part["step"] == 200
+    assert np.array_equal(full["x"], part["x"])
+    assert np.array_equal(full["p"], part["p"])
+
+
+def test_error_paths():
+    from paper_1411_3019_amd import md
+    s = gen.sphere(300, 8.0, 1)
+    print("[gpu] error paths", flush=True)
+    g = md.System(gpu_params(s), "sphere", s.surf)
+    with pytest.raises(md.MDError) as e:
+        g.step(1)
+    assert e.value.code == md.MD_ESTATE
+    bad = s.x.copy()
+    bad[5] *= 1.001
+    with pytest.raises(md.MDError) as e:
+        g.set_particles(bad, s.p)
+    assert e.value.code == md.MD_EOFFSURF
+    badp = s.p.copy()
+    badp[7] += 0.1 * s.x[7] / 8.0
+    with pytest.raises(md.MDError) as e:
+        g.set_particles(s.x, badp)
+    assert e.value.code == md.MD_EOFFSURF
+    g.close()
+    # a Newton cap of one iteration cannot reach round-off: reported, not silent
+    g = gpu_system(s, newton_max_iter=1)
+    with pytest.raises(md.MDError) as e:
+        g.step(5)
+    assert e.value.code == md.MD_ENEWTON
+    g.close()
+    with pytest.raises(md.MDError) as e:
+        md.System(md.Params(dt=-1.0))
+    assert e.value.code == md.MD_EINVAL
+
+
+def test_full_size_torus_2m_one_step():
+    """The 2,000,000-particle torus workload at full size in the launch
+    configuration the benchmark times (FP32 forces, graphs, skin 0.3): one step,
+    every particle compared with the oracle's full FP64 step."""
+    s, run = gen.torus_lj_2m()
+    kw = dict(dt=run["dt"], rc=run["rc"], seed=run["seed"], force_fp64=0)
+    print(f"[gpu] full-size torus one step n={s.n}", flush=True)
+    ref, f0, st0, st = _one_step(s, 1, **kw)
+    ex, ep, ef = rel_pos_err(st["x"], ref.x), rel_err(st["p"], ref.p), rel_err(st["f"], ref.f)
+    report("torus2m 1-step", x=ex, p=ep, f=ef, f0=rel_err(st0["f"], f0))
+    assert ex < POS_TOL
+    assert ep < 1e-6
+    d = ref.diag()
+    assert abs(st["diag"]["kT"] / d["kT"] - 1) < 1e-7
+    assert st["diag"]["gdist_max"] < 1e-13 * 800.0
+
+
+def test_msd_statistics_torus():
+    """Trajectory statistics: MSD(t) of an interacting LJ system on a torus
+    (area fraction 0.4, the large workload's shape at 20,000 particles) from the
+    GPU (FP32 forces) and the oracle agree within 2% at every sampled time."""
+    from workloads.gen import torus_radii_for
+    Rt, r = torus_radii_for(20000, 0.4)
+    s = gen.torus(20000, Rt, r, 21)
+    kw = dict(dt=0.002, rc=2.5, seed=17, force_fp64=0)
+    print(f"[gpu] MSD torus n={s.n}", flush=True)
+    P = oracle_params(s, **kw)
+    ref = o.State(P, s.x, s.p)
+    g = gpu_system(s, **kw)
+    worst = 0.0
+    for _ in range(5):
+        ref.run(100)
+        g.step(100)
+        st = g.get_state(want_force=False)
+        m_ref = np.mean(np.sum((ref.x - s.x) ** 2, axis=1))
+        m_gpu = np.mean(np.sum((st["x"] - s.x) ** 2, axis=1))
+        worst = max(worst, abs(m_gpu / m_ref - 1))
+    g.close()
+    report("torus20k MSD", worst_rel=worst)
+    assert worst < 0.02

@@ -1,0 +1,89 @@
+"""GPU tests of the batched pool (many resident jobs advanced by shared
+launches) and of the continuous-batching loop.
+
+Bar: each job's result in the mix is bit-identical to the same job run alone
+(one context, per-step launches); a job's result agrees with the oracle."""
+import numpy as np
+import pytest
+
+from oracle import oracle as o
+from workloads import gen
+
+from _common import oracle_params, rel_pos_err, report
+
+pytestmark = pytest.mark.gpu
+
+
+def _serving_jobs(ids, nsteps=None, force_fp64=None):
+    from paper_1411_3019_amd import serve
+    from paper_1411_3019_amd.md import Params
+    jobs = []
+    for jid in ids:
+        s, run = gen.serving_job(jid)
+        prm = Params(dt=run["dt"], kT=run["kT"], gamma=run["gamma"], rc=run["rc"], pair="lj",
+                     force_fp64=run["force_fp64"] if force_fp64 is None else force_fp64(jid), seed=run["seed"])
+        jobs.append(serve.Job(jid, 0.0, prm, s.surface, s.surf, s.x, s.p,
+                              run["steps"] if nsteps is None else nsteps(jid)))
+    return jobs
+
+
+def test_alone_vs_mix_bitwise():
+    from paper_1411_3019_amd import serve
+    ids = list(range(10))
+    steps = lambda j: 150 + 37 * j
+    mix = _serving_jobs(ids, steps, force_fp64=lambda j: int(j % 3 == 0))
+    print("[gpu] pool mix of", [(j.surface, j.n, j.nsteps) for j in mix], flush=True)
+    serve.serve(mix, 256 << 20, 16, chunk=32, realtime=False, keep_results=True)
+    alone = _serving_jobs(ids, steps, force_fp64=lambda j: int(j % 3 == 0))
+    serve.run_plain(alone, realtime=False, keep_results=True)
+    for a, b in zip(mix, alone):
+        assert a.status == 0
+        assert np.array_equal(a.result["x"], b.result["x"]), a.jid
+        assert np.array_equal(a.result["p"], b.result["p"]), a.jid
+        assert a.result["diag"]["step"] == a.nsteps
+
+
+def test_pool_job_matches_oracle():
+    from paper_1411_3019_amd import serve
+    jobs = _serving_jobs([3, 4, 5], lambda j: 100)
+    serve.serve(jobs, 128 << 20, 8, chunk=32, realtime=False, keep_results=True)
+    for j in jobs:
+        s, run = gen.serving_job(j.jid)
+        P = oracle_params(s, dt=run["dt"], rc=run["rc"], seed=run["seed"])
+        ref = o.State(P, s.x, s.p).run(100)
+        e = rel_pos_err(j.result["x"], ref.x)
+        report(f"pool job {j.jid} ({j.surface}, n={j.n}) 100 steps", x=e)
+        assert e < 1e-6
+
+
+def test_admission_backpressure_small_budget():
+    """A budget that holds only a few jobs: MD_EAGAIN keeps the rest waiting;
+    all of them finish, and the pool never holds more than the budget."""
+    from paper_1411_3019_amd import md, serve
+    jobs = _serving_jobs(range(20, 32), lambda j: 64)
+    need = max(md.footprint(j.n, j.surface, j.surf, j.params) for j in jobs)
+    budget = max(3 * need, 2 << 20)
+    print(f"[gpu] backpressure budget={budget} max_job={need}", flush=True)
+    serve.serve(jobs, budget, 64, chunk=32, realtime=False)
+    assert all(j.status == 0 and j.finished is not None for j in jobs)
+    starts = sorted(j.admitted for j in jobs)
+    assert starts[-1] > starts[0]
+
+
+def test_pool_usage_and_release():
+    from paper_1411_3019_amd import md
+    jobs = _serving_jobs([40, 41])
+    pool = md.Pool(64 << 20, 4)
+    ids = [pool.admit(j.params, j.surface, j.surf, j.x, j.p, 10) for j in jobs]
+    u = pool.usage()
+    assert u["jobs"] == 2 and u["particles"] == sum(j.n for j in jobs)
+    pool.run(10)
+    done = sorted(pool.poll())
+    assert done == sorted(ids)
+    rc, res = pool.fetch(ids[0])
+    assert rc == 0 and res["diag"]["step"] == 10
+    pool.release(ids[0])
+    assert pool.usage()["jobs"] == 1
+    with pytest.raises(md.MDError):
+        pool.release(ids[0])
+    pool.close()

@@ -287,3 +287,40 @@ def torus_lj_2m(n: int = 2_000_000, seed: int = 7, phi: float = 0.4) -> tuple[Sy
     run = dict(dt=0.002, kT=1.0, gamma=1.0, eps=1.0, sigma=1.0, rc=2.5, pair="lj", seed=7,
                force_fp64=0, steps=10000)
     return s, run
+
+
+# ----------------------------------------------------------------------------- serving stream
+
+SERVING_SURFACES = ("sphere", "ellipsoid", "torus")
+
+
+def serving_job(jid: int, seed: int = 5, nmin: int = 64, nmax: int = 16384, smin: float = 1e3,
+                smax: float = 1e4) -> tuple[System, dict]:
+    """Job jid of the serving stream: N log-uniform in [nmin, nmax], surface
+    uniform over sphere / prolate spheroid (1:1:1.5) / torus (r = Rt/3), area
+    fraction uniform in [0.1, 0.5], steps log-uniform in [smin, smax]; WCA,
+    kT = 1, gamma = 1, dt = 0.001; Philox key (seed << 32) + jid."""
+    rng = np.random.Generator(np.random.PCG64([seed, jid]))
+    n = int(round(math.exp(rng.uniform(math.log(nmin), math.log(nmax)))))
+    kind = SERVING_SURFACES[int(rng.integers(0, 3))]
+    phi = float(rng.uniform(0.1, 0.5))
+    steps = int(round(math.exp(rng.uniform(math.log(smin), math.log(smax)))))
+    init_seed = int(rng.integers(0, 2 ** 31))
+    if kind == "sphere":
+        s = sphere(n, sphere_radius_for(n, phi), init_seed)
+    elif kind == "ellipsoid":
+        a, b, c = prolate_axes_for(n, phi)
+        s = ellipsoid(n, a, b, c, init_seed)
+    else:
+        Rt, r = torus_radii_for(n, phi)
+        s = torus(n, Rt, r, init_seed)
+    s.meta.update(phi=phi, jid=jid)
+    run = dict(dt=0.001, kT=1.0, gamma=1.0, eps=1.0, sigma=1.0, rc=WCA_RC, pair="lj", force_fp64=0,
+               seed=(seed << 32) + jid, steps=steps)
+    return s, run
+
+
+def poisson_arrivals(count: int, rate: float, seed: int = 5) -> np.ndarray:
+    """Arrival times (s) of a Poisson stream: cumulative exponential gaps."""
+    rng = np.random.Generator(np.random.PCG64([seed, 0x5eed]))
+    return np.cumsum(rng.exponential(1.0 / rate, size=count))
