@@ -94,15 +94,75 @@ def cpu_baseline(s, run, budget_s: float = 12.0):
                       f"linked cells, OpenMP; {t:.1f} s"}
 
 
+def serving_bench(njobs: int, nplain: int, rate: float, budget_gb: float):
+    """Batched serving of the job stream against one-job-at-a-time plain launches.
+
+    Jobs: N log-uniform in [64, 16384] on a sphere / prolate spheroid / torus at
+    area fraction U[0.1, 0.5], WCA, dt 0.001, steps log-uniform in [1e3, 1e4],
+    FP32 forces, per-job Philox key; arrivals Poisson at `rate` jobs/s.
+      closed loop: every job queued at t = 0; throughput in jobs/s and
+        particle-steps/s (batched over all njobs; plain over the first nplain);
+      open loop: arrivals in real time; latency = completion - arrival.
+    """
+    from paper_1411_3019_amd import serve
+    from paper_1411_3019_amd.md import Params
+    from workloads import gen
+
+    arrivals = gen.poisson_arrivals(njobs, rate)
+
+    def jobs(count):
+        out = []
+        for jid in range(count):
+            s, run = gen.serving_job(jid)
+            prm = Params(dt=run["dt"], kT=run["kT"], gamma=run["gamma"], rc=run["rc"], pair="lj",
+                         force_fp64=run["force_fp64"], seed=run["seed"])
+            out.append(serve.Job(jid, float(arrivals[jid]), prm, s.surface, s.surf, s.x, s.p, run["steps"]))
+        return out
+
+    t0 = time.perf_counter()
+    J = jobs(njobs)
+    log(f"[serve] generated {njobs} jobs ({sum(j.n for j in J)} particles) in {time.perf_counter() - t0:.1f} s")
+    budget = int(budget_gb * (1 << 30))
+    t0 = time.perf_counter()
+    serve.serve(J, budget, 1024, realtime=False)
+    closed = serve.summarize(J, time.perf_counter() - t0)
+    log(f"[serve] batched closed loop: {closed}")
+    P = jobs(nplain)
+    t0 = time.perf_counter()
+    serve.run_plain(P, realtime=False)
+    plain = serve.summarize(P, time.perf_counter() - t0)
+    log(f"[serve] plain closed loop ({nplain} jobs): {plain}")
+    J = jobs(njobs)
+    serve.serve(J, budget, 1024, realtime=True)
+    opened = serve.summarize(J)
+    log(f"[serve] batched open loop at {rate}/s: {opened}")
+    P = jobs(nplain)
+    serve.run_plain(P, realtime=True)
+    plain_open = serve.summarize(P)
+    log(f"[serve] plain open loop ({nplain} jobs): {plain_open}")
+    return {
+        "workload": f"{njobs} jobs, Poisson {rate:g}/s, N logU[64,16384], steps logU[1e3,1e4], sphere/spheroid/torus, "
+                    "WCA, fp32 forces",
+        "batched_closed": closed, "plain_closed": plain,
+        "throughput_ratio_particle_steps": closed["particle_steps_per_s"] / plain["particle_steps_per_s"],
+        "batched_open": opened, "plain_open": plain_open,
+        "plain_queue_stable": plain["jobs_per_s"] > rate,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10000)
     ap.add_argument("--warmup", type=int, default=300)
     ap.add_argument("--n", type=int, default=2_000_000)
-    ap.add_argument("--skin", type=float, default=0.3)
+    ap.add_argument("--skin", type=float, default=0.5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="launch steps one by one instead of hipGraph chunks")
+    ap.add_argument("--serving-jobs", type=int, default=400, help="0 skips the serving measurement")
+    ap.add_argument("--serving-plain-jobs", type=int, default=40)
+    ap.add_argument("--serving-rate", type=float, default=200.0)
+    ap.add_argument("--serving-budget-gb", type=float, default=16.0)
     args = ap.parse_args()
     if args.no_graph:
         os.environ["MD_NO_GRAPH"] = "1"
@@ -176,6 +236,9 @@ def main():
             "wall_ms": wall * 1e3,
         },
     }
+    if args.serving_jobs > 0:
+        out["serving"] = serving_bench(args.serving_jobs, args.serving_plain_jobs, args.serving_rate,
+                                       args.serving_budget_gb)
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on the host (bounded sample)")
         out["cpu_baseline"] = cpu_baseline(s, run)

@@ -63,13 +63,13 @@ struct JobBook {
 
 // Device buffers, passed by value to every kernel.
 struct DevBufs {
-  double* X[2];        // positions, SoA [3][C]; parity flips every step
-  double* P[2];        // momenta, SoA [3][C]; parity flips at rebuilds
+  double* X[2];        // positions, AoS [C][3]; parity flips every step
+  double* P[2];        // momenta, AoS [C][3]; parity flips at rebuilds
   uint32_t* ID[2];     // particle index within its job; parity flips at rebuilds
   uint8_t* FLG[2];     // 1 = constrained
   double* MASS[2];     // per-particle mass (jobs with non-uniform mass)
-  double* FC;          // combined force handed in by the caller, SoA [3][C], by job offset + id
-  double* OX;          // outputs of the finish kernel, by job offset + id
+  double* FC;          // combined force handed in by the caller, AoS [C][3], by job offset + id
+  double* OX;          // outputs of the finish kernel (AoS [C][3]), by job offset + id
   double* OP;
   double* OF;
   double* OD;          // [4][C]: kinetic energy, potential energy share, |g|/|n|, |n.v|/|n|
@@ -82,6 +82,7 @@ struct DevBufs {
   uint32_t* RASTER;    // raster cell index per slot
   uint32_t* CID;       // compact cell index per slot
   uint32_t* RANK;      // rank within the cell per slot
+  uint32_t* INV;       // slot of each particle index after the last sort, by job offset + index
   JobDev* jobs;
   JobBook* book;
   int64_t C;           // slot capacity (SoA stride)
@@ -98,10 +99,11 @@ __device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32
                                               uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
-    const uint32_t lo0 = 0xD2511F53u * c0;
-    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
-    const uint32_t lo1 = 0xCD9E8D57u * c2;
+    // one 32x32->64 multiply (v_mad_u64_u32) gives both halves
+    const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+    const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
     const uint32_t n0 = hi1 ^ c1 ^ k0;
     const uint32_t n2 = hi0 ^ c3 ^ k1;
     c0 = n0;
@@ -294,15 +296,16 @@ __device__ __forceinline__ void min_image(const JobDev& J, double& dx, double& d
 
 // Force coefficient c of one pair, F_i += c (x_i - x_j), for r^2 < rc^2
 // (Eq. S1: -dV/dr / r); zero beyond the cut-off.
-template <typename real>
-__device__ __forceinline__ real pair_coef(const JobDev& J, double r2, real eps24, real sig2, real dphic, bool smooth) {
+template <typename real, bool kSmooth>
+__device__ __forceinline__ real pair_coef(const JobDev& J, double r2, real eps24, real sig2, real dphic) {
   if (!(r2 < J.rc2)) return (real)0;
   const real r2r = (real)r2;
-  const real inv = (real)1 / r2r;
+  // FP32: the hardware reciprocal (1 ulp); FP64: a correctly rounded division
+  const real inv = sizeof(real) == 8 ? (real)(1.0 / (double)r2r) : (real)__builtin_amdgcn_rcpf((float)r2r);
   const real s2 = sig2 * inv;
   const real s6 = s2 * s2 * s2;
   real coef = eps24 * inv * s6 * ((real)2 * s6 - (real)1);
-  if (smooth) {
+  if (kSmooth) {
     const real rinv = sizeof(real) == 8 ? (real)(1.0 / sqrt((double)r2r)) : (real)rsqrtf((float)r2r);
     coef += dphic * rinv;
   }
@@ -313,11 +316,12 @@ __device__ __forceinline__ real pair_coef(const JobDev& J, double r2, real eps24
 // list is sorted by particle index).  FP32 variant: separations and the
 // cut-off test in FP64, the force in FP32 with FP32 accumulation.  The loop
 // issues the gathers of four neighbours before using them; the additions
-// still happen one neighbour at a time in list order.
-template <bool kF64>
-__device__ __forceinline__ void pair_forces(const JobDev& J, const DevBufs& B, const double* __restrict__ X,
-                                            int64_t i, double xi, double yi, double zi, double& Fx, double& Fy,
-                                            double& Fz) {
+// still happen one neighbour at a time in list order.  Specialised on the
+// potential's form and on periodicity so the loop carries no dead work.
+template <bool kF64, bool kSmooth, bool kPer>
+__device__ __forceinline__ void pair_forces_impl(const JobDev& J, const DevBufs& B, const double* __restrict__ X,
+                                                 int64_t i, double xi, double yi, double zi, double& Fx,
+                                                 double& Fy, double& Fz) {
   using real = typename std::conditional<kF64, double, float>::type;
   const int64_t C = B.C;
   const int cnt = (int)B.NCNT[i];
@@ -326,8 +330,6 @@ __device__ __forceinline__ void pair_forces(const JobDev& J, const DevBufs& B, c
   const real eps24 = (real)(24.0 * J.eps);
   const real sig2 = (real)J.sig2;
   const real dphic = (real)J.dphic;
-  const bool smooth = J.pair_kind == kPairLJSmooth;
-  const bool anyper = J.periodic[0] | J.periodic[1] | J.periodic[2];
   int k = 0;
   for (; k + 4 <= cnt; k += 4) {
     int64_t j[4];
@@ -336,16 +338,16 @@ __device__ __forceinline__ void pair_forces(const JobDev& J, const DevBufs& B, c
     for (int u = 0; u < 4; ++u) j[u] = nl[(int64_t)(k + u) * C];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      ax[u] = X[j[u]];
-      ay[u] = X[C + j[u]];
-      az[u] = X[2 * C + j[u]];
+      ax[u] = X[3 * j[u]];
+      ay[u] = X[3 * j[u] + 1];
+      az[u] = X[3 * j[u] + 2];
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       double dx = xi - ax[u], dy = yi - ay[u], dz = zi - az[u];
-      if (anyper) min_image(J, dx, dy, dz);
+      if (kPer) min_image(J, dx, dy, dz);
       const double r2 = dx * dx + dy * dy + dz * dz;
-      const real c = pair_coef<real>(J, r2, eps24, sig2, dphic, smooth);
+      const real c = pair_coef<real, kSmooth>(J, r2, eps24, sig2, dphic);
       fx += c * (real)dx;
       fy += c * (real)dy;
       fz += c * (real)dz;
@@ -353,10 +355,10 @@ __device__ __forceinline__ void pair_forces(const JobDev& J, const DevBufs& B, c
   }
   for (; k < cnt; ++k) {
     const int64_t j = nl[(int64_t)k * C];
-    double dx = xi - X[j], dy = yi - X[C + j], dz = zi - X[2 * C + j];
-    if (anyper) min_image(J, dx, dy, dz);
+    double dx = xi - X[3 * j], dy = yi - X[3 * j + 1], dz = zi - X[3 * j + 2];
+    if (kPer) min_image(J, dx, dy, dz);
     const double r2 = dx * dx + dy * dy + dz * dz;
-    const real c = pair_coef<real>(J, r2, eps24, sig2, dphic, smooth);
+    const real c = pair_coef<real, kSmooth>(J, r2, eps24, sig2, dphic);
     fx += c * (real)dx;
     fy += c * (real)dy;
     fz += c * (real)dz;
@@ -364,6 +366,25 @@ __device__ __forceinline__ void pair_forces(const JobDev& J, const DevBufs& B, c
   Fx = (double)fx;
   Fy = (double)fy;
   Fz = (double)fz;
+}
+
+template <bool kF64>
+__device__ __forceinline__ void pair_forces(const JobDev& J, const DevBufs& B, const double* __restrict__ X,
+                                            int64_t i, double xi, double yi, double zi, double& Fx, double& Fy,
+                                            double& Fz) {
+  const bool smooth = J.pair_kind == kPairLJSmooth;
+  const bool per = J.periodic[0] | J.periodic[1] | J.periodic[2];
+  if (smooth) {
+    if (per)
+      pair_forces_impl<kF64, true, true>(J, B, X, i, xi, yi, zi, Fx, Fy, Fz);
+    else
+      pair_forces_impl<kF64, true, false>(J, B, X, i, xi, yi, zi, Fx, Fy, Fz);
+  } else {
+    if (per)
+      pair_forces_impl<kF64, false, true>(J, B, X, i, xi, yi, zi, Fx, Fy, Fz);
+    else
+      pair_forces_impl<kF64, false, false>(J, B, X, i, xi, yi, zi, Fx, Fy, Fz);
+  }
 }
 
 // Energy share U_i = 1/2 sum_j V_ij (Eq. S1), FP64, for diagnostics.
@@ -377,7 +398,7 @@ __device__ __forceinline__ double pair_energy(const JobDev& J, const DevBufs& B,
   double u = 0.0;
   for (int k = 0; k < cnt; ++k) {
     const int64_t j = B.NL[(int64_t)k * C + i];
-    double dx = xi - X[j], dy = yi - X[C + j], dz = zi - X[2 * C + j];
+    double dx = xi - X[3 * j], dy = yi - X[3 * j + 1], dz = zi - X[3 * j + 2];
     if (anyper) min_image(J, dx, dy, dz);
     const double r2 = dx * dx + dy * dy + dz * dz;
     if (!(r2 < J.rc2)) continue;
@@ -388,6 +409,16 @@ __device__ __forceinline__ double pair_energy(const JobDev& J, const DevBufs& B,
     u += 0.5 * v;
   }
   return u;
+}
+
+// Workgroup-uniform values read from memory are moved to scalar registers, so
+// that everything addressed through them (the job record in particular) is
+// loaded with scalar loads instead of occupying vector registers.
+__device__ __forceinline__ int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uniform_i64(int64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
 // XCD-aware workgroup order: the dispatcher deals workgroups round-robin over

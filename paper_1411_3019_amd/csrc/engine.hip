@@ -170,7 +170,7 @@ int validate_params(const md_params& p) {
 
 // Bytes of device state per particle slot (excluding the neighbour list).
 constexpr int64_t kSlotBytes = 2 * 24 /*X*/ + 2 * 24 /*P*/ + 2 * 4 /*ID*/ + 2 * 1 /*FLG*/ + 2 * 8 /*MASS*/ +
-                               24 /*FC*/ + 3 * 24 /*OX,OP,OF*/ + 32 /*OD*/ + 4 /*NCNT*/ + 4 * 5 /*rebuild*/;
+                               24 /*FC*/ + 3 * 24 /*OX,OP,OF*/ + 32 /*OD*/ + 4 /*NCNT*/ + 4 * 6 /*rebuild*/;
 
 struct HostJob {
   bool used = false;
@@ -336,7 +336,7 @@ struct Engine {
       if (e) (void)hipEventDestroy(e), e = nullptr;
     void* ptrs[] = {B.X[0], B.X[1], B.P[0], B.P[1], B.ID[0], B.ID[1], B.FLG[0], B.FLG[1], B.MASS[0], B.MASS[1],
                     B.FC, B.OX, B.OP, B.OF, B.OD, B.NL, B.NCNT, B.BM, B.WOFF, B.CCNT, B.CSTART, B.RASTER,
-                    B.CID, B.RANK, B.jobs, B.book, step_tiles_job, step_tiles_first, step_counts, aux_tiles_job,
+                    B.CID, B.RANK, B.INV, B.jobs, B.book, step_tiles_job, step_tiles_first, step_counts, aux_tiles_job,
                     aux_tiles_first, chunks_d, chunk_sums, ranges_d};
     for (void* p : ptrs)
       if (p) (void)hipFree(p);
@@ -410,6 +410,7 @@ struct Engine {
     MDCHK(dalloc(&B.RASTER, C));
     MDCHK(dalloc(&B.CID, C));
     MDCHK(dalloc(&B.RANK, C));
+    MDCHK(dalloc(&B.INV, C));
     MDCHK(dalloc(&B.jobs, max_jobs));
     MDCHK(dalloc(&B.book, max_jobs));
     HIPCHK(hipMemsetAsync(B.book, 0, sizeof(JobBook) * max_jobs, stream));
@@ -602,20 +603,10 @@ struct Engine {
     h.last_build = step0;
     // upload: SoA positions, momenta, forces; ids in order; flags; masses
     if (n > 0) {
-      MDCHK(ensure_stage(sizeof(double) * 3 * n));
-      double* st = (double*)stage;
-      auto put_soa = [&](double* dst, const double* src) -> int {
-        HIPCHK(hipStreamSynchronize(stream));
-        for (int k = 0; k < 3; ++k)
-          for (int64_t i = 0; i < n; ++i) st[k * n + i] = src[3 * i + k];
-        for (int k = 0; k < 3; ++k)
-          HIPCHK(hipMemcpyAsync(dst + k * C + h.off, st + k * n, sizeof(double) * n, hipMemcpyHostToDevice,
-                                stream));
-        return MD_OK;
-      };
-      MDCHK(put_soa(B.X[0], x));
-      MDCHK(put_soa(B.P[0], p));
-      if (fcomb) MDCHK(put_soa(B.FC, fcomb));
+      // positions, momenta and forces are AoS on both sides: plain copies
+      MDCHK(upload(B.X[0] + 3 * h.off, x, sizeof(double) * 3 * n));
+      MDCHK(upload(B.P[0] + 3 * h.off, p, sizeof(double) * 3 * n));
+      if (fcomb) MDCHK(upload(B.FC + 3 * h.off, fcomb, sizeof(double) * 3 * n));
       std::vector<uint32_t> ids(n);
       for (int64_t i = 0; i < n; ++i) ids[i] = (uint32_t)i;
       MDCHK(upload(B.ID[0] + h.off, ids.data(), sizeof(uint32_t) * n));
@@ -722,7 +713,7 @@ struct Engine {
     hipLaunchKernelGGL(k_scan_c, dim3(nc), dim3(kScanThreads), 0, stream, B.CSTART, chunks_d + nb, chunk_sums + nb);
     hipLaunchKernelGGL(k_scatter, dim3(ntiles), dim3(kTile), 0, stream, B, aux_tiles_job, aux_tiles_first);
     for (int attempt = 0; attempt < 3; ++attempt) {
-      const size_t lds = (size_t)kmax * kNlistBlock * 2 * sizeof(uint32_t);
+      const size_t lds = (size_t)kmax * kNlistBlock * sizeof(uint32_t);
       if (lds > 160 * 1024) return MD_ENOMEM;
       hipLaunchKernelGGL(k_nlist, dim3(4 * ntiles), dim3(kNlistBlock), lds, stream, B, aux_tiles_job,
                          aux_tiles_first);
@@ -815,10 +806,10 @@ struct Engine {
   void enqueue_steps(int t0, int k) {
     for (int t = t0; t < t0 + k; ++t) {
       if (grid64 > 0)
-        hipLaunchKernelGGL(k_step<true>, dim3(grid64), dim3(kTile), 0, stream, B, step_tiles_job, step_tiles_first,
+        hipLaunchKernelGGL(k_step_f64, dim3(grid64), dim3(kTile), 0, stream, B, step_tiles_job, step_tiles_first,
                            step_counts, t);
       if (grid32 > 0)
-        hipLaunchKernelGGL(k_step<false>, dim3(grid32), dim3(kTile), 0, stream, B, step_tiles_job + tile_cap,
+        hipLaunchKernelGGL(k_step_f32, dim3(grid32), dim3(kTile), 0, stream, B, step_tiles_job + tile_cap,
                            step_tiles_first + tile_cap, step_counts + 1, t);
     }
   }
@@ -976,22 +967,16 @@ struct Engine {
     const int64_t n = h.n;
     MDCHK(ensure_stage(sizeof(double) * 13 * n));
     double* st = (double*)stage;
-    auto get_rows = [&](const double* src, int rows, double* dst) -> int {
-      for (int k = 0; k < rows; ++k)
-        HIPCHK(hipMemcpyAsync(dst + k * n, src + k * C + h.off, sizeof(double) * n, hipMemcpyDeviceToHost, stream));
-      return MD_OK;
-    };
-    MDCHK(get_rows(B.OX, 3, st));
-    MDCHK(get_rows(B.OP, 3, st + 3 * n));
-    MDCHK(get_rows(B.OF, 3, st + 6 * n));
-    MDCHK(get_rows(B.OD, 4, st + 9 * n));
+    HIPCHK(hipMemcpyAsync(st, B.OX + 3 * h.off, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipMemcpyAsync(st + 3 * n, B.OP + 3 * h.off, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipMemcpyAsync(st + 6 * n, B.OF + 3 * h.off, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, stream));
+    for (int k = 0; k < 4; ++k)
+      HIPCHK(hipMemcpyAsync(st + (9 + k) * n, B.OD + k * C + h.off, sizeof(double) * n, hipMemcpyDeviceToHost,
+                            stream));
     HIPCHK(hipStreamSynchronize(stream));
-    for (int64_t i = 0; i < n; ++i)
-      for (int k = 0; k < 3; ++k) {
-        if (x) x[3 * i + k] = st[k * n + i];
-        if (p) p[3 * i + k] = st[(3 + k) * n + i];
-        if (f) f[3 * i + k] = st[(6 + k) * n + i];
-      }
+    if (x) std::memcpy(x, st, sizeof(double) * 3 * n);
+    if (p) std::memcpy(p, st + 3 * n, sizeof(double) * 3 * n);
+    if (f) std::memcpy(f, st + 6 * n, sizeof(double) * 3 * n);
     if (diag) {
       double K = 0.0, U = 0.0, gd = 0.0, nv = 0.0, ndof = 0.0;
       for (int64_t i = 0; i < n; ++i) {

@@ -50,37 +50,48 @@ __device__ __forceinline__ void record_error(JobBook& K, int code, uint32_t id) 
   atomicOr(&K.flags, (int)kFlagError);
 }
 
-// Combined force f^s of Algorithm S1 for one particle (FP64 arithmetic; the
-// normals come from the FP64 or the FP32 Box-Muller transform with kF64).
+// Random part of the combined force of Algorithm S1 for one particle:
+// 1/2 sqrt(m) k (xi^s + xi^{s-1}) (at a start: sqrt(m) k xi^s, the previous
+// draw being taken equal to this one).  Independent of the pair forces, so it
+// is computed while the neighbour gathers are in flight.
 template <bool kF64>
-__device__ __forceinline__ void combined_force(const JobDev& J, const DevBufs& B, int64_t i, uint32_t id,
-                                               double m, long long s, double Fx, double Fy, double Fz,
-                                               double px, double py, double pz, bool start, double& fx,
-                                               double& fy, double& fz) {
+__device__ __forceinline__ void langevin_kick(const JobDev& J, uint32_t id, double m, long long s, bool start,
+                                              double& rx, double& ry, double& rz) {
+  rx = ry = rz = 0.0;
+  if (!(J.gamma > 0.0) || (J.mode == kModeStartGiven && start)) return;
+  double a0, a1, a2;
+  langevin_normals<kF64>(J.seed, id, s, a0, a1, a2);
+  const double k = sqrt(m) * J.noise_k;
+  if (start) {
+    rx = k * a0;
+    ry = k * a1;
+    rz = k * a2;
+  } else {
+    double r0, r1, r2;
+    langevin_normals<kF64>(J.seed, id, s - 1, r0, r1, r2);
+    const double hk = 0.5 * k;
+    rx = hk * (a0 + r0);
+    ry = hk * (a1 + r1);
+    rz = hk * (a2 + r2);
+  }
+}
+
+// Combined force f^s = b [F - gamma p + random part] (Algorithm S1); at a
+// start with a force handed in by the caller, that force.
+__device__ __forceinline__ void combined_force(const JobDev& J, const DevBufs& B, uint32_t id, bool start, double Fx,
+                                               double Fy, double Fz, double px, double py, double pz, double rx,
+                                               double ry, double rz, double& fx, double& fy, double& fz) {
   if (J.mode == kModeStartGiven && start) {
     const int64_t o = J.off + id;
-    fx = B.FC[o];
-    fy = B.FC[B.C + o];
-    fz = B.FC[2 * B.C + o];
+    fx = B.FC[3 * o];
+    fy = B.FC[3 * o + 1];
+    fz = B.FC[3 * o + 2];
     return;
   }
   if (J.gamma > 0.0) {
-    double a0, a1, a2;
-    langevin_normals<kF64>(J.seed, id, s, a0, a1, a2);
-    const double k = sqrt(m) * J.noise_k;
-    if (start) {
-      // no earlier draw exists: the previous draw is taken equal to this one
-      fx = J.b * (Fx - J.gamma * px + k * a0);
-      fy = J.b * (Fy - J.gamma * py + k * a1);
-      fz = J.b * (Fz - J.gamma * pz + k * a2);
-    } else {
-      double r0, r1, r2;
-      langevin_normals<kF64>(J.seed, id, s - 1, r0, r1, r2);
-      const double hk = 0.5 * k;
-      fx = J.b * (Fx - J.gamma * px + hk * (a0 + r0));
-      fy = J.b * (Fy - J.gamma * py + hk * (a1 + r1));
-      fz = J.b * (Fz - J.gamma * pz + hk * (a2 + r2));
-    }
+    fx = J.b * (Fx - J.gamma * px + rx);
+    fy = J.b * (Fy - J.gamma * py + ry);
+    fz = J.b * (Fz - J.gamma * pz + rz);
   } else {
     fx = Fx;
     fy = Fy;
@@ -89,18 +100,16 @@ __device__ __forceinline__ void combined_force(const JobDev& J, const DevBufs& B
 }
 
 template <bool kF64>
-__global__ void __launch_bounds__(kTile) k_step(DevBufs B, const int* __restrict__ tile_job,
-                                                const int64_t* __restrict__ tile_first,
-                                                const int* __restrict__ ntiles_ptr, int t) {
-  __shared__ double red[kTile / 64];
-  __shared__ int redi[kTile / 64];
+__device__ __forceinline__ void step_body(const DevBufs& B, const int* __restrict__ tile_job,
+                                          const int64_t* __restrict__ tile_first, const int* __restrict__ ntiles_ptr,
+                                          int t, double* red, int* redi) {
   // the grid may be larger than the tile list (it is sized once per graph);
   // surplus workgroups leave at once
-  const int ntiles = *ntiles_ptr;
+  const int ntiles = uniform_int(*ntiles_ptr);
   if ((int)blockIdx.x >= ntiles) return;
   const int b = xcd_remap((int)blockIdx.x, ntiles);
-  const int job = tile_job[b];
-  const int64_t first = tile_first[b];
+  const int job = uniform_int(tile_job[b]);
+  const int64_t first = uniform_i64(tile_first[b]);
   const JobDev& J = B.jobs[job];
   JobBook& K = B.book[job];
   if (K.flags != 0 || t >= J.remaining) return;
@@ -128,17 +137,21 @@ __global__ void __launch_bounds__(kTile) k_step(DevBufs B, const int* __restrict
   double disp = 0.0;
   int iters = 0;
   if (i < J.off + J.n) {
-    const double xi = X[i], yi = X[C + i], zi = X[2 * C + i];
+    const double xi = X[3 * i], yi = X[3 * i + 1], zi = X[3 * i + 2];
+    const uint32_t id = B.ID[J.scur][i];
+    const double m = J.uniform_mass ? J.mass : B.MASS[J.scur][i];
+    // noise first: pure arithmetic that overlaps the latency of the list and
+    // neighbour loads issued next
+    double rx, ry, rz;
+    langevin_kick<kF64>(J, id, m, s, start, rx, ry, rz);
     double Fx = 0.0, Fy = 0.0, Fz = 0.0;
     if (J.pair_kind != kPairNone) pair_forces<kF64>(J, B, X, i, xi, yi, zi, Fx, Fy, Fz);
-    // the particle's own momentum and tags are loaded after the force loop,
+    // the particle's own momentum and flag are loaded after the force loop,
     // which keeps them out of the loop's live registers
-    double px = P[i], py = P[C + i], pz = P[2 * C + i];
-    const uint32_t id = B.ID[J.scur][i];
+    double px = P[3 * i], py = P[3 * i + 1], pz = P[3 * i + 2];
     const bool cons = B.FLG[J.scur][i] != 0;
-    const double m = J.uniform_mass ? J.mass : B.MASS[J.scur][i];
     double fx, fy, fz;
-    combined_force<kF64>(J, B, i, id, m, s, Fx, Fy, Fz, px, py, pz, start, fx, fy, fz);
+    combined_force(J, B, id, start, Fx, Fy, Fz, px, py, pz, rx, ry, rz, fx, fy, fz);
     double nx = 0.0, ny = 0.0, nz = 0.0, g0 = 0.0;
     if (cons) g0 = surf_eval(J, xi, yi, zi, nx, ny, nz);
     // momentum stage of step s-1 -> s: tangent projection (closed form of the linear Newton)
@@ -170,12 +183,12 @@ __global__ void __launch_bounds__(kTile) k_step(DevBufs B, const int* __restrict
       y1 = yi + dtm * py;
       z1 = zi + dtm * pz;
     }
-    Xo[i] = x1;
-    Xo[C + i] = y1;
-    Xo[2 * C + i] = z1;
-    P[i] = px;
-    P[C + i] = py;
-    P[2 * C + i] = pz;
+    Xo[3 * i] = x1;
+    Xo[3 * i + 1] = y1;
+    Xo[3 * i + 2] = z1;
+    P[3 * i] = px;
+    P[3 * i + 1] = py;
+    P[3 * i + 2] = pz;
     const double dx = x1 - xi, dy = y1 - yi, dz = z1 - zi;
     disp = sqrt(dx * dx + dy * dy + dz * dz);
     if (!(disp <= 1e300) || !(fabs(px) + fabs(py) + fabs(pz) <= 1e300)) {
@@ -188,21 +201,44 @@ __global__ void __launch_bounds__(kTile) k_step(DevBufs B, const int* __restrict
   if (threadIdx.x == 0 && im > 0) atomicMax(&K.newton_max, im);
 }
 
+#ifndef MDK_STEP32_WAVES
+#define MDK_STEP32_WAVES 5
+#endif
+
+// FP32 pair forces (and FP32 Box-Muller): occupancy target MDK_STEP32_WAVES
+// wavefronts per SIMD.
+__global__ void __launch_bounds__(kTile) __attribute__((amdgpu_waves_per_eu(MDK_STEP32_WAVES, 8)))
+k_step_f32(DevBufs B, const int* __restrict__ tile_job, const int64_t* __restrict__ tile_first,
+           const int* __restrict__ ntiles_ptr, int t) {
+  __shared__ double red[kTile / 64];
+  __shared__ int redi[kTile / 64];
+  step_body<false>(B, tile_job, tile_first, ntiles_ptr, t, red, redi);
+}
+
+// FP64 pair forces and FP64 Box-Muller.
+__global__ void __launch_bounds__(kTile) k_step_f64(DevBufs B, const int* __restrict__ tile_job,
+                                                    const int64_t* __restrict__ tile_first,
+                                                    const int* __restrict__ ntiles_ptr, int t) {
+  __shared__ double red[kTile / 64];
+  __shared__ int redi[kTile / 64];
+  step_body<true>(B, tile_job, tile_first, ntiles_ptr, t, red, redi);
+}
+
 // Finish: state at the current step m (x^m, p^m, f^m) and per-particle
 // diagnostics, written by particle index.
 template <bool kF64>
 __global__ void __launch_bounds__(kTile) k_finish(DevBufs B, const int* __restrict__ tile_job,
                                                   const int64_t* __restrict__ tile_first) {
-  const int job = tile_job[blockIdx.x];
-  const int64_t first = tile_first[blockIdx.x];
+  const int job = uniform_int(tile_job[blockIdx.x]);
+  const int64_t first = uniform_i64(tile_first[blockIdx.x]);
   const JobDev& J = B.jobs[job];
   const int64_t C = B.C;
   const int64_t i = first + threadIdx.x;
   if (i >= J.off + J.n) return;
   const double* __restrict__ X = B.X[J.xcur];
   const double* __restrict__ P = B.P[J.pcur];
-  const double xi = X[i], yi = X[C + i], zi = X[2 * C + i];
-  double px = P[i], py = P[C + i], pz = P[2 * C + i];
+  const double xi = X[3 * i], yi = X[3 * i + 1], zi = X[3 * i + 2];
+  double px = P[3 * i], py = P[3 * i + 1], pz = P[3 * i + 2];
   const uint32_t id = B.ID[J.scur][i];
   const bool cons = B.FLG[J.scur][i] != 0;
   const double m = J.uniform_mass ? J.mass : B.MASS[J.scur][i];
@@ -213,8 +249,9 @@ __global__ void __launch_bounds__(kTile) k_finish(DevBufs B, const int* __restri
     pair_forces<kF64>(J, B, X, i, xi, yi, zi, Fx, Fy, Fz);
     Ui = pair_energy(J, B, X, i, xi, yi, zi);
   }
-  double fx, fy, fz;
-  combined_force<kF64>(J, B, i, id, m, s, Fx, Fy, Fz, px, py, pz, start, fx, fy, fz);
+  double rx, ry, rz, fx, fy, fz;
+  langevin_kick<kF64>(J, id, m, s, start, rx, ry, rz);
+  combined_force(J, B, id, start, Fx, Fy, Fz, px, py, pz, rx, ry, rz, fx, fy, fz);
   double nx = 0.0, ny = 0.0, nz = 0.0, g = 0.0;
   if (cons) g = surf_eval(J, xi, yi, zi, nx, ny, nz);
   if (!start) {
@@ -229,15 +266,15 @@ __global__ void __launch_bounds__(kTile) k_finish(DevBufs B, const int* __restri
     }
   }
   const int64_t o = J.off + id;
-  B.OX[o] = xi;
-  B.OX[C + o] = yi;
-  B.OX[2 * C + o] = zi;
-  B.OP[o] = px;
-  B.OP[C + o] = py;
-  B.OP[2 * C + o] = pz;
-  B.OF[o] = fx;
-  B.OF[C + o] = fy;
-  B.OF[2 * C + o] = fz;
+  B.OX[3 * o] = xi;
+  B.OX[3 * o + 1] = yi;
+  B.OX[3 * o + 2] = zi;
+  B.OP[3 * o] = px;
+  B.OP[3 * o + 1] = py;
+  B.OP[3 * o + 2] = pz;
+  B.OF[3 * o] = fx;
+  B.OF[3 * o + 1] = fy;
+  B.OF[3 * o + 2] = fz;
   B.OD[o] = 0.5 * (px * px + py * py + pz * pz) / m;
   B.OD[C + o] = Ui;
   double gd = 0.0, nv = 0.0;
@@ -283,46 +320,60 @@ __global__ void k_zero_ranges(uint32_t* __restrict__ base, const Range* __restri
     base[r.start + k] = 0u;
 }
 
-// Wavefront-level combining of atomics on equal addresses: after a build the
-// particles are stored in cell order, so neighbouring lanes usually hit the
-// same bitmap word / cell counter.  One lane per distinct key issues the atomic.
+// Wavefront-level combining of atomics on equal addresses.  After a build the
+// particles are stored in cell order, so neighbouring lanes usually share a
+// bitmap word / cell counter.  Lanes are grouped into runs of equal keys; the
+// runs of a wavefront issue their atomics in one instruction (runs with equal
+// keys that are not adjacent simply issue separate atomics).
 constexpr uint32_t kNoKey = 0xFFFFFFFFu;
+
+__device__ __forceinline__ unsigned long long lanemask_le(int lane) {
+  return lane == 63 ? ~0ull : ((1ull << (lane + 1)) - 1ull);
+}
+
+// First lane of the run of equal keys that contains this lane.
+__device__ __forceinline__ int run_start(uint32_t key, int lane, unsigned long long* heads_out) {
+  const uint32_t prev = __shfl_up(key, 1, 64);
+  const bool head = lane == 0 || prev != key;
+  const unsigned long long heads = __ballot(head);
+  *heads_out = heads;
+  return 63 - __clzll((long long)(heads & lanemask_le(lane)));
+}
 
 __global__ void __launch_bounds__(kTile) k_mark(DevBufs B, const int* __restrict__ tile_job,
                                                 const int64_t* __restrict__ tile_first) {
-  const int job = tile_job[blockIdx.x];
+  const int job = uniform_int(tile_job[blockIdx.x]);
   const JobDev& J = B.jobs[job];
-  const int64_t i = tile_first[blockIdx.x] + threadIdx.x;
+  const int64_t i = uniform_i64(tile_first[blockIdx.x]) + threadIdx.x;
   const bool valid = i < J.off + J.n;
   uint32_t key = kNoKey, bits = 0u;
   if (valid) {
     const double* X = B.X[J.xcur];
-    const int64_t C = B.C;
-    const int cx = cell_coord(J, 0, X[i]), cy = cell_coord(J, 1, X[C + i]), cz = cell_coord(J, 2, X[2 * C + i]);
+    const int cx = cell_coord(J, 0, X[3 * i]), cy = cell_coord(J, 1, X[3 * i + 1]),
+              cz = cell_coord(J, 2, X[3 * i + 2]);
     const uint32_t r = raster_of(J, cx, cy, cz);
     B.RASTER[i] = r;
     key = r >> 5;
     bits = 1u << (r & 31);
   }
   const int lane = threadIdx.x & 63;
-  for (;;) {
-    const unsigned long long act = __ballot(key != kNoKey);
-    if (act == 0ull) break;
-    const int leader = __ffsll((long long)act) - 1;
-    const uint32_t k0 = __shfl(key, leader, 64);
-    const bool mine = key == k0;
-    uint32_t v = mine ? bits : 0u;
-    for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o, 64);
-    if (lane == leader) atomicOr(&B.BM[J.bm_off + k0], v);
-    if (mine) key = kNoKey;
+  unsigned long long heads;
+  const int start = run_start(key, lane, &heads);
+  // OR over the run, accumulated towards its last lane
+  uint32_t v = bits;
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t t = __shfl_up(v, o, 64);
+    if (lane - o >= start) v |= t;
   }
+  const bool tail = lane == 63 || ((heads >> (lane + 1)) & 1ull);
+  if (tail && key != kNoKey) atomicOr(&B.BM[J.bm_off + key], v);
 }
 
 __global__ void __launch_bounds__(kTile) k_count(DevBufs B, const int* __restrict__ tile_job,
                                                  const int64_t* __restrict__ tile_first) {
-  const int job = tile_job[blockIdx.x];
+  const int job = uniform_int(tile_job[blockIdx.x]);
   const JobDev& J = B.jobs[job];
-  const int64_t i = tile_first[blockIdx.x] + threadIdx.x;
+  const int64_t i = uniform_i64(tile_first[blockIdx.x]) + threadIdx.x;
   const bool valid = i < J.off + J.n;
   uint32_t key = kNoKey;
   if (valid) {
@@ -332,30 +383,23 @@ __global__ void __launch_bounds__(kTile) k_count(DevBufs B, const int* __restric
     B.CID[i] = key;
   }
   const int lane = threadIdx.x & 63;
-  const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  uint32_t rank = 0u;
-  for (;;) {
-    const unsigned long long act = __ballot(key != kNoKey);
-    if (act == 0ull) break;
-    const int leader = __ffsll((long long)act) - 1;
-    const uint32_t k0 = __shfl(key, leader, 64);
-    const unsigned long long m = __ballot(key == k0);
-    uint32_t base = 0u;
-    if (lane == leader) base = atomicAdd(&B.CCNT[J.off + k0], (uint32_t)__popcll(m));
-    base = __shfl(base, leader, 64);
-    if (key == k0) {
-      rank = base + (uint32_t)__popcll(m & below);
-      key = kNoKey;
-    }
+  unsigned long long heads;
+  const int start = run_start(key, lane, &heads);
+  uint32_t base = 0u;
+  if (start == lane && key != kNoKey) {
+    const unsigned long long later = heads & ~lanemask_le(lane);
+    const int next = later ? __ffsll((long long)later) - 1 : 64;
+    base = atomicAdd(&B.CCNT[J.off + key], (uint32_t)(next - lane));
   }
-  if (valid) B.RANK[i] = rank;
+  base = __shfl(base, start, 64);
+  if (valid) B.RANK[i] = base + (uint32_t)(lane - start);
 }
 
 __global__ void __launch_bounds__(kTile) k_scatter(DevBufs B, const int* __restrict__ tile_job,
                                                    const int64_t* __restrict__ tile_first) {
-  const int job = tile_job[blockIdx.x];
+  const int job = uniform_int(tile_job[blockIdx.x]);
   const JobDev& J = B.jobs[job];
-  const int64_t i = tile_first[blockIdx.x] + threadIdx.x;
+  const int64_t i = uniform_i64(tile_first[blockIdx.x]) + threadIdx.x;
   if (i >= J.off + J.n) return;
   const int64_t C = B.C;
   const int64_t d = J.off + B.CSTART[J.off + B.CID[i]] + B.RANK[i];
@@ -365,34 +409,14 @@ __global__ void __launch_bounds__(kTile) k_scatter(DevBufs B, const int* __restr
   double* Pd = B.P[J.pcur ^ 1];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    Xd[k * C + d] = Xs[k * C + i];
-    Pd[k * C + d] = Ps[k * C + i];
+    Xd[3 * d + k] = Xs[3 * i + k];
+    Pd[3 * d + k] = Ps[3 * i + k];
   }
-  B.ID[J.scur ^ 1][d] = B.ID[J.scur][i];
+  const uint32_t id = B.ID[J.scur][i];
+  B.ID[J.scur ^ 1][d] = id;
+  B.INV[J.off + id] = (uint32_t)(d - J.off);
   B.FLG[J.scur ^ 1][d] = B.FLG[J.scur][i];
   if (!J.uniform_mass) B.MASS[J.scur ^ 1][d] = B.MASS[J.scur][i];
-}
-
-// Offsets of the stencil along one dimension, without repeats when the
-// periodic cell count is below 3.
-__device__ __forceinline__ int stencil(const JobDev& J, int k, int c, int* out) {
-  const int nc = J.nc[k];
-  if (J.periodic[k]) {
-    if (nc >= 3) {
-      out[0] = (c + nc - 1) % nc;
-      out[1] = c;
-      out[2] = (c + 1) % nc;
-      return 3;
-    }
-    out[0] = 0;
-    if (nc == 2) out[1] = 1;
-    return nc;
-  }
-  int m = 0;
-  if (c > 0) out[m++] = c - 1;
-  out[m++] = c;
-  if (c + 1 < nc) out[m++] = c + 1;
-  return m;
 }
 
 // Occupied cells with raster index below r, for the compact cell index.
@@ -404,77 +428,122 @@ __device__ __forceinline__ uint32_t cells_before(const DevBufs& B, const JobDev&
 // One wavefront per workgroup; each lane builds the list of one slot of the
 // freshly sorted order.  Slots are in raster cell order (x-major, z fastest),
 // so for each of the 9 (dx, dy) columns of the 27-cell stencil the cells
-// z-1..z+1 are one contiguous slot range, found from two popcount lookups.
-// Accepted neighbours are kept sorted by particle index in LDS
-// ([kmax][64], lane-minor so lanes hit distinct banks).
+// z-1..z+1 are one contiguous slot range (two when z wraps), found from two
+// popcount lookups.  All lookups are issued first and the ranges parked in
+// LDS; candidates are then read four at a time.  Accepted neighbours are kept
+// sorted by particle index in LDS ([kmax][64], lane-minor so lanes hit
+// distinct banks).
+// Cell coordinate c + d along dimension k for a stencil offset d in {-1,0,1}:
+// wrapped when periodic (offsets that would repeat a cell when the periodic
+// count is below 3 are dropped), dropped outside a non-periodic grid.
+__device__ __forceinline__ bool stencil_coord(const JobDev& J, int k, int c, int d, int& out) {
+  const int nc = J.nc[k];
+  if (J.periodic[k]) {
+    if (nc < 3 && (d < 0 || d >= nc)) return false;
+    out = (c + d + nc) % nc;
+    return true;
+  }
+  out = c + d;
+  return out >= 0 && out < nc;
+}
+
+// Slot ranges (relative to the job) of one stencil column: cells (x, y, z-1..z+1),
+// split in two runs when z wraps.
+struct ColumnRange {
+  uint32_t b0, e0, b1, e1;
+};
+
+__device__ __forceinline__ ColumnRange column_range(const DevBufs& B, const JobDev& J, int cx, int cy, int col,
+                                                    int za0, int zb0, int za1, int zb1) {
+  ColumnRange r{0u, 0u, 0u, 0u};
+  int ax, ay;
+  if (!stencil_coord(J, 0, cx, col / 3 - 1, ax) || !stencil_coord(J, 1, cy, col % 3 - 1, ay)) return r;
+  const int64_t base = J.off;
+  const uint32_t c0 = ((uint32_t)ax * (uint32_t)J.nc[1] + (uint32_t)ay) * (uint32_t)J.nc[2];
+  r.b0 = B.CSTART[base + cells_before(B, J, c0 + (uint32_t)za0)];
+  r.e0 = B.CSTART[base + cells_before(B, J, c0 + (uint32_t)zb0 + 1u)];
+  if (zb1 >= za1) {
+    r.b1 = B.CSTART[base + cells_before(B, J, c0 + (uint32_t)za1)];
+    r.e1 = B.CSTART[base + cells_before(B, J, c0 + (uint32_t)zb1 + 1u)];
+  }
+  return r;
+}
+
 __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const int* __restrict__ tile_job,
                                                        const int64_t* __restrict__ tile_first) {
   extern __shared__ uint32_t lds[];
   const int kmax = B.kmax;
   uint32_t* kid = lds;
-  uint32_t* kslot = lds + kmax * kNlistBlock;
-  const int job = tile_job[blockIdx.x >> 2];
+  const int job = uniform_int(tile_job[blockIdx.x >> 2]);
   const JobDev& J = B.jobs[job];
-  const int64_t i = tile_first[blockIdx.x >> 2] + (blockIdx.x & 3) * kNlistBlock + threadIdx.x;
+  const int64_t i = uniform_i64(tile_first[blockIdx.x >> 2]) + (blockIdx.x & 3) * kNlistBlock + threadIdx.x;
   if (i >= J.off + J.n) return;
   const int lane = threadIdx.x;
-  const int64_t C = B.C;
   const int xs = J.xcur ^ 1, ss = J.scur ^ 1;  // the sorted copies written by k_scatter
   const double* __restrict__ X = B.X[xs];
   const uint32_t* __restrict__ ID = B.ID[ss];
-  const double xi = X[i], yi = X[C + i], zi = X[2 * C + i];
+  const double xi = X[3 * i], yi = X[3 * i + 1], zi = X[3 * i + 2];
   const int cx = cell_coord(J, 0, xi), cy = cell_coord(J, 1, yi), cz = cell_coord(J, 2, zi);
-  int sx[3], sy[3];
-  const int nx = stencil(J, 0, cx, sx), ny = stencil(J, 1, cy, sy);
   // z runs: [za0, zb0] and possibly a wrapped [za1, zb1]
   const int ncz = J.nc[2];
-  int za[2], zb[2], nrun;
+  int za0, zb0, za1 = 0, zb1 = -1;
   if (J.periodic[2] && ncz >= 3) {
     if (cz == 0) {
-      za[0] = 0, zb[0] = 1, za[1] = ncz - 1, zb[1] = ncz - 1, nrun = 2;
+      za0 = 0, zb0 = 1, za1 = ncz - 1, zb1 = ncz - 1;
     } else if (cz == ncz - 1) {
-      za[0] = 0, zb[0] = 0, za[1] = cz - 1, zb[1] = cz, nrun = 2;
+      za0 = 0, zb0 = 0, za1 = cz - 1, zb1 = cz;
     } else {
-      za[0] = cz - 1, zb[0] = cz + 1, nrun = 1;
+      za0 = cz - 1, zb0 = cz + 1;
     }
   } else if (J.periodic[2]) {
-    za[0] = 0, zb[0] = ncz - 1, nrun = 1;
+    za0 = 0, zb0 = ncz - 1;
   } else {
-    za[0] = cz > 0 ? cz - 1 : 0;
-    zb[0] = cz + 1 < ncz ? cz + 1 : ncz - 1;
-    nrun = 1;
+    za0 = cz > 0 ? cz - 1 : 0;
+    zb0 = cz + 1 < ncz ? cz + 1 : ncz - 1;
   }
-  const bool anyper = J.periodic[0] | J.periodic[1] | J.periodic[2];
   const int64_t base = J.off;
+  const bool anyper = J.periodic[0] | J.periodic[1] | J.periodic[2];
   int cnt = 0;
-  for (int a = 0; a < nx; ++a)
-    for (int bb = 0; bb < ny; ++bb)
-      for (int q = 0; q < nrun; ++q) {
-        const uint32_t r0 = raster_of(J, sx[a], sy[bb], za[q]);
-        const uint32_t r1 = raster_of(J, sx[a], sy[bb], zb[q]) + 1u;
-        const int64_t beg = base + B.CSTART[base + cells_before(B, J, r0)];
-        const int64_t end = base + B.CSTART[base + cells_before(B, J, r1)];
-        for (int64_t j = beg; j < end; ++j) {
-          if (j == i) continue;
-          double dx = xi - X[j], dy = yi - X[C + j], dz = zi - X[2 * C + j];
-          if (anyper) min_image(J, dx, dy, dz);
-          if (dx * dx + dy * dy + dz * dz >= J.rlist2) continue;
-          const uint32_t qid = ID[j];
-          if (cnt < kmax) {
-            int k = cnt;
-            while (k > 0 && kid[(k - 1) * kNlistBlock + lane] > qid) {
-              kid[k * kNlistBlock + lane] = kid[(k - 1) * kNlistBlock + lane];
-              kslot[k * kNlistBlock + lane] = kslot[(k - 1) * kNlistBlock + lane];
-              --k;
-            }
-            kid[k * kNlistBlock + lane] = qid;
-            kslot[k * kNlistBlock + lane] = (uint32_t)j;
-          }
-          ++cnt;
-        }
+  auto consider = [&](int64_t j, double ax, double ay, double az) {
+    if (j == i) return;
+    double dx = xi - ax, dy = yi - ay, dz = zi - az;
+    if (anyper) min_image(J, dx, dy, dz);
+    if (dx * dx + dy * dy + dz * dz >= J.rlist2) return;
+    const uint32_t qid = ID[j];
+    if (cnt < kmax) {
+      int k = cnt;
+      while (k > 0 && kid[(k - 1) * kNlistBlock + lane] > qid) {
+        kid[k * kNlistBlock + lane] = kid[(k - 1) * kNlistBlock + lane];
+        --k;
       }
+      kid[k * kNlistBlock + lane] = qid;
+    }
+    ++cnt;
+  };
+  auto scan = [&](uint32_t b, uint32_t e) {
+    int64_t j = base + b;
+    const int64_t end = base + e;
+    for (; j + 2 <= end; j += 2) {
+      const double ax0 = X[3 * j], ay0 = X[3 * j + 1], az0 = X[3 * j + 2];
+      const double ax1 = X[3 * j + 3], ay1 = X[3 * j + 4], az1 = X[3 * j + 5];
+      consider(j, ax0, ay0, az0);
+      consider(j + 1, ax1, ay1, az1);
+    }
+    if (j < end) consider(j, X[3 * j], X[3 * j + 1], X[3 * j + 2]);
+  };
+  // the next column's lookups are in flight while this column is scanned
+  ColumnRange cur = column_range(B, J, cx, cy, 0, za0, zb0, za1, zb1);
+  for (int col = 0; col < 9; ++col) {
+    ColumnRange nxt{0u, 0u, 0u, 0u};
+    if (col + 1 < 9) nxt = column_range(B, J, cx, cy, col + 1, za0, zb0, za1, zb1);
+    scan(cur.b0, cur.e0);
+    scan(cur.b1, cur.e1);
+    cur = nxt;
+  }
+  const int64_t C = B.C;
   const int stored = cnt < kmax ? cnt : kmax;
-  for (int k = 0; k < stored; ++k) B.NL[(int64_t)k * C + i] = kslot[k * kNlistBlock + lane];
+  // particle indices back to slots through the inverse permutation of the sort
+  for (int k = 0; k < stored; ++k) B.NL[(int64_t)k * C + i] = (uint32_t)base + B.INV[base + kid[k * kNlistBlock + lane]];
   B.NCNT[i] = (uint32_t)stored;
   atomicMax(&B.book[job].nl_max, cnt);
   atomicAdd(&B.book[job].nl_sum, (unsigned long long)stored);
