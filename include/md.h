@@ -187,6 +187,18 @@ int md_get_state(md_ctx* ctx, double* x, double* p, double* fcomb, int64_t* step
 /* Counters and event-timed GPU work of this context (see md_stats). */
 int md_get_stats(md_ctx* ctx, md_stats* stats);
 
+/* Autotune the neighbour-list skin on the live system.  For each candidate
+ * (skins[0..nskins), or a built-in set {0.2, 0.3, 0.4, 0.5, 0.6, 0.8} sigma
+ * when skins is NULL) the lists are rebuilt with that skin and the system is
+ * advanced trial_steps steps while the wall time per step is measured; the
+ * fastest skin stays in effect.  The system really advances
+ * nskins * trial_steps steps: because results do not depend on the skin, the
+ * trajectory is the one md_step would have produced.  best_skin and
+ * best_us_per_step may be NULL.  Candidates whose cell grid does not fit the
+ * context's memory are skipped. */
+int md_tune(md_ctx* ctx, int trial_steps, const double* skins, int nskins, double* best_skin,
+            double* best_us_per_step);
+
 /* Release every resource of the context. */
 void md_destroy(md_ctx* ctx);
 

@@ -17,6 +17,7 @@ namespace mdk {
 
 constexpr int kTile = 256;          // particles per workgroup in per-particle kernels
 constexpr int kNlistBlock = 64;     // one wavefront per workgroup in the list build
+constexpr int kNlistPerTile = kTile / kNlistBlock;
 
 enum : int { kSurfNone = 0, kSurfPlane = 1, kSurfSphere = 2, kSurfEllipsoid = 3, kSurfTorus = 4,
              kSurfCylinder = 5, kSurfHeight = 6 };

@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -186,6 +187,8 @@ struct HostJob {
   int newton_max = 0, nl_max = 0, err_id = -1;
   double A_now = 0.0;
   double rate_prev = 0.0;  // displacement per step while the previous list was in use
+  double ext_lo[3] = {0, 0, 0}, ext_len[3] = {0, 0, 0};  // region the cell grid covers
+  bool have_ext = false;
   double ndof = 0.0;
 };
 
@@ -241,13 +244,17 @@ int make_grid(HostJob& h, const double* x) {
       } else if (have[k] && !free_particles) {
         a = lo[k] - rlist;
         b = hi[k] + rlist;
+      } else if (h.have_ext || x == nullptr) {
+        // re-planning an existing job (or sizing without particles): keep the region
+        a = h.ext_lo[k];
+        b = h.ext_lo[k] + h.ext_len[k];
       } else {
         a = b = h.n > 0 ? x[k] : 0.0;
         for (int64_t i = 1; i < h.n; ++i) a = std::min(a, x[3 * i + k]), b = std::max(b, x[3 * i + k]);
         a -= rlist;
         b += rlist;
       }
-      const double L = b - a;
+      const double L = std::max(b - a, rlist);
       int nc = (int)std::floor(L / rlist);
       nc = std::max(1, std::min(nc, 1 << 20));
       d.nc[k] = nc;
@@ -256,6 +263,8 @@ int make_grid(HostJob& h, const double* x) {
       d.box_len[k] = L;
       d.inv_box_len[k] = 1.0 / L;
       d.periodic[k] = 0;
+      h.ext_lo[k] = a;
+      h.ext_len[k] = L;
     }
     total *= d.nc[k];
   }
@@ -272,6 +281,7 @@ int make_grid(HostJob& h, const double* x) {
     }
   }
   h.bm_words = total / 32 + 1;  // one spare word: the end of the last z-run is addressable
+  h.have_ext = true;
   return MD_OK;
 }
 
@@ -631,6 +641,33 @@ struct Engine {
     step_tiles_valid = false;
   }
 
+  // Change a job's skin: new list radius and cell grid; the list is rebuilt
+  // before the next step.
+  int set_skin(int j, double skin) {
+    HostJob& h = jobs[j];
+    HostJob trial = h;
+    trial.prm.skin = skin;
+    fill_constants(trial);
+    MDCHK(make_grid(trial, nullptr));
+    if (trial.bm_words > h.bm_words) {
+      words.release(h.bm_off, h.bm_words);
+      const int64_t off = words.alloc(trial.bm_words, 1);
+      if (off < 0) {
+        const int64_t back = words.alloc(h.bm_words, 1);  // the freed segment is still there
+        h.bm_off = back;
+        return MD_ENOMEM;
+      }
+      trial.bm_off = off;
+    } else {
+      trial.bm_words = h.bm_words;  // keep the larger segment
+    }
+    trial.dev.bm_off = trial.bm_off;
+    trial.built = false;
+    trial.rate_prev = 0.0;
+    h = trial;
+    return MD_OK;
+  }
+
   // ------------------------------------------------------------------ rebuild
   int grow_kmax(int need) {
     int nk = kmax;
@@ -715,7 +752,7 @@ struct Engine {
     for (int attempt = 0; attempt < 3; ++attempt) {
       const size_t lds = (size_t)kmax * kNlistBlock * sizeof(uint32_t);
       if (lds > 160 * 1024) return MD_ENOMEM;
-      hipLaunchKernelGGL(k_nlist, dim3(4 * ntiles), dim3(kNlistBlock), lds, stream, B, aux_tiles_job,
+      hipLaunchKernelGGL(k_nlist, dim3(kNlistPerTile * ntiles), dim3(kNlistBlock), lds, stream, B, aux_tiles_job,
                          aux_tiles_first);
       HIPCHK(hipGetLastError());
       HIPCHK(hipEventRecord(ev[3], stream));
@@ -1105,6 +1142,13 @@ int md_set_particles(md_ctx* ctx, int64_t n, const double* x, const double* p, c
   if (n > 0 && (!x || !p)) return MD_EINVAL;
   int64_t nslots = 0, nwords = 0;
   MDCHK(plan_job(ctx->prm, ctx->surf_kind, ctx->surf, n, x, &nslots, &nwords));
+  {
+    // room for the finest grid md_tune may choose (skin 0.2)
+    md_params fine = ctx->prm;
+    fine.skin = 0.2;
+    int64_t s2 = 0, w2 = 0;
+    if (plan_job(fine, ctx->surf_kind, ctx->surf, n, x, &s2, &w2) == MD_OK) nwords = std::max(nwords, w2);
+  }
   Engine* e = ctx->eng;
   if (e && ctx->job >= 0) e->drop(ctx->job);
   ctx->job = -1;
@@ -1157,6 +1201,39 @@ int md_get_state(md_ctx* ctx, double* x, double* p, double* fcomb, int64_t* step
   Engine* e = ctx->eng;
   if (step) *step = e->jobs[ctx->job].step;
   return e->finish(ctx->job, x, p, fcomb, diag);
+}
+
+int md_tune(md_ctx* ctx, int trial_steps, const double* skins, int nskins, double* best_skin,
+            double* best_us_per_step) {
+  static const double kDefaultSkins[] = {0.2, 0.3, 0.4, 0.5, 0.6, 0.8};
+  if (!ctx || trial_steps <= 0 || nskins < 0 || (nskins > 0 && !skins)) return MD_EINVAL;
+  if (!ctx->have_particles) return MD_ESTATE;
+  if (!skins || nskins == 0) {
+    skins = kDefaultSkins;
+    nskins = (int)(sizeof(kDefaultSkins) / sizeof(kDefaultSkins[0]));
+  }
+  for (int q = 0; q < nskins; ++q)
+    if (!(skins[q] > 0.0)) return MD_EINVAL;
+  Engine* e = ctx->eng;
+  const int j = ctx->job;
+  double best = -1.0, best_us = 1e300;
+  for (int q = 0; q < nskins; ++q) {
+    if (e->set_skin(j, skins[q]) != MD_OK) continue;
+    const auto t0 = std::chrono::steady_clock::now();
+    MDCHK(md_step(ctx, trial_steps));
+    const double us =
+        std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count() / trial_steps;
+    if (us < best_us) {
+      best_us = us;
+      best = skins[q];
+    }
+  }
+  if (best < 0.0) return MD_ENOMEM;
+  MDCHK(e->set_skin(j, best));
+  ctx->prm.skin = best;
+  if (best_skin) *best_skin = best;
+  if (best_us_per_step) *best_us_per_step = best_us;
+  return MD_OK;
 }
 
 int md_get_stats(md_ctx* ctx, md_stats* stats) {

@@ -474,9 +474,10 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const int* __r
   extern __shared__ uint32_t lds[];
   const int kmax = B.kmax;
   uint32_t* kid = lds;
-  const int job = uniform_int(tile_job[blockIdx.x >> 2]);
+  const int tile = (int)blockIdx.x / kNlistPerTile;
+  const int job = uniform_int(tile_job[tile]);
   const JobDev& J = B.jobs[job];
-  const int64_t i = uniform_i64(tile_first[blockIdx.x >> 2]) + (blockIdx.x & 3) * kNlistBlock + threadIdx.x;
+  const int64_t i = uniform_i64(tile_first[tile]) + ((int)blockIdx.x % kNlistPerTile) * kNlistBlock + threadIdx.x;
   if (i >= J.off + J.n) return;
   const int lane = threadIdx.x;
   const int xs = J.xcur ^ 1, ss = J.scur ^ 1;  // the sorted copies written by k_scatter

@@ -23,7 +23,7 @@ MD_OK, MD_EINVAL, MD_ESTATE, MD_EOFFSURF, MD_ENEWTON, MD_ENAN, MD_ENOMEM, MD_EAG
 SYMBOLS = ["md_create", "md_set_surface", "md_set_particles", "md_step", "md_get_state", "md_destroy",
            "md_strerror", "md_job_footprint", "md_pool_create", "md_pool_admit", "md_pool_run", "md_pool_poll",
            "md_pool_fetch", "md_pool_release", "md_pool_usage", "md_pool_destroy", "md_get_stats",
-           "md_pool_get_stats"]
+           "md_pool_get_stats", "md_tune"]
 
 
 class MDError(RuntimeError):
@@ -145,12 +145,13 @@ def lib():
         L.md_pool_release.argtypes = [vp, C.c_int]
         L.md_pool_usage.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int64), C.POINTER(C.c_size_t)]
         L.md_get_stats.argtypes = [vp, C.POINTER(_Stats)]
+        L.md_tune.argtypes = [vp, C.c_int, dp, C.c_int, dp, dp]
         L.md_pool_get_stats.argtypes = [vp, C.POINTER(_Stats)]
         L.md_pool_destroy.argtypes = [vp]
         L.md_pool_destroy.restype = None
         for name in ("md_create", "md_set_surface", "md_set_particles", "md_step", "md_get_state",
                      "md_pool_create", "md_pool_admit", "md_pool_run", "md_pool_poll", "md_pool_fetch",
-                     "md_pool_release", "md_pool_usage", "md_get_stats", "md_pool_get_stats"):
+                     "md_pool_release", "md_pool_usage", "md_get_stats", "md_pool_get_stats", "md_tune"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -228,6 +229,15 @@ class System:
         st = _Stats()
         _check(lib().md_get_stats(self._h, C.byref(st)), "md_get_stats")
         return st.to_dict()
+
+    def tune(self, trial_steps: int, skins=None):
+        """Autotune the list skin on the live system (advances len(skins) * trial_steps steps)."""
+        arr = None if skins is None else np.ascontiguousarray(skins, dtype=np.float64)
+        best = C.c_double(0.0)
+        us = C.c_double(0.0)
+        _check(lib().md_tune(self._h, int(trial_steps), _dp(arr), 0 if arr is None else len(arr), C.byref(best),
+                             C.byref(us)), "md_tune")
+        return best.value, us.value
 
     def close(self):
         if self._h:

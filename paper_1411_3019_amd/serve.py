@@ -52,6 +52,9 @@ def serve(jobs, budget_bytes: int, max_jobs: int, chunk: int = 32, realtime: boo
     """Run `jobs` through one pool; returns (jobs, pool stats).  With
     realtime=False every job counts as arrived at t = 0 (closed loop)."""
     make = pool_factory or (lambda: md.Pool(budget_bytes, max_jobs))
+    if not realtime:
+        for j in jobs:
+            j.arrival = 0.0  # closed loop: every job is waiting at t = 0
     pool = make()
     pending = collections.deque(sorted(jobs, key=lambda j: j.arrival))
     waiting = collections.deque()
@@ -94,6 +97,9 @@ def serve(jobs, budget_bytes: int, max_jobs: int, chunk: int = 32, realtime: boo
 def run_plain(jobs, realtime: bool = True, keep_results: bool = False, clock=time.perf_counter,
               sleep=time.sleep):
     """One job at a time, per-step launches without graphs."""
+    if not realtime:
+        for j in jobs:
+            j.arrival = 0.0
     prev = os.environ.get("MD_NO_GRAPH")
     os.environ["MD_NO_GRAPH"] = "1"
     t0 = clock()

@@ -205,3 +205,23 @@ def test_msd_statistics_torus():
     g.close()
     report("torus20k MSD", worst_rel=worst)
     assert worst < 0.02
+
+
+def test_autotune_keeps_trajectory():
+    """md_tune advances the live system while timing candidate skins; the
+    trajectory is the same bits as plain stepping (results do not depend on
+    the skin)."""
+    s = gen.torus(6000, 40.0, 13.3, 31)
+    kw = dict(dt=0.002, rc=2.5, seed=12, force_fp64=0)
+    print("[gpu] autotune torus 6000", flush=True)
+    g = gpu_system(s, **kw)
+    best, us = g.tune(40, skins=[0.25, 0.45, 0.7])
+    a = g.get_state()
+    g.close()
+    assert best in (0.25, 0.45, 0.7) and us > 0.0
+    g = gpu_system(s, **kw)
+    g.step(120)
+    b = g.get_state()
+    g.close()
+    assert a["step"] == b["step"] == 120
+    assert np.array_equal(a["x"], b["x"]) and np.array_equal(a["p"], b["p"])
