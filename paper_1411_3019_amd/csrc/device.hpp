@@ -23,7 +23,6 @@ enum : int { kSurfNone = 0, kSurfPlane = 1, kSurfSphere = 2, kSurfEllipsoid = 3,
              kSurfCylinder = 5, kSurfHeight = 6 };
 enum : int { kPairNone = 0, kPairLJ = 1, kPairLJSmooth = 2 };
 enum : int { kModeSteady = 0, kModeStart = 1, kModeStartGiven = 2 };
-enum : int { kFlagStale = 1, kFlagError = 2 };
 enum : int { kErrNewton = 1, kErrNaN = 2 };
 
 // Per-job constants, written by the host before each launch set.
@@ -48,18 +47,16 @@ struct JobDev {
   int64_t step0, remaining;
 };
 
-// Per-job bookkeeping written by the device.
+// Per-job bookkeeping written by the device.  Touched by atomics only on
+// rare events (a list going stale, an error, a new Newton maximum), so that
+// workgroups never contend for these words in the common case.
+constexpr long long kNever = 0x7FFFFFFFFFFFFFFFLL;
 struct JobBook {
-  double acc[2];                    // accumulated max displacement, by step parity
-  unsigned long long dmax[3];       // per-step max displacement (bit pattern of a double >= 0)
-  int flags;                        // kFlagStale | kFlagError
+  long long stop_at;                // first step that must not run: stale list or error (kNever if none)
   int err_code;
   int err_id;
   int newton_max;
-  int nl_max;
   int pad1;
-  long long stale_step;
-  unsigned long long nl_sum;        // neighbours summed over the job's particles at the last build
 };
 
 // Device buffers, passed by value to every kernel.
@@ -84,6 +81,8 @@ struct DevBufs {
   uint32_t* CID;       // compact cell index per slot
   uint32_t* RANK;      // rank within the cell per slot
   uint32_t* INV;       // slot of each particle index after the last sort, by job offset + index
+  double* TACC;        // per tile (slot / kTile): accumulated max displacement since the last build
+  uint32_t* NLSTAT;    // per list-build workgroup: (max count, sum of counts)
   JobDev* jobs;
   JobBook* book;
   int64_t C;           // slot capacity (SoA stride)

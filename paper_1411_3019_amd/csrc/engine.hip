@@ -185,6 +185,7 @@ struct HostJob {
   bool built = false, done = false, reported = false;
   int status = MD_OK;
   int newton_max = 0, nl_max = 0, err_id = -1;
+  double nl_sum = 0.0;
   double A_now = 0.0;
   double rate_prev = 0.0;  // displacement per step while the previous list was in use
   double ext_lo[3] = {0, 0, 0}, ext_len[3] = {0, 0, 0};  // region the cell grid covers
@@ -321,6 +322,8 @@ struct Engine {
   int64_t range_cap = 0;
   // pinned host staging
   JobBook* book_h = nullptr;
+  std::vector<double> tacc_h;      // host copy of the per-tile displacement accumulators
+  std::vector<uint32_t> nlstat_h;  // host copy of the list-build statistics
   char* stage = nullptr;
   size_t stage_cap = 0;
   // step graphs
@@ -346,7 +349,7 @@ struct Engine {
       if (e) (void)hipEventDestroy(e), e = nullptr;
     void* ptrs[] = {B.X[0], B.X[1], B.P[0], B.P[1], B.ID[0], B.ID[1], B.FLG[0], B.FLG[1], B.MASS[0], B.MASS[1],
                     B.FC, B.OX, B.OP, B.OF, B.OD, B.NL, B.NCNT, B.BM, B.WOFF, B.CCNT, B.CSTART, B.RASTER,
-                    B.CID, B.RANK, B.INV, B.jobs, B.book, step_tiles_job, step_tiles_first, step_counts, aux_tiles_job,
+                    B.CID, B.RANK, B.INV, B.TACC, B.NLSTAT, B.jobs, B.book, step_tiles_job, step_tiles_first, step_counts, aux_tiles_job,
                     aux_tiles_first, chunks_d, chunk_sums, ranges_d};
     for (void* p : ptrs)
       if (p) (void)hipFree(p);
@@ -421,11 +424,20 @@ struct Engine {
     MDCHK(dalloc(&B.CID, C));
     MDCHK(dalloc(&B.RANK, C));
     MDCHK(dalloc(&B.INV, C));
+    MDCHK(dalloc(&B.TACC, C / kTile + 1));
+    HIPCHK(hipMemsetAsync(B.TACC, 0, sizeof(double) * (C / kTile + 1), stream));
     MDCHK(dalloc(&B.jobs, max_jobs));
     MDCHK(dalloc(&B.book, max_jobs));
-    HIPCHK(hipMemsetAsync(B.book, 0, sizeof(JobBook) * max_jobs, stream));
+    {
+      std::vector<JobBook> fresh(max_jobs);
+      for (auto& k : fresh) k = JobBook{kNever, 0, 0, 0, 0};
+      HIPCHK(hipMemcpy(B.book, fresh.data(), sizeof(JobBook) * max_jobs, hipMemcpyHostToDevice));
+    }
     HIPCHK(hipMemsetAsync(B.NCNT, 0, sizeof(uint32_t) * C, stream));
     tile_cap = C / kTile + max_jobs + 8;
+    MDCHK(dalloc(&B.NLSTAT, 2 * kNlistPerTile * tile_cap));
+    tacc_h.assign(C / kTile + 1, 0.0);
+    nlstat_h.assign(2 * kNlistPerTile * tile_cap, 0u);
     MDCHK(dalloc(&step_tiles_job, 2 * tile_cap));
     MDCHK(dalloc(&step_tiles_first, 2 * tile_cap));
     MDCHK(dalloc(&step_counts, 2));
@@ -435,7 +447,7 @@ struct Engine {
     chunk_cap = (C + max_jobs) / kScanChunk + BMW / kScanChunk + 4 * max_jobs + 16;
     MDCHK(dalloc(&chunks_d, chunk_cap));
     MDCHK(dalloc(&chunk_sums, chunk_cap));
-    range_cap = 2 * max_jobs + 4;
+    range_cap = 3 * max_jobs + 4;
     MDCHK(dalloc(&ranges_d, range_cap));
     HIPCHK(hipHostMalloc((void**)&book_h, sizeof(JobBook) * max_jobs, hipHostMallocDefault));
     for (auto& e : ev) HIPCHK(hipEventCreate(&e));
@@ -691,12 +703,14 @@ struct Engine {
     std::vector<int64_t> tf;
     std::vector<Chunk> cb, cc;
     std::vector<Range> rb, rcnt;
+    std::vector<Range> rtacc;
     for (int j : set) {
       HostJob& h = jobs[j];
       h.dev.remaining = 0;
       tiles_of(h, j, tj, tf);
       rb.push_back({h.bm_off, h.bm_words});
       rcnt.push_back({h.off, h.n + 1});
+      rtacc.push_back({2 * (h.off / kTile), 2 * ((h.n + kTile - 1) / kTile)});  // doubles as word pairs
       int first = (int)cb.size();
       for (int64_t s = 0; s < h.bm_words; s += kScanChunk)
         cb.push_back({h.bm_off + s, (int)std::min<int64_t>(kScanChunk, h.bm_words - s), first});
@@ -712,7 +726,7 @@ struct Engine {
       return MD_OK;
     }
     if ((int64_t)(cb.size() + cc.size()) > chunk_cap || (int64_t)tj.size() > tile_cap ||
-        (int64_t)(rb.size() + rcnt.size()) > range_cap)
+        (int64_t)(rb.size() + rcnt.size() + rtacc.size()) > range_cap)
       return MD_ENOMEM;
     MDCHK(upload_jobs());
     MDCHK(upload(aux_tiles_job, tj.data(), sizeof(int) * tj.size()));
@@ -723,6 +737,7 @@ struct Engine {
     MDCHK(upload(chunks_d, call.data(), sizeof(Chunk) * call.size()));
     std::vector<Range> rall(rb);
     rall.insert(rall.end(), rcnt.begin(), rcnt.end());
+    rall.insert(rall.end(), rtacc.begin(), rtacc.end());
     MDCHK(upload(ranges_d, rall.data(), sizeof(Range) * rall.size()));
     const int ntiles = (int)tj.size();
     HIPCHK(hipEventRecord(ev[2], stream));
@@ -731,9 +746,9 @@ struct Engine {
                        (int)rb.size());
     hipLaunchKernelGGL(k_zero_ranges, dim3(64, (unsigned)rcnt.size()), dim3(256), 0, stream, B.CCNT,
                        ranges_d + rb.size(), (int)rcnt.size());
-    for (int j : set) {
-      std::memset(&book_h[j], 0, sizeof(JobBook));
-    }
+    hipLaunchKernelGGL(k_zero_ranges, dim3(4, (unsigned)rtacc.size()), dim3(256), 0, stream, (uint32_t*)B.TACC,
+                       ranges_d + rb.size() + rcnt.size(), (int)rtacc.size());
+    for (int j : set) book_h[j] = JobBook{kNever, 0, 0, 0, 0};
     // reset bookkeeping of the rebuilt jobs (small copies, pinned source)
     for (int j : set) HIPCHK(hipMemcpyAsync(&B.book[j], &book_h[j], sizeof(JobBook), hipMemcpyHostToDevice, stream));
     hipLaunchKernelGGL(k_mark, dim3(ntiles), dim3(kTile), 0, stream, B, aux_tiles_job, aux_tiles_first);
@@ -756,18 +771,24 @@ struct Engine {
                          aux_tiles_first);
       HIPCHK(hipGetLastError());
       HIPCHK(hipEventRecord(ev[3], stream));
-      MDCHK(read_book());
+      const size_t nblk = (size_t)kNlistPerTile * ntiles;
+      HIPCHK(hipMemcpyAsync(nlstat_h.data(), B.NLSTAT, sizeof(uint32_t) * 2 * nblk, hipMemcpyDeviceToHost, stream));
+      HIPCHK(hipStreamSynchronize(stream));
       stats.rebuild_ms += elapsed_ms(ev[2], ev[3]);
       stats.builds += 1;
+      for (int j : set) {
+        jobs[j].nl_max = 0;
+        jobs[j].nl_sum = 0.0;
+      }
+      for (size_t b = 0; b < nblk; ++b) {
+        HostJob& h = jobs[tj[b / kNlistPerTile]];
+        h.nl_max = std::max<int>(h.nl_max, (int)nlstat_h[2 * b]);
+        h.nl_sum += (double)nlstat_h[2 * b + 1];
+      }
       int need = 0;
-      for (int j : set) need = std::max(need, book_h[j].nl_max);
+      for (int j : set) need = std::max(need, jobs[j].nl_max);
       if (need <= kmax) break;
       MDCHK(grow_kmax(need + need / 8 + 2));
-      for (int j : set) {
-        book_h[j].nl_sum = 0ull;
-        HIPCHK(hipMemcpyAsync(&B.book[j].nl_sum, &book_h[j].nl_sum, sizeof(unsigned long long),
-                              hipMemcpyHostToDevice, stream));
-      }
     }
     for (int j : set) {
       HostJob& h = jobs[j];
@@ -779,8 +800,7 @@ struct Engine {
       h.A_now = 0.0;
       h.last_build = h.step;
       h.rebuilds += 1;
-      h.nl_max = book_h[j].nl_max;
-      nl_sum_all += (double)book_h[j].nl_sum;
+      nl_sum_all += h.nl_sum;
       nl_n_all += (double)h.n;
     }
     if (nl_n_all > 0) stats.nl_mean = nl_sum_all / nl_n_all;
@@ -932,35 +952,29 @@ struct Engine {
     stats.step_kernel_ms += elapsed_ms(ev[0], ev[1]);
     stats.chunks += 1;
     stats.step_launches += (int64_t)kq * ((grid64 > 0) + (grid32 > 0));
+    HIPCHK(hipMemcpy(tacc_h.data(), B.TACC, sizeof(double) * tacc_h.size(), hipMemcpyDeviceToHost));
     int64_t adv = 0;
     for (int j = 0; j < max_jobs; ++j) {
       HostJob& h = jobs[j];
       if (!h.used || h.dev.remaining == 0) continue;
       const JobBook& K = book_h[j];
       int64_t done = h.dev.remaining;
-      if (K.flags & kFlagError) {
+      if (K.stop_at < h.step + done) done = std::max<int64_t>(0, K.stop_at - h.step);
+      h.newton_max = std::max(h.newton_max, K.newton_max);
+      if (K.err_code != 0) {
         h.status = K.err_code == kErrNewton ? MD_ENEWTON : MD_ENAN;
         h.err_id = K.err_id;
         h.done = true;
         step_tiles_valid = false;
         continue;
       }
-      if (K.flags & kFlagStale) {
-        done = K.stale_step - h.step;
-        h.built = false;
-      }
       h.step += done;
       if (done & 1) h.dev.xcur ^= 1;
       if (done > 0) h.dev.mode = kModeSteady;
-      h.newton_max = std::max(h.newton_max, K.newton_max);
-      const long long s = h.step;
-      h.A_now = K.acc[(s + 1) & 1] + [&] {
-        double v;
-        unsigned long long u = K.dmax[(s + 2) % 3];
-        std::memcpy(&v, &u, sizeof(v));
-        return v;
-      }();
-      if (h.A_now > h.dev.half_skin) h.built = false;
+      double a = 0.0;
+      for (int64_t t = h.off / kTile; t < (h.off + h.n + kTile - 1) / kTile; ++t) a = std::max(a, tacc_h[t]);
+      h.A_now = a;
+      if (K.stop_at != kNever || h.A_now > h.dev.half_skin) h.built = false;
       if (h.step >= h.target) {
         h.done = true;
         step_tiles_valid = false;

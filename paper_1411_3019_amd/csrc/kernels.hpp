@@ -20,18 +20,15 @@
 
 namespace mdk {
 
-// Maximum of a non-negative double over the workgroup, then atomically into
-// *dst (the bit patterns of non-negative doubles order like the values).
-__device__ __forceinline__ void block_max_to(double v, unsigned long long* dst, double* red) {
+// Maximum over the workgroup (result valid in thread 0).
+__device__ __forceinline__ double block_max(double v, double* red) {
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (lane == 0) red[wave] = v;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double m = red[0];
-    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = fmax(m, red[w]);
-    atomicMax(dst, (unsigned long long)__double_as_longlong(m));
-  }
+  double m = red[0];
+  for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = fmax(m, red[w]);
+  return m;
 }
 
 __device__ __forceinline__ int block_max_int(int v, int* red) {
@@ -45,9 +42,10 @@ __device__ __forceinline__ int block_max_int(int v, int* red) {
   return m;
 }
 
-__device__ __forceinline__ void record_error(JobBook& K, int code, uint32_t id) {
+// An error at step s stops the job from step s + 1 on.
+__device__ __forceinline__ void record_error(JobBook& K, int code, uint32_t id, long long s) {
   if (atomicCAS(&K.err_code, 0, code) == 0) K.err_id = (int)id;
-  atomicOr(&K.flags, (int)kFlagError);
+  atomicMin(&K.stop_at, s + 1);
 }
 
 // Random part of the combined force of Algorithm S1 for one particle:
@@ -112,29 +110,19 @@ __device__ __forceinline__ void step_body(const DevBufs& B, const int* __restric
   const int64_t first = uniform_i64(tile_first[b]);
   const JobDev& J = B.jobs[job];
   JobBook& K = B.book[job];
-  if (K.flags != 0 || t >= J.remaining) return;
+  if (t >= J.remaining) return;
   const long long s = J.step0 + t;
+  // a tile whose accumulated displacement passed skin/2 during step s-1 (or an
+  // error) set stop_at <= s: the lists are no longer valid for forces at x^s
+  if (s >= K.stop_at) return;
   const bool start = (J.mode != kModeSteady) && (t == 0);
-  // list validity: accumulated displacement since the last build, through step s-1
-  const double A = K.acc[(s + 1) & 1] + __longlong_as_double((long long)K.dmax[(s + 2) % 3]);
-  if (A > J.half_skin) {
-    if (threadIdx.x == 0) {
-      K.stale_step = s;
-      atomicOr(&K.flags, (int)kFlagStale);
-    }
-    return;
-  }
-  if (first == J.off && threadIdx.x == 0) {
-    K.acc[s & 1] = A;
-    K.dmax[(s + 1) % 3] = 0ull;
-  }
   const int xin = J.xcur ^ (t & 1);
   const double* __restrict__ X = B.X[xin];
   double* __restrict__ Xo = B.X[xin ^ 1];
   double* __restrict__ P = B.P[J.pcur];
   const int64_t C = B.C;
   const int64_t i = first + threadIdx.x;
-  double disp = 0.0;
+  double disp2 = 0.0;
   int iters = 0;
   if (i < J.off + J.n) {
     const double xi = X[3 * i], yi = X[3 * i + 1], zi = X[3 * i + 2];
@@ -174,7 +162,7 @@ __device__ __forceinline__ void step_body(const DevBufs& B, const int* __restric
     if (cons) {
       iters = rattle_position(J, m, xi, yi, zi, g0, nx, ny, nz, px, py, pz, x1, y1, z1);
       if (iters < 0) {
-        record_error(K, kErrNewton, id);
+        record_error(K, kErrNewton, id, s);
         iters = -iters;
       }
     } else {
@@ -190,15 +178,23 @@ __device__ __forceinline__ void step_body(const DevBufs& B, const int* __restric
     P[3 * i + 1] = py;
     P[3 * i + 2] = pz;
     const double dx = x1 - xi, dy = y1 - yi, dz = z1 - zi;
-    disp = sqrt(dx * dx + dy * dy + dz * dz);
-    if (!(disp <= 1e300) || !(fabs(px) + fabs(py) + fabs(pz) <= 1e300)) {
-      record_error(K, kErrNaN, id);
-      disp = 0.0;
+    disp2 = dx * dx + dy * dy + dz * dz;
+    if (!(disp2 <= 1e300) || !(fabs(px) + fabs(py) + fabs(pz) <= 1e300)) {
+      record_error(K, kErrNaN, id, s);
+      disp2 = 0.0;
     }
   }
-  block_max_to(disp, &K.dmax[s % 3], red);
+  // per-tile bound on the displacement since the last build: sum over steps of
+  // the tile's largest displacement; only this workgroup touches its tile
+  const double m2 = block_max(disp2, red);
   const int im = block_max_int(iters, redi);
-  if (threadIdx.x == 0 && im > 0) atomicMax(&K.newton_max, im);
+  if (threadIdx.x == 0) {
+    const int64_t tile = first / kTile;
+    const double a = B.TACC[tile] + sqrt(m2);
+    B.TACC[tile] = a;
+    if (a > J.half_skin) atomicMin(&K.stop_at, s + 1);
+    if (im > K.newton_max) atomicMax(&K.newton_max, im);
+  }
 }
 
 #ifndef MDK_STEP32_WAVES
@@ -478,76 +474,85 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const int* __r
   const int job = uniform_int(tile_job[tile]);
   const JobDev& J = B.jobs[job];
   const int64_t i = uniform_i64(tile_first[tile]) + ((int)blockIdx.x % kNlistPerTile) * kNlistBlock + threadIdx.x;
-  if (i >= J.off + J.n) return;
-  const int lane = threadIdx.x;
-  const int xs = J.xcur ^ 1, ss = J.scur ^ 1;  // the sorted copies written by k_scatter
-  const double* __restrict__ X = B.X[xs];
-  const uint32_t* __restrict__ ID = B.ID[ss];
-  const double xi = X[3 * i], yi = X[3 * i + 1], zi = X[3 * i + 2];
-  const int cx = cell_coord(J, 0, xi), cy = cell_coord(J, 1, yi), cz = cell_coord(J, 2, zi);
-  // z runs: [za0, zb0] and possibly a wrapped [za1, zb1]
-  const int ncz = J.nc[2];
-  int za0, zb0, za1 = 0, zb1 = -1;
-  if (J.periodic[2] && ncz >= 3) {
-    if (cz == 0) {
-      za0 = 0, zb0 = 1, za1 = ncz - 1, zb1 = ncz - 1;
-    } else if (cz == ncz - 1) {
-      za0 = 0, zb0 = 0, za1 = cz - 1, zb1 = cz;
-    } else {
-      za0 = cz - 1, zb0 = cz + 1;
-    }
-  } else if (J.periodic[2]) {
-    za0 = 0, zb0 = ncz - 1;
-  } else {
-    za0 = cz > 0 ? cz - 1 : 0;
-    zb0 = cz + 1 < ncz ? cz + 1 : ncz - 1;
-  }
-  const int64_t base = J.off;
-  const bool anyper = J.periodic[0] | J.periodic[1] | J.periodic[2];
-  int cnt = 0;
-  auto consider = [&](int64_t j, double ax, double ay, double az) {
-    if (j == i) return;
-    double dx = xi - ax, dy = yi - ay, dz = zi - az;
-    if (anyper) min_image(J, dx, dy, dz);
-    if (dx * dx + dy * dy + dz * dz >= J.rlist2) return;
-    const uint32_t qid = ID[j];
-    if (cnt < kmax) {
-      int k = cnt;
-      while (k > 0 && kid[(k - 1) * kNlistBlock + lane] > qid) {
-        kid[k * kNlistBlock + lane] = kid[(k - 1) * kNlistBlock + lane];
-        --k;
+  int cnt = 0, stored = 0;
+  if (i < J.off + J.n) {
+    const int lane = threadIdx.x;
+    const int xs = J.xcur ^ 1, ss = J.scur ^ 1;  // the sorted copies written by k_scatter
+    const double* __restrict__ X = B.X[xs];
+    const uint32_t* __restrict__ ID = B.ID[ss];
+    const double xi = X[3 * i], yi = X[3 * i + 1], zi = X[3 * i + 2];
+    const int cx = cell_coord(J, 0, xi), cy = cell_coord(J, 1, yi), cz = cell_coord(J, 2, zi);
+    // z runs: [za0, zb0] and possibly a wrapped [za1, zb1]
+    const int ncz = J.nc[2];
+    int za0, zb0, za1 = 0, zb1 = -1;
+    if (J.periodic[2] && ncz >= 3) {
+      if (cz == 0) {
+        za0 = 0, zb0 = 1, za1 = ncz - 1, zb1 = ncz - 1;
+      } else if (cz == ncz - 1) {
+        za0 = 0, zb0 = 0, za1 = cz - 1, zb1 = cz;
+      } else {
+        za0 = cz - 1, zb0 = cz + 1;
       }
-      kid[k * kNlistBlock + lane] = qid;
+    } else if (J.periodic[2]) {
+      za0 = 0, zb0 = ncz - 1;
+    } else {
+      za0 = cz > 0 ? cz - 1 : 0;
+      zb0 = cz + 1 < ncz ? cz + 1 : ncz - 1;
     }
-    ++cnt;
-  };
-  auto scan = [&](uint32_t b, uint32_t e) {
-    int64_t j = base + b;
-    const int64_t end = base + e;
-    for (; j + 2 <= end; j += 2) {
-      const double ax0 = X[3 * j], ay0 = X[3 * j + 1], az0 = X[3 * j + 2];
-      const double ax1 = X[3 * j + 3], ay1 = X[3 * j + 4], az1 = X[3 * j + 5];
-      consider(j, ax0, ay0, az0);
-      consider(j + 1, ax1, ay1, az1);
+    const int64_t base = J.off;
+    const bool anyper = J.periodic[0] | J.periodic[1] | J.periodic[2];
+    auto consider = [&](int64_t j, double ax, double ay, double az) {
+      if (j == i) return;
+      double dx = xi - ax, dy = yi - ay, dz = zi - az;
+      if (anyper) min_image(J, dx, dy, dz);
+      if (dx * dx + dy * dy + dz * dz >= J.rlist2) return;
+      const uint32_t qid = ID[j];
+      if (cnt < kmax) {
+        int k = cnt;
+        while (k > 0 && kid[(k - 1) * kNlistBlock + lane] > qid) {
+          kid[k * kNlistBlock + lane] = kid[(k - 1) * kNlistBlock + lane];
+          --k;
+        }
+        kid[k * kNlistBlock + lane] = qid;
+      }
+      ++cnt;
+    };
+    auto scan = [&](uint32_t b, uint32_t e) {
+      int64_t j = base + b;
+      const int64_t end = base + e;
+      for (; j + 2 <= end; j += 2) {
+        const double ax0 = X[3 * j], ay0 = X[3 * j + 1], az0 = X[3 * j + 2];
+        const double ax1 = X[3 * j + 3], ay1 = X[3 * j + 4], az1 = X[3 * j + 5];
+        consider(j, ax0, ay0, az0);
+        consider(j + 1, ax1, ay1, az1);
+      }
+      if (j < end) consider(j, X[3 * j], X[3 * j + 1], X[3 * j + 2]);
+    };
+    // the next column's lookups are in flight while this column is scanned
+    ColumnRange cur = column_range(B, J, cx, cy, 0, za0, zb0, za1, zb1);
+    for (int col = 0; col < 9; ++col) {
+      ColumnRange nxt{0u, 0u, 0u, 0u};
+      if (col + 1 < 9) nxt = column_range(B, J, cx, cy, col + 1, za0, zb0, za1, zb1);
+      scan(cur.b0, cur.e0);
+      scan(cur.b1, cur.e1);
+      cur = nxt;
     }
-    if (j < end) consider(j, X[3 * j], X[3 * j + 1], X[3 * j + 2]);
-  };
-  // the next column's lookups are in flight while this column is scanned
-  ColumnRange cur = column_range(B, J, cx, cy, 0, za0, zb0, za1, zb1);
-  for (int col = 0; col < 9; ++col) {
-    ColumnRange nxt{0u, 0u, 0u, 0u};
-    if (col + 1 < 9) nxt = column_range(B, J, cx, cy, col + 1, za0, zb0, za1, zb1);
-    scan(cur.b0, cur.e0);
-    scan(cur.b1, cur.e1);
-    cur = nxt;
+    const int64_t C = B.C;
+    stored = cnt < kmax ? cnt : kmax;
+    // particle indices back to slots through the inverse permutation of the sort
+    for (int k = 0; k < stored; ++k) B.NL[(int64_t)k * C + i] = (uint32_t)base + B.INV[base + kid[k * kNlistBlock + lane]];
+    B.NCNT[i] = (uint32_t)stored;
   }
-  const int64_t C = B.C;
-  const int stored = cnt < kmax ? cnt : kmax;
-  // particle indices back to slots through the inverse permutation of the sort
-  for (int k = 0; k < stored; ++k) B.NL[(int64_t)k * C + i] = (uint32_t)base + B.INV[base + kid[k * kNlistBlock + lane]];
-  B.NCNT[i] = (uint32_t)stored;
-  atomicMax(&B.book[job].nl_max, cnt);
-  atomicAdd(&B.book[job].nl_sum, (unsigned long long)stored);
+  // list statistics of this workgroup, no atomics
+  uint32_t mx = (uint32_t)cnt, sm = (uint32_t)stored;
+  for (int o = 32; o > 0; o >>= 1) {
+    mx = max(mx, (uint32_t)__shfl_xor((int)mx, o, 64));
+    sm += (uint32_t)__shfl_xor((int)sm, o, 64);
+  }
+  if (threadIdx.x == 0) {
+    B.NLSTAT[2 * blockIdx.x] = mx;
+    B.NLSTAT[2 * blockIdx.x + 1] = sm;
+  }
 }
 
 // ---------------------------------------------------------------------------
