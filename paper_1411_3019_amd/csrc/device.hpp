@@ -81,6 +81,7 @@ struct DevBufs {
   uint32_t* CID;       // compact cell index per slot
   uint32_t* RANK;      // rank within the cell per slot
   uint32_t* INV;       // slot of each particle index after the last sort, by job offset + index
+  uint32_t* SRC;       // old slot (job-relative) of each new slot during a sort
   double* TACC;        // per tile (slot / kTile): accumulated max displacement since the last build
   uint32_t* NLSTAT;    // per list-build workgroup: (max count, sum of counts)
   JobDev* jobs;
@@ -315,9 +316,14 @@ __device__ __forceinline__ real pair_coef(const JobDev& J, double r2, real eps24
 // Pair forces on slot i from its neighbour list, summed in list order (the
 // list is sorted by particle index).  FP32 variant: separations and the
 // cut-off test in FP64, the force in FP32 with FP32 accumulation.  The loop
-// issues the gathers of four neighbours before using them; the additions
+// issues the gathers of kForceBatch neighbours before using them; the additions
 // still happen one neighbour at a time in list order.  Specialised on the
 // potential's form and on periodicity so the loop carries no dead work.
+#ifndef MDK_FORCE_BATCH
+#define MDK_FORCE_BATCH 4
+#endif
+constexpr int kForceBatch = MDK_FORCE_BATCH;  // neighbour gathers in flight per force-loop iteration
+
 template <bool kF64, bool kSmooth, bool kPer>
 __device__ __forceinline__ void pair_forces_impl(const JobDev& J, const DevBufs& B, const double* __restrict__ X,
                                                  int64_t i, double xi, double yi, double zi, double& Fx,
@@ -331,19 +337,19 @@ __device__ __forceinline__ void pair_forces_impl(const JobDev& J, const DevBufs&
   const real sig2 = (real)J.sig2;
   const real dphic = (real)J.dphic;
   int k = 0;
-  for (; k + 4 <= cnt; k += 4) {
-    int64_t j[4];
-    double ax[4], ay[4], az[4];
+  for (; k + kForceBatch <= cnt; k += kForceBatch) {
+    int64_t j[kForceBatch];
+    double ax[kForceBatch], ay[kForceBatch], az[kForceBatch];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) j[u] = nl[(int64_t)(k + u) * C];
+    for (int u = 0; u < kForceBatch; ++u) j[u] = nl[(int64_t)(k + u) * C];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < kForceBatch; ++u) {
       ax[u] = X[3 * j[u]];
       ay[u] = X[3 * j[u] + 1];
       az[u] = X[3 * j[u] + 2];
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < kForceBatch; ++u) {
       double dx = xi - ax[u], dy = yi - ay[u], dz = zi - az[u];
       if (kPer) min_image(J, dx, dy, dz);
       const double r2 = dx * dx + dy * dy + dz * dz;

@@ -391,14 +391,28 @@ __global__ void __launch_bounds__(kTile) k_count(DevBufs B, const int* __restric
   if (valid) B.RANK[i] = base + (uint32_t)(lane - start);
 }
 
-__global__ void __launch_bounds__(kTile) k_scatter(DevBufs B, const int* __restrict__ tile_job,
-                                                   const int64_t* __restrict__ tile_first) {
+// Destination of every slot in the new (cell) order: SRC[new slot] = old slot,
+// and the inverse permutation by particle index.
+__global__ void __launch_bounds__(kTile) k_perm(DevBufs B, const int* __restrict__ tile_job,
+                                                const int64_t* __restrict__ tile_first) {
   const int job = uniform_int(tile_job[blockIdx.x]);
   const JobDev& J = B.jobs[job];
   const int64_t i = uniform_i64(tile_first[blockIdx.x]) + threadIdx.x;
   if (i >= J.off + J.n) return;
-  const int64_t C = B.C;
   const int64_t d = J.off + B.CSTART[J.off + B.CID[i]] + B.RANK[i];
+  B.SRC[d] = (uint32_t)(i - J.off);
+  B.INV[J.off + B.ID[J.scur][i]] = (uint32_t)(d - J.off);
+}
+
+// Gather the state into the new order: consecutive threads write consecutive
+// slots (whole cache lines), the reads follow the permutation.
+__global__ void __launch_bounds__(kTile) k_gather(DevBufs B, const int* __restrict__ tile_job,
+                                                  const int64_t* __restrict__ tile_first) {
+  const int job = uniform_int(tile_job[blockIdx.x]);
+  const JobDev& J = B.jobs[job];
+  const int64_t d = uniform_i64(tile_first[blockIdx.x]) + threadIdx.x;
+  if (d >= J.off + J.n) return;
+  const int64_t i = J.off + B.SRC[d];
   const double* Xs = B.X[J.xcur];
   double* Xd = B.X[J.xcur ^ 1];
   const double* Ps = B.P[J.pcur];
@@ -408,9 +422,7 @@ __global__ void __launch_bounds__(kTile) k_scatter(DevBufs B, const int* __restr
     Xd[3 * d + k] = Xs[3 * i + k];
     Pd[3 * d + k] = Ps[3 * i + k];
   }
-  const uint32_t id = B.ID[J.scur][i];
-  B.ID[J.scur ^ 1][d] = id;
-  B.INV[J.off + id] = (uint32_t)(d - J.off);
+  B.ID[J.scur ^ 1][d] = B.ID[J.scur][i];
   B.FLG[J.scur ^ 1][d] = B.FLG[J.scur][i];
   if (!J.uniform_mass) B.MASS[J.scur ^ 1][d] = B.MASS[J.scur][i];
 }
@@ -421,14 +433,6 @@ __device__ __forceinline__ uint32_t cells_before(const DevBufs& B, const JobDev&
   return B.WOFF[w] + __popc(B.BM[w] & ((1u << (r & 31)) - 1u));
 }
 
-// One wavefront per workgroup; each lane builds the list of one slot of the
-// freshly sorted order.  Slots are in raster cell order (x-major, z fastest),
-// so for each of the 9 (dx, dy) columns of the 27-cell stencil the cells
-// z-1..z+1 are one contiguous slot range (two when z wraps), found from two
-// popcount lookups.  All lookups are issued first and the ranges parked in
-// LDS; candidates are then read four at a time.  Accepted neighbours are kept
-// sorted by particle index in LDS ([kmax][64], lane-minor so lanes hit
-// distinct banks).
 // Cell coordinate c + d along dimension k for a stencil offset d in {-1,0,1}:
 // wrapped when periodic (offsets that would repeat a cell when the periodic
 // count is below 3 are dropped), dropped outside a non-periodic grid.
@@ -477,7 +481,7 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const int* __r
   int cnt = 0, stored = 0;
   if (i < J.off + J.n) {
     const int lane = threadIdx.x;
-    const int xs = J.xcur ^ 1, ss = J.scur ^ 1;  // the sorted copies written by k_scatter
+    const int xs = J.xcur ^ 1, ss = J.scur ^ 1;  // the sorted copies written by k_gather
     const double* __restrict__ X = B.X[xs];
     const uint32_t* __restrict__ ID = B.ID[ss];
     const double xi = X[3 * i], yi = X[3 * i + 1], zi = X[3 * i + 2];
@@ -520,13 +524,14 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const int* __r
     auto scan = [&](uint32_t b, uint32_t e) {
       int64_t j = base + b;
       const int64_t end = base + e;
-      for (; j + 2 <= end; j += 2) {
-        const double ax0 = X[3 * j], ay0 = X[3 * j + 1], az0 = X[3 * j + 2];
-        const double ax1 = X[3 * j + 3], ay1 = X[3 * j + 4], az1 = X[3 * j + 5];
-        consider(j, ax0, ay0, az0);
-        consider(j + 1, ax1, ay1, az1);
+      for (; j + 4 <= end; j += 4) {
+        double a[12];
+#pragma unroll
+        for (int u = 0; u < 12; ++u) a[u] = X[3 * j + u];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) consider(j + u, a[3 * u], a[3 * u + 1], a[3 * u + 2]);
       }
-      if (j < end) consider(j, X[3 * j], X[3 * j + 1], X[3 * j + 2]);
+      for (; j < end; ++j) consider(j, X[3 * j], X[3 * j + 1], X[3 * j + 2]);
     };
     // the next column's lookups are in flight while this column is scanned
     ColumnRange cur = column_range(B, J, cx, cy, 0, za0, zb0, za1, zb1);
