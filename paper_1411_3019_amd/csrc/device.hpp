@@ -52,12 +52,15 @@ struct JobDev {
 // workgroups never contend for these words in the common case.
 constexpr long long kNever = 0x7FFFFFFFFFFFFFFFLL;
 struct JobBook {
-  long long stop_at;                // first step that must not run: stale list or error (kNever if none)
+  long long stop_at;                // first step that must not run: stale list, list overflow or error (kNever if none)
   int err_code;
   int err_id;
   int newton_max;
-  int pad1;
+  int nl_max;                       // largest neighbour count of the last list build (above kmax: overflow)
+  double nl_sum;                    // sum of the stored neighbour counts of the last list build
+  double a_now;                     // largest per-tile displacement bound since the last list build
 };
+__host__ __device__ constexpr JobBook fresh_book() { return JobBook{kNever, 0, 0, 0, 0, 0.0, 0.0}; }
 
 // Device buffers, passed by value to every kernel.
 struct DevBufs {
@@ -83,7 +86,7 @@ struct DevBufs {
   uint32_t* INV;       // slot of each particle index after the last sort, by job offset + index
   uint32_t* SRC;       // old slot (job-relative) of each new slot during a sort
   double* TACC;        // per tile (slot / kTile): accumulated max displacement since the last build
-  uint32_t* NLSTAT;    // per list-build workgroup: (max count, sum of counts)
+  uint32_t* NLSTAT;    // per group of 64 slots, from the last list build: (max count, sum of stored counts)
   JobDev* jobs;
   JobBook* book;
   int64_t C;           // slot capacity (SoA stride)

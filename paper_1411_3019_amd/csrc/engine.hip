@@ -34,6 +34,7 @@ namespace {
 constexpr int kDefaultKmax = 16;
 constexpr int kMaxChunk = 64;
 constexpr int kPoolChunk = 32;
+constexpr size_t kArenaBytes = (size_t)4 << 20;  // pinned staging for small uploads
 
 #define HIPCHK(expr)                   \
   do {                                 \
@@ -186,6 +187,7 @@ struct HostJob {
   int status = MD_OK;
   int newton_max = 0, nl_max = 0, err_id = -1;
   double nl_sum = 0.0;
+  bool lists_pending = false;  // list statistics of the last build not read back yet
   double A_now = 0.0;
   double rate_prev = 0.0;  // displacement per step while the previous list was in use
   double ext_lo[3] = {0, 0, 0}, ext_len[3] = {0, 0, 0};  // region the cell grid covers
@@ -322,15 +324,19 @@ struct Engine {
   int64_t range_cap = 0;
   // pinned host staging
   JobBook* book_h = nullptr;
-  std::vector<double> tacc_h;      // host copy of the per-tile displacement accumulators
-  std::vector<uint32_t> nlstat_h;  // host copy of the list-build statistics
-  char* stage = nullptr;
+  char* stage = nullptr;           // bulk transfers (admission, results); free once the stream is drained
   size_t stage_cap = 0;
+  char* arena = nullptr;           // small uploads, bump-allocated; recycled when the stream is drained
+  size_t arena_used = 0;
+  std::map<void*, std::vector<char>> uploaded;  // last contents of descriptor arrays that rarely change
+  bool build_timing_pending = false;
   // step graphs
   std::map<GraphKey, hipGraphExec_t> graphs;
   bool step_tiles_valid = false;
   md_stats stats{};
+  static constexpr int kSubEvents = 16;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t ev_sub[kSubEvents] = {};
   std::vector<int> last_tj[2];
   std::vector<int64_t> last_tf[2];
   size_t nl_bytes = 0;
@@ -346,6 +352,8 @@ struct Engine {
     if (device >= 0) (void)hipSetDevice(device);
     drop_graphs();
     for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e), e = nullptr;
+    for (auto& e : ev_sub)
       if (e) (void)hipEventDestroy(e), e = nullptr;
     void* ptrs[] = {B.X[0], B.X[1], B.P[0], B.P[1], B.ID[0], B.ID[1], B.FLG[0], B.FLG[1], B.MASS[0], B.MASS[1],
                     B.FC, B.OX, B.OP, B.OF, B.OD, B.NL, B.NCNT, B.BM, B.WOFF, B.CCNT, B.CSTART, B.RASTER,
@@ -363,9 +371,13 @@ struct Engine {
     ranges_d = nullptr;
     if (book_h) (void)hipHostFree(book_h);
     if (stage) (void)hipHostFree(stage);
+    if (arena) (void)hipHostFree(arena);
     book_h = nullptr;
     stage = nullptr;
+    arena = nullptr;
     stage_cap = 0;
+    arena_used = 0;
+    uploaded.clear();
     if (own_stream && stream) (void)hipStreamDestroy(stream);
     stream = nullptr;
     own_stream = false;
@@ -430,15 +442,13 @@ struct Engine {
     MDCHK(dalloc(&B.jobs, max_jobs));
     MDCHK(dalloc(&B.book, max_jobs));
     {
-      std::vector<JobBook> fresh(max_jobs);
-      for (auto& k : fresh) k = JobBook{kNever, 0, 0, 0, 0};
+      std::vector<JobBook> fresh(max_jobs, fresh_book());
       HIPCHK(hipMemcpy(B.book, fresh.data(), sizeof(JobBook) * max_jobs, hipMemcpyHostToDevice));
     }
     HIPCHK(hipMemsetAsync(B.NCNT, 0, sizeof(uint32_t) * C, stream));
     tile_cap = C / kTile + max_jobs + 8;
-    MDCHK(dalloc(&B.NLSTAT, 2 * kNlistPerTile * tile_cap));
-    tacc_h.assign(C / kTile + 1, 0.0);
-    nlstat_h.assign(2 * kNlistPerTile * tile_cap, 0u);
+    MDCHK(dalloc(&B.NLSTAT, 2 * (C / kNlistBlock + 1)));
+    HIPCHK(hipMemsetAsync(B.NLSTAT, 0, sizeof(uint32_t) * 2 * (C / kNlistBlock + 1), stream));
     MDCHK(dalloc(&step_tiles_job, 2 * tile_cap));
     MDCHK(dalloc(&step_tiles_first, 2 * tile_cap));
     MDCHK(dalloc(&step_counts, 2));
@@ -451,8 +461,16 @@ struct Engine {
     range_cap = 3 * max_jobs + 4;
     MDCHK(dalloc(&ranges_d, range_cap));
     HIPCHK(hipHostMalloc((void**)&book_h, sizeof(JobBook) * max_jobs, hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&arena, kArenaBytes, hipHostMallocDefault));
     for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+    for (auto& e : ev_sub) HIPCHK(hipEventCreate(&e));
+    return sync();
+  }
+
+  // Drain the stream; every staged upload has then been consumed.
+  int sync() {
     HIPCHK(hipStreamSynchronize(stream));
+    arena_used = 0;
     return MD_OK;
   }
 
@@ -467,10 +485,20 @@ struct Engine {
   }
 
   // Stage host bytes in pinned memory and copy them to the device, in order on
-  // the stream.  The stream is drained first so the staging area is free.
+  // the stream.  Small uploads take the next piece of the arena and do not
+  // wait; the arena is recycled when the stream is drained (at the latest when
+  // it is full).  Large uploads drain the stream and use the bulk stage.
   int upload(void* dst, const void* src, size_t bytes) {
     if (bytes == 0) return MD_OK;
-    HIPCHK(hipStreamSynchronize(stream));
+    const size_t need = (bytes + 255) & ~(size_t)255;
+    if (need <= kArenaBytes) {
+      if (arena_used + need > kArenaBytes) MDCHK(sync());
+      std::memcpy(arena + arena_used, src, bytes);
+      HIPCHK(hipMemcpyAsync(dst, arena + arena_used, bytes, hipMemcpyHostToDevice, stream));
+      arena_used += need;
+      return MD_OK;
+    }
+    MDCHK(sync());
     if (bytes > stage_cap) {
       if (stage) (void)hipHostFree(stage);
       stage = nullptr;
@@ -483,8 +511,19 @@ struct Engine {
     return MD_OK;
   }
 
+  // Upload unless dst already holds exactly these bytes from an earlier upload
+  // (for descriptor arrays that only uploads write).
+  int upload_cached(void* dst, const void* src, size_t bytes) {
+    auto it = uploaded.find(dst);
+    if (it != uploaded.end() && it->second.size() == bytes && std::memcmp(it->second.data(), src, bytes) == 0)
+      return MD_OK;
+    MDCHK(upload(dst, src, bytes));
+    uploaded[dst].assign((const char*)src, (const char*)src + bytes);
+    return MD_OK;
+  }
+
   int ensure_stage(size_t bytes) {
-    HIPCHK(hipStreamSynchronize(stream));
+    MDCHK(sync());
     if (bytes > stage_cap) {
       if (stage) (void)hipHostFree(stage);
       stage = nullptr;
@@ -503,8 +542,7 @@ struct Engine {
 
   int read_book() {
     HIPCHK(hipMemcpyAsync(book_h, B.book, sizeof(JobBook) * max_jobs, hipMemcpyDeviceToHost, stream));
-    HIPCHK(hipStreamSynchronize(stream));
-    return MD_OK;
+    return sync();
   }
 
   static void tiles_of(const HostJob& h, int j, std::vector<int>& tj, std::vector<int64_t>& tf) {
@@ -688,7 +726,7 @@ struct Engine {
     uint32_t* nl = nullptr;
     MDCHK(dalloc(&nl, (size_t)nk * C));
     HIPCHK(hipMemcpyAsync(nl, B.NL, sizeof(uint32_t) * (size_t)kmax * C, hipMemcpyDeviceToDevice, stream));
-    HIPCHK(hipStreamSynchronize(stream));
+    MDCHK(sync());
     (void)hipFree(B.NL);
     B.NL = nl;
     kmax = nk;
@@ -698,6 +736,10 @@ struct Engine {
     return MD_OK;
   }
 
+  // Sort the jobs of `set` into cell order and build their neighbour lists.
+  // Nothing here waits for the device: the list statistics (and an overflow
+  // of the list capacity, which also stops the job before its first step on
+  // the new lists) are read back with the job records after the next chunk.
   int rebuild(const std::vector<int>& set) {
     if (set.empty()) return MD_OK;
     std::vector<int> tj;
@@ -708,6 +750,7 @@ struct Engine {
     for (int j : set) {
       HostJob& h = jobs[j];
       h.dev.remaining = 0;
+      h.dev.step0 = h.step;
       tiles_of(h, j, tj, tf);
       rb.push_back({h.bm_off, h.bm_words});
       rcnt.push_back({h.off, h.n + 1});
@@ -729,19 +772,21 @@ struct Engine {
     if ((int64_t)(cb.size() + cc.size()) > chunk_cap || (int64_t)tj.size() > tile_cap ||
         (int64_t)(rb.size() + rcnt.size() + rtacc.size()) > range_cap)
       return MD_ENOMEM;
+    const size_t lds = nlist_lds_bytes(kmax);
+    if (lds > 160 * 1024) return MD_ENOMEM;
     MDCHK(upload_jobs());
-    MDCHK(upload(aux_tiles_job, tj.data(), sizeof(int) * tj.size()));
-    MDCHK(upload(aux_tiles_first, tf.data(), sizeof(int64_t) * tf.size()));
+    MDCHK(upload_cached(aux_tiles_job, tj.data(), sizeof(int) * tj.size()));
+    MDCHK(upload_cached(aux_tiles_first, tf.data(), sizeof(int64_t) * tf.size()));
     std::vector<Chunk> call(cb);
     call.insert(call.end(), cc.begin(), cc.end());
     // seg_first stays relative to each sub-list: the two scans get separate base pointers
-    MDCHK(upload(chunks_d, call.data(), sizeof(Chunk) * call.size()));
+    MDCHK(upload_cached(chunks_d, call.data(), sizeof(Chunk) * call.size()));
     std::vector<Range> rall(rb);
     rall.insert(rall.end(), rcnt.begin(), rcnt.end());
     rall.insert(rall.end(), rtacc.begin(), rtacc.end());
-    MDCHK(upload(ranges_d, rall.data(), sizeof(Range) * rall.size()));
+    MDCHK(upload_cached(ranges_d, rall.data(), sizeof(Range) * rall.size()));
     const int ntiles = (int)tj.size();
-    HIPCHK(hipEventRecord(ev[2], stream));
+    if (!build_timing_pending) HIPCHK(hipEventRecord(ev[2], stream));
     // zero bitmaps and cell counters
     hipLaunchKernelGGL(k_zero_ranges, dim3(64, (unsigned)rb.size()), dim3(256), 0, stream, B.BM, ranges_d,
                        (int)rb.size());
@@ -749,9 +794,12 @@ struct Engine {
                        ranges_d + rb.size(), (int)rcnt.size());
     hipLaunchKernelGGL(k_zero_ranges, dim3(4, (unsigned)rtacc.size()), dim3(256), 0, stream, (uint32_t*)B.TACC,
                        ranges_d + rb.size() + rcnt.size(), (int)rtacc.size());
-    for (int j : set) book_h[j] = JobBook{kNever, 0, 0, 0, 0};
-    // reset bookkeeping of the rebuilt jobs (small copies, pinned source)
-    for (int j : set) HIPCHK(hipMemcpyAsync(&B.book[j], &book_h[j], sizeof(JobBook), hipMemcpyHostToDevice, stream));
+    // k_mark resets the job records of jobs with particles; the others are reset here
+    for (int j : set) {
+      if (jobs[j].n > 0) continue;
+      book_h[j] = fresh_book();
+      HIPCHK(hipMemcpyAsync(&B.book[j], &book_h[j], sizeof(JobBook), hipMemcpyHostToDevice, stream));
+    }
     hipLaunchKernelGGL(k_mark, dim3(ntiles), dim3(kTile), 0, stream, B, aux_tiles_job, aux_tiles_first);
     // bitmap popcount prefix (segmented by job)
     const int nb = (int)cb.size(), nc = (int)cc.size();
@@ -766,50 +814,66 @@ struct Engine {
     hipLaunchKernelGGL(k_scan_c, dim3(nc), dim3(kScanThreads), 0, stream, B.CSTART, chunks_d + nb, chunk_sums + nb);
     hipLaunchKernelGGL(k_perm, dim3(ntiles), dim3(kTile), 0, stream, B, aux_tiles_job, aux_tiles_first);
     hipLaunchKernelGGL(k_gather, dim3(ntiles), dim3(kTile), 0, stream, B, aux_tiles_job, aux_tiles_first);
-    for (int attempt = 0; attempt < 3; ++attempt) {
-      const size_t lds = (size_t)kmax * kNlistBlock * sizeof(uint32_t);
-      if (lds > 160 * 1024) return MD_ENOMEM;
-      hipLaunchKernelGGL(k_nlist, dim3(kNlistPerTile * ntiles), dim3(kNlistBlock), lds, stream, B, aux_tiles_job,
-                         aux_tiles_first);
-      HIPCHK(hipGetLastError());
-      HIPCHK(hipEventRecord(ev[3], stream));
-      const size_t nblk = (size_t)kNlistPerTile * ntiles;
-      HIPCHK(hipMemcpyAsync(nlstat_h.data(), B.NLSTAT, sizeof(uint32_t) * 2 * nblk, hipMemcpyDeviceToHost, stream));
-      HIPCHK(hipStreamSynchronize(stream));
-      stats.rebuild_ms += elapsed_ms(ev[2], ev[3]);
-      stats.builds += 1;
-      for (int j : set) {
-        jobs[j].nl_max = 0;
-        jobs[j].nl_sum = 0.0;
-      }
-      for (size_t b = 0; b < nblk; ++b) {
-        HostJob& h = jobs[tj[b / kNlistPerTile]];
-        h.nl_max = std::max<int>(h.nl_max, (int)nlstat_h[2 * b]);
-        h.nl_sum += (double)nlstat_h[2 * b + 1];
-      }
-      int need = 0;
-      for (int j : set) need = std::max(need, jobs[j].nl_max);
-      if (need <= kmax) break;
-      MDCHK(grow_kmax(need + need / 8 + 2));
-    }
+    hipLaunchKernelGGL(k_nlist, dim3(kNlistPerTile * ntiles), dim3(kNlistBlock), lds, stream, B, aux_tiles_job,
+                       aux_tiles_first);
+    hipLaunchKernelGGL(k_job_stats, dim3(max_jobs), dim3(kStatsThreads), 0, stream, B, 1);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventRecord(ev[3], stream));
+    build_timing_pending = true;
+    stats.builds += 1;
     for (int j : set) {
       HostJob& h = jobs[j];
       h.dev.xcur ^= 1;
       h.dev.pcur ^= 1;
       h.dev.scur ^= 1;
       h.built = true;
+      h.lists_pending = true;
       if (h.step > h.last_build && h.A_now > 0.0) h.rate_prev = h.A_now / (double)(h.step - h.last_build);
       h.A_now = 0.0;
       h.last_build = h.step;
       h.rebuilds += 1;
-      nl_sum_all += h.nl_sum;
-      nl_n_all += (double)h.n;
     }
-    if (nl_n_all > 0) stats.nl_mean = nl_sum_all / nl_n_all;
-    nl_sum_all = nl_n_all = 0.0;
     return MD_OK;
   }
-  double nl_sum_all = 0.0, nl_n_all = 0.0;
+
+  // After a drained stream: take the list statistics of the last builds from
+  // the job records in book_h, and the build time.  Returns the largest list
+  // length found (for a capacity check).
+  int collect_build_stats() {
+    if (build_timing_pending) {
+      stats.rebuild_ms += elapsed_ms(ev[2], ev[3]);
+      build_timing_pending = false;
+    }
+    int need = 0;
+    double sum = 0.0, cnt = 0.0;
+    for (int j = 0; j < max_jobs; ++j) {
+      HostJob& h = jobs[j];
+      if (!h.used || !h.lists_pending) continue;
+      h.lists_pending = false;
+      if (h.n == 0) continue;
+      h.nl_max = book_h[j].nl_max;
+      h.nl_sum = book_h[j].nl_sum;
+      need = std::max(need, h.nl_max);
+      sum += h.nl_sum;
+      cnt += (double)h.n;
+    }
+    if (cnt > 0) stats.nl_mean = sum / cnt;
+    return need;
+  }
+
+  // Build the lists of `set` and wait for them; on a capacity overflow grow the
+  // capacity and build again (for callers that use the lists at once).
+  int rebuild_now(const std::vector<int>& set) {
+    for (int attempt = 0; attempt < 4; ++attempt) {
+      MDCHK(rebuild(set));
+      MDCHK(read_book());
+      const int need = collect_build_stats();
+      if (need <= kmax) return MD_OK;
+      MDCHK(grow_kmax(need + need / 8 + 2));
+      for (int j : set) jobs[j].built = false;
+    }
+    return MD_ENOMEM;
+  }
 
   // ------------------------------------------------------------------ stepping
   bool steppable(const HostJob& h) const { return h.used && h.status == MD_OK && !h.done && h.step < h.target; }
@@ -897,13 +961,15 @@ struct Engine {
 
   // Steps a job can take before its list goes stale: the remaining half skin
   // over the larger of the displacement rates of this and the previous list.
+  // A list that goes stale earlier stops its job on the device, so the
+  // estimate need not be conservative.
   static int predict_chunk(const HostJob& h) {
     const int64_t since = h.step - h.last_build;
     double rate = h.rate_prev;
     if (since > 0 && h.A_now > 0.0) rate = std::max(rate, h.A_now / (double)since);
     if (!(rate > 0.0)) return 16;
     const double left = (h.dev.half_skin - h.A_now) / rate;
-    return (int)std::max(0.0, std::min(1e6, std::floor(0.8 * left)));
+    return (int)std::max(0.0, std::min(1e6, std::floor(left)));
   }
 
   // One chunk of at most kcap steps for every steppable job; rebuilds first
@@ -911,9 +977,12 @@ struct Engine {
   // eager = true (pools): rebuild every job whose list would go stale within
   // the chunk, and run the full chunk; eager = false (one system): rebuild only
   // when the list is (nearly) stale and shorten the chunk to the prediction.
+  // A chunk of k steps is a run of cached graphs of power-of-two lengths (the
+  // binary digits of k), with the job records for each uploaded before it; the
+  // host waits once, for the job records at the end.
   int run_chunk(int kcap, bool use_graph, int64_t* advanced, bool eager = false) {
     std::vector<int> need;
-    int k = std::min(kcap, kMaxChunk);
+    const int k = std::min(kcap, kMaxChunk);
     for (int j = 0; j < max_jobs; ++j) {
       HostJob& h = jobs[j];
       if (!steppable(h)) continue;
@@ -937,30 +1006,47 @@ struct Engine {
       *advanced = 0;
       return MD_OK;
     }
-    // a power of two keeps the number of distinct graphs small
-    int kq = 1;
-    while (kq * 2 <= kk) kq *= 2;
+    std::vector<int64_t> cap(max_jobs, 0);
     for (int j = 0; j < max_jobs; ++j) {
       HostJob& h = jobs[j];
+      cap[j] = steppable(h) ? std::min<int64_t>(h.target - h.step, kk) : 0;
       h.dev.step0 = h.step;
-      h.dev.remaining = steppable(h) ? std::min<int64_t>(h.target - h.step, kq) : 0;
+      h.dev.remaining = cap[j];
     }
     MDCHK(prepare_step_tiles());
-    MDCHK(upload_jobs());
-    HIPCHK(hipEventRecord(ev[0], stream));
-    MDCHK(launch_chunk(kq, use_graph));
-    HIPCHK(hipEventRecord(ev[1], stream));
+    std::vector<JobDev> tab(max_jobs);
+    int t0 = 0, nsub = 0;
+    for (int len = kMaxChunk; len >= 1; len >>= 1) {
+      if (!(kk & len)) continue;
+      for (int j = 0; j < max_jobs; ++j) {
+        const HostJob& h = jobs[j];
+        JobDev d = h.dev;
+        d.step0 = h.step + t0;
+        d.remaining = std::max<int64_t>(0, std::min<int64_t>(cap[j] - t0, len));
+        d.xcur = h.dev.xcur ^ (t0 & 1);
+        if (t0 > 0) d.mode = kModeSteady;
+        tab[j] = d;
+      }
+      MDCHK(upload(B.jobs, tab.data(), sizeof(JobDev) * max_jobs));
+      HIPCHK(hipEventRecord(ev_sub[2 * nsub], stream));
+      MDCHK(launch_chunk(len, use_graph));
+      HIPCHK(hipEventRecord(ev_sub[2 * nsub + 1], stream));
+      ++nsub;
+      t0 += len;
+    }
+    hipLaunchKernelGGL(k_job_stats, dim3(max_jobs), dim3(kStatsThreads), 0, stream, B, 0);
+    HIPCHK(hipGetLastError());
     MDCHK(read_book());
-    stats.step_kernel_ms += elapsed_ms(ev[0], ev[1]);
+    for (int q = 0; q < nsub; ++q) stats.step_kernel_ms += elapsed_ms(ev_sub[2 * q], ev_sub[2 * q + 1]);
     stats.chunks += 1;
-    stats.step_launches += (int64_t)kq * ((grid64 > 0) + (grid32 > 0));
-    HIPCHK(hipMemcpy(tacc_h.data(), B.TACC, sizeof(double) * tacc_h.size(), hipMemcpyDeviceToHost));
+    stats.step_launches += (int64_t)kk * ((grid64 > 0) + (grid32 > 0));
+    const int longest = collect_build_stats();
     int64_t adv = 0;
     for (int j = 0; j < max_jobs; ++j) {
       HostJob& h = jobs[j];
-      if (!h.used || h.dev.remaining == 0) continue;
+      if (!h.used || cap[j] == 0) continue;
       const JobBook& K = book_h[j];
-      int64_t done = h.dev.remaining;
+      int64_t done = cap[j];
       if (K.stop_at < h.step + done) done = std::max<int64_t>(0, K.stop_at - h.step);
       h.newton_max = std::max(h.newton_max, K.newton_max);
       if (K.err_code != 0) {
@@ -973,9 +1059,8 @@ struct Engine {
       h.step += done;
       if (done & 1) h.dev.xcur ^= 1;
       if (done > 0) h.dev.mode = kModeSteady;
-      double a = 0.0;
-      for (int64_t t = h.off / kTile; t < (h.off + h.n + kTile - 1) / kTile; ++t) a = std::max(a, tacc_h[t]);
-      h.A_now = a;
+      h.A_now = K.a_now;
+      // a stale list, or one that overflowed its capacity, is built again
       if (K.stop_at != kNever || h.A_now > h.dev.half_skin) h.built = false;
       if (h.step >= h.target) {
         h.done = true;
@@ -985,6 +1070,7 @@ struct Engine {
       stats.steps += done;
       stats.particle_steps += done * h.n;
     }
+    if (longest > kmax) MDCHK(grow_kmax(longest + longest / 8 + 2));
     *advanced = adv;
     return MD_OK;
   }
@@ -1001,15 +1087,15 @@ struct Engine {
       }
       return h.status;
     }
-    if (h.status == MD_OK && (!h.built || h.A_now > h.dev.half_skin)) MDCHK(rebuild({j}));
+    if (h.status == MD_OK && (!h.built || h.A_now > h.dev.half_skin)) MDCHK(rebuild_now({j}));
     h.dev.step0 = h.step;
     h.dev.remaining = 0;
     MDCHK(upload_jobs());
     std::vector<int> tj;
     std::vector<int64_t> tf;
     tiles_of(h, j, tj, tf);
-    MDCHK(upload(aux_tiles_job, tj.data(), sizeof(int) * tj.size()));
-    MDCHK(upload(aux_tiles_first, tf.data(), sizeof(int64_t) * tf.size()));
+    MDCHK(upload_cached(aux_tiles_job, tj.data(), sizeof(int) * tj.size()));
+    MDCHK(upload_cached(aux_tiles_first, tf.data(), sizeof(int64_t) * tf.size()));
     if (h.dev.force_fp64)
       hipLaunchKernelGGL(k_finish<true>, dim3((unsigned)tj.size()), dim3(kTile), 0, stream, B, aux_tiles_job,
                          aux_tiles_first);
@@ -1026,7 +1112,7 @@ struct Engine {
     for (int k = 0; k < 4; ++k)
       HIPCHK(hipMemcpyAsync(st + (9 + k) * n, B.OD + k * C + h.off, sizeof(double) * n, hipMemcpyDeviceToHost,
                             stream));
-    HIPCHK(hipStreamSynchronize(stream));
+    MDCHK(sync());
     if (x) std::memcpy(x, st, sizeof(double) * 3 * n);
     if (p) std::memcpy(p, st + 3 * n, sizeof(double) * 3 * n);
     if (f) std::memcpy(f, st + 6 * n, sizeof(double) * 3 * n);

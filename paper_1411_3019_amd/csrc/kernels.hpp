@@ -342,6 +342,8 @@ __global__ void __launch_bounds__(kTile) k_mark(DevBufs B, const int* __restrict
   const JobDev& J = B.jobs[job];
   const int64_t i = uniform_i64(tile_first[blockIdx.x]) + threadIdx.x;
   const bool valid = i < J.off + J.n;
+  // a list build starts the job's bookkeeping afresh
+  if (i == J.off) B.book[job] = fresh_book();
   uint32_t key = kNoKey, bits = 0u;
   if (valid) {
     const double* X = B.X[J.xcur];
@@ -469,96 +471,163 @@ __device__ __forceinline__ ColumnRange column_range(const DevBufs& B, const JobD
   return r;
 }
 
+// Insert particle index q into this lane's list, kept sorted by particle index
+// in LDS ([kmax][64], lane-minor so lanes hit distinct banks).  cnt counts every
+// candidate accepted, stored or not (cnt > kmax signals overflow).
+__device__ __forceinline__ void list_insert(uint32_t* kid, int lane, int kmax, int& cnt, uint32_t q) {
+  if (cnt < kmax) {
+    int k = cnt;
+    while (k > 0 && kid[(k - 1) * kNlistBlock + lane] > q) {
+      kid[k * kNlistBlock + lane] = kid[(k - 1) * kNlistBlock + lane];
+      --k;
+    }
+    kid[k * kNlistBlock + lane] = q;
+  }
+  ++cnt;
+}
+
+// z cells of the stencil around cz: [za0, zb0] and, when z wraps, [za1, zb1].
+__device__ __forceinline__ void z_runs(const JobDev& J, int cz, int& za0, int& zb0, int& za1, int& zb1) {
+  const int ncz = J.nc[2];
+  za1 = 0, zb1 = -1;
+  if (J.periodic[2] && ncz >= 3) {
+    if (cz == 0) {
+      za0 = 0, zb0 = 1, za1 = ncz - 1, zb1 = ncz - 1;
+    } else if (cz == ncz - 1) {
+      za0 = 0, zb0 = 0, za1 = cz - 1, zb1 = cz;
+    } else {
+      za0 = cz - 1, zb0 = cz + 1;
+    }
+  } else if (J.periodic[2]) {
+    za0 = 0, zb0 = ncz - 1;
+  } else {
+    za0 = cz > 0 ? cz - 1 : 0;
+    zb0 = cz + 1 < ncz ? cz + 1 : ncz - 1;
+  }
+}
+
+// One lane walks its own 27-cell stencil: 9 contiguous z-runs of slots, the next
+// column's lookups in flight while the current one is scanned.
+__device__ __forceinline__ void nlist_lane(const DevBufs& B, const JobDev& J, const double* __restrict__ X,
+                                           const uint32_t* __restrict__ ID, int64_t i, double xi, double yi,
+                                           double zi, int cx, int cy, int cz, uint32_t* kid, int lane, int kmax,
+                                           int& cnt) {
+  int za0, zb0, za1, zb1;
+  z_runs(J, cz, za0, zb0, za1, zb1);
+  const int64_t base = J.off;
+  const bool anyper = J.periodic[0] | J.periodic[1] | J.periodic[2];
+  auto consider = [&](int64_t j, double ax, double ay, double az) {
+    if (j == i) return;
+    double dx = xi - ax, dy = yi - ay, dz = zi - az;
+    if (anyper) min_image(J, dx, dy, dz);
+    if (dx * dx + dy * dy + dz * dz >= J.rlist2) return;
+    list_insert(kid, lane, kmax, cnt, ID[j]);
+  };
+  auto scan = [&](uint32_t b, uint32_t e) {
+    int64_t j = base + b;
+    const int64_t end = base + e;
+    for (; j + 4 <= end; j += 4) {
+      double a[12];
+#pragma unroll
+      for (int u = 0; u < 12; ++u) a[u] = X[3 * j + u];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) consider(j + u, a[3 * u], a[3 * u + 1], a[3 * u + 2]);
+    }
+    for (; j < end; ++j) consider(j, X[3 * j], X[3 * j + 1], X[3 * j + 2]);
+  };
+  ColumnRange cur = column_range(B, J, cx, cy, 0, za0, zb0, za1, zb1);
+  for (int col = 0; col < 9; ++col) {
+    ColumnRange nxt{0u, 0u, 0u, 0u};
+    if (col + 1 < 9) nxt = column_range(B, J, cx, cy, col + 1, za0, zb0, za1, zb1);
+    scan(cur.b0, cur.e0);
+    scan(cur.b1, cur.e1);
+    cur = nxt;
+  }
+}
+
+// Neighbour-list build, one lane per slot of the freshly sorted (raster cell)
+// order, one wavefront per workgroup.  Each lane walks its own stencil; the
+// list is kept sorted by particle index in LDS and mapped back to slots through
+// the inverse permutation of the sort.
 __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const int* __restrict__ tile_job,
                                                        const int64_t* __restrict__ tile_first) {
-  extern __shared__ uint32_t lds[];
+  extern __shared__ uint32_t kid[];  // sorted lists [kmax][64]
   const int kmax = B.kmax;
-  uint32_t* kid = lds;
   const int tile = (int)blockIdx.x / kNlistPerTile;
   const int job = uniform_int(tile_job[tile]);
   const JobDev& J = B.jobs[job];
-  const int64_t i = uniform_i64(tile_first[tile]) + ((int)blockIdx.x % kNlistPerTile) * kNlistBlock + threadIdx.x;
-  int cnt = 0, stored = 0;
+  const int lane = threadIdx.x;
+  const int64_t i = uniform_i64(tile_first[tile]) + ((int)blockIdx.x % kNlistPerTile) * kNlistBlock + lane;
+  const int64_t base = J.off;
+  int cnt = 0;
   if (i < J.off + J.n) {
-    const int lane = threadIdx.x;
-    const int xs = J.xcur ^ 1, ss = J.scur ^ 1;  // the sorted copies written by k_gather
-    const double* __restrict__ X = B.X[xs];
-    const uint32_t* __restrict__ ID = B.ID[ss];
+    const double* __restrict__ X = B.X[J.xcur ^ 1];  // the sorted copies written by k_gather
+    const uint32_t* __restrict__ ID = B.ID[J.scur ^ 1];
     const double xi = X[3 * i], yi = X[3 * i + 1], zi = X[3 * i + 2];
     const int cx = cell_coord(J, 0, xi), cy = cell_coord(J, 1, yi), cz = cell_coord(J, 2, zi);
-    // z runs: [za0, zb0] and possibly a wrapped [za1, zb1]
-    const int ncz = J.nc[2];
-    int za0, zb0, za1 = 0, zb1 = -1;
-    if (J.periodic[2] && ncz >= 3) {
-      if (cz == 0) {
-        za0 = 0, zb0 = 1, za1 = ncz - 1, zb1 = ncz - 1;
-      } else if (cz == ncz - 1) {
-        za0 = 0, zb0 = 0, za1 = cz - 1, zb1 = cz;
-      } else {
-        za0 = cz - 1, zb0 = cz + 1;
-      }
-    } else if (J.periodic[2]) {
-      za0 = 0, zb0 = ncz - 1;
-    } else {
-      za0 = cz > 0 ? cz - 1 : 0;
-      zb0 = cz + 1 < ncz ? cz + 1 : ncz - 1;
-    }
-    const int64_t base = J.off;
-    const bool anyper = J.periodic[0] | J.periodic[1] | J.periodic[2];
-    auto consider = [&](int64_t j, double ax, double ay, double az) {
-      if (j == i) return;
-      double dx = xi - ax, dy = yi - ay, dz = zi - az;
-      if (anyper) min_image(J, dx, dy, dz);
-      if (dx * dx + dy * dy + dz * dz >= J.rlist2) return;
-      const uint32_t qid = ID[j];
-      if (cnt < kmax) {
-        int k = cnt;
-        while (k > 0 && kid[(k - 1) * kNlistBlock + lane] > qid) {
-          kid[k * kNlistBlock + lane] = kid[(k - 1) * kNlistBlock + lane];
-          --k;
-        }
-        kid[k * kNlistBlock + lane] = qid;
-      }
-      ++cnt;
-    };
-    auto scan = [&](uint32_t b, uint32_t e) {
-      int64_t j = base + b;
-      const int64_t end = base + e;
-      for (; j + 4 <= end; j += 4) {
-        double a[12];
-#pragma unroll
-        for (int u = 0; u < 12; ++u) a[u] = X[3 * j + u];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) consider(j + u, a[3 * u], a[3 * u + 1], a[3 * u + 2]);
-      }
-      for (; j < end; ++j) consider(j, X[3 * j], X[3 * j + 1], X[3 * j + 2]);
-    };
-    // the next column's lookups are in flight while this column is scanned
-    ColumnRange cur = column_range(B, J, cx, cy, 0, za0, zb0, za1, zb1);
-    for (int col = 0; col < 9; ++col) {
-      ColumnRange nxt{0u, 0u, 0u, 0u};
-      if (col + 1 < 9) nxt = column_range(B, J, cx, cy, col + 1, za0, zb0, za1, zb1);
-      scan(cur.b0, cur.e0);
-      scan(cur.b1, cur.e1);
-      cur = nxt;
-    }
+    nlist_lane(B, J, X, ID, i, xi, yi, zi, cx, cy, cz, kid, lane, kmax, cnt);
+    const int stored = cnt < kmax ? cnt : kmax;
     const int64_t C = B.C;
-    stored = cnt < kmax ? cnt : kmax;
-    // particle indices back to slots through the inverse permutation of the sort
     for (int k = 0; k < stored; ++k) B.NL[(int64_t)k * C + i] = (uint32_t)base + B.INV[base + kid[k * kNlistBlock + lane]];
     B.NCNT[i] = (uint32_t)stored;
   }
-  // list statistics of this workgroup, no atomics
-  uint32_t mx = (uint32_t)cnt, sm = (uint32_t)stored;
+  // list statistics of these 64 slots (no atomics); an overflow stops the job
+  // before its first step on these lists
+  uint32_t mx = (uint32_t)cnt, sm = (uint32_t)(cnt < kmax ? cnt : kmax);
   for (int o = 32; o > 0; o >>= 1) {
     mx = max(mx, (uint32_t)__shfl_xor((int)mx, o, 64));
     sm += (uint32_t)__shfl_xor((int)sm, o, 64);
   }
-  if (threadIdx.x == 0) {
-    B.NLSTAT[2 * blockIdx.x] = mx;
-    B.NLSTAT[2 * blockIdx.x + 1] = sm;
+  const int64_t g0 = i - lane;
+  if (lane == 0 && g0 < J.off + J.n) {
+    B.NLSTAT[2 * (g0 / kNlistBlock)] = mx;
+    B.NLSTAT[2 * (g0 / kNlistBlock) + 1] = sm;
+    if ((int)mx > kmax) atomicMin(&B.book[job].stop_at, (long long)J.step0);
   }
 }
+
+// Per-job reductions read by the host after a chunk of steps: the largest
+// per-tile displacement bound and, after list builds, the list statistics.
+// One workgroup per job record.
+constexpr int kStatsThreads = 1024;
+__global__ void __launch_bounds__(kStatsThreads) k_job_stats(DevBufs B, int with_lists) {
+  __shared__ double ra[kStatsThreads / 64], rs[kStatsThreads / 64];
+  __shared__ uint32_t rm[kStatsThreads / 64];
+  const int job = blockIdx.x;
+  const JobDev& J = B.jobs[job];
+  if (J.n <= 0) return;
+  double a = 0.0, sm = 0.0;
+  uint32_t mx = 0u;
+  const int64_t t1 = (J.off + J.n + kTile - 1) / kTile;
+  for (int64_t t = J.off / kTile + threadIdx.x; t < t1; t += kStatsThreads) a = fmax(a, B.TACC[t]);
+  if (with_lists) {
+    const int64_t g1 = (J.off + J.n + kNlistBlock - 1) / kNlistBlock;
+    for (int64_t g = J.off / kNlistBlock + threadIdx.x; g < g1; g += kStatsThreads) {
+      mx = max(mx, B.NLSTAT[2 * g]);
+      sm += (double)B.NLSTAT[2 * g + 1];
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    a = fmax(a, __shfl_xor(a, o, 64));
+    sm += __shfl_xor(sm, o, 64);
+    mx = max(mx, (uint32_t)__shfl_xor((int)mx, o, 64));
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) ra[w] = a, rs[w] = sm, rm[w] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 1; q < kStatsThreads / 64; ++q) a = fmax(a, ra[q]), sm += rs[q], mx = max(mx, rm[q]);
+    JobBook& K = B.book[job];
+    K.a_now = a;
+    if (with_lists) {
+      K.nl_max = (int)mx;
+      K.nl_sum = sm;
+    }
+  }
+}
+
+// Dynamic LDS of k_nlist for a list capacity kmax.
+constexpr size_t nlist_lds_bytes(int kmax) { return (size_t)kmax * kNlistBlock * sizeof(uint32_t); }
 
 // ---------------------------------------------------------------------------
 // Segmented exclusive scan, three passes, staged in LDS.
