@@ -85,6 +85,7 @@ struct DevBufs {
   uint32_t* RANK;      // rank within the cell per slot
   uint32_t* INV;       // slot of each particle index after the last sort, by job offset + index
   uint32_t* SRC;       // old slot (job-relative) of each new slot during a sort
+  float4* PK;          // list-build candidates in the sorted order: FP32 position, particle index bits
   double* TACC;        // per tile (slot / kTile): accumulated max displacement since the last build
   uint32_t* NLSTAT;    // per group of 64 slots, from the last list build: (max count, sum of stored counts)
   JobDev* jobs;

@@ -172,7 +172,8 @@ int validate_params(const md_params& p) {
 
 // Bytes of device state per particle slot (excluding the neighbour list).
 constexpr int64_t kSlotBytes = 2 * 24 /*X*/ + 2 * 24 /*P*/ + 2 * 4 /*ID*/ + 2 * 1 /*FLG*/ + 2 * 8 /*MASS*/ +
-                               24 /*FC*/ + 3 * 24 /*OX,OP,OF*/ + 32 /*OD*/ + 4 /*NCNT*/ + 4 * 7 /*rebuild*/;
+                               24 /*FC*/ + 3 * 24 /*OX,OP,OF*/ + 32 /*OD*/ + 4 /*NCNT*/ + 4 * 7 /*rebuild*/ +
+                               16 /*PK*/;
 
 struct HostJob {
   bool used = false;
@@ -357,7 +358,7 @@ struct Engine {
       if (e) (void)hipEventDestroy(e), e = nullptr;
     void* ptrs[] = {B.X[0], B.X[1], B.P[0], B.P[1], B.ID[0], B.ID[1], B.FLG[0], B.FLG[1], B.MASS[0], B.MASS[1],
                     B.FC, B.OX, B.OP, B.OF, B.OD, B.NL, B.NCNT, B.BM, B.WOFF, B.CCNT, B.CSTART, B.RASTER,
-                    B.CID, B.RANK, B.INV, B.SRC, B.TACC, B.NLSTAT, B.jobs, B.book, step_tiles_job, step_tiles_first, step_counts, aux_tiles_job,
+                    B.CID, B.RANK, B.INV, B.SRC, B.PK, B.TACC, B.NLSTAT, B.jobs, B.book, step_tiles_job, step_tiles_first, step_counts, aux_tiles_job,
                     aux_tiles_first, chunks_d, chunk_sums, ranges_d};
     for (void* p : ptrs)
       if (p) (void)hipFree(p);
@@ -437,6 +438,7 @@ struct Engine {
     MDCHK(dalloc(&B.RANK, C));
     MDCHK(dalloc(&B.INV, C));
     MDCHK(dalloc(&B.SRC, C));
+    MDCHK(dalloc(&B.PK, C));
     MDCHK(dalloc(&B.TACC, C / kTile + 1));
     HIPCHK(hipMemsetAsync(B.TACC, 0, sizeof(double) * (C / kTile + 1), stream));
     MDCHK(dalloc(&B.jobs, max_jobs));

@@ -424,9 +424,11 @@ __global__ void __launch_bounds__(kTile) k_gather(DevBufs B, const int* __restri
     Xd[3 * d + k] = Xs[3 * i + k];
     Pd[3 * d + k] = Ps[3 * i + k];
   }
-  B.ID[J.scur ^ 1][d] = B.ID[J.scur][i];
+  const uint32_t id = B.ID[J.scur][i];
+  B.ID[J.scur ^ 1][d] = id;
   B.FLG[J.scur ^ 1][d] = B.FLG[J.scur][i];
   if (!J.uniform_mass) B.MASS[J.scur ^ 1][d] = B.MASS[J.scur][i];
+  B.PK[d] = make_float4((float)Xs[3 * i], (float)Xs[3 * i + 1], (float)Xs[3 * i + 2], __uint_as_float(id));
 }
 
 // Occupied cells with raster index below r, for the compact cell index.
@@ -507,33 +509,53 @@ __device__ __forceinline__ void z_runs(const JobDev& J, int cz, int& za0, int& z
 }
 
 // One lane walks its own 27-cell stencil: 9 contiguous z-runs of slots, the next
-// column's lookups in flight while the current one is scanned.
-__device__ __forceinline__ void nlist_lane(const DevBufs& B, const JobDev& J, const double* __restrict__ X,
-                                           const uint32_t* __restrict__ ID, int64_t i, double xi, double yi,
+// column's lookups in flight while the current one is scanned.  Candidates are
+// read from the packed FP32 records (one 16-byte load each), kListBatch at a
+// time; the last batch of a run is padded with repeats of its last record.
+// The FP32 distance test uses the list radius widened by a bound on the FP32
+// rounding of both positions and of the separation (times eight), so it accepts
+// every pair closer than the list radius; the few extra pairs it may accept lie
+// beyond the cut-off and add nothing to the forces.
+#ifndef MDK_LIST_BATCH
+#define MDK_LIST_BATCH 4
+#endif
+constexpr int kListBatch = MDK_LIST_BATCH;
+
+__device__ __forceinline__ void min_image_f(const JobDev& J, float& dx, float& dy, float& dz) {
+  if (J.periodic[0]) dx -= (float)J.box_len[0] * rintf(dx * (float)J.inv_box_len[0]);
+  if (J.periodic[1]) dy -= (float)J.box_len[1] * rintf(dy * (float)J.inv_box_len[1]);
+  if (J.periodic[2]) dz -= (float)J.box_len[2] * rintf(dz * (float)J.inv_box_len[2]);
+}
+
+__device__ __forceinline__ void nlist_lane(const DevBufs& B, const JobDev& J, int64_t i, double xi, double yi,
                                            double zi, int cx, int cy, int cz, uint32_t* kid, int lane, int kmax,
                                            int& cnt) {
   int za0, zb0, za1, zb1;
   z_runs(J, cz, za0, zb0, za1, zb1);
   const int64_t base = J.off;
   const bool anyper = J.periodic[0] | J.periodic[1] | J.periodic[2];
-  auto consider = [&](int64_t j, double ax, double ay, double az) {
-    if (j == i) return;
-    double dx = xi - ax, dy = yi - ay, dz = zi - az;
-    if (anyper) min_image(J, dx, dy, dz);
-    if (dx * dx + dy * dy + dz * dz >= J.rlist2) return;
-    list_insert(kid, lane, kmax, cnt, ID[j]);
-  };
+  const float4* __restrict__ PK = B.PK;
+  double lper = 0.0;
+  for (int k = 0; k < 3; ++k)
+    if (J.periodic[k]) lper = fmax(lper, J.box_len[k]);
+  const double rl = sqrt(J.rlist2);
+  const double delta = 0x1p-21 * (2.0 * fmax(fabs(xi), fmax(fabs(yi), fabs(zi))) + 3.0 * rl + lper);
+  const float thr = (float)((rl + delta) * (rl + delta) * (1.0 + 0x1p-20));
+  const float xf = (float)xi, yf = (float)yi, zf = (float)zi;
   auto scan = [&](uint32_t b, uint32_t e) {
-    int64_t j = base + b;
     const int64_t end = base + e;
-    for (; j + 4 <= end; j += 4) {
-      double a[12];
+    for (int64_t j = base + b; j < end; j += kListBatch) {
+      float4 r[kListBatch];
 #pragma unroll
-      for (int u = 0; u < 12; ++u) a[u] = X[3 * j + u];
+      for (int u = 0; u < kListBatch; ++u) r[u] = PK[j + u < end ? j + u : end - 1];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) consider(j + u, a[3 * u], a[3 * u + 1], a[3 * u + 2]);
+      for (int u = 0; u < kListBatch; ++u) {
+        float dx = xf - r[u].x, dy = yf - r[u].y, dz = zf - r[u].z;
+        if (anyper) min_image_f(J, dx, dy, dz);
+        const float d2 = dx * dx + dy * dy + dz * dz;
+        if (j + u < end && j + u != i && d2 < thr) list_insert(kid, lane, kmax, cnt, __float_as_uint(r[u].w));
+      }
     }
-    for (; j < end; ++j) consider(j, X[3 * j], X[3 * j + 1], X[3 * j + 2]);
   };
   ColumnRange cur = column_range(B, J, cx, cy, 0, za0, zb0, za1, zb1);
   for (int col = 0; col < 9; ++col) {
@@ -562,13 +584,21 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const int* __r
   int cnt = 0;
   if (i < J.off + J.n) {
     const double* __restrict__ X = B.X[J.xcur ^ 1];  // the sorted copies written by k_gather
-    const uint32_t* __restrict__ ID = B.ID[J.scur ^ 1];
     const double xi = X[3 * i], yi = X[3 * i + 1], zi = X[3 * i + 2];
     const int cx = cell_coord(J, 0, xi), cy = cell_coord(J, 1, yi), cz = cell_coord(J, 2, zi);
-    nlist_lane(B, J, X, ID, i, xi, yi, zi, cx, cy, cz, kid, lane, kmax, cnt);
+    nlist_lane(B, J, i, xi, yi, zi, cx, cy, cz, kid, lane, kmax, cnt);
     const int stored = cnt < kmax ? cnt : kmax;
     const int64_t C = B.C;
-    for (int k = 0; k < stored; ++k) B.NL[(int64_t)k * C + i] = (uint32_t)base + B.INV[base + kid[k * kNlistBlock + lane]];
+    // particle indices back to slots, four lookups in flight at a time
+    int k = 0;
+    for (; k + 4 <= stored; k += 4) {
+      uint32_t v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = B.INV[base + kid[(k + u) * kNlistBlock + lane]];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) B.NL[(int64_t)(k + u) * C + i] = (uint32_t)base + v[u];
+    }
+    for (; k < stored; ++k) B.NL[(int64_t)k * C + i] = (uint32_t)base + B.INV[base + kid[k * kNlistBlock + lane]];
     B.NCNT[i] = (uint32_t)stored;
   }
   // list statistics of these 64 slots (no atomics); an overflow stops the job
