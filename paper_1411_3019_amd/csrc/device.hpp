@@ -317,11 +317,20 @@ __device__ __forceinline__ real pair_coef(const JobDev& J, double r2, real eps24
   return coef;
 }
 
-// Pair forces on slot i from its neighbour list, summed in list order (the
-// list is sorted by particle index).  FP32 variant: separations and the
-// cut-off test in FP64, the force in FP32 with FP32 accumulation.  The loop
-// issues the gathers of kForceBatch neighbours before using them; the additions
-// still happen one neighbour at a time in list order.  Specialised on the
+// Rounds t to a multiple of 2^-32 (for |t| < 2^19).  Sums of such values are
+// exact in FP64 while their magnitude stays below 2^21, so they do not depend
+// on the order of the terms.
+__device__ __forceinline__ double on_grid(double t) {
+  constexpr double kM = 0x1.8p20;  // 1.5 * 2^20: t + kM has an ulp of 2^-32
+  return (t + kM) - kM;
+}
+
+// Pair forces on slot i from its neighbour list.  FP64 class: FP64 terms
+// summed in list order, the list being sorted by particle index.  FP32 class:
+// separations and the cut-off test in FP64, the term in FP32, rounded onto the
+// 2^-32 grid and summed in FP64, which makes the sum exact and independent of
+// the list order (the lists of this class are in slot order).  The loop issues
+// the gathers of kForceBatch neighbours before using them.  Specialised on the
 // potential's form and on periodicity so the loop carries no dead work.
 #ifndef MDK_FORCE_BATCH
 #define MDK_FORCE_BATCH 4
@@ -336,10 +345,24 @@ __device__ __forceinline__ void pair_forces_impl(const JobDev& J, const DevBufs&
   const int64_t C = B.C;
   const int cnt = (int)B.NCNT[i];
   const uint32_t* __restrict__ nl = B.NL + i;
-  real fx = 0, fy = 0, fz = 0;
+  double fx = 0.0, fy = 0.0, fz = 0.0;
   const real eps24 = (real)(24.0 * J.eps);
   const real sig2 = (real)J.sig2;
   const real dphic = (real)J.dphic;
+  auto add = [&](double dx, double dy, double dz) {
+    if (kPer) min_image(J, dx, dy, dz);
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    const real c = pair_coef<real, kSmooth>(J, r2, eps24, sig2, dphic);
+    if (kF64) {
+      fx += c * dx;
+      fy += c * dy;
+      fz += c * dz;
+    } else {
+      fx += on_grid((double)(c * (real)dx));
+      fy += on_grid((double)(c * (real)dy));
+      fz += on_grid((double)(c * (real)dz));
+    }
+  };
   int k = 0;
   for (; k + kForceBatch <= cnt; k += kForceBatch) {
     int64_t j[kForceBatch];
@@ -353,29 +376,15 @@ __device__ __forceinline__ void pair_forces_impl(const JobDev& J, const DevBufs&
       az[u] = X[3 * j[u] + 2];
     }
 #pragma unroll
-    for (int u = 0; u < kForceBatch; ++u) {
-      double dx = xi - ax[u], dy = yi - ay[u], dz = zi - az[u];
-      if (kPer) min_image(J, dx, dy, dz);
-      const double r2 = dx * dx + dy * dy + dz * dz;
-      const real c = pair_coef<real, kSmooth>(J, r2, eps24, sig2, dphic);
-      fx += c * (real)dx;
-      fy += c * (real)dy;
-      fz += c * (real)dz;
-    }
+    for (int u = 0; u < kForceBatch; ++u) add(xi - ax[u], yi - ay[u], zi - az[u]);
   }
   for (; k < cnt; ++k) {
     const int64_t j = nl[(int64_t)k * C];
-    double dx = xi - X[3 * j], dy = yi - X[3 * j + 1], dz = zi - X[3 * j + 2];
-    if (kPer) min_image(J, dx, dy, dz);
-    const double r2 = dx * dx + dy * dy + dz * dz;
-    const real c = pair_coef<real, kSmooth>(J, r2, eps24, sig2, dphic);
-    fx += c * (real)dx;
-    fy += c * (real)dy;
-    fz += c * (real)dz;
+    add(xi - X[3 * j], yi - X[3 * j + 1], zi - X[3 * j + 2]);
   }
-  Fx = (double)fx;
-  Fy = (double)fy;
-  Fz = (double)fz;
+  Fx = fx;
+  Fy = fy;
+  Fz = fz;
 }
 
 template <bool kF64>
@@ -397,7 +406,8 @@ __device__ __forceinline__ void pair_forces(const JobDev& J, const DevBufs& B, c
   }
 }
 
-// Energy share U_i = 1/2 sum_j V_ij (Eq. S1), FP64, for diagnostics.
+// Energy share U_i = 1/2 sum_j V_ij (Eq. S1), FP64, for diagnostics; for the
+// FP32 class the terms go on the exact-sum grid like the forces.
 __device__ __forceinline__ double pair_energy(const JobDev& J, const DevBufs& B, const double* __restrict__ X,
                                               int64_t i, double xi, double yi, double zi) {
   const int64_t C = B.C;
@@ -416,7 +426,8 @@ __device__ __forceinline__ double pair_energy(const JobDev& J, const DevBufs& B,
     const double s6 = s2 * s2 * s2;
     double v = 4.0 * J.eps * s6 * (s6 - 1.0) - J.phic;
     if (smooth) v -= (sqrt(r2) - rc) * J.dphic;
-    u += 0.5 * v;
+    // FP32 class: lists in slot order, terms on the exact-sum grid
+    u += J.force_fp64 ? 0.5 * v : on_grid(0.5 * v);
   }
   return u;
 }

@@ -488,6 +488,13 @@ __device__ __forceinline__ void list_insert(uint32_t* kid, int lane, int kmax, i
   ++cnt;
 }
 
+// Append slot q to this lane's list in LDS (lists of the FP32 class stay in
+// the order the stencil walk finds them, which is slot order).
+__device__ __forceinline__ void list_append(uint32_t* kid, int lane, int kmax, int& cnt, uint32_t q) {
+  if (cnt < kmax) kid[cnt * kNlistBlock + lane] = q;
+  ++cnt;
+}
+
 // z cells of the stencil around cz: [za0, zb0] and, when z wraps, [za1, zb1].
 __device__ __forceinline__ void z_runs(const JobDev& J, int cz, int& za0, int& zb0, int& za1, int& zb1) {
   const int ncz = J.nc[2];
@@ -527,6 +534,7 @@ __device__ __forceinline__ void min_image_f(const JobDev& J, float& dx, float& d
   if (J.periodic[2]) dz -= (float)J.box_len[2] * rintf(dz * (float)J.inv_box_len[2]);
 }
 
+template <bool kSorted>
 __device__ __forceinline__ void nlist_lane(const DevBufs& B, const JobDev& J, int64_t i, double xi, double yi,
                                            double zi, int cx, int cy, int cz, uint32_t* kid, int lane, int kmax,
                                            int& cnt) {
@@ -553,7 +561,12 @@ __device__ __forceinline__ void nlist_lane(const DevBufs& B, const JobDev& J, in
         float dx = xf - r[u].x, dy = yf - r[u].y, dz = zf - r[u].z;
         if (anyper) min_image_f(J, dx, dy, dz);
         const float d2 = dx * dx + dy * dy + dz * dz;
-        if (j + u < end && j + u != i && d2 < thr) list_insert(kid, lane, kmax, cnt, __float_as_uint(r[u].w));
+        if (j + u < end && j + u != i && d2 < thr) {
+          if (kSorted)
+            list_insert(kid, lane, kmax, cnt, __float_as_uint(r[u].w));
+          else
+            list_append(kid, lane, kmax, cnt, (uint32_t)(j + u - base));
+        }
       }
     }
   };
@@ -568,9 +581,12 @@ __device__ __forceinline__ void nlist_lane(const DevBufs& B, const JobDev& J, in
 }
 
 // Neighbour-list build, one lane per slot of the freshly sorted (raster cell)
-// order, one wavefront per workgroup.  Each lane walks its own stencil; the
-// list is kept sorted by particle index in LDS and mapped back to slots through
-// the inverse permutation of the sort.
+// order, one wavefront per workgroup.  Each lane walks its own stencil and
+// stages its list in LDS.  FP64 class: kept sorted by particle index and mapped
+// back to slots through the inverse permutation of the sort, so that the FP64
+// force sums run in particle-index order.  FP32 class: slots in the order the
+// walk finds them (ascending), since its force sums do not depend on the order;
+// neighbouring lanes then read neighbouring memory in the force loop.
 __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const int* __restrict__ tile_job,
                                                        const int64_t* __restrict__ tile_first) {
   extern __shared__ uint32_t kid[];  // sorted lists [kmax][64]
@@ -586,19 +602,28 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const int* __r
     const double* __restrict__ X = B.X[J.xcur ^ 1];  // the sorted copies written by k_gather
     const double xi = X[3 * i], yi = X[3 * i + 1], zi = X[3 * i + 2];
     const int cx = cell_coord(J, 0, xi), cy = cell_coord(J, 1, yi), cz = cell_coord(J, 2, zi);
-    nlist_lane(B, J, i, xi, yi, zi, cx, cy, cz, kid, lane, kmax, cnt);
-    const int stored = cnt < kmax ? cnt : kmax;
     const int64_t C = B.C;
-    // particle indices back to slots, four lookups in flight at a time
-    int k = 0;
-    for (; k + 4 <= stored; k += 4) {
-      uint32_t v[4];
+    int stored;
+    if (J.force_fp64) {
+      // FP64 class: sorted by particle index, mapped back to slots through the
+      // inverse permutation, four lookups in flight at a time
+      nlist_lane<true>(B, J, i, xi, yi, zi, cx, cy, cz, kid, lane, kmax, cnt);
+      stored = cnt < kmax ? cnt : kmax;
+      int k = 0;
+      for (; k + 4 <= stored; k += 4) {
+        uint32_t v[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) v[u] = B.INV[base + kid[(k + u) * kNlistBlock + lane]];
+        for (int u = 0; u < 4; ++u) v[u] = B.INV[base + kid[(k + u) * kNlistBlock + lane]];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) B.NL[(int64_t)(k + u) * C + i] = (uint32_t)base + v[u];
+        for (int u = 0; u < 4; ++u) B.NL[(int64_t)(k + u) * C + i] = (uint32_t)base + v[u];
+      }
+      for (; k < stored; ++k) B.NL[(int64_t)k * C + i] = (uint32_t)base + B.INV[base + kid[k * kNlistBlock + lane]];
+    } else {
+      // FP32 class: slot order, as found
+      nlist_lane<false>(B, J, i, xi, yi, zi, cx, cy, cz, kid, lane, kmax, cnt);
+      stored = cnt < kmax ? cnt : kmax;
+      for (int k = 0; k < stored; ++k) B.NL[(int64_t)k * C + i] = (uint32_t)base + kid[k * kNlistBlock + lane];
     }
-    for (; k < stored; ++k) B.NL[(int64_t)k * C + i] = (uint32_t)base + B.INV[base + kid[k * kNlistBlock + lane]];
     B.NCNT[i] = (uint32_t)stored;
   }
   // list statistics of these 64 slots (no atomics); an overflow stops the job

@@ -97,13 +97,15 @@ def test_sphere_1000_steps():
     assert st["diag"]["newton_iter_max"] <= 4
 
 
-def test_deterministic_rerun_and_schedule_independence():
+@pytest.mark.parametrize("force_fp64", [0, 1])
+def test_deterministic_rerun_and_schedule_independence(force_fp64):
     """Bitwise: the same run twice; and a different skin (so different rebuild
-    steps and list contents) gives the same bits, because neighbours are summed
-    in particle-index order."""
+    steps, slot orders and list contents) gives the same bits.  FP64 class: the
+    lists are sorted by particle index; FP32 class: the pair terms are summed
+    exactly, so the order of the slot-ordered lists does not matter."""
     s = gen.torus(4000, 30.0, 10.0, 12)
-    kw = dict(dt=0.002, rc=2.5, seed=3, force_fp64=0)
-    print("[gpu] determinism torus 4000", flush=True)
+    kw = dict(dt=0.002, rc=2.5, seed=3, force_fp64=force_fp64)
+    print(f"[gpu] determinism torus 4000 force_fp64={force_fp64}", flush=True)
     outs = []
     for skin in (0.3, 0.3, 0.7):
         g = gpu_system(s, skin=skin, **kw)
