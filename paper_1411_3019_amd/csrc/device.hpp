@@ -18,6 +18,8 @@ namespace mdk {
 constexpr int kTile = 256;          // particles per workgroup in per-particle kernels
 constexpr int kNlistBlock = 64;     // one wavefront per workgroup in the list build
 constexpr int kNlistPerTile = kTile / kNlistBlock;
+constexpr int kStepBlock = 64;      // step kernel: one wavefront per workgroup
+constexpr int kStepPerTile = kTile / kStepBlock;
 
 enum : int { kSurfNone = 0, kSurfPlane = 1, kSurfSphere = 2, kSurfEllipsoid = 3, kSurfTorus = 4,
              kSurfCylinder = 5, kSurfHeight = 6 };
@@ -86,7 +88,7 @@ struct DevBufs {
   uint32_t* INV;       // slot of each particle index after the last sort, by job offset + index
   uint32_t* SRC;       // old slot (job-relative) of each new slot during a sort
   float4* PK;          // list-build candidates in the sorted order: FP32 position, particle index bits
-  double* TACC;        // per tile (slot / kTile): accumulated max displacement since the last build
+  double* TACC;        // per group of 64 slots: accumulated max displacement since the last build
   uint32_t* NLSTAT;    // per group of 64 slots, from the last list build: (max count, sum of stored counts)
   JobDev* jobs;
   JobBook* book;

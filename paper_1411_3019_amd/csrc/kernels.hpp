@@ -97,20 +97,22 @@ __device__ __forceinline__ void combined_force(const JobDev& J, const DevBufs& B
   }
 }
 
+// One wavefront per workgroup, kStepPerTile workgroups per tile: wavefronts
+// share no barrier, so each leaves as soon as its own particles are done.
 template <bool kF64>
 __device__ __forceinline__ void step_body(const DevBufs& B, const int* __restrict__ tile_job,
                                           const int64_t* __restrict__ tile_first, const int* __restrict__ ntiles_ptr,
-                                          int t, double* red, int* redi) {
-  // the grid may be larger than the tile list (it is sized once per graph);
+                                          int t) {
+  // the grid may be larger than the group list (it is sized once per graph);
   // surplus workgroups leave at once
-  const int ntiles = uniform_int(*ntiles_ptr);
-  if ((int)blockIdx.x >= ntiles) return;
-  const int b = xcd_remap((int)blockIdx.x, ntiles);
-  const int job = uniform_int(tile_job[b]);
-  const int64_t first = uniform_i64(tile_first[b]);
+  const int ngroups = uniform_int(*ntiles_ptr) * kStepPerTile;
+  if ((int)blockIdx.x >= ngroups) return;
+  const int v = xcd_remap((int)blockIdx.x, ngroups);
+  const int job = uniform_int(tile_job[v / kStepPerTile]);
+  const int64_t first = uniform_i64(tile_first[v / kStepPerTile]) + (v % kStepPerTile) * kStepBlock;
   const JobDev& J = B.jobs[job];
   JobBook& K = B.book[job];
-  if (t >= J.remaining) return;
+  if (t >= J.remaining || first >= J.off + J.n) return;
   const long long s = J.step0 + t;
   // a tile whose accumulated displacement passed skin/2 during step s-1 (or an
   // error) set stop_at <= s: the lists are no longer valid for forces at x^s
@@ -184,14 +186,18 @@ __device__ __forceinline__ void step_body(const DevBufs& B, const int* __restric
       disp2 = 0.0;
     }
   }
-  // per-tile bound on the displacement since the last build: sum over steps of
-  // the tile's largest displacement; only this workgroup touches its tile
-  const double m2 = block_max(disp2, red);
-  const int im = block_max_int(iters, redi);
+  // per-group bound on the displacement since the last build: sum over steps of
+  // the group's largest displacement; only this wavefront touches its entry
+  double m2 = disp2;
+  int im = iters;
+  for (int o = 32; o > 0; o >>= 1) {
+    m2 = fmax(m2, __shfl_xor(m2, o, 64));
+    im = max(im, __shfl_xor(im, o, 64));
+  }
   if (threadIdx.x == 0) {
-    const int64_t tile = first / kTile;
-    const double a = B.TACC[tile] + sqrt(m2);
-    B.TACC[tile] = a;
+    const int64_t g = first / kStepBlock;
+    const double a = B.TACC[g] + sqrt(m2);
+    B.TACC[g] = a;
     if (a > J.half_skin) atomicMin(&K.stop_at, s + 1);
     if (im > K.newton_max) atomicMax(&K.newton_max, im);
   }
@@ -203,21 +209,17 @@ __device__ __forceinline__ void step_body(const DevBufs& B, const int* __restric
 
 // FP32 pair forces (and FP32 Box-Muller): occupancy target MDK_STEP32_WAVES
 // wavefronts per SIMD.
-__global__ void __launch_bounds__(kTile) __attribute__((amdgpu_waves_per_eu(MDK_STEP32_WAVES, 8)))
+__global__ void __launch_bounds__(kStepBlock) __attribute__((amdgpu_waves_per_eu(MDK_STEP32_WAVES, 8)))
 k_step_f32(DevBufs B, const int* __restrict__ tile_job, const int64_t* __restrict__ tile_first,
            const int* __restrict__ ntiles_ptr, int t) {
-  __shared__ double red[kTile / 64];
-  __shared__ int redi[kTile / 64];
-  step_body<false>(B, tile_job, tile_first, ntiles_ptr, t, red, redi);
+  step_body<false>(B, tile_job, tile_first, ntiles_ptr, t);
 }
 
 // FP64 pair forces and FP64 Box-Muller.
-__global__ void __launch_bounds__(kTile) k_step_f64(DevBufs B, const int* __restrict__ tile_job,
-                                                    const int64_t* __restrict__ tile_first,
-                                                    const int* __restrict__ ntiles_ptr, int t) {
-  __shared__ double red[kTile / 64];
-  __shared__ int redi[kTile / 64];
-  step_body<true>(B, tile_job, tile_first, ntiles_ptr, t, red, redi);
+__global__ void __launch_bounds__(kStepBlock) k_step_f64(DevBufs B, const int* __restrict__ tile_job,
+                                                         const int64_t* __restrict__ tile_first,
+                                                         const int* __restrict__ ntiles_ptr, int t) {
+  step_body<true>(B, tile_job, tile_first, ntiles_ptr, t);
 }
 
 // Finish: state at the current step m (x^m, p^m, f^m) and per-particle
@@ -653,8 +655,8 @@ __global__ void __launch_bounds__(kStatsThreads) k_job_stats(DevBufs B, int with
   if (J.n <= 0) return;
   double a = 0.0, sm = 0.0;
   uint32_t mx = 0u;
-  const int64_t t1 = (J.off + J.n + kTile - 1) / kTile;
-  for (int64_t t = J.off / kTile + threadIdx.x; t < t1; t += kStatsThreads) a = fmax(a, B.TACC[t]);
+  const int64_t t1 = (J.off + J.n + kStepBlock - 1) / kStepBlock;
+  for (int64_t t = J.off / kStepBlock + threadIdx.x; t < t1; t += kStatsThreads) a = fmax(a, B.TACC[t]);
   if (with_lists) {
     const int64_t g1 = (J.off + J.n + kNlistBlock - 1) / kNlistBlock;
     for (int64_t g = J.off / kNlistBlock + threadIdx.x; g < g1; g += kStatsThreads) {
