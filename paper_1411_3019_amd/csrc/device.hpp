@@ -15,11 +15,10 @@
 
 namespace mdk {
 
+constexpr int kGroup = 64;          // slots per wavefront; per displacement accumulator and list statistic
 constexpr int kTile = 256;          // particles per workgroup in per-particle kernels
-constexpr int kNlistBlock = 64;     // one wavefront per workgroup in the list build
+constexpr int kNlistBlock = kTile;  // threads per workgroup in the list build
 constexpr int kNlistPerTile = kTile / kNlistBlock;
-constexpr int kStepBlock = 64;      // step kernel: one wavefront per workgroup
-constexpr int kStepPerTile = kTile / kStepBlock;
 
 enum : int { kSurfNone = 0, kSurfPlane = 1, kSurfSphere = 2, kSurfEllipsoid = 3, kSurfTorus = 4,
              kSurfCylinder = 5, kSurfHeight = 6 };

@@ -439,8 +439,8 @@ struct Engine {
     MDCHK(dalloc(&B.INV, C));
     MDCHK(dalloc(&B.SRC, C));
     MDCHK(dalloc(&B.PK, C));
-    MDCHK(dalloc(&B.TACC, C / kStepBlock + 1));
-    HIPCHK(hipMemsetAsync(B.TACC, 0, sizeof(double) * (C / kStepBlock + 1), stream));
+    MDCHK(dalloc(&B.TACC, C / kGroup + 1));
+    HIPCHK(hipMemsetAsync(B.TACC, 0, sizeof(double) * (C / kGroup + 1), stream));
     MDCHK(dalloc(&B.jobs, max_jobs));
     MDCHK(dalloc(&B.book, max_jobs));
     {
@@ -449,8 +449,8 @@ struct Engine {
     }
     HIPCHK(hipMemsetAsync(B.NCNT, 0, sizeof(uint32_t) * C, stream));
     tile_cap = C / kTile + max_jobs + 8;
-    MDCHK(dalloc(&B.NLSTAT, 2 * (C / kNlistBlock + 1)));
-    HIPCHK(hipMemsetAsync(B.NLSTAT, 0, sizeof(uint32_t) * 2 * (C / kNlistBlock + 1), stream));
+    MDCHK(dalloc(&B.NLSTAT, 2 * (C / kGroup + 1)));
+    HIPCHK(hipMemsetAsync(B.NLSTAT, 0, sizeof(uint32_t) * 2 * (C / kGroup + 1), stream));
     MDCHK(dalloc(&step_tiles_job, 2 * tile_cap));
     MDCHK(dalloc(&step_tiles_first, 2 * tile_cap));
     MDCHK(dalloc(&step_counts, 2));
@@ -756,7 +756,7 @@ struct Engine {
       tiles_of(h, j, tj, tf);
       rb.push_back({h.bm_off, h.bm_words});
       rcnt.push_back({h.off, h.n + 1});
-      rtacc.push_back({2 * (h.off / kStepBlock), 2 * ((h.n + kStepBlock - 1) / kStepBlock)});  // doubles as word pairs
+      rtacc.push_back({2 * (h.off / kGroup), 2 * ((h.n + kGroup - 1) / kGroup)});  // doubles as word pairs
       int first = (int)cb.size();
       for (int64_t s = 0; s < h.bm_words; s += kScanChunk)
         cb.push_back({h.bm_off + s, (int)std::min<int64_t>(kScanChunk, h.bm_words - s), first});
@@ -915,9 +915,6 @@ struct Engine {
       last_tf[c].swap(tf[c]);
     }
     MDCHK(upload(step_counts, counts, sizeof(counts)));
-    // one step workgroup per kStepBlock slots of each tile
-    counts[0] *= kStepPerTile;
-    counts[1] *= kStepPerTile;
     const int want64 = grid_for(counts[0]), want32 = grid_for(counts[1]);
     auto fits = [](int grid, int count, int want) {
       if (count == 0) return grid == 0;
@@ -934,10 +931,10 @@ struct Engine {
   void enqueue_steps(int t0, int k) {
     for (int t = t0; t < t0 + k; ++t) {
       if (grid64 > 0)
-        hipLaunchKernelGGL(k_step_f64, dim3(grid64), dim3(kStepBlock), 0, stream, B, step_tiles_job, step_tiles_first,
+        hipLaunchKernelGGL(k_step_f64, dim3(grid64), dim3(kTile), 0, stream, B, step_tiles_job, step_tiles_first,
                            step_counts, t);
       if (grid32 > 0)
-        hipLaunchKernelGGL(k_step_f32, dim3(grid32), dim3(kStepBlock), 0, stream, B, step_tiles_job + tile_cap,
+        hipLaunchKernelGGL(k_step_f32, dim3(grid32), dim3(kTile), 0, stream, B, step_tiles_job + tile_cap,
                            step_tiles_first + tile_cap, step_counts + 1, t);
     }
   }

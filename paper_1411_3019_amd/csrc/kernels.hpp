@@ -97,19 +97,21 @@ __device__ __forceinline__ void combined_force(const JobDev& J, const DevBufs& B
   }
 }
 
-// One wavefront per workgroup, kStepPerTile workgroups per tile: wavefronts
-// share no barrier, so each leaves as soon as its own particles are done.
+// One workgroup per tile; each wavefront works on its own 64 slots of the
+// tile and shares no barrier with the others, so it leaves as soon as its own
+// particles are done.  (Workgroups of one wavefront would be capped by the
+// per-CU workgroup limit well below the register-bound occupancy.)
 template <bool kF64>
 __device__ __forceinline__ void step_body(const DevBufs& B, const int* __restrict__ tile_job,
                                           const int64_t* __restrict__ tile_first, const int* __restrict__ ntiles_ptr,
                                           int t) {
-  // the grid may be larger than the group list (it is sized once per graph);
+  // the grid may be larger than the tile list (it is sized once per graph);
   // surplus workgroups leave at once
-  const int ngroups = uniform_int(*ntiles_ptr) * kStepPerTile;
-  if ((int)blockIdx.x >= ngroups) return;
-  const int v = xcd_remap((int)blockIdx.x, ngroups);
-  const int job = uniform_int(tile_job[v / kStepPerTile]);
-  const int64_t first = uniform_i64(tile_first[v / kStepPerTile]) + (v % kStepPerTile) * kStepBlock;
+  const int ntiles = uniform_int(*ntiles_ptr);
+  if ((int)blockIdx.x >= ntiles) return;
+  const int b = xcd_remap((int)blockIdx.x, ntiles);
+  const int job = uniform_int(tile_job[b]);
+  const int64_t first = uniform_i64(tile_first[b]) + (int64_t)uniform_int((int)threadIdx.x / kGroup) * kGroup;
   const JobDev& J = B.jobs[job];
   JobBook& K = B.book[job];
   if (t >= J.remaining || first >= J.off + J.n) return;
@@ -123,7 +125,7 @@ __device__ __forceinline__ void step_body(const DevBufs& B, const int* __restric
   double* __restrict__ Xo = B.X[xin ^ 1];
   double* __restrict__ P = B.P[J.pcur];
   const int64_t C = B.C;
-  const int64_t i = first + threadIdx.x;
+  const int64_t i = first + (threadIdx.x % kGroup);
   double disp2 = 0.0;
   int iters = 0;
   if (i < J.off + J.n) {
@@ -194,8 +196,8 @@ __device__ __forceinline__ void step_body(const DevBufs& B, const int* __restric
     m2 = fmax(m2, __shfl_xor(m2, o, 64));
     im = max(im, __shfl_xor(im, o, 64));
   }
-  if (threadIdx.x == 0) {
-    const int64_t g = first / kStepBlock;
+  if (threadIdx.x % kGroup == 0) {
+    const int64_t g = first / kGroup;
     const double a = B.TACC[g] + sqrt(m2);
     B.TACC[g] = a;
     if (a > J.half_skin) atomicMin(&K.stop_at, s + 1);
@@ -209,16 +211,16 @@ __device__ __forceinline__ void step_body(const DevBufs& B, const int* __restric
 
 // FP32 pair forces (and FP32 Box-Muller): occupancy target MDK_STEP32_WAVES
 // wavefronts per SIMD.
-__global__ void __launch_bounds__(kStepBlock) __attribute__((amdgpu_waves_per_eu(MDK_STEP32_WAVES, 8)))
+__global__ void __launch_bounds__(kTile) __attribute__((amdgpu_waves_per_eu(MDK_STEP32_WAVES, 8)))
 k_step_f32(DevBufs B, const int* __restrict__ tile_job, const int64_t* __restrict__ tile_first,
            const int* __restrict__ ntiles_ptr, int t) {
   step_body<false>(B, tile_job, tile_first, ntiles_ptr, t);
 }
 
 // FP64 pair forces and FP64 Box-Muller.
-__global__ void __launch_bounds__(kStepBlock) k_step_f64(DevBufs B, const int* __restrict__ tile_job,
-                                                         const int64_t* __restrict__ tile_first,
-                                                         const int* __restrict__ ntiles_ptr, int t) {
+__global__ void __launch_bounds__(kTile) k_step_f64(DevBufs B, const int* __restrict__ tile_job,
+                                                    const int64_t* __restrict__ tile_first,
+                                                    const int* __restrict__ ntiles_ptr, int t) {
   step_body<true>(B, tile_job, tile_first, ntiles_ptr, t);
 }
 
@@ -476,7 +478,7 @@ __device__ __forceinline__ ColumnRange column_range(const DevBufs& B, const JobD
 }
 
 // Insert particle index q into this lane's list, kept sorted by particle index
-// in LDS ([kmax][64], lane-minor so lanes hit distinct banks).  cnt counts every
+// in LDS ([kmax][kNlistBlock], thread-minor so lanes hit distinct banks).  cnt counts every
 // candidate accepted, stored or not (cnt > kmax signals overflow).
 __device__ __forceinline__ void list_insert(uint32_t* kid, int lane, int kmax, int& cnt, uint32_t q) {
   if (cnt < kmax) {
@@ -583,7 +585,7 @@ __device__ __forceinline__ void nlist_lane(const DevBufs& B, const JobDev& J, in
 }
 
 // Neighbour-list build, one lane per slot of the freshly sorted (raster cell)
-// order, one wavefront per workgroup.  Each lane walks its own stencil and
+// order, one workgroup per tile.  Each lane walks its own stencil and
 // stages its list in LDS.  FP64 class: kept sorted by particle index and mapped
 // back to slots through the inverse permutation of the sort, so that the FP64
 // force sums run in particle-index order.  FP32 class: slots in the order the
@@ -591,7 +593,7 @@ __device__ __forceinline__ void nlist_lane(const DevBufs& B, const JobDev& J, in
 // neighbouring lanes then read neighbouring memory in the force loop.
 __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const int* __restrict__ tile_job,
                                                        const int64_t* __restrict__ tile_first) {
-  extern __shared__ uint32_t kid[];  // sorted lists [kmax][64]
+  extern __shared__ uint32_t kid[];  // lists [kmax][kNlistBlock]
   const int kmax = B.kmax;
   const int tile = (int)blockIdx.x / kNlistPerTile;
   const int job = uniform_int(tile_job[tile]);
@@ -635,10 +637,10 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const int* __r
     mx = max(mx, (uint32_t)__shfl_xor((int)mx, o, 64));
     sm += (uint32_t)__shfl_xor((int)sm, o, 64);
   }
-  const int64_t g0 = i - lane;
-  if (lane == 0 && g0 < J.off + J.n) {
-    B.NLSTAT[2 * (g0 / kNlistBlock)] = mx;
-    B.NLSTAT[2 * (g0 / kNlistBlock) + 1] = sm;
+  const int64_t g0 = i - (lane % kGroup);
+  if (lane % kGroup == 0 && g0 < J.off + J.n) {
+    B.NLSTAT[2 * (g0 / kGroup)] = mx;
+    B.NLSTAT[2 * (g0 / kGroup) + 1] = sm;
     if ((int)mx > kmax) atomicMin(&B.book[job].stop_at, (long long)J.step0);
   }
 }
@@ -655,11 +657,11 @@ __global__ void __launch_bounds__(kStatsThreads) k_job_stats(DevBufs B, int with
   if (J.n <= 0) return;
   double a = 0.0, sm = 0.0;
   uint32_t mx = 0u;
-  const int64_t t1 = (J.off + J.n + kStepBlock - 1) / kStepBlock;
-  for (int64_t t = J.off / kStepBlock + threadIdx.x; t < t1; t += kStatsThreads) a = fmax(a, B.TACC[t]);
+  const int64_t t1 = (J.off + J.n + kGroup - 1) / kGroup;
+  for (int64_t t = J.off / kGroup + threadIdx.x; t < t1; t += kStatsThreads) a = fmax(a, B.TACC[t]);
   if (with_lists) {
-    const int64_t g1 = (J.off + J.n + kNlistBlock - 1) / kNlistBlock;
-    for (int64_t g = J.off / kNlistBlock + threadIdx.x; g < g1; g += kStatsThreads) {
+    const int64_t g1 = (J.off + J.n + kGroup - 1) / kGroup;
+    for (int64_t g = J.off / kGroup + threadIdx.x; g < g1; g += kStatsThreads) {
       mx = max(mx, B.NLSTAT[2 * g]);
       sm += (double)B.NLSTAT[2 * g + 1];
     }
