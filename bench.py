@@ -14,14 +14,17 @@ Prints one JSON line:
   value       particle-steps/s over the timed steps (wall clock around md_step)
   roofline    the fused step kernel: algorithmic bytes per launch / mean launch
               time from HIP events on the library's stream, against 8 TB/s
-  cpu_baseline the FP64 oracle on the host cores, one full step of the same
-              2M-particle system (kind "oracle")
+  cpu_baseline the FP64 oracle on the host cores, full steps of the same
+              2M-particle system for about 12 s (kind "oracle")
+  shard_250k, e4  secondary: the step at one GPU's share of an 8-way split,
+              and the sphere-vs-plane cost ratio of the paper's comparison
 """
 from __future__ import annotations
 
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -83,7 +86,7 @@ def cpu_baseline(s, run, budget_s: float = 12.0):
                  rc=run["rc"], pair=run["pair"], surface=s.surface, surf=s.surf, seed=run["seed"], use_cells=1)
     st = o.State(P, s.x, s.p)
     steps, t = 0, 0.0
-    while steps < 5 and t < budget_s:
+    while steps < 50 and t < budget_s:
         t0 = time.perf_counter()
         st.run(1)
         t += time.perf_counter() - t0
@@ -92,6 +95,55 @@ def cpu_baseline(s, run, budget_s: float = 12.0):
     return {"value": s.n * steps / t, "unit": "particle-steps/s", "cores": cores, "kind": "oracle",
             "sample": f"{steps} full time step(s) of the same {s.n}-particle torus system, FP64, "
                       f"linked cells, OpenMP; {t:.1f} s"}
+
+
+def timed_steps(s, run, skin: float, steps: int, warmup: int):
+    """Steps per second of one system (after warm-up), and the mean step-kernel
+    launch time from the library's HIP-event timing."""
+    from paper_1411_3019_amd import md
+    prm = md.Params(dt=run["dt"], kT=run["kT"], gamma=run["gamma"], eps=run.get("eps", 1.0),
+                    sigma=run.get("sigma", 1.0), rc=run["rc"], pair=run["pair"], force_fp64=run["force_fp64"],
+                    skin=skin, seed=run["seed"], box_lo=s.box_lo, box_hi=s.box_hi, periodic=s.periodic)
+    sysm = md.System(prm, s.surface, s.surf)
+    sysm.set_particles(s.x, s.p, mass=s.mass, cons=s.cons)
+    sysm.step(warmup)
+    device_sync()
+    st0 = sysm.stats()
+    t0 = time.perf_counter()
+    sysm.step(steps)
+    device_sync()
+    wall = time.perf_counter() - t0
+    st1 = sysm.stats()
+    sysm.close()
+    launches = max(1, st1["step_launches"] - st0["step_launches"])
+    return {"particle_steps_per_s": s.n * steps / wall, "ms_per_step": wall * 1e3 / steps,
+            "step_kernel_us": (st1["step_kernel_ms"] - st0["step_kernel_ms"]) * 1e3 / launches,
+            "nl_mean": st1["nl_mean"]}
+
+
+def extra_benches(skin: float):
+    """Secondary measurements (not the headline figure):
+      shard_250k  the step at one GPU's share of an 8-way split of the 2M torus
+                  (250,000 particles, same density and potential);
+      e4          the paper's cost comparison of RATTLE on a sphere with the plane
+                  (where RATTLE reduces to 2-D velocity Verlet), 1,000,000 LJ
+                  particles each at area fraction 0.4, same potential and step."""
+    from workloads import gen
+    out = {}
+    s, run = gen.torus_lj_2m(250_000)
+    out["shard_250k"] = dict(workload="torus, 250000 LJ particles, area fraction 0.4", skin=skin,
+                             **timed_steps(s, run, skin, 2000, 300))
+    log(f"[bench] shard 250k: {out['shard_250k']}")
+    n = 1_000_000
+    run = dict(dt=0.002, kT=1.0, gamma=1.0, rc=2.5, pair="lj", force_fp64=0, seed=11)
+    sph = gen.sphere(n, gen.sphere_radius_for(n, 0.4), 11)
+    pla = gen.plane(n, math.sqrt(n * math.pi / 4.0 / 0.4), 11)
+    a = timed_steps(sph, run, skin, 2000, 300)
+    b = timed_steps(pla, run, skin, 2000, 300)
+    out["e4"] = {"workload": "1000000 LJ particles (rc 2.5) at area fraction 0.4: sphere vs periodic plane",
+                 "sphere": a, "plane": b, "time_ratio_sphere_over_plane": a["ms_per_step"] / b["ms_per_step"]}
+    log(f"[bench] e4: sphere {a['ms_per_step']:.4f} ms/step, plane {b['ms_per_step']:.4f} ms/step")
+    return out
 
 
 def serving_bench(njobs: int, nplain: int, rate: float, budget_gb: float):
@@ -163,6 +215,7 @@ def main():
     ap.add_argument("--serving-plain-jobs", type=int, default=40)
     ap.add_argument("--serving-rate", type=float, default=200.0)
     ap.add_argument("--serving-budget-gb", type=float, default=16.0)
+    ap.add_argument("--no-extra", action="store_true", help="skip the 250k-shard and sphere-vs-plane measurements")
     args = ap.parse_args()
     if args.no_graph:
         os.environ["MD_NO_GRAPH"] = "1"
@@ -236,6 +289,8 @@ def main():
             "wall_ms": wall * 1e3,
         },
     }
+    if not args.no_extra:
+        out.update(extra_benches(args.skin))
     if args.serving_jobs > 0:
         out["serving"] = serving_bench(args.serving_jobs, args.serving_plain_jobs, args.serving_rate,
                                        args.serving_budget_gb)
