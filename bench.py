@@ -127,7 +127,9 @@ def extra_benches(skin: float):
                   (250,000 particles, same density and potential);
       e4          the paper's cost comparison of RATTLE on a sphere with the plane
                   (where RATTLE reduces to 2-D velocity Verlet), 1,000,000 LJ
-                  particles each at area fraction 0.4, same potential and step."""
+                  particles each at area fraction 0.4, same potential and step;
+      membrane    1.85M particles, mostly free, around a constrained height-field
+                  membrane (periodic box)."""
     from workloads import gen
     out = {}
     s, run = gen.torus_lj_2m(250_000)
@@ -143,6 +145,11 @@ def extra_benches(skin: float):
     out["e4"] = {"workload": "1000000 LJ particles (rc 2.5) at area fraction 0.4: sphere vs periodic plane",
                  "sphere": a, "plane": b, "time_ratio_sphere_over_plane": a["ms_per_step"] / b["ms_per_step"]}
     log(f"[bench] e4: sphere {a['ms_per_step']:.4f} ms/step, plane {b['ms_per_step']:.4f} ms/step")
+    s, run = gen.membrane_mixed()
+    out["membrane"] = dict(workload=f"height-field membrane, {int(s.cons.sum())} constrained + "
+                                    f"{s.n - int(s.cons.sum())} free WCA particles, periodic 400x400x60",
+                           skin=skin, **timed_steps(s, run, skin, 2000, 300))
+    log(f"[bench] membrane: {out['membrane']}")
     return out
 
 

@@ -87,8 +87,10 @@ extern "C" {
 /* ---- parameters --------------------------------------------------------------
  * gamma is the rate 1/tau of Algorithm S1 (friction m gamma, noise
  * sqrt(2 m kT gamma / dt)); gamma = 0 gives plain constant-energy dynamics.
- * force_fp64 = 1 computes pair forces in FP64; 0 computes them in FP32 with
- * FP32 accumulation from FP64 separations.  Positions, momenta, the RATTLE
+ * force_fp64 = 1 computes pair forces in FP64, summed in particle-index order;
+ * 0 computes each pair term in FP32 from the FP64 separation and sums the terms
+ * exactly (each rounded to a 2^-32 grid, accumulated in FP64), so the result
+ * does not depend on the order of the terms.  Positions, momenta, the RATTLE
  * solves and the tangent projection are always FP64.
  * newton_tol is the paper's eta on ||r||_inf (Section 2.2); 0 iterates to
  * round-off (stop when the Newton update is within 16 ulp of the position).
@@ -113,6 +115,9 @@ typedef struct md_params {
   uint64_t seed;          /* Philox key of the Langevin noise                   */
   double newton_tol;
   int newton_max_iter;    /* 0 selects 32                                       */
+  int newton_frozen;      /* 1: position-stage Newton keeps the normal of x^m in
+                             its Jacobian (the frozen-normal variant, SI,
+                             Performance); 0: full Newton (default)            */
   int device;             /* HIP device ordinal                                 */
   void* stream;           /* hipStream_t or NULL                                */
 } md_params;

@@ -74,6 +74,9 @@ typedef struct {
   double eta;           /* Newton tolerance on ||r||_inf; 0: iterate to round-off */
   int max_iter;         /* Newton iteration cap (0 is read as 32)               */
   int use_cells;        /* 1: linked-cell search; 0: all pairs                  */
+  int frozen;           /* 1: the constraint row of the position-stage Jacobian
+                           keeps n(x^m) instead of n at the iterate (the
+                           frozen-normal variant of SI, Performance)          */
 } mdo_params;
 
 /* Philox4x32-10 block function: out = Philox(ctr, key). */

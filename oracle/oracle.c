@@ -437,10 +437,12 @@ int mdo_position_stage(const mdo_params* P, const double xm[3], const double pm[
     for (int k = 0; k < 3; ++k) r[k] = xm[k] - xn[k] + (dt / m) * ph[k];
     r[3] = mdo_surface_g(P, xn, nn);
     const double c = dt * dt / (2.0 * m);
+    /* full Newton: dg/dx at the iterate; frozen normal: at x^m (SI, Performance) */
+    const double* jr = P->frozen ? nm : nn;
     double J[4][4] = {{-1.0, 0.0, 0.0, -c * nm[0]},
                       {0.0, -1.0, 0.0, -c * nm[1]},
                       {0.0, 0.0, -1.0, -c * nm[2]},
-                      {nn[0], nn[1], nn[2], 0.0}};
+                      {jr[0], jr[1], jr[2], 0.0}};
     double d[4];
     if (solve4(J, r, d) != 0) return MDO_ENEWTON;
     for (int k = 0; k < 3; ++k) xn[k] -= d[k];

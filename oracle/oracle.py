@@ -44,7 +44,7 @@ class _Params(C.Structure):
         ("box_lo", C.c_double * 3), ("box_hi", C.c_double * 3),
         ("periodic", C.c_int * 3),
         ("seed", C.c_uint64), ("eta", C.c_double), ("max_iter", C.c_int),
-        ("use_cells", C.c_int),
+        ("use_cells", C.c_int), ("frozen", C.c_int),
     ]
 
 
@@ -67,6 +67,7 @@ class Params:
     eta: float = 0.0
     max_iter: int = 32
     use_cells: int = 1
+    frozen: int = 0
 
     def to_c(self) -> _Params:
         p = _Params()
@@ -86,6 +87,7 @@ class Params:
         p.eta = self.eta
         p.max_iter = self.max_iter
         p.use_cells = self.use_cells
+        p.frozen = self.frozen
         return p
 
 

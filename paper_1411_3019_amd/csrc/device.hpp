@@ -42,7 +42,7 @@ struct JobDev {
   int periodic[3];
   int surf_kind, pair_kind, force_fp64, uniform_mass;
   int newton_cap, mode, xcur, pcur;
-  int scur, pad0;
+  int scur, newton_frozen;
   uint64_t seed;
   int64_t off, n, bm_off;
   int64_t step0, remaining;
@@ -271,7 +271,8 @@ __device__ __forceinline__ int rattle_position(const JobDev& J, double m, double
     ++it;
     double mx, my, mz;
     const double g = surf_eval(J, xc, yc, zc, mx, my, mz);
-    const double dl = g / (c * (mx * nx + my * ny + mz * nz));
+    // full Newton: dg/dx at the iterate; frozen normal: at x^m (SI, Performance)
+    const double dl = g / (c * (J.newton_frozen ? nn : mx * nx + my * ny + mz * nz));
     lam += dl;
     const double xn = xt - c * lam * nx, yn = yt - c * lam * ny, zn = zt - c * lam * nz;
     if (J.newton_tol > 0.0) {

@@ -165,6 +165,7 @@ int validate_params(const md_params& p) {
   if (p.pair_kind < MD_PAIR_NONE || p.pair_kind > MD_PAIR_LJ_SMOOTH) return MD_EINVAL;
   if (p.pair_kind != MD_PAIR_NONE && (!(p.eps >= 0.0) || !(p.sigma > 0.0) || !(p.rc > 0.0))) return MD_EINVAL;
   if (p.skin < 0.0 || p.newton_tol < 0.0 || p.newton_max_iter < 0) return MD_EINVAL;
+  if (p.newton_frozen != 0 && p.newton_frozen != 1) return MD_EINVAL;
   for (int k = 0; k < 3; ++k)
     if (p.periodic[k] && !(p.box_hi[k] > p.box_lo[k])) return MD_EINVAL;
   return MD_OK;
@@ -580,6 +581,7 @@ struct Engine {
     d.force_fp64 = p.force_fp64 ? 1 : 0;
     d.newton_tol = p.newton_tol;
     d.newton_cap = p.newton_max_iter > 0 ? p.newton_max_iter : 32;
+    d.newton_frozen = p.newton_frozen;
     d.seed = p.seed;
     d.surf_kind = h.surf_kind;
     for (int k = 0; k < MD_SURF_MAXPRM; ++k) d.surf[k] = h.surf[k];

@@ -38,7 +38,7 @@ class _Params(C.Structure):
         ("eps", C.c_double), ("sigma", C.c_double), ("rc", C.c_double),
         ("pair_kind", C.c_int), ("force_fp64", C.c_int), ("skin", C.c_double),
         ("box_lo", C.c_double * 3), ("box_hi", C.c_double * 3), ("periodic", C.c_int * 3),
-        ("seed", C.c_uint64), ("newton_tol", C.c_double), ("newton_max_iter", C.c_int),
+        ("seed", C.c_uint64), ("newton_tol", C.c_double), ("newton_max_iter", C.c_int), ("newton_frozen", C.c_int),
         ("device", C.c_int), ("stream", C.c_void_p),
     ]
 
@@ -91,6 +91,7 @@ class Params:
     seed: int = 0
     newton_tol: float = 0.0
     newton_max_iter: int = 32
+    newton_frozen: int = 0
     device: int = 0
     stream: int | None = None
 
@@ -108,6 +109,7 @@ class Params:
         p.seed = int(self.seed) & 0xFFFFFFFFFFFFFFFF
         p.newton_tol = self.newton_tol
         p.newton_max_iter = self.newton_max_iter
+        p.newton_frozen = int(self.newton_frozen)
         p.device = self.device
         p.stream = self.stream
         return p

@@ -14,7 +14,8 @@ def oracle_params(s: gen.System, **kw) -> o.Params:
     return o.Params(surface=s.surface, surf=s.surf, box_lo=s.box_lo, box_hi=s.box_hi, periodic=s.periodic,
                     dt=kw.get("dt", 0.001), kT=kw.get("kT", 1.0), gamma=kw.get("gamma", 1.0),
                     eps=kw.get("eps", 1.0), sigma=kw.get("sigma", 1.0), rc=kw.get("rc", WCA),
-                    pair=kw.get("pair", "lj"), seed=kw.get("seed", 0), eta=kw.get("newton_tol", 0.0))
+                    pair=kw.get("pair", "lj"), seed=kw.get("seed", 0), eta=kw.get("newton_tol", 0.0),
+                    frozen=kw.get("newton_frozen", 0))
 
 
 def gpu_params(s: gen.System, **kw):
@@ -24,7 +25,7 @@ def gpu_params(s: gen.System, **kw):
                      eps=kw.get("eps", 1.0), sigma=kw.get("sigma", 1.0), rc=kw.get("rc", WCA),
                      pair=kw.get("pair", "lj"), force_fp64=kw.get("force_fp64", 1), skin=kw.get("skin", 0.3),
                      seed=kw.get("seed", 0), newton_tol=kw.get("newton_tol", 0.0),
-                     newton_max_iter=kw.get("newton_max_iter", 32))
+                     newton_max_iter=kw.get("newton_max_iter", 32), newton_frozen=kw.get("newton_frozen", 0))
 
 
 def gpu_system(s: gen.System, **kw):

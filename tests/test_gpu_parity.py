@@ -40,6 +40,8 @@ CASES = {
     "ellipsoid_wca": lambda: (gen.ellipsoid(2000, 16.0, 16.0, 24.0, 4), dict(dt=0.001, rc=WCA, seed=3)),
     "height_mixed": lambda: (gen.height_membrane(800, 1500, 40.0, 40.0, 24.0, 4.0, 40.0, 5),
                              dict(dt=0.002, rc=WCA, seed=11, force_fp64=0)),
+    "torus_frozen": lambda: (gen.torus(3000, 26.1, 8.7, 10), dict(dt=0.002, rc=2.5, seed=13, force_fp64=1,
+                                                                  newton_frozen=1)),
     "plane_lj_smooth": lambda: (gen.plane(1500, 50.0, 6), dict(dt=0.002, rc=2.5, pair="lj_smooth", seed=1)),
     "cylinder_lj": lambda: (gen.cylinder(1500, 8.0, 60.0, 7), dict(dt=0.002, rc=2.5, seed=2, force_fp64=0)),
     "sphere_nve": lambda: (gen.sphere(800, 12.0, 9), dict(dt=0.001, rc=WCA, gamma=0.0)),
@@ -66,7 +68,7 @@ def test_one_step_map(case):
 
 
 @pytest.mark.parametrize("case", ["sphere_wca_fp64", "torus_lj_fp32", "height_mixed", "ellipsoid_wca",
-                                  "sphere_eta"])
+                                  "sphere_eta", "torus_frozen"])
 def test_short_trajectory(case):
     """50 steps: trajectories still agree point-wise (chaos has not amplified the
     round-off yet); constraint residuals at round-off on both sides."""
@@ -169,10 +171,10 @@ def test_error_paths():
 
 def test_full_size_torus_2m_one_step():
     """The 2,000,000-particle torus workload at full size in the launch
-    configuration the benchmark times (FP32 forces, graphs, skin 0.3): one step,
+    configuration the benchmark times (FP32 forces, graphs, skin 0.5): one step,
     every particle compared with the oracle's full FP64 step."""
     s, run = gen.torus_lj_2m()
-    kw = dict(dt=run["dt"], rc=run["rc"], seed=run["seed"], force_fp64=0)
+    kw = dict(dt=run["dt"], rc=run["rc"], seed=run["seed"], force_fp64=0, skin=0.5)
     print(f"[gpu] full-size torus one step n={s.n}", flush=True)
     ref, f0, st0, st = _one_step(s, 1, **kw)
     ex, ep, ef = rel_pos_err(st["x"], ref.x), rel_err(st["p"], ref.p), rel_err(st["f"], ref.f)
@@ -182,6 +184,24 @@ def test_full_size_torus_2m_one_step():
     d = ref.diag()
     assert abs(st["diag"]["kT"] / d["kT"] - 1) < 1e-7
     assert st["diag"]["gdist_max"] < 1e-13 * 800.0
+
+
+def test_full_size_membrane_one_step():
+    """The crowded-membrane workload at full size (78k constrained particles on a
+    periodic height field, 1.77M free particles around it; FP32 forces, skin
+    0.5): one step, every particle compared with the oracle."""
+    s, run = gen.membrane_mixed()
+    kw = dict(dt=run["dt"], rc=run["rc"], seed=run["seed"], force_fp64=0, skin=0.5)
+    print(f"[gpu] full-size membrane one step n={s.n}", flush=True)
+    ref, f0, st0, st = _one_step(s, 1, **kw)
+    ex, ep, ef = rel_pos_err(st["x"], ref.x), rel_err(st["p"], ref.p), rel_err(st["f"], ref.f)
+    report("membrane 1-step", x=ex, p=ep, f=ef, f0=rel_err(st0["f"], f0))
+    assert ex < POS_TOL
+    assert ep < 1e-6
+    assert ef < 1e-4
+    d = ref.diag()
+    assert abs(st["diag"]["kT"] / d["kT"] - 1) < 1e-7
+    assert st["diag"]["gdist_max"] < 1e-12
 
 
 def test_msd_statistics_torus():

@@ -132,6 +132,29 @@ def test_momentum_stage_is_tangent_projection(kind, prm):
         assert it <= 3
 
 
+@pytest.mark.parametrize("kind,prm", SURFS)
+def test_frozen_normal_reaches_the_newton_root(kind, prm):
+    """The frozen-normal iteration (the Jacobian's constraint row kept at
+    x^m) is a chord method for the same equations: it converges (linearly
+    rather than quadratically) to the same root as full Newton (SI,
+    Performance: no visible effect)."""
+    rng = np.random.default_rng(21)
+    P = o.Params(dt=DT, surface=kind, surf=prm)
+    Pf = o.Params(dt=DT, surface=kind, surf=prm, frozen=1)
+    worst = 0.0
+    for _ in range(40):
+        xm = _point_on(kind, prm, rng)
+        pm, fm = _random_tangent_state(P, xm, rng)
+        xn, ph, lam, it = o.position_stage(P, xm, pm, fm, 1.0)
+        xf, phf, lamf, itf = o.position_stage(Pf, xm, pm, fm, 1.0)
+        scale = max(1.0, np.abs(xn).max())
+        worst = max(worst, np.abs(xf - xn).max() / scale)
+        assert np.abs(xf - xn).max() <= 64e-16 * scale
+        g, n1 = o.surface_g(Pf, xf)
+        assert abs(g) / np.linalg.norm(n1) < 1e-14 * scale * 8
+    assert worst < 64e-16
+
+
 def test_eta_rule_close_to_roundoff_rule():
     rng = np.random.default_rng(9)
     prm = (0.0, 0.0, 0.0, 10.0, 3.5)

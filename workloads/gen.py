@@ -289,6 +289,18 @@ def torus_lj_2m(n: int = 2_000_000, seed: int = 7, phi: float = 0.4) -> tuple[Sy
     return s, run
 
 
+def membrane_mixed(seed: int = 3, n_c: int = 77_955, n_b: int = 1_772_349) -> tuple[System, dict]:
+    """Crowded membrane: a height field z = 10 sin(2 pi x/100) sin(2 pi y/100) in a
+    periodic 400 x 400 x 60 box carrying n_c constrained WCA particles (area
+    fraction 0.35 of the membrane's 1.749e5 sigma^2), plus n_b free WCA particles
+    at volume fraction 0.1 of the volume outside the slab |z - h| < 1; kT 1,
+    gamma 1, dt 0.002, FP32 pair forces."""
+    s = height_membrane(n_c, n_b, 400.0, 400.0, 60.0, 10.0, 100.0, seed)
+    run = dict(dt=0.002, kT=1.0, gamma=1.0, eps=1.0, sigma=1.0, rc=2.0 ** (1.0 / 6.0), pair="lj", seed=seed,
+               force_fp64=0, steps=5000)
+    return s, run
+
+
 # ----------------------------------------------------------------------------- serving stream
 
 SERVING_SURFACES = ("sphere", "ellipsoid", "torus")
