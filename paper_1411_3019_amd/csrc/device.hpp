@@ -75,7 +75,8 @@ struct DevBufs {
   double* OP;
   double* OF;
   double* OD;          // [4][C]: kinetic energy, potential energy share, |g|/|n|, |n.v|/|n|
-  uint32_t* NL;        // neighbour slots, column-major [kmax][C]
+  uint32_t* NL;        // neighbour slots: entry k of slot i at ((k/4) C + i) 4 + k%4, i.e. rows of uint4
+                       // [kmax/4][C] (kmax is a multiple of 4), four entries per load
   uint32_t* NCNT;      // neighbour count per slot
   uint32_t* BM;        // occupied-cell bitmap words (per job segment)
   uint32_t* WOFF;      // exclusive popcount prefix per bitmap word (job-local)
@@ -346,7 +347,7 @@ __device__ __forceinline__ void pair_forces_impl(const JobDev& J, const DevBufs&
   using real = typename std::conditional<kF64, double, float>::type;
   const int64_t C = B.C;
   const int cnt = (int)B.NCNT[i];
-  const uint32_t* __restrict__ nl = B.NL + i;
+  const uint4* __restrict__ nl = reinterpret_cast<const uint4*>(B.NL) + i;
   double fx = 0.0, fy = 0.0, fz = 0.0;
   const real eps24 = (real)(24.0 * J.eps);
   const real sig2 = (real)J.sig2;
@@ -365,12 +366,12 @@ __device__ __forceinline__ void pair_forces_impl(const JobDev& J, const DevBufs&
       fz += on_grid((double)(c * (real)dz));
     }
   };
+  static_assert(kForceBatch == 4, "one uint4 row of the list per batch");
   int k = 0;
   for (; k + kForceBatch <= cnt; k += kForceBatch) {
-    int64_t j[kForceBatch];
+    const uint4 q = nl[(int64_t)(k >> 2) * C];
+    const int64_t j[kForceBatch] = {(int64_t)q.x, (int64_t)q.y, (int64_t)q.z, (int64_t)q.w};
     double ax[kForceBatch], ay[kForceBatch], az[kForceBatch];
-#pragma unroll
-    for (int u = 0; u < kForceBatch; ++u) j[u] = nl[(int64_t)(k + u) * C];
 #pragma unroll
     for (int u = 0; u < kForceBatch; ++u) {
       ax[u] = X[3 * j[u]];
@@ -380,9 +381,15 @@ __device__ __forceinline__ void pair_forces_impl(const JobDev& J, const DevBufs&
 #pragma unroll
     for (int u = 0; u < kForceBatch; ++u) add(xi - ax[u], yi - ay[u], zi - az[u]);
   }
-  for (; k < cnt; ++k) {
-    const int64_t j = nl[(int64_t)k * C];
-    add(xi - X[3 * j], yi - X[3 * j + 1], zi - X[3 * j + 2]);
+  if (k < cnt) {
+    const uint4 q = nl[(int64_t)(k >> 2) * C];
+    const uint32_t jt[3] = {q.x, q.y, q.z};
+#pragma unroll
+    for (int u = 0; u < 3; ++u)
+      if (k + u < cnt) {
+        const int64_t j = jt[u];
+        add(xi - X[3 * j], yi - X[3 * j + 1], zi - X[3 * j + 2]);
+      }
   }
   Fx = fx;
   Fy = fy;
@@ -419,7 +426,7 @@ __device__ __forceinline__ double pair_energy(const JobDev& J, const DevBufs& B,
   const double rc = sqrt(J.rc2);
   double u = 0.0;
   for (int k = 0; k < cnt; ++k) {
-    const int64_t j = B.NL[(int64_t)k * C + i];
+    const int64_t j = B.NL[(((int64_t)(k >> 2) * C + i) << 2) + (k & 3)];
     double dx = xi - X[3 * j], dy = yi - X[3 * j + 1], dz = zi - X[3 * j + 2];
     if (anyper) min_image(J, dx, dy, dz);
     const double r2 = dx * dx + dy * dy + dz * dz;

@@ -727,6 +727,7 @@ struct Engine {
   int grow_kmax(int need) {
     int nk = kmax;
     while (nk < need) nk = nk + nk / 2 + 4;
+    nk = (nk + 3) & ~3;  // whole uint4 rows
     uint32_t* nl = nullptr;
     MDCHK(dalloc(&nl, (size_t)nk * C));
     HIPCHK(hipMemcpyAsync(nl, B.NL, sizeof(uint32_t) * (size_t)kmax * C, hipMemcpyDeviceToDevice, stream));

@@ -613,20 +613,25 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const int* __r
       // inverse permutation, four lookups in flight at a time
       nlist_lane<true>(B, J, i, xi, yi, zi, cx, cy, cz, kid, lane, kmax, cnt);
       stored = cnt < kmax ? cnt : kmax;
-      int k = 0;
-      for (; k + 4 <= stored; k += 4) {
+      for (int k = 0; k < stored; k += 4) {
         uint32_t v[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) v[u] = B.INV[base + kid[(k + u) * kNlistBlock + lane]];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) B.NL[(int64_t)(k + u) * C + i] = (uint32_t)base + v[u];
+        for (int u = 0; u < 4; ++u) {
+          const uint32_t q = k + u < stored ? kid[(k + u) * kNlistBlock + lane] : 0u;  // 0: a valid index
+          v[u] = k + u < stored ? (uint32_t)base + B.INV[base + q] : 0u;
+        }
+        reinterpret_cast<uint4*>(B.NL)[(int64_t)(k >> 2) * C + i] = make_uint4(v[0], v[1], v[2], v[3]);
       }
-      for (; k < stored; ++k) B.NL[(int64_t)k * C + i] = (uint32_t)base + B.INV[base + kid[k * kNlistBlock + lane]];
     } else {
       // FP32 class: slot order, as found
       nlist_lane<false>(B, J, i, xi, yi, zi, cx, cy, cz, kid, lane, kmax, cnt);
       stored = cnt < kmax ? cnt : kmax;
-      for (int k = 0; k < stored; ++k) B.NL[(int64_t)k * C + i] = (uint32_t)base + kid[k * kNlistBlock + lane];
+      for (int k = 0; k < stored; k += 4) {
+        uint32_t v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = k + u < stored ? (uint32_t)base + kid[(k + u) * kNlistBlock + lane] : 0u;
+        reinterpret_cast<uint4*>(B.NL)[(int64_t)(k >> 2) * C + i] = make_uint4(v[0], v[1], v[2], v[3]);
+      }
     }
     B.NCNT[i] = (uint32_t)stored;
   }
