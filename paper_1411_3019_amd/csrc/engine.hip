@@ -768,9 +768,12 @@ struct Engine {
         cc.push_back({h.off + s, (int)std::min<int64_t>(kScanChunk, h.n + 1 - s), first});
     }
     if (tj.empty()) {
+      // only empty jobs: nothing to sort; their records start afresh
       for (int j : set) {
         jobs[j].built = true;
         jobs[j].A_now = 0.0;
+        book_h[j] = fresh_book();
+        HIPCHK(hipMemcpyAsync(&B.book[j], &book_h[j], sizeof(JobBook), hipMemcpyHostToDevice, stream));
       }
       return MD_OK;
     }

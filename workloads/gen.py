@@ -163,6 +163,21 @@ def ellipsoid(n: int, a: float, b: float, c: float, seed: int, dmin: float = 0.9
     return System(x, p, "ellipsoid", (0.0, 0.0, 0.0, a, b, c), meta=dict(a=a, b=b, c=c))
 
 
+def box_gas(n: int, L: float, seed: int, dmin: float = 0.9, kT: float = 1.0, mass=None) -> System:
+    """n free particles (no surface) uniform in a periodic cube of side L, with
+    Maxwell-Boltzmann momenta in all three directions."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    lo, hi, per = (0.0, 0.0, 0.0), (L, L, L), (1, 1, 1)
+
+    def sampler(rng, m):
+        return rng.uniform(0.0, L, size=(m, 3))
+
+    x = _fill(sampler, n, dmin, rng, lo, hi, per)
+    p = _tangent_momenta(rng, np.zeros((n, 3)), kT, mass)
+    return System(x, p, "none", (), lo, hi, per, mass=None if mass is None else np.asarray(mass, dtype=np.float64),
+                  meta=dict(L=L))
+
+
 def _height(x, y, A, L):
     k = 2.0 * np.pi / L
     return A * np.sin(k * x) * np.sin(k * y)
