@@ -59,6 +59,27 @@ enum {
   MDO_ENOMEM = -6
 };
 
+/* Bead model of the capsid example (SI, Virus capsid self-assembly): bead
+ * types with additive size mixing, truncated-shifted LJ per type pair (only
+ * between beads of different molecules), linear molecules of bpm consecutive
+ * particle indices with harmonic bonds V = kb (r - r0)^2 between neighbours and
+ * bends V = ka (theta - theta0)^2 on consecutive triples (theta: the angle at
+ * the middle bead between its two bonds, pi when straight), and a repulsive LJ
+ * wall about the surface centre, 4 ew [(sw/d)^12 - (sw/d)^6 + 1/4] for
+ * d = r - Rw < 2^(1/6) sw.  ntypes = 0 disables the model. */
+#define MDO_MAX_TYPES 4
+typedef struct {
+  int ntypes;
+  int bpm;              /* beads per molecule; 0: no molecules            */
+  double sigma[MDO_MAX_TYPES];
+  double eps[MDO_MAX_TYPES][MDO_MAX_TYPES];  /* LJ well depth per type pair */
+  double rc[MDO_MAX_TYPES][MDO_MAX_TYPES];  /* 0: 2^(1/6) sigma_ij (purely repulsive) */
+  double kb;
+  double r0[MDO_MAX_TYPES][MDO_MAX_TYPES];  /* 0: 2^(1/6) (sigma_i + sigma_j) / 4 */
+  double ka, theta0;
+  double wall_eps, wall_sigma, wall_radius; /* wall_eps 0: no wall        */
+} mdo_model;
+
 typedef struct {
   double dt;            /* time step                                            */
   double kT;            /* thermal energy                                       */
@@ -77,6 +98,9 @@ typedef struct {
   int frozen;           /* 1: the constraint row of the position-stage Jacobian
                            keeps n(x^m) instead of n at the iterate (the
                            frozen-normal variant of SI, Performance)          */
+  mdo_model model;      /* bead model (model.ntypes > 0); rc must then be the
+                           largest pair cut-off (cell size)                   */
+  const uint8_t* types; /* bead type per particle (NULL: all type 0)          */
 } mdo_params;
 
 /* Philox4x32-10 block function: out = Philox(ctr, key). */

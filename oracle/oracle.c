@@ -201,20 +201,148 @@ static void min_image(const mdo_params* P, double d[3]) {
   }
 }
 
+/* ------------------------------------------------------------------------ */
+/* Bead model (SI, Virus capsid self-assembly).                              */
+/* ------------------------------------------------------------------------ */
+
+static int type_of(const mdo_params* P, int64_t i) { return P->types ? P->types[i] : 0; }
+
+static double model_sigma(const mdo_model* M, int a, int b) { return 0.5 * (M->sigma[a] + M->sigma[b]); }
+
+static double model_rc(const mdo_model* M, int a, int b) {
+  return M->rc[a][b] > 0.0 ? M->rc[a][b] : pow(2.0, 1.0 / 6.0) * model_sigma(M, a, b);
+}
+
+static double model_r0(const mdo_model* M, int a, int b) {
+  return M->r0[a][b] > 0.0 ? M->r0[a][b] : pow(2.0, 1.0 / 6.0) * (M->sigma[a] + M->sigma[b]) / 4.0;
+}
+
+/* Truncated-shifted LJ of the type pair (a, b): energy and c with force c*d. */
+static double model_pair(const mdo_model* M, int a, int b, double r2, double* coef) {
+  const double r = sqrt(r2), s = model_sigma(M, a, b), rc = model_rc(M, a, b);
+  double dphi, dphic;
+  const double phi = lj_phi(M->eps[a][b], s, r, &dphi);
+  const double phic = lj_phi(M->eps[a][b], s, rc, &dphic);
+  *coef = -dphi / r;
+  return phi - phic;
+}
+
+static int same_molecule(const mdo_model* M, int64_t i, int64_t j) { return M->bpm > 0 && i / M->bpm == j / M->bpm; }
+
+/* Bond between i and j: force on i and energy kb (r - r0)^2. */
+static double bond_term(const mdo_params* P, const double* x, int64_t i, int64_t j, double f[3]) {
+  const mdo_model* M = &P->model;
+  double d[3] = {x[3 * i] - x[3 * j], x[3 * i + 1] - x[3 * j + 1], x[3 * i + 2] - x[3 * j + 2]};
+  min_image(P, d);
+  const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+  const double r0 = model_r0(M, type_of(P, i), type_of(P, j));
+  const double c = -2.0 * M->kb * (r - r0) / r;
+  for (int k = 0; k < 3; ++k) f[k] = c * d[k];
+  return M->kb * (r - r0) * (r - r0);
+}
+
+/* Bend at b between bonds b->a and b->c: force on particle `on` (one of a, b,
+ * c) and energy ka (theta - theta0)^2, theta = angle between x_a - x_b and
+ * x_c - x_b.  dV/dx = 2 ka (theta - theta0) dtheta/dcos dcos/dx with dtheta/dcos
+ * = -1/sin(theta); where sin(theta) vanishes, (theta - theta0)/sin(theta) takes
+ * its limit (-1 at theta = theta0 = pi, the straight molecule). */
+static double bend_term(const mdo_params* P, const double* x, int64_t a, int64_t b, int64_t c, int64_t on,
+                        double f[3]) {
+  const mdo_model* M = &P->model;
+  double u[3] = {x[3 * a] - x[3 * b], x[3 * a + 1] - x[3 * b + 1], x[3 * a + 2] - x[3 * b + 2]};
+  double v[3] = {x[3 * c] - x[3 * b], x[3 * c + 1] - x[3 * b + 1], x[3 * c + 2] - x[3 * b + 2]};
+  min_image(P, u);
+  min_image(P, v);
+  const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2], vv = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+  const double nu = sqrt(uu), nv = sqrt(vv);
+  double cs = (u[0] * v[0] + u[1] * v[1] + u[2] * v[2]) / (nu * nv);
+  if (cs > 1.0) cs = 1.0;
+  if (cs < -1.0) cs = -1.0;
+  const double th = acos(cs), sn = sqrt(1.0 - cs * cs);
+  const double dth = th - M->theta0;
+  double ratio;
+  if (sn > 1e-12) ratio = dth / sn;
+  else ratio = (fabs(dth) < 1e-6) ? (th > 1.5 ? -1.0 : 1.0) : dth / 1e-12;
+  /* F = -dV/dx = 2 ka ratio dcos/dx */
+  const double k2 = 2.0 * M->ka * ratio;
+  double ga[3], gc[3];
+  for (int k = 0; k < 3; ++k) {
+    ga[k] = v[k] / (nu * nv) - cs * u[k] / uu;
+    gc[k] = u[k] / (nu * nv) - cs * v[k] / vv;
+  }
+  for (int k = 0; k < 3; ++k) {
+    const double g = on == a ? ga[k] : (on == c ? gc[k] : -(ga[k] + gc[k]));
+    f[k] = k2 * g;
+  }
+  return M->ka * dth * dth;
+}
+
+/* Wall about the surface centre: force on i and energy. */
+static double wall_term(const mdo_params* P, const double* x, int64_t i, double f[3]) {
+  const mdo_model* M = &P->model;
+  f[0] = f[1] = f[2] = 0.0;
+  if (!(M->wall_eps > 0.0)) return 0.0;
+  double d[3] = {x[3 * i] - P->surf[0], x[3 * i + 1] - P->surf[1], x[3 * i + 2] - P->surf[2]};
+  const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+  const double s = r - M->wall_radius;
+  if (!(s < pow(2.0, 1.0 / 6.0) * M->wall_sigma) || !(r > 0.0)) return 0.0;
+  double dphi;
+  const double phi = lj_phi(M->wall_eps, M->wall_sigma, s, &dphi);
+  for (int k = 0; k < 3; ++k) f[k] = -dphi * d[k] / r;
+  return phi + M->wall_eps;
+}
+
+/* Bonded and wall forces on i, in a fixed order: bonds to i-1 and i+1, bends
+ * centred at i-1, i and i+1, the wall.  Returns i's energy share (half of each
+ * bond, a third of each bend, all of its wall term). */
+static double bonded_i(const mdo_params* P, int64_t n, const double* x, int64_t i, double Fi[3]) {
+  const mdo_model* M = &P->model;
+  double u = 0.0, f[3];
+  if (M->bpm > 1) {
+    const int64_t m0 = (i / M->bpm) * M->bpm, m1 = m0 + M->bpm < n ? m0 + M->bpm : n;
+    if (i - 1 >= m0) {
+      u += 0.5 * bond_term(P, x, i, i - 1, f);
+      for (int k = 0; k < 3; ++k) Fi[k] += f[k];
+    }
+    if (i + 1 < m1) {
+      u += 0.5 * bond_term(P, x, i, i + 1, f);
+      for (int k = 0; k < 3; ++k) Fi[k] += f[k];
+    }
+    for (int64_t b = i - 1; b <= i + 1; ++b) {
+      if (b - 1 < m0 || b + 1 >= m1) continue;
+      u += bend_term(P, x, b - 1, b, b + 1, i, f) / 3.0;
+      for (int k = 0; k < 3; ++k) Fi[k] += f[k];
+    }
+  }
+  u += wall_term(P, x, i, f);
+  for (int k = 0; k < 3; ++k) Fi[k] += f[k];
+  return u;
+}
+
 /* Interaction of i with the candidates js[0..nj) (ascending, may include i). */
 static void accumulate_i(const mdo_params* P, int64_t i, const double* x, const int64_t* js,
                          int64_t nj, double Fi[3], double* Ui) {
   const double rc2 = P->rc * P->rc;
+  const int model = P->model.ntypes > 0;
+  const int ti = model ? type_of(P, i) : 0;
   double f0 = 0.0, f1 = 0.0, f2 = 0.0, u = 0.0;
   for (int64_t t = 0; t < nj; ++t) {
     const int64_t j = js[t];
     if (j == i) continue;
+    if (model && same_molecule(&P->model, i, j)) continue;
     double d[3] = {x[3 * i] - x[3 * j], x[3 * i + 1] - x[3 * j + 1], x[3 * i + 2] - x[3 * j + 2]};
     min_image(P, d);
     const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-    if (r2 >= rc2) continue;
-    double c;
-    const double v = pair_term(P, r2, &c);
+    double c, v;
+    if (model) {
+      const int tj = type_of(P, j);
+      const double rcij = model_rc(&P->model, ti, tj);
+      if (r2 >= rcij * rcij) continue;
+      v = model_pair(&P->model, ti, tj, r2, &c);
+    } else {
+      if (r2 >= rc2) continue;
+      v = pair_term(P, r2, &c);
+    }
     f0 += c * d[0];
     f1 += c * d[1];
     f2 += c * d[2];
@@ -352,6 +480,7 @@ int mdo_forces(const mdo_params* P, int64_t n, const double* x, double* F, doubl
           qsort(js, (size_t)nj, sizeof(int64_t), cmp_i64);
         }
         accumulate_i(P, i, x, js, nj, &F[3 * i], &ui[i]);
+        if (P->model.ntypes > 0) ui[i] += bonded_i(P, n, x, i, &F[3 * i]);
       }
       free(js);
     }

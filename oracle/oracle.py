@@ -8,6 +8,7 @@ Arrays are numpy float64 in AoS layout, shape (n, 3).
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 import subprocess
 from dataclasses import dataclass, field
@@ -35,6 +36,56 @@ def build(force: bool = False) -> str:
     return LIB_PATH
 
 
+MAX_TYPES = 4
+
+
+class _Model(C.Structure):
+    _fields_ = [
+        ("ntypes", C.c_int), ("bpm", C.c_int), ("sigma", C.c_double * MAX_TYPES),
+        ("eps", (C.c_double * MAX_TYPES) * MAX_TYPES),
+        ("rc", (C.c_double * MAX_TYPES) * MAX_TYPES), ("kb", C.c_double),
+        ("r0", (C.c_double * MAX_TYPES) * MAX_TYPES), ("ka", C.c_double), ("theta0", C.c_double),
+        ("wall_eps", C.c_double), ("wall_sigma", C.c_double), ("wall_radius", C.c_double),
+    ]
+
+
+@dataclass
+class Model:
+    """Bead model (capsid example of the SI): see mdo.h."""
+    sigma: tuple = (1.0,)
+    eps: float = 1.0                            # well depth of the pairs not in eps_pairs
+    eps_pairs: dict = field(default_factory=dict)  # {(a, b): eps}
+    rc: dict = field(default_factory=dict)      # {(a, b): rc}; absent: 2^(1/6) sigma_ab
+    bpm: int = 0
+    kb: float = 0.0
+    r0: dict = field(default_factory=dict)      # {(a, b): r0}; absent: 2^(1/6) (sigma_a + sigma_b) / 4
+    ka: float = 0.0
+    theta0: float = math.pi
+    wall_eps: float = 0.0
+    wall_sigma: float = 1.0
+    wall_radius: float = 0.0
+
+    def to_c(self) -> _Model:
+        m = _Model()
+        m.ntypes = len(self.sigma)
+        m.bpm = self.bpm
+        for a, s in enumerate(self.sigma):
+            m.sigma[a] = s
+        for a in range(MAX_TYPES):
+            for b in range(MAX_TYPES):
+                m.eps[a][b] = self.eps
+        for (a, b), v in self.eps_pairs.items():
+            m.eps[a][b] = m.eps[b][a] = v
+        for (a, b), v in self.rc.items():
+            m.rc[a][b] = m.rc[b][a] = v
+        m.kb = self.kb
+        for (a, b), v in self.r0.items():
+            m.r0[a][b] = m.r0[b][a] = v
+        m.ka, m.theta0 = self.ka, self.theta0
+        m.wall_eps, m.wall_sigma, m.wall_radius = self.wall_eps, self.wall_sigma, self.wall_radius
+        return m
+
+
 class _Params(C.Structure):
     _fields_ = [
         ("dt", C.c_double), ("kT", C.c_double), ("gamma", C.c_double),
@@ -45,6 +96,7 @@ class _Params(C.Structure):
         ("periodic", C.c_int * 3),
         ("seed", C.c_uint64), ("eta", C.c_double), ("max_iter", C.c_int),
         ("use_cells", C.c_int), ("frozen", C.c_int),
+        ("model", _Model), ("types", C.POINTER(C.c_uint8)),
     ]
 
 
@@ -68,6 +120,8 @@ class Params:
     max_iter: int = 32
     use_cells: int = 1
     frozen: int = 0
+    model: Model | None = None
+    types: np.ndarray | None = None
 
     def to_c(self) -> _Params:
         p = _Params()
@@ -88,6 +142,11 @@ class Params:
         p.max_iter = self.max_iter
         p.use_cells = self.use_cells
         p.frozen = self.frozen
+        if self.model is not None:
+            p.model = self.model.to_c()
+        if self.types is not None:
+            self._types_c = np.ascontiguousarray(self.types, dtype=np.uint8)
+            p.types = self._types_c.ctypes.data_as(C.POINTER(C.c_uint8))
         return p
 
 

@@ -63,6 +63,7 @@ class System:
     cons: np.ndarray | None = None
     mass: np.ndarray | None = None
     meta: dict = field(default_factory=dict)
+    types: np.ndarray | None = None
 
     @property
     def n(self) -> int:
@@ -176,6 +177,45 @@ def box_gas(n: int, L: float, seed: int, dmin: float = 0.9, kT: float = 1.0, mas
     p = _tangent_momenta(rng, np.zeros((n, 3)), kT, mass)
     return System(x, p, "none", (), lo, hi, per, mass=None if mass is None else np.asarray(mass, dtype=np.float64),
                   meta=dict(L=L))
+
+
+def capsomeres(n_mol: int, R: float, seed: int, sizes=(1.0, 1.35, 1.75, 1.0), bonds=None, dmin: float = 1.8,
+               max_tilt: float = 0.3, kT: float = 1.0, mass_by_volume: bool = True) -> System:
+    """n_mol linear molecules of len(sizes) beads standing on a sphere of radius R:
+    bead 0 (the base) on the sphere and constrained, the others along a
+    direction tilted from the outward normal by a random angle up to max_tilt,
+    spaced by the bond lengths (default 2^(1/6) (s_a + s_b) / 4).  Bead k has
+    type k; masses scale with bead volume (smallest 1).  Bases are placed by
+    random sequential adsorption with minimum distance dmin."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    B = len(sizes)
+    if bonds is None:
+        bonds = [2.0 ** (1.0 / 6.0) * (sizes[k] + sizes[k + 1]) / 4.0 for k in range(B - 1)]
+
+    def sampler(rng, m):
+        return R * _unit(rng.standard_normal((m, 3)))
+
+    base = _fill(sampler, n_mol, dmin, rng)
+    nh = _unit(base)
+    # tilt: rotate the normal towards a random tangent direction
+    t = rng.standard_normal((n_mol, 3))
+    t -= np.sum(t * nh, axis=1, keepdims=True) * nh
+    t = _unit(t)
+    ang = rng.uniform(0.0, max_tilt, size=n_mol)
+    d = np.cos(ang)[:, None] * nh + np.sin(ang)[:, None] * t
+    x = np.zeros((n_mol * B, 3))
+    offs = np.concatenate([[0.0], np.cumsum(bonds)])
+    for k in range(B):
+        x[k::B] = base + offs[k] * d
+    types = np.tile(np.arange(B, dtype=np.uint8), n_mol)
+    smin = min(sizes)
+    mass = np.array([(s / smin) ** 3 for s in sizes])[types] if mass_by_volume else np.ones(n_mol * B)
+    p = rng.standard_normal((n_mol * B, 3)) * np.sqrt(mass * kT)[:, None]
+    p[0::B] -= np.sum(p[0::B] * nh, axis=1, keepdims=True) * nh
+    cons = np.zeros(n_mol * B, dtype=np.uint8)
+    cons[0::B] = 1
+    return System(x, p, "sphere", (0.0, 0.0, 0.0, R), cons=cons, mass=mass, types=types,
+                  meta=dict(R=R, bpm=B, sizes=tuple(sizes), bonds=tuple(bonds)))
 
 
 def _height(x, y, A, L):
