@@ -122,6 +122,43 @@ typedef struct md_params {
   void* stream;           /* hipStream_t or NULL                                */
 } md_params;
 
+/* ---- bead model ----------------------------------------------------------------
+ * The bead model of the capsid example (SI, Virus capsid self-assembly), for
+ * one system (md_create contexts; pools run plain pair potentials only):
+ *  - bead types 0..ntypes-1 with sizes sigma[a]; sigma_ab = (sigma_a + sigma_b)/2
+ *    (additive mixing);
+ *  - truncated-shifted LJ per type pair, V = phi(r) - phi(rc_ab) for r < rc_ab,
+ *    phi = 4 eps_ab [(sigma_ab/r)^12 - (sigma_ab/r)^6]; rc_ab = 0 selects
+ *    2^(1/6) sigma_ab (purely repulsive); only between beads of different
+ *    molecules;
+ *  - molecules: particles kB .. kB+B-1 (B = beads_per_molecule, particle
+ *    indices as passed to md_set_particles) form a linear molecule, with bonds
+ *    V = kb (r - r0_ab)^2 between consecutive beads (r0_ab = 0 selects
+ *    2^(1/6)(sigma_a + sigma_b)/4) and bends V = ka (theta - theta0)^2 on
+ *    consecutive triples, theta the angle at the middle bead between its two
+ *    bonds (pi when straight);
+ *  - a repulsive wall about the surface centre c, for d = |x - c| - wall_radius
+ *    below 2^(1/6) wall_sigma: V = 4 wall_eps [(s/d)^12 - (s/d)^6 + 1/4],
+ *    s = wall_sigma; wall_eps = 0: no wall.
+ * Requires pair_kind MD_PAIR_LJ and force_fp64 = 1; params.rc is not used (the
+ * cell grid and lists use the largest rc_ab).  Tables are symmetric: entry
+ * [a][b] is used for a <= b. */
+#define MD_MAX_TYPES 4
+typedef struct md_model {
+  int ntypes;                              /* 1 .. MD_MAX_TYPES                     */
+  int beads_per_molecule;                  /* 0: no molecules (no bonds, bends or exclusions) */
+  double sigma[MD_MAX_TYPES];
+  double eps[MD_MAX_TYPES][MD_MAX_TYPES];
+  double rc[MD_MAX_TYPES][MD_MAX_TYPES];
+  double kb;
+  double r0[MD_MAX_TYPES][MD_MAX_TYPES];
+  double ka;
+  double theta0;
+  double wall_eps;
+  double wall_sigma;
+  double wall_radius;
+} md_model;
+
 /* Diagnostics of the current state (computed by md_get_state / md_pool_fetch).
  * K = sum p^2/2m, U = sum_{i<j} V_ij, kT = 2K/N_dof (Section 3.1),
  * gdist_max = max |g|/|n| over constrained particles, nv_max = max |n.p|/(|n| m). */
@@ -164,6 +201,13 @@ int md_create(const md_params* params, md_ctx** out);
 /* Set the constraint g(x) = 0 (kind and prm as listed above, nprm values).
  * Must precede md_set_particles. */
 int md_set_surface(md_ctx* ctx, int kind, const double* prm, int nprm);
+
+/* Bead model for the next md_set_particles (see md_model): copies *model and
+ * types[0..n) (the bead type of each particle, by particle index); n must equal
+ * the particle count given to md_set_particles.  model = NULL removes the
+ * model.  MD_EINVAL for a type outside 0..ntypes-1, a non-positive size or
+ * well depth, or negative stiffnesses. */
+int md_set_model(md_ctx* ctx, const md_model* model, const uint8_t* types, int64_t n);
 
 /* Set the particles: n positions x and momenta p (host, AoS, n*3 doubles).
  * mass: n masses or NULL (all 1).  constrained: n flags or NULL (all

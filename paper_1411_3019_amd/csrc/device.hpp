@@ -43,6 +43,7 @@ struct JobDev {
   int surf_kind, pair_kind, force_fp64, uniform_mass;
   int newton_cap, mode, xcur, pcur;
   int scur, newton_frozen;
+  int model, bpm;                   // bead model of the job (record in DevBufs::models); beads per molecule
   uint64_t seed;
   int64_t off, n, bm_off;
   int64_t step0, remaining;
@@ -62,6 +63,21 @@ struct JobBook {
   double a_now;                     // largest per-tile displacement bound since the last list build
 };
 __host__ __device__ constexpr JobBook fresh_book() { return JobBook{kNever, 0, 0, 0, 0, 0.0, 0.0}; }
+
+// Bead model of one job (SI, Virus capsid self-assembly), tables by type pair
+// a * kMaxTypes + b (symmetric).
+constexpr int kMaxTypes = 4;
+struct ModelDev {
+  double sig2[kMaxTypes * kMaxTypes];
+  double eps4[kMaxTypes * kMaxTypes];
+  double eps24[kMaxTypes * kMaxTypes];
+  double rc2[kMaxTypes * kMaxTypes];
+  double phic[kMaxTypes * kMaxTypes];   // phi(rc_ab), the energy shift
+  double r0[kMaxTypes * kMaxTypes];
+  double kb, ka, theta0;
+  double wall_eps, wall_sig, wall_radius, wall_cut;  // wall_cut = 2^(1/6) wall_sig
+  int ntypes, bpm;
+};
 
 // Device buffers, passed by value to every kernel.
 struct DevBufs {
@@ -88,6 +104,8 @@ struct DevBufs {
   uint32_t* INV;       // slot of each particle index after the last sort, by job offset + index
   uint32_t* SRC;       // old slot (job-relative) of each new slot during a sort
   float4* PK;          // list-build candidates in the sorted order: FP32 position, particle index bits
+  uint8_t* TYPE[2];    // bead type (jobs with a bead model); parity as ID
+  const ModelDev* models;  // per job
   double* TACC;        // per group of 64 slots: accumulated max displacement since the last build
   uint32_t* NLSTAT;    // per group of 64 slots, from the last list build: (max count, sum of stored counts)
   JobDev* jobs;
@@ -439,6 +457,188 @@ __device__ __forceinline__ double pair_energy(const JobDev& J, const DevBufs& B,
     u += J.force_fp64 ? 0.5 * v : on_grid(0.5 * v);
   }
   return u;
+}
+
+// ---------------------------------------------------------------------------
+// Bead model (SI, Virus capsid self-assembly), FP64 class only.
+// ---------------------------------------------------------------------------
+
+// Pair forces on slot i (type ti) from its list, typed truncated-shifted LJ;
+// pairs inside a molecule are not in the list.  Summed in list order (sorted
+// by particle index).
+template <bool kPer>
+__device__ __forceinline__ void pair_forces_model(const JobDev& J, const ModelDev& M, const DevBufs& B,
+                                                  const double* __restrict__ X, int64_t i, int ti, double xi,
+                                                  double yi, double zi, double& Fx, double& Fy, double& Fz) {
+  const int64_t C = B.C;
+  const int cnt = (int)B.NCNT[i];
+  const uint4* __restrict__ nl = reinterpret_cast<const uint4*>(B.NL) + i;
+  const uint8_t* __restrict__ T = B.TYPE[J.scur];
+  double fx = 0.0, fy = 0.0, fz = 0.0;
+  for (int k = 0; k < cnt; k += 4) {
+    const uint4 q = nl[(int64_t)(k >> 2) * C];
+    const uint32_t jq[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (k + u >= cnt) break;
+      const int64_t j = jq[u];
+      const int p = ti * kMaxTypes + T[j];
+      double dx = xi - X[3 * j], dy = yi - X[3 * j + 1], dz = zi - X[3 * j + 2];
+      if (kPer) min_image(J, dx, dy, dz);
+      const double r2 = dx * dx + dy * dy + dz * dz;
+      if (!(r2 < M.rc2[p])) continue;
+      const double inv = 1.0 / r2;
+      const double s2 = M.sig2[p] * inv;
+      const double s6 = s2 * s2 * s2;
+      const double c = M.eps24[p] * inv * s6 * (2.0 * s6 - 1.0);
+      fx += c * dx;
+      fy += c * dy;
+      fz += c * dz;
+    }
+  }
+  Fx = fx;
+  Fy = fy;
+  Fz = fz;
+}
+
+// Energy share of slot i from the typed pairs (half of each pair).
+__device__ __forceinline__ double pair_energy_model(const JobDev& J, const ModelDev& M, const DevBufs& B,
+                                                    const double* __restrict__ X, int64_t i, int ti, double xi,
+                                                    double yi, double zi) {
+  const int64_t C = B.C;
+  const int cnt = (int)B.NCNT[i];
+  const uint8_t* __restrict__ T = B.TYPE[J.scur];
+  const bool anyper = J.periodic[0] | J.periodic[1] | J.periodic[2];
+  double u = 0.0;
+  for (int k = 0; k < cnt; ++k) {
+    const int64_t j = B.NL[(((int64_t)(k >> 2) * C + i) << 2) + (k & 3)];
+    const int p = ti * kMaxTypes + T[j];
+    double dx = xi - X[3 * j], dy = yi - X[3 * j + 1], dz = zi - X[3 * j + 2];
+    if (anyper) min_image(J, dx, dy, dz);
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    if (!(r2 < M.rc2[p])) continue;
+    const double s2 = M.sig2[p] / r2;
+    const double s6 = s2 * s2 * s2;
+    u += 0.5 * (M.eps4[p] * s6 * (s6 - 1.0) - M.phic[p]);
+  }
+  return u;
+}
+
+// Position of the particle with job-local index id (through the inverse
+// permutation of the last sort).
+__device__ __forceinline__ void pos_of(const JobDev& J, const DevBufs& B, const double* __restrict__ X,
+                                       int64_t id, double* out) {
+  const int64_t s = J.off + B.INV[J.off + id];
+  out[0] = X[3 * s];
+  out[1] = X[3 * s + 1];
+  out[2] = X[3 * s + 2];
+}
+
+// Bonds to the previous and next bead, bends centred at the previous, this and
+// the next bead, and the wall, added to F in that order; returns the energy
+// share of this bead (half of each bond, a third of each bend, its wall term).
+// The bend force is 2 ka (theta - theta0)/sin(theta) times the gradient of
+// cos(theta); where sin(theta) vanishes that ratio takes its limit (-1 at
+// theta = theta0 = pi).
+__device__ __forceinline__ double bonded_forces(const JobDev& J, const ModelDev& M, const DevBufs& B,
+                                                const double* __restrict__ X, int64_t id, const int* tid,
+                                                const double* xs, double& Fx, double& Fy, double& Fz) {
+  // xs: positions of beads id-2 .. id+2 (3 doubles each; those outside the
+  // molecule unused); tid: their types
+  double u = 0.0;
+  const int64_t bpm = M.bpm;
+  const int64_t m0 = bpm > 0 ? (id / bpm) * bpm : id, m1 = bpm > 0 ? min(m0 + bpm, (int64_t)J.n) : id + 1;
+  const double* xi = xs + 6;
+  auto bond = [&](int q) {  // partner slot q in xs (1 or 3)
+    double d[3] = {xi[0] - xs[3 * q], xi[1] - xs[3 * q + 1], xi[2] - xs[3 * q + 2]};
+    if (J.periodic[0] | J.periodic[1] | J.periodic[2]) min_image(J, d[0], d[1], d[2]);
+    const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    const double r0 = M.r0[tid[2] * kMaxTypes + tid[q]];
+    const double c = -2.0 * M.kb * (r - r0) / r;
+    Fx += c * d[0];
+    Fy += c * d[1];
+    Fz += c * d[2];
+    u += 0.5 * (M.kb * (r - r0) * (r - r0));
+  };
+  if (bpm > 1) {
+    if (id - 1 >= m0) bond(1);
+    if (id + 1 < m1) bond(3);
+    for (int cb = 1; cb <= 3; ++cb) {  // bend centred at bead id - 2 + cb
+      const int64_t b = id - 2 + cb;
+      if (b - 1 < m0 || b + 1 >= m1) continue;
+      const double* xa = xs + 3 * (cb - 1);
+      const double* xb = xs + 3 * cb;
+      const double* xc = xs + 3 * (cb + 1);
+      double uu_[3] = {xa[0] - xb[0], xa[1] - xb[1], xa[2] - xb[2]};
+      double vv_[3] = {xc[0] - xb[0], xc[1] - xb[1], xc[2] - xb[2]};
+      if (J.periodic[0] | J.periodic[1] | J.periodic[2]) {
+        min_image(J, uu_[0], uu_[1], uu_[2]);
+        min_image(J, vv_[0], vv_[1], vv_[2]);
+      }
+      const double uu = uu_[0] * uu_[0] + uu_[1] * uu_[1] + uu_[2] * uu_[2];
+      const double vv = vv_[0] * vv_[0] + vv_[1] * vv_[1] + vv_[2] * vv_[2];
+      const double nu = sqrt(uu), nv = sqrt(vv);
+      double cs = (uu_[0] * vv_[0] + uu_[1] * vv_[1] + uu_[2] * vv_[2]) / (nu * nv);
+      cs = fmin(1.0, fmax(-1.0, cs));
+      const double th = acos(cs), sn = sqrt(1.0 - cs * cs);
+      const double dth = th - M.theta0;
+      double ratio;
+      if (sn > 1e-12)
+        ratio = dth / sn;
+      else
+        ratio = fabs(dth) < 1e-6 ? (th > 1.5 ? -1.0 : 1.0) : dth / 1e-12;
+      const double k2 = 2.0 * M.ka * ratio;
+      // this bead is the first end (cb = 3), the middle (cb = 2) or the second end (cb = 1)
+      double g[3];
+      for (int k = 0; k < 3; ++k) {
+        const double ga = vv_[k] / (nu * nv) - cs * uu_[k] / uu;
+        const double gc = uu_[k] / (nu * nv) - cs * vv_[k] / vv;
+        g[k] = cb == 3 ? ga : (cb == 1 ? gc : -(ga + gc));
+      }
+      Fx += k2 * g[0];
+      Fy += k2 * g[1];
+      Fz += k2 * g[2];
+      u += (M.ka * dth * dth) / 3.0;
+    }
+  }
+  if (M.wall_eps > 0.0) {
+    double d[3] = {xi[0] - J.surf[0], xi[1] - J.surf[1], xi[2] - J.surf[2]};
+    const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    const double s = r - M.wall_radius;
+    double f[3] = {0.0, 0.0, 0.0};
+    if (s < M.wall_cut && r > 0.0) {
+      const double sr = M.wall_sig / s;
+      const double s6 = sr * sr * sr * sr * sr * sr, s12 = s6 * s6;
+      const double dphi = -24.0 * M.wall_eps * (2.0 * s12 - s6) / s;
+      for (int k = 0; k < 3; ++k) f[k] = -dphi * d[k] / r;
+      u += 4.0 * M.wall_eps * (s12 - s6) + M.wall_eps;
+    }
+    Fx += f[0];
+    Fy += f[1];
+    Fz += f[2];
+  }
+  return u;
+}
+
+// Gather the positions and types of beads id-2 .. id+2 of id's molecule.
+__device__ __forceinline__ void molecule_window(const JobDev& J, const ModelDev& M, const DevBufs& B,
+                                                const double* __restrict__ X, int64_t id, double xi, double yi,
+                                                double zi, int ti, double* xs, int* tid) {
+  const int64_t bpm = M.bpm;
+  const int64_t m0 = bpm > 0 ? (id / bpm) * bpm : id, m1 = bpm > 0 ? min(m0 + bpm, (int64_t)J.n) : id + 1;
+  const uint8_t* __restrict__ T = B.TYPE[J.scur];
+  for (int q = 0; q < 5; ++q) {
+    const int64_t g = id - 2 + q;
+    tid[q] = 0;
+    xs[3 * q] = xs[3 * q + 1] = xs[3 * q + 2] = 0.0;
+    if (q == 2) {
+      xs[6] = xi, xs[7] = yi, xs[8] = zi;
+      tid[2] = ti;
+    } else if (g >= m0 && g < m1) {
+      pos_of(J, B, X, g, xs + 3 * q);
+      tid[q] = T[J.off + B.INV[J.off + g]];
+    }
+  }
 }
 
 // Workgroup-uniform values read from memory are moved to scalar registers, so

@@ -195,6 +195,8 @@ struct HostJob {
   double ext_lo[3] = {0, 0, 0}, ext_len[3] = {0, 0, 0};  // region the cell grid covers
   bool have_ext = false;
   double ndof = 0.0;
+  bool model = false;  // bead model (record uploaded to DevBufs::models at admission)
+  ModelDev mdev{};
 };
 
 // Per-job cell grid over the region the particles can occupy.
@@ -359,7 +361,7 @@ struct Engine {
       if (e) (void)hipEventDestroy(e), e = nullptr;
     void* ptrs[] = {B.X[0], B.X[1], B.P[0], B.P[1], B.ID[0], B.ID[1], B.FLG[0], B.FLG[1], B.MASS[0], B.MASS[1],
                     B.FC, B.OX, B.OP, B.OF, B.OD, B.NL, B.NCNT, B.BM, B.WOFF, B.CCNT, B.CSTART, B.RASTER,
-                    B.CID, B.RANK, B.INV, B.SRC, B.PK, B.TACC, B.NLSTAT, B.jobs, B.book, step_tiles_job, step_tiles_first, step_counts, aux_tiles_job,
+                    B.CID, B.RANK, B.INV, B.SRC, B.PK, B.TYPE[0], B.TYPE[1], (void*)B.models, B.TACC, B.NLSTAT, B.jobs, B.book, step_tiles_job, step_tiles_first, step_counts, aux_tiles_job,
                     aux_tiles_first, chunks_d, chunk_sums, ranges_d};
     for (void* p : ptrs)
       if (p) (void)hipFree(p);
@@ -440,9 +442,16 @@ struct Engine {
     MDCHK(dalloc(&B.INV, C));
     MDCHK(dalloc(&B.SRC, C));
     MDCHK(dalloc(&B.PK, C));
+    MDCHK(dalloc(&B.TYPE[0], C));
+    MDCHK(dalloc(&B.TYPE[1], C));
     MDCHK(dalloc(&B.TACC, C / kGroup + 1));
     HIPCHK(hipMemsetAsync(B.TACC, 0, sizeof(double) * (C / kGroup + 1), stream));
     MDCHK(dalloc(&B.jobs, max_jobs));
+    {
+      ModelDev* md = nullptr;
+      MDCHK(dalloc(&md, max_jobs));
+      B.models = md;
+    }
     MDCHK(dalloc(&B.book, max_jobs));
     {
       std::vector<JobBook> fresh(max_jobs, fresh_book());
@@ -582,6 +591,8 @@ struct Engine {
     d.newton_tol = p.newton_tol;
     d.newton_cap = p.newton_max_iter > 0 ? p.newton_max_iter : 32;
     d.newton_frozen = p.newton_frozen;
+    d.model = h.model ? 1 : 0;
+    d.bpm = h.model ? h.mdev.bpm : 0;
     d.seed = p.seed;
     d.surf_kind = h.surf_kind;
     for (int k = 0; k < MD_SURF_MAXPRM; ++k) d.surf[k] = h.surf[k];
@@ -620,8 +631,9 @@ struct Engine {
   // Place a job: allocate its slots and bitmap words, upload its state.
   int admit(const md_params& prm, int surf_kind, const double* surf, int64_t n, const double* x,
             const double* p, const double* mass, const uint8_t* cons, const double* fcomb, int64_t step0,
-            int64_t target, int* job_id) {
+            int64_t target, int* job_id, const ModelDev* model = nullptr, const uint8_t* types = nullptr) {
     MDCHK(validate_params(prm));
+    if (model && (prm.pair_kind != MD_PAIR_LJ || !prm.force_fp64 || (n > 0 && !types))) return MD_EINVAL;
     if (n < 0 || (n > 0 && (!x || !p)) || n > 0xFFFFFFF0LL) return MD_EINVAL;
     int j = -1;
     for (int q = 0; q < max_jobs; ++q)
@@ -636,6 +648,10 @@ struct Engine {
     h.surf_kind = surf_kind;
     for (int k = 0; k < MD_SURF_MAXPRM; ++k) h.surf[k] = surf ? surf[k] : 0.0;
     h.n = n;
+    if (model) {
+      h.model = true;
+      h.mdev = *model;
+    }
     fill_constants(h);
     MDCHK(validate_particles(h, x, p, mass, cons));
     MDCHK(make_grid(h, x));
@@ -680,7 +696,9 @@ struct Engine {
       MDCHK(upload(B.FLG[0] + h.off, fl.data(), n));
       for (int64_t i = 0; i < n; ++i) h.ndof += fl[i] ? 2.0 : 3.0;
       if (!uniform) MDCHK(upload(B.MASS[0] + h.off, mass, sizeof(double) * n));
+      if (model) MDCHK(upload(B.TYPE[0] + h.off, types, n));
     }
+    if (model) MDCHK(upload(const_cast<ModelDev*>(B.models) + j, model, sizeof(ModelDev)));
     jobs[j] = h;
     step_tiles_valid = false;
     *job_id = j;
@@ -1194,7 +1212,62 @@ struct md_ctx {
   bool have_particles = false;
   Engine* eng = nullptr;
   int job = -1;
+  bool have_model = false;  // bead model for the next md_set_particles
+  ModelDev model{};
+  double model_rc = 0.0;    // largest pair cut-off of the model
+  std::vector<uint8_t> types;
 };
+
+namespace {
+
+// Bead-model tables in the device form: symmetric per type pair, the
+// defaults (rc_ab = 0, r0_ab = 0) resolved, the LJ shift at the cut-off.
+int build_model(const md_model& m, ModelDev& d, double& rc_max) {
+  if (m.ntypes < 1 || m.ntypes > MD_MAX_TYPES || m.beads_per_molecule < 0) return MD_EINVAL;
+  static_assert(MD_MAX_TYPES == kMaxTypes, "type table size");
+  std::memset(&d, 0, sizeof(d));
+  const double c6 = std::pow(2.0, 1.0 / 6.0);
+  rc_max = 0.0;
+  for (int a = 0; a < m.ntypes; ++a)
+    if (!(m.sigma[a] > 0.0) || !std::isfinite(m.sigma[a])) return MD_EINVAL;
+  for (int a = 0; a < m.ntypes; ++a)
+    for (int b = a; b < m.ntypes; ++b) {
+      const double eps = m.eps[a][b], rcin = m.rc[a][b], r0in = m.r0[a][b];
+      if (!(eps > 0.0) || !std::isfinite(eps) || !(rcin >= 0.0) || !std::isfinite(rcin) || !(r0in >= 0.0) ||
+          !std::isfinite(r0in))
+        return MD_EINVAL;
+      const double s = 0.5 * (m.sigma[a] + m.sigma[b]);
+      const double rc = rcin > 0.0 ? rcin : c6 * s;
+      const double sr = s / rc, s6 = sr * sr * sr * sr * sr * sr;
+      const double r0 = r0in > 0.0 ? r0in : c6 * (m.sigma[a] + m.sigma[b]) / 4.0;
+      for (int q = 0; q < 2; ++q) {
+        const int k = q == 0 ? a * kMaxTypes + b : b * kMaxTypes + a;
+        d.sig2[k] = s * s;
+        d.eps4[k] = 4.0 * eps;
+        d.eps24[k] = 24.0 * eps;
+        d.rc2[k] = rc * rc;
+        d.phic[k] = 4.0 * eps * (s6 * s6 - s6);
+        d.r0[k] = r0;
+      }
+      rc_max = std::max(rc_max, rc);
+    }
+  if (!(m.kb >= 0.0) || !(m.ka >= 0.0) || !std::isfinite(m.kb) || !std::isfinite(m.ka) ||
+      !(m.theta0 >= 0.0 && m.theta0 <= M_PI) || !(m.wall_eps >= 0.0) || !std::isfinite(m.wall_eps) ||
+      !std::isfinite(m.wall_radius) || (m.wall_eps > 0.0 && !(m.wall_sigma > 0.0 && std::isfinite(m.wall_sigma))))
+    return MD_EINVAL;
+  d.kb = m.kb;
+  d.ka = m.ka;
+  d.theta0 = m.theta0;
+  d.wall_eps = m.wall_eps;
+  d.wall_sig = m.wall_sigma;
+  d.wall_radius = m.wall_radius;
+  d.wall_cut = c6 * m.wall_sigma;
+  d.ntypes = m.ntypes;
+  d.bpm = m.beads_per_molecule;
+  return MD_OK;
+}
+
+}  // namespace
 
 struct md_pool {
   Engine eng;
@@ -1246,15 +1319,45 @@ int md_set_surface(md_ctx* ctx, int kind, const double* prm, int nprm) {
   return MD_OK;
 }
 
+int md_set_model(md_ctx* ctx, const md_model* model, const uint8_t* types, int64_t n) {
+  if (!ctx) return MD_EINVAL;
+  if (!model) {
+    ctx->have_model = false;
+    ctx->types.clear();
+    return MD_OK;
+  }
+  if (n < 0 || (n > 0 && !types)) return MD_EINVAL;
+  if (ctx->prm.pair_kind != MD_PAIR_LJ || !ctx->prm.force_fp64) return MD_EINVAL;
+  ModelDev d;
+  double rc_max = 0.0;
+  MDCHK(build_model(*model, d, rc_max));
+  for (int64_t i = 0; i < n; ++i)
+    if (types[i] >= model->ntypes) return MD_EINVAL;
+  try {
+    ctx->types.assign(types, types + n);
+  } catch (...) {
+    return MD_ENOMEM;
+  }
+  ctx->model = d;
+  ctx->model_rc = rc_max;
+  ctx->have_model = true;
+  return MD_OK;
+}
+
 int md_set_particles(md_ctx* ctx, int64_t n, const double* x, const double* p, const double* mass,
                      const uint8_t* constrained, const double* fcomb, int64_t step0) {
   if (!ctx || n < 0 || step0 < 0) return MD_EINVAL;
   if (n > 0 && (!x || !p)) return MD_EINVAL;
+  md_params prm = ctx->prm;
+  if (ctx->have_model) {
+    if ((int64_t)ctx->types.size() != n) return MD_EINVAL;
+    prm.rc = ctx->model_rc;  // the cell grid and the lists cover the largest pair cut-off
+  }
   int64_t nslots = 0, nwords = 0;
-  MDCHK(plan_job(ctx->prm, ctx->surf_kind, ctx->surf, n, x, &nslots, &nwords));
+  MDCHK(plan_job(prm, ctx->surf_kind, ctx->surf, n, x, &nslots, &nwords));
   {
     // room for the finest grid md_tune may choose (skin 0.2)
-    md_params fine = ctx->prm;
+    md_params fine = prm;
     fine.skin = 0.2;
     int64_t s2 = 0, w2 = 0;
     if (plan_job(fine, ctx->surf_kind, ctx->surf, n, x, &s2, &w2) == MD_OK) nwords = std::max(nwords, w2);
@@ -1278,7 +1381,8 @@ int md_set_particles(md_ctx* ctx, int64_t n, const double* x, const double* p, c
     ctx->eng = e;
   }
   int j = -1;
-  MDCHK(e->admit(ctx->prm, ctx->surf_kind, ctx->surf, n, x, p, mass, constrained, fcomb, step0, step0, &j));
+  MDCHK(e->admit(prm, ctx->surf_kind, ctx->surf, n, x, p, mass, constrained, fcomb, step0, step0, &j,
+                 ctx->have_model ? &ctx->model : nullptr, ctx->have_model ? ctx->types.data() : nullptr));
   ctx->job = j;
   ctx->have_particles = true;
   return MD_OK;

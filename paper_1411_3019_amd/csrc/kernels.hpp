@@ -48,6 +48,25 @@ __device__ __forceinline__ void record_error(JobBook& K, int code, uint32_t id, 
   atomicMin(&K.stop_at, s + 1);
 }
 
+// Bead-model forces on slot i (particle index id): typed pairs, then bonds,
+// bends and the wall; returns the particle's energy share (kEnergy).
+template <bool kEnergy>
+__device__ __forceinline__ double model_forces(const JobDev& J, const ModelDev& M, const DevBufs& B,
+                                               const double* __restrict__ X, int64_t i, uint32_t id, double xi,
+                                               double yi, double zi, double& Fx, double& Fy, double& Fz) {
+  const int ti = B.TYPE[J.scur][i];
+  if (J.periodic[0] | J.periodic[1] | J.periodic[2])
+    pair_forces_model<true>(J, M, B, X, i, ti, xi, yi, zi, Fx, Fy, Fz);
+  else
+    pair_forces_model<false>(J, M, B, X, i, ti, xi, yi, zi, Fx, Fy, Fz);
+  double u = kEnergy ? pair_energy_model(J, M, B, X, i, ti, xi, yi, zi) : 0.0;
+  double xs[15];
+  int tid[5];
+  molecule_window(J, M, B, X, id, xi, yi, zi, ti, xs, tid);
+  u += bonded_forces(J, M, B, X, id, tid, xs, Fx, Fy, Fz);
+  return u;
+}
+
 // Random part of the combined force of Algorithm S1 for one particle:
 // 1/2 sqrt(m) k (xi^s + xi^{s-1}) (at a start: sqrt(m) k xi^s, the previous
 // draw being taken equal to this one).  Independent of the pair forces, so it
@@ -137,7 +156,12 @@ __device__ __forceinline__ void step_body(const DevBufs& B, const int* __restric
     double rx, ry, rz;
     langevin_kick<kF64>(J, id, m, s, start, rx, ry, rz);
     double Fx = 0.0, Fy = 0.0, Fz = 0.0;
-    if (J.pair_kind != kPairNone) pair_forces<kF64>(J, B, X, i, xi, yi, zi, Fx, Fy, Fz);
+    if (J.pair_kind != kPairNone) {
+      if (kF64 && J.model)
+        model_forces<false>(J, B.models[job], B, X, i, id, xi, yi, zi, Fx, Fy, Fz);
+      else
+        pair_forces<kF64>(J, B, X, i, xi, yi, zi, Fx, Fy, Fz);
+    }
     // the particle's own momentum and flag are loaded after the force loop,
     // which keeps them out of the loop's live registers
     double px = P[3 * i], py = P[3 * i + 1], pz = P[3 * i + 2];
@@ -246,8 +270,12 @@ __global__ void __launch_bounds__(kTile) k_finish(DevBufs B, const int* __restri
   const long long s = J.step0;
   double Fx = 0.0, Fy = 0.0, Fz = 0.0, Ui = 0.0;
   if (J.pair_kind != kPairNone) {
-    pair_forces<kF64>(J, B, X, i, xi, yi, zi, Fx, Fy, Fz);
-    Ui = pair_energy(J, B, X, i, xi, yi, zi);
+    if (kF64 && J.model) {
+      Ui = model_forces<true>(J, B.models[job], B, X, i, id, xi, yi, zi, Fx, Fy, Fz);
+    } else {
+      pair_forces<kF64>(J, B, X, i, xi, yi, zi, Fx, Fy, Fz);
+      Ui = pair_energy(J, B, X, i, xi, yi, zi);
+    }
   }
   double rx, ry, rz, fx, fy, fz;
   langevin_kick<kF64>(J, id, m, s, start, rx, ry, rz);
@@ -432,6 +460,7 @@ __global__ void __launch_bounds__(kTile) k_gather(DevBufs B, const int* __restri
   B.ID[J.scur ^ 1][d] = id;
   B.FLG[J.scur ^ 1][d] = B.FLG[J.scur][i];
   if (!J.uniform_mass) B.MASS[J.scur ^ 1][d] = B.MASS[J.scur][i];
+  if (J.model) B.TYPE[J.scur ^ 1][d] = B.TYPE[J.scur][i];
   B.PK[d] = make_float4((float)Xs[3 * i], (float)Xs[3 * i + 1], (float)Xs[3 * i + 2], __uint_as_float(id));
 }
 
@@ -541,7 +570,7 @@ __device__ __forceinline__ void min_image_f(const JobDev& J, float& dx, float& d
 template <bool kSorted>
 __device__ __forceinline__ void nlist_lane(const DevBufs& B, const JobDev& J, int64_t i, double xi, double yi,
                                            double zi, int cx, int cy, int cz, uint32_t* kid, int lane, int kmax,
-                                           int& cnt) {
+                                           int& cnt, uint32_t myid) {
   int za0, zb0, za1, zb1;
   z_runs(J, cz, za0, zb0, za1, zb1);
   const int64_t base = J.off;
@@ -554,6 +583,8 @@ __device__ __forceinline__ void nlist_lane(const DevBufs& B, const JobDev& J, in
   const double delta = 0x1p-21 * (2.0 * fmax(fabs(xi), fmax(fabs(yi), fabs(zi))) + 3.0 * rl + lper);
   const float thr = (float)((rl + delta) * (rl + delta) * (1.0 + 0x1p-20));
   const float xf = (float)xi, yf = (float)yi, zf = (float)zi;
+  // candidates with particle index in [mstart, mstart + bpm) share this molecule
+  const uint32_t bpm = (uint32_t)J.bpm, mstart = bpm != 0u ? (myid / bpm) * bpm : 0u;
   auto scan = [&](uint32_t b, uint32_t e) {
     const int64_t end = base + e;
     for (int64_t j = base + b; j < end; j += kListBatch) {
@@ -565,7 +596,9 @@ __device__ __forceinline__ void nlist_lane(const DevBufs& B, const JobDev& J, in
         float dx = xf - r[u].x, dy = yf - r[u].y, dz = zf - r[u].z;
         if (anyper) min_image_f(J, dx, dy, dz);
         const float d2 = dx * dx + dy * dy + dz * dz;
-        if (j + u < end && j + u != i && d2 < thr) {
+        // bead model: no pair terms inside a molecule
+        const bool excl = __float_as_uint(r[u].w) - mstart < bpm;
+        if (j + u < end && j + u != i && d2 < thr && !excl) {
           if (kSorted)
             list_insert(kid, lane, kmax, cnt, __float_as_uint(r[u].w));
           else
@@ -611,7 +644,7 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const int* __r
     if (J.force_fp64) {
       // FP64 class: sorted by particle index, mapped back to slots through the
       // inverse permutation, four lookups in flight at a time
-      nlist_lane<true>(B, J, i, xi, yi, zi, cx, cy, cz, kid, lane, kmax, cnt);
+      nlist_lane<true>(B, J, i, xi, yi, zi, cx, cy, cz, kid, lane, kmax, cnt, B.ID[J.scur ^ 1][i]);
       stored = cnt < kmax ? cnt : kmax;
       for (int k = 0; k < stored; k += 4) {
         uint32_t v[4];
@@ -624,7 +657,7 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const int* __r
       }
     } else {
       // FP32 class: slot order, as found
-      nlist_lane<false>(B, J, i, xi, yi, zi, cx, cy, cz, kid, lane, kmax, cnt);
+      nlist_lane<false>(B, J, i, xi, yi, zi, cx, cy, cz, kid, lane, kmax, cnt, B.ID[J.scur ^ 1][i]);
       stored = cnt < kmax ? cnt : kmax;
       for (int k = 0; k < stored; k += 4) {
         uint32_t v[4];

@@ -23,7 +23,8 @@ MD_OK, MD_EINVAL, MD_ESTATE, MD_EOFFSURF, MD_ENEWTON, MD_ENAN, MD_ENOMEM, MD_EAG
 SYMBOLS = ["md_create", "md_set_surface", "md_set_particles", "md_step", "md_get_state", "md_destroy",
            "md_strerror", "md_job_footprint", "md_pool_create", "md_pool_admit", "md_pool_run", "md_pool_poll",
            "md_pool_fetch", "md_pool_release", "md_pool_usage", "md_pool_destroy", "md_get_stats",
-           "md_pool_get_stats", "md_tune"]
+           "md_pool_get_stats", "md_tune", "md_set_model"]
+MD_MAX_TYPES = 4
 
 
 class MDError(RuntimeError):
@@ -63,6 +64,52 @@ class _Stats(C.Structure):
 
     def to_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class _Model(C.Structure):
+    _fields_ = [
+        ("ntypes", C.c_int), ("beads_per_molecule", C.c_int), ("sigma", C.c_double * MD_MAX_TYPES),
+        ("eps", (C.c_double * MD_MAX_TYPES) * MD_MAX_TYPES), ("rc", (C.c_double * MD_MAX_TYPES) * MD_MAX_TYPES),
+        ("kb", C.c_double), ("r0", (C.c_double * MD_MAX_TYPES) * MD_MAX_TYPES), ("ka", C.c_double),
+        ("theta0", C.c_double), ("wall_eps", C.c_double), ("wall_sigma", C.c_double), ("wall_radius", C.c_double),
+    ]
+
+
+@dataclass
+class Model:
+    """Bead model of md_set_model: bead sizes by type, LJ well depth (eps for
+    every type pair, eps_pairs overriding pairs), per-pair cut-offs rc (absent:
+    purely repulsive), linear molecules of beads_per_molecule consecutive
+    particles with bond stiffness kb, rest lengths r0 (absent: the default of
+    the header), bend stiffness ka about theta0, and the repulsive wall."""
+    sigma: tuple = (1.0,)
+    eps: float = 1.0
+    eps_pairs: dict = field(default_factory=dict)
+    rc: dict = field(default_factory=dict)
+    beads_per_molecule: int = 0
+    kb: float = 0.0
+    r0: dict = field(default_factory=dict)
+    ka: float = 0.0
+    theta0: float = 3.141592653589793
+    wall_eps: float = 0.0
+    wall_sigma: float = 1.0
+    wall_radius: float = 0.0
+
+    def to_c(self) -> _Model:
+        m = _Model()
+        m.ntypes = len(self.sigma)
+        m.beads_per_molecule = int(self.beads_per_molecule)
+        for a, v in enumerate(self.sigma):
+            m.sigma[a] = float(v)
+        for a in range(MD_MAX_TYPES):
+            for b in range(MD_MAX_TYPES):
+                m.eps[a][b] = float(self.eps)
+        for table, src in ((m.eps, self.eps_pairs), (m.rc, self.rc), (m.r0, self.r0)):
+            for (a, b), v in src.items():
+                table[a][b] = table[b][a] = float(v)
+        m.kb, m.ka, m.theta0 = float(self.kb), float(self.ka), float(self.theta0)
+        m.wall_eps, m.wall_sigma, m.wall_radius = float(self.wall_eps), float(self.wall_sigma), float(self.wall_radius)
+        return m
 
 
 class _JobDesc(C.Structure):
@@ -133,6 +180,7 @@ def lib():
         L.md_create.argtypes = [C.POINTER(_Params), C.POINTER(vp)]
         L.md_set_surface.argtypes = [vp, C.c_int, dp, C.c_int]
         L.md_set_particles.argtypes = [vp, C.c_int64, dp, dp, dp, u8, dp, C.c_int64]
+        L.md_set_model.argtypes = [vp, C.POINTER(_Model), u8, C.c_int64]
         L.md_step.argtypes = [vp, C.c_int64]
         L.md_get_state.argtypes = [vp, dp, dp, dp, C.POINTER(C.c_int64), C.POINTER(_Diag)]
         L.md_destroy.argtypes = [vp]
@@ -151,7 +199,7 @@ def lib():
         L.md_pool_get_stats.argtypes = [vp, C.POINTER(_Stats)]
         L.md_pool_destroy.argtypes = [vp]
         L.md_pool_destroy.restype = None
-        for name in ("md_create", "md_set_surface", "md_set_particles", "md_step", "md_get_state",
+        for name in ("md_create", "md_set_surface", "md_set_particles", "md_set_model", "md_step", "md_get_state",
                      "md_pool_create", "md_pool_admit", "md_pool_run", "md_pool_poll", "md_pool_fetch",
                      "md_pool_release", "md_pool_usage", "md_get_stats", "md_pool_get_stats", "md_tune"):
             getattr(L, name).restype = C.c_int
@@ -201,6 +249,15 @@ class System:
     def set_surface(self, surface: str, surf):
         q = np.ascontiguousarray(list(surf) + [0.0] * (8 - len(surf)), dtype=np.float64)
         _check(lib().md_set_surface(self._h, SURF[surface], _dp(q), len(surf)), "md_set_surface")
+
+    def set_model(self, model: Model | None, types=None):
+        """Bead model and per-particle types for the next set_particles."""
+        if model is None:
+            _check(lib().md_set_model(self._h, None, None, 0), "md_set_model")
+            return
+        t = np.ascontiguousarray(types, dtype=np.uint8).reshape(-1)
+        self._model = model.to_c()
+        _check(lib().md_set_model(self._h, C.byref(self._model), _u8(t), t.shape[0]), "md_set_model")
 
     def set_particles(self, x, p, mass=None, cons=None, fcomb=None, step0=0):
         x = np.asarray(x)

@@ -59,10 +59,30 @@ def _struct_fields(name):
 
 
 @pytest.mark.parametrize("cname,pyname", [("md_params", "_Params"), ("md_diag", "_Diag"),
-                                          ("md_job_desc", "_JobDesc")])
+                                          ("md_job_desc", "_JobDesc"), ("md_model", "_Model")])
 def test_struct_layout_matches_header(cname, pyname):
     from paper_1411_3019_amd import md
     assert [f for f, _ in getattr(md, pyname)._fields_] == _struct_fields(cname)
+
+
+def test_struct_sizes_match_the_c_compiler(tmp_path):
+    """sizeof of each ABI struct as the host C compiler lays it out equals the
+    ctypes structure's size."""
+    import shutil
+    import subprocess
+    from paper_1411_3019_amd import md
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    pairs = [("md_params", "_Params"), ("md_diag", "_Diag"), ("md_job_desc", "_JobDesc"), ("md_model", "_Model"),
+             ("md_stats", "_Stats")]
+    src = tmp_path / "sz.c"
+    src.write_text('#include <stdio.h>\n#include "md.h"\nint main(void) {\n'
+                   + "".join(f'  printf("%zu\\n", sizeof({c}));\n' for c, _ in pairs) + "  return 0;\n}\n")
+    exe = tmp_path / "sz"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    sizes = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    assert sizes == [C.sizeof(getattr(md, p)) for _, p in pairs]
 
 
 def test_strerror_without_gpu(libmd):

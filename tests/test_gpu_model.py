@@ -1,0 +1,184 @@
+"""GPU: the bead model of the capsid example (SI, Virus capsid self-assembly)
+against the FP64 oracle: four-bead capsomeres with the base bead on a sphere
+(RATTLE) and three free beads, typed truncated-shifted LJ with additive size
+mixing (well depth 4 kT; like pairs of types 1 and 2, the paper's types 2 and
+3, attract out to 4 sigma_0, every other pair purely repulsive), harmonic
+bonds (kb = 50) and bends (ka = 250 about pi), the repulsive wall about the
+sphere centre, and no pair terms inside a molecule.
+
+Bar: FP64 pair, bonded and constraint arithmetic on both sides, so the
+one-step map agrees to round-off (positions 1e-12 relative, momenta and
+forces 1e-9) and short trajectories stay within 1e-6; bitwise determinism
+across list schedules (lists sorted by particle index); constant-energy runs
+conserve H as well as the oracle does."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as o
+from workloads import gen
+
+from _common import rel_err, rel_pos_err, report
+
+pytestmark = pytest.mark.gpu
+
+SIZES = (1.0, 1.35, 1.75, 1.0)
+
+
+def _models(wall_radius):
+    """The same model for the oracle and for the library."""
+    from paper_1411_3019_amd import md
+    kw = dict(sigma=SIZES, eps=4.0, rc={(1, 1): 4.0, (2, 2): 4.0}, kb=50.0, ka=250.0, theta0=math.pi,
+              wall_eps=1.0 if wall_radius is not None else 0.0, wall_sigma=1.0,
+              wall_radius=wall_radius if wall_radius is not None else 0.0)
+    return o.Model(bpm=4, **kw), md.Model(beads_per_molecule=4, **kw)
+
+
+def _capsid(n_mol=600, R=16.0, seed=5):
+    s = gen.capsomeres(n_mol, R, seed, sizes=SIZES)
+    return s, R - 2.0
+
+
+def _pair(s, wall_radius, dt=0.002, gamma=1.0, seed=3, skin=0.3, step0=0):
+    """(oracle state, library system) on the same input."""
+    from paper_1411_3019_amd import md
+    om, gm = _models(wall_radius)
+    rc = 4.0
+    P = o.Params(dt=dt, surface=s.surface, surf=s.surf, box_lo=s.box_lo, box_hi=s.box_hi, periodic=s.periodic,
+                 rc=rc, pair="lj", gamma=gamma, seed=seed, model=om, types=s.types)
+    ref = o.State(P, s.x, s.p, mass=s.mass, cons=s.cons, step0=step0)
+    prm = md.Params(dt=dt, gamma=gamma, seed=seed, rc=rc, pair="lj", force_fp64=1, skin=skin,
+                    box_lo=s.box_lo, box_hi=s.box_hi, periodic=s.periodic)
+    g = md.System(prm, s.surface, s.surf)
+    g.set_model(gm, s.types)
+    g.set_particles(s.x, s.p, mass=s.mass, cons=s.cons, step0=step0)
+    return ref, g
+
+
+CASES = {
+    "capsid_sphere": lambda: _capsid(),
+    "rods_periodic": lambda: (gen.rods_box(300, 34.0, 3, sizes=SIZES), None),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_model_one_step_map(case):
+    s, rw = CASES[case]()
+    print(f"[gpu] bead model one-step {case} n={s.n}", flush=True)
+    ref, g = _pair(s, rw)
+    f0 = ref.f.copy()
+    st0 = g.get_state()
+    ref.run(1)
+    g.step(1)
+    st = g.get_state()
+    g.close()
+    e0 = rel_err(st0["f"], f0)
+    ex, ep, ef = rel_pos_err(st["x"], ref.x), rel_err(st["p"], ref.p), rel_err(st["f"], ref.f)
+    report(f"model {case} 1-step", x=ex, p=ep, f=ef, f0=e0)
+    assert e0 < 1e-9
+    assert ex < 1e-12
+    assert ep < 1e-9
+    assert ef < 1e-9
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_model_short_trajectory(case):
+    s, rw = CASES[case]()
+    print(f"[gpu] bead model 100-step {case} n={s.n}", flush=True)
+    ref, g = _pair(s, rw)
+    ref.run(100)
+    g.step(100)
+    st = g.get_state()
+    g.close()
+    d = ref.diag()
+    ex, ep = rel_pos_err(st["x"], ref.x), rel_err(st["p"], ref.p)
+    report(f"model {case} 100-step", x=ex, p=ep, dK=abs(st["diag"]["K"] / d["K"] - 1),
+           dU=abs(st["diag"]["U"] - d["U"]), rebuilds=st["diag"]["rebuilds"])
+    assert ex < 1e-6
+    assert ep < 1e-5
+    assert abs(st["diag"]["K"] - d["K"]) <= 1e-6 * abs(d["K"])
+    assert abs(st["diag"]["U"] - d["U"]) <= 1e-6 * max(1.0, abs(d["U"]))
+    if s.cons is not None and s.cons.any():
+        assert st["diag"]["gdist_max"] < 1e-13 * max(1.0, np.abs(st["x"]).max())
+
+
+def test_model_deterministic_across_list_schedules():
+    """Different skins rebuild at different steps with different slot orders;
+    the FP64 lists are kept in particle-index order, so the bits agree."""
+    s, rw = _capsid(400, 13.5, 8)
+    print(f"[gpu] bead model determinism n={s.n}", flush=True)
+    outs = []
+    for skin in (0.3, 0.3, 0.8):
+        _, g = _pair(s, rw, skin=skin, seed=11)
+        g.step(300)
+        outs.append(g.get_state())
+        g.close()
+    assert outs[2]["diag"]["rebuilds"] != outs[0]["diag"]["rebuilds"]
+    for k in (1, 2):
+        assert np.array_equal(outs[0]["x"], outs[k]["x"]) and np.array_equal(outs[0]["p"], outs[k]["p"])
+
+
+def test_model_nve_energy():
+    """No thermostat, dt = 1e-3: H = K + U (pairs, bonds, bends, wall)
+    conserved to the oracle's level on the same run."""
+    s, rw = _capsid(300, 12.0, 6)
+    print(f"[gpu] bead model NVE n={s.n}", flush=True)
+    ref, g = _pair(s, rw, dt=0.001, gamma=0.0)
+    g.step(500)
+    ref.run(500)
+    d0, r0 = g.get_state()["diag"], ref.diag()
+    H0, Hr0 = d0["K"] + d0["U"], r0["K"] + r0["U"]
+    assert abs(H0 / Hr0 - 1) < 1e-8
+    dev_g, dev_r = [], []
+    for _ in range(6):
+        g.step(500)
+        ref.run(500)
+        d, r = g.get_state()["diag"], ref.diag()
+        dev_g.append(abs((d["K"] + d["U"]) / H0 - 1))
+        dev_r.append(abs((r["K"] + r["U"]) / Hr0 - 1))
+    g.close()
+    report("model NVE 3500 steps", gpu_max_dH=max(dev_g), oracle_max_dH=max(dev_r))
+    assert max(dev_g) < 1e-3
+    assert max(dev_g) < 10 * max(dev_r) + 1e-6
+
+
+def test_model_resume_is_exact():
+    s, rw = _capsid(300, 12.0, 9)
+    print(f"[gpu] bead model resume n={s.n}", flush=True)
+    _, g = _pair(s, rw, seed=4)
+    g.step(150)
+    full = g.get_state()
+    g.close()
+    _, g = _pair(s, rw, seed=4)
+    g.step(70)
+    mid = g.get_state()
+    g.set_particles(mid["x"], mid["p"], mass=s.mass, cons=s.cons, fcomb=mid["f"], step0=mid["step"])
+    g.step(80)
+    part = g.get_state()
+    g.close()
+    assert part["step"] == 150
+    assert np.array_equal(full["x"], part["x"]) and np.array_equal(full["p"], part["p"])
+
+
+def test_model_argument_checks():
+    from paper_1411_3019_amd import md
+    s, rw = _capsid(50, 6.0, 2)
+    _, gm = _models(rw)
+    prm = md.Params(dt=0.002, rc=4.0, pair="lj", force_fp64=0)
+    g = md.System(prm, s.surface, s.surf)
+    with pytest.raises(md.MDError):  # FP32 force class
+        g.set_model(gm, s.types)
+    g.close()
+    prm = md.Params(dt=0.002, rc=4.0, pair="lj", force_fp64=1)
+    g = md.System(prm, s.surface, s.surf)
+    bad = s.types.copy()
+    bad[3] = 4
+    with pytest.raises(md.MDError):  # type outside 0..ntypes-1
+        g.set_model(gm, bad)
+    g.set_model(gm, s.types[:-4])
+    with pytest.raises(md.MDError):  # type count differs from the particle count
+        g.set_particles(s.x, s.p, mass=s.mass, cons=s.cons)
+    g.set_model(None)
+    g.set_particles(s.x, s.p, mass=s.mass, cons=s.cons)  # plain LJ again
+    g.close()

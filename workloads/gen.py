@@ -218,6 +218,36 @@ def capsomeres(n_mol: int, R: float, seed: int, sizes=(1.0, 1.35, 1.75, 1.0), bo
                   meta=dict(R=R, bpm=B, sizes=tuple(sizes), bonds=tuple(bonds)))
 
 
+def rods_box(n_mol: int, L: float, seed: int, sizes=(1.0, 1.35, 1.75, 1.0), dmin: float = 4.0,
+             kT: float = 1.0) -> System:
+    """n_mol free linear molecules (no surface, nothing constrained) in a
+    periodic cube of side L: centres by random sequential adsorption with
+    minimum distance dmin, random orientations, beads spaced by the default
+    bond lengths and wrapped into the box (so some bonds cross its faces).
+    Bead k has type k; masses scale with bead volume (smallest 1)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    B = len(sizes)
+    bonds = [2.0 ** (1.0 / 6.0) * (sizes[k] + sizes[k + 1]) / 4.0 for k in range(B - 1)]
+    lo, hi, per = (0.0, 0.0, 0.0), (L, L, L), (1, 1, 1)
+
+    def sampler(rng, m):
+        return rng.uniform(0.0, L, size=(m, 3))
+
+    c = _fill(sampler, n_mol, dmin, rng, lo, hi, per)
+    d = _unit(rng.standard_normal((n_mol, 3)))
+    offs = np.concatenate([[0.0], np.cumsum(bonds)])
+    offs -= 0.5 * offs[-1]
+    x = np.zeros((n_mol * B, 3))
+    for k in range(B):
+        x[k::B] = np.mod(c + offs[k] * d, L)
+    types = np.tile(np.arange(B, dtype=np.uint8), n_mol)
+    smin = min(sizes)
+    mass = np.array([(s / smin) ** 3 for s in sizes])[types]
+    p = rng.standard_normal((n_mol * B, 3)) * np.sqrt(mass * kT)[:, None]
+    return System(x, p, "none", (), lo, hi, per, mass=mass, types=types,
+                  meta=dict(L=L, bpm=B, sizes=tuple(sizes), bonds=tuple(bonds)))
+
+
 def _height(x, y, A, L):
     k = 2.0 * np.pi / L
     return A * np.sin(k * x) * np.sin(k * y)
