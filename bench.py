@@ -97,7 +97,7 @@ def cpu_baseline(s, run, budget_s: float = 12.0):
                       f"linked cells, OpenMP; {t:.1f} s"}
 
 
-def timed_steps(s, run, skin: float, steps: int, warmup: int):
+def timed_steps(s, run, skin: float, steps: int, warmup: int, model=None):
     """Steps per second of one system (after warm-up), and the mean step-kernel
     launch time from the library's HIP-event timing."""
     from paper_1411_3019_amd import md
@@ -105,6 +105,8 @@ def timed_steps(s, run, skin: float, steps: int, warmup: int):
                     sigma=run.get("sigma", 1.0), rc=run["rc"], pair=run["pair"], force_fp64=run["force_fp64"],
                     skin=skin, seed=run["seed"], box_lo=s.box_lo, box_hi=s.box_hi, periodic=s.periodic)
     sysm = md.System(prm, s.surface, s.surf)
+    if model is not None:
+        sysm.set_model(model, s.types)
     sysm.set_particles(s.x, s.p, mass=s.mass, cons=s.cons)
     sysm.step(warmup)
     device_sync()
@@ -129,7 +131,10 @@ def extra_benches(skin: float):
                   (where RATTLE reduces to 2-D velocity Verlet), 1,000,000 LJ
                   particles each at area fraction 0.4, same potential and step;
       membrane    1.85M particles, mostly free, around a constrained height-field
-                  membrane (periodic box)."""
+                  membrane (periodic box);
+      capsid      the bead model of the SI's capsid example at scale: 500,000
+                  four-bead capsomeres (2M beads) on one spherical template,
+                  FP64 forces."""
     from workloads import gen
     out = {}
     s, run = gen.torus_lj_2m(250_000)
@@ -150,7 +155,23 @@ def extra_benches(skin: float):
                                     f"{s.n - int(s.cons.sum())} free WCA particles, periodic 400x400x60",
                            skin=skin, **timed_steps(s, run, skin, 2000, 300))
     log(f"[bench] membrane: {out['membrane']}")
+    out["capsid"] = capsid_bench(skin)
     return out
+
+
+def capsid_bench(skin: float, steps: int = 1000, warmup: int = 200):
+    from paper_1411_3019_amd import md
+    from workloads import gen
+    s, run = gen.capsid_2m()
+    mp = gen.capsid_model()
+    model = md.Model(sigma=mp["sigma"], eps=mp["eps"], rc=mp["rc"], beads_per_molecule=mp["beads_per_molecule"],
+                     kb=mp["kb"], ka=mp["ka"], theta0=mp["theta0"], wall_eps=mp["wall_eps"],
+                     wall_sigma=mp["wall_sigma"], wall_radius=run["R"] - mp["wall_inset"])
+    res = dict(workload=f"capsid bead model: {s.n // 4} four-bead capsomeres ({s.n} beads) on a sphere "
+                        f"R={run['R']:.1f}, typed LJ (eps 4, attractive like pairs to 4 sigma_0), bonds, bends, "
+                        "wall, fp64 forces", skin=skin, **timed_steps(s, run, skin, steps, warmup, model=model))
+    log(f"[bench] capsid: {res}")
+    return res
 
 
 def serving_bench(njobs: int, nplain: int, rate: float, budget_gb: float):

@@ -204,9 +204,9 @@ int md_set_surface(md_ctx* ctx, int kind, const double* prm, int nprm);
 
 /* Bead model for the next md_set_particles (see md_model): copies *model and
  * types[0..n) (the bead type of each particle, by particle index); n must equal
- * the particle count given to md_set_particles.  model = NULL removes the
- * model.  MD_EINVAL for a type outside 0..ntypes-1, a non-positive size or
- * well depth, or negative stiffnesses. */
+ * the particle count given to md_set_particles, and below 2^30.  model = NULL
+ * removes the model.  MD_EINVAL for a type outside 0..ntypes-1, a non-positive
+ * size or well depth, or negative stiffnesses. */
 int md_set_model(md_ctx* ctx, const md_model* model, const uint8_t* types, int64_t n);
 
 /* Set the particles: n positions x and momenta p (host, AoS, n*3 doubles).

@@ -67,6 +67,11 @@ __host__ __device__ constexpr JobBook fresh_book() { return JobBook{kNever, 0, 0
 // Bead model of one job (SI, Virus capsid self-assembly), tables by type pair
 // a * kMaxTypes + b (symmetric).
 constexpr int kMaxTypes = 4;
+// Bead-model jobs carry the bead type in the top two bits of the candidate
+// record's particle index (such jobs hold fewer than 2^30 particles).
+constexpr int kTypeShift = 30;
+constexpr uint32_t kIdMask = (1u << kTypeShift) - 1u;
+
 struct ModelDev {
   double sig2[kMaxTypes * kMaxTypes];
   double eps4[kMaxTypes * kMaxTypes];

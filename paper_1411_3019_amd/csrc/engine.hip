@@ -633,7 +633,8 @@ struct Engine {
             const double* p, const double* mass, const uint8_t* cons, const double* fcomb, int64_t step0,
             int64_t target, int* job_id, const ModelDev* model = nullptr, const uint8_t* types = nullptr) {
     MDCHK(validate_params(prm));
-    if (model && (prm.pair_kind != MD_PAIR_LJ || !prm.force_fp64 || (n > 0 && !types))) return MD_EINVAL;
+    if (model && (prm.pair_kind != MD_PAIR_LJ || !prm.force_fp64 || (n > 0 && !types) || n > (int64_t)kIdMask))
+      return MD_EINVAL;
     if (n < 0 || (n > 0 && (!x || !p)) || n > 0xFFFFFFF0LL) return MD_EINVAL;
     int j = -1;
     for (int q = 0; q < max_jobs; ++q)
@@ -840,8 +841,14 @@ struct Engine {
     hipLaunchKernelGGL(k_scan_c, dim3(nc), dim3(kScanThreads), 0, stream, B.CSTART, chunks_d + nb, chunk_sums + nb);
     hipLaunchKernelGGL(k_perm, dim3(ntiles), dim3(kTile), 0, stream, B, aux_tiles_job, aux_tiles_first);
     hipLaunchKernelGGL(k_gather, dim3(ntiles), dim3(kTile), 0, stream, B, aux_tiles_job, aux_tiles_first);
-    hipLaunchKernelGGL(k_nlist, dim3(kNlistPerTile * ntiles), dim3(kNlistBlock), lds, stream, B, aux_tiles_job,
-                       aux_tiles_first);
+    bool any_model = false;
+    for (int j : set) any_model = any_model || jobs[j].model;
+    if (any_model)
+      hipLaunchKernelGGL(k_nlist<true>, dim3(kNlistPerTile * ntiles), dim3(kNlistBlock), lds, stream, B,
+                         aux_tiles_job, aux_tiles_first);
+    else
+      hipLaunchKernelGGL(k_nlist<false>, dim3(kNlistPerTile * ntiles), dim3(kNlistBlock), lds, stream, B,
+                         aux_tiles_job, aux_tiles_first);
     hipLaunchKernelGGL(k_job_stats, dim3(max_jobs), dim3(kStatsThreads), 0, stream, B, 1);
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(ev[3], stream));

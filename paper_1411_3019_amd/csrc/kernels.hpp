@@ -460,8 +460,14 @@ __global__ void __launch_bounds__(kTile) k_gather(DevBufs B, const int* __restri
   B.ID[J.scur ^ 1][d] = id;
   B.FLG[J.scur ^ 1][d] = B.FLG[J.scur][i];
   if (!J.uniform_mass) B.MASS[J.scur ^ 1][d] = B.MASS[J.scur][i];
-  if (J.model) B.TYPE[J.scur ^ 1][d] = B.TYPE[J.scur][i];
-  B.PK[d] = make_float4((float)Xs[3 * i], (float)Xs[3 * i + 1], (float)Xs[3 * i + 2], __uint_as_float(id));
+  uint32_t w = id;
+  if (J.model) {
+    // bead model: the type rides in the top two bits of the record's index
+    const uint8_t t = B.TYPE[J.scur][i];
+    B.TYPE[J.scur ^ 1][d] = t;
+    w |= (uint32_t)t << kTypeShift;
+  }
+  B.PK[d] = make_float4((float)Xs[3 * i], (float)Xs[3 * i + 1], (float)Xs[3 * i + 2], __uint_as_float(w));
 }
 
 // Occupied cells with raster index below r, for the compact cell index.
@@ -567,10 +573,12 @@ __device__ __forceinline__ void min_image_f(const JobDev& J, float& dx, float& d
   if (J.periodic[2]) dz -= (float)J.box_len[2] * rintf(dz * (float)J.inv_box_len[2]);
 }
 
-template <bool kSorted>
+// kModel: bead model (FP64 class): each candidate is tested against the list
+// radius of its type pair, rc_ab + skin, and pairs inside a molecule are left out.
+template <bool kSorted, bool kModel>
 __device__ __forceinline__ void nlist_lane(const DevBufs& B, const JobDev& J, int64_t i, double xi, double yi,
                                            double zi, int cx, int cy, int cz, uint32_t* kid, int lane, int kmax,
-                                           int& cnt, uint32_t myid) {
+                                           int& cnt, uint32_t myid, const ModelDev* M, int ti) {
   int za0, zb0, za1, zb1;
   z_runs(J, cz, za0, zb0, za1, zb1);
   const int64_t base = J.off;
@@ -583,8 +591,19 @@ __device__ __forceinline__ void nlist_lane(const DevBufs& B, const JobDev& J, in
   const double delta = 0x1p-21 * (2.0 * fmax(fabs(xi), fmax(fabs(yi), fabs(zi))) + 3.0 * rl + lper);
   const float thr = (float)((rl + delta) * (rl + delta) * (1.0 + 0x1p-20));
   const float xf = (float)xi, yf = (float)yi, zf = (float)zi;
-  // candidates with particle index in [mstart, mstart + bpm) share this molecule
-  const uint32_t bpm = (uint32_t)J.bpm, mstart = bpm != 0u ? (myid / bpm) * bpm : 0u;
+  // bead model: list radius per partner type (rounding bound as above, which
+  // covers the shorter radii too); candidates with particle index in
+  // [mstart, mstart + bpm) share this molecule
+  float tthr[kMaxTypes];
+  if (kModel) {
+    const double skin = 2.0 * J.half_skin;
+#pragma unroll
+    for (int b = 0; b < kMaxTypes; ++b) {
+      const double r = sqrt(M->rc2[ti * kMaxTypes + b]) + skin;
+      tthr[b] = (float)((r + delta) * (r + delta) * (1.0 + 0x1p-20));
+    }
+  }
+  const uint32_t bpm = (uint32_t)J.bpm, mstart = bpm != 0u ? (myid / bpm) * bpm : 0u;  // bpm = 0: no molecules
   auto scan = [&](uint32_t b, uint32_t e) {
     const int64_t end = base + e;
     for (int64_t j = base + b; j < end; j += kListBatch) {
@@ -596,11 +615,21 @@ __device__ __forceinline__ void nlist_lane(const DevBufs& B, const JobDev& J, in
         float dx = xf - r[u].x, dy = yf - r[u].y, dz = zf - r[u].z;
         if (anyper) min_image_f(J, dx, dy, dz);
         const float d2 = dx * dx + dy * dy + dz * dz;
-        // bead model: no pair terms inside a molecule
-        const bool excl = __float_as_uint(r[u].w) - mstart < bpm;
-        if (j + u < end && j + u != i && d2 < thr && !excl) {
+        const uint32_t w = __float_as_uint(r[u].w);
+        uint32_t q;
+        bool take;
+        if (kModel) {
+          const uint32_t tj = w >> kTypeShift;
+          q = w & kIdMask;
+          const float t = tj == 0u ? tthr[0] : (tj == 1u ? tthr[1] : (tj == 2u ? tthr[2] : tthr[3]));
+          take = d2 < t && q - mstart >= bpm;
+        } else {
+          q = w;
+          take = d2 < thr && w - mstart >= bpm;
+        }
+        if (j + u < end && j + u != i && take) {
           if (kSorted)
-            list_insert(kid, lane, kmax, cnt, __float_as_uint(r[u].w));
+            list_insert(kid, lane, kmax, cnt, q);
           else
             list_append(kid, lane, kmax, cnt, (uint32_t)(j + u - base));
         }
@@ -624,6 +653,9 @@ __device__ __forceinline__ void nlist_lane(const DevBufs& B, const JobDev& J, in
 // force sums run in particle-index order.  FP32 class: slots in the order the
 // walk finds them (ascending), since its force sums do not depend on the order;
 // neighbouring lanes then read neighbouring memory in the force loop.
+// kWithModel: the instance launched when a bead-model job is among those built
+// (the plain instance keeps the model path out of its register budget).
+template <bool kWithModel>
 __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const int* __restrict__ tile_job,
                                                        const int64_t* __restrict__ tile_first) {
   extern __shared__ uint32_t kid[];  // lists [kmax][kNlistBlock]
@@ -644,7 +676,11 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const int* __r
     if (J.force_fp64) {
       // FP64 class: sorted by particle index, mapped back to slots through the
       // inverse permutation, four lookups in flight at a time
-      nlist_lane<true>(B, J, i, xi, yi, zi, cx, cy, cz, kid, lane, kmax, cnt, B.ID[J.scur ^ 1][i]);
+      if (kWithModel && J.model)
+        nlist_lane<true, kWithModel>(B, J, i, xi, yi, zi, cx, cy, cz, kid, lane, kmax, cnt, B.ID[J.scur ^ 1][i],
+                               B.models + job, B.TYPE[J.scur ^ 1][i]);
+      else
+        nlist_lane<true, false>(B, J, i, xi, yi, zi, cx, cy, cz, kid, lane, kmax, cnt, 0u, nullptr, 0);
       stored = cnt < kmax ? cnt : kmax;
       for (int k = 0; k < stored; k += 4) {
         uint32_t v[4];
@@ -657,7 +693,7 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const int* __r
       }
     } else {
       // FP32 class: slot order, as found
-      nlist_lane<false>(B, J, i, xi, yi, zi, cx, cy, cz, kid, lane, kmax, cnt, B.ID[J.scur ^ 1][i]);
+      nlist_lane<false, false>(B, J, i, xi, yi, zi, cx, cy, cz, kid, lane, kmax, cnt, 0u, nullptr, 0);
       stored = cnt < kmax ? cnt : kmax;
       for (int k = 0; k < stored; k += 4) {
         uint32_t v[4];

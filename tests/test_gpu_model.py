@@ -182,3 +182,38 @@ def test_model_argument_checks():
     g.set_model(None)
     g.set_particles(s.x, s.p, mass=s.mass, cons=s.cons)  # plain LJ again
     g.close()
+
+
+def test_full_size_capsid_2m_one_step():
+    """The 2,000,000-bead capsid workload in the benchmark's launch
+    configuration (skin 0.5): one step, every bead compared with the oracle."""
+    from paper_1411_3019_amd import md
+    s, run = gen.capsid_2m()
+    mp = gen.capsid_model()
+    common = dict(sigma=mp["sigma"], eps=mp["eps"], rc=mp["rc"], kb=mp["kb"], ka=mp["ka"], theta0=mp["theta0"],
+                  wall_eps=mp["wall_eps"], wall_sigma=mp["wall_sigma"], wall_radius=run["R"] - mp["wall_inset"])
+    om = o.Model(bpm=mp["beads_per_molecule"], **common)
+    gm = md.Model(beads_per_molecule=mp["beads_per_molecule"], **common)
+    print(f"[gpu] full-size capsid one step n={s.n}", flush=True)
+    P = o.Params(dt=run["dt"], surface=s.surface, surf=s.surf, rc=run["rc"], pair="lj", gamma=run["gamma"],
+                 kT=run["kT"], seed=run["seed"], model=om, types=s.types)
+    ref = o.State(P, s.x, s.p, mass=s.mass, cons=s.cons)
+    f0 = ref.f.copy()
+    ref.run(1)
+    prm = md.Params(dt=run["dt"], kT=run["kT"], gamma=run["gamma"], seed=run["seed"], rc=run["rc"], pair="lj",
+                    force_fp64=1, skin=0.5)
+    g = md.System(prm, s.surface, s.surf)
+    g.set_model(gm, s.types)
+    g.set_particles(s.x, s.p, mass=s.mass, cons=s.cons)
+    st0 = g.get_state()
+    g.step(1)
+    st = g.get_state()
+    g.close()
+    ex, ep, ef = rel_pos_err(st["x"], ref.x), rel_err(st["p"], ref.p), rel_err(st["f"], ref.f)
+    report("capsid2m 1-step", x=ex, p=ep, f=ef, f0=rel_err(st0["f"], f0))
+    assert ex < 1e-12
+    assert ep < 1e-9
+    assert ef < 1e-9
+    d = ref.diag()
+    assert abs(st["diag"]["U"] / d["U"] - 1) < 1e-9
+    assert st["diag"]["gdist_max"] < 1e-13 * 600.0

@@ -186,7 +186,10 @@ def capsomeres(n_mol: int, R: float, seed: int, sizes=(1.0, 1.35, 1.75, 1.0), bo
     direction tilted from the outward normal by a random angle up to max_tilt,
     spaced by the bond lengths (default 2^(1/6) (s_a + s_b) / 4).  Bead k has
     type k; masses scale with bead volume (smallest 1).  Bases are placed by
-    random sequential adsorption with minimum distance dmin."""
+    random sequential adsorption with minimum distance dmin.  Molecules whose
+    tilted beads come closer than 0.95 sigma_ab to a bead of another molecule
+    are stood upright (repeated until no such contact is left)."""
+    from scipy.spatial import cKDTree
     rng = np.random.Generator(np.random.PCG64(seed))
     B = len(sizes)
     if bonds is None:
@@ -202,12 +205,23 @@ def capsomeres(n_mol: int, R: float, seed: int, sizes=(1.0, 1.35, 1.75, 1.0), bo
     t -= np.sum(t * nh, axis=1, keepdims=True) * nh
     t = _unit(t)
     ang = rng.uniform(0.0, max_tilt, size=n_mol)
-    d = np.cos(ang)[:, None] * nh + np.sin(ang)[:, None] * t
-    x = np.zeros((n_mol * B, 3))
     offs = np.concatenate([[0.0], np.cumsum(bonds)])
-    for k in range(B):
-        x[k::B] = base + offs[k] * d
     types = np.tile(np.arange(B, dtype=np.uint8), n_mol)
+    sz = np.asarray(sizes, dtype=np.float64)[types]
+    x = np.zeros((n_mol * B, 3))
+    while True:
+        d = np.cos(ang)[:, None] * nh + np.sin(ang)[:, None] * t
+        for k in range(B):
+            x[k::B] = base + offs[k] * d
+        pr = cKDTree(x).query_pairs(0.95 * float(max(sizes)), output_type="ndarray")
+        pr = pr[pr[:, 0] // B != pr[:, 1] // B]
+        r = np.linalg.norm(x[pr[:, 0]] - x[pr[:, 1]], axis=1)
+        bad = pr[r < 0.95 * 0.5 * (sz[pr[:, 0]] + sz[pr[:, 1]])]
+        mol = np.unique(bad // B)
+        mol = mol[ang[mol] != 0.0]
+        if mol.size == 0:
+            break
+        ang[mol] = 0.0
     smin = min(sizes)
     mass = np.array([(s / smin) ** 3 for s in sizes])[types] if mass_by_volume else np.ones(n_mol * B)
     p = rng.standard_normal((n_mol * B, 3)) * np.sqrt(mass * kT)[:, None]
@@ -389,6 +403,27 @@ def membrane_mixed(seed: int = 3, n_c: int = 77_955, n_b: int = 1_772_349) -> tu
 # ----------------------------------------------------------------------------- serving stream
 
 SERVING_SURFACES = ("sphere", "ellipsoid", "torus")
+
+
+def capsid_model(sizes=(1.0, 1.35, 1.75, 1.0)) -> dict:
+    """Bead-model parameters of the SI's capsid example: four beads (red base,
+    grey, beige, blue), well depth 4 kT for every pair, like pairs of the
+    beige and of the grey type (types 1 and 2 here) attracting out to
+    4 sigma_0, all others purely repulsive; kb = 50, ka = 250 about pi; the
+    wall: eps_w = sigma_w = 1, its radius 2 sigma_0 inside the template (a
+    choice: the SI does not give it)."""
+    return dict(sigma=tuple(sizes), eps=4.0, rc={(1, 1): 4.0, (2, 2): 4.0}, beads_per_molecule=len(sizes),
+                kb=50.0, ka=250.0, theta0=math.pi, wall_eps=1.0, wall_sigma=1.0, wall_inset=2.0)
+
+
+def capsid_2m(seed: int = 21, n_mol: int = 500_000, area_per_mol: float = 6.0) -> tuple[System, dict]:
+    """500,000 four-bead capsomeres (2,000,000 beads) on one spherical template
+    with area_per_mol sigma_0^2 of template per capsomere (R = 488.6), beige
+    size 1.75 (mid-range of the SI's table), Langevin kT = 1, gamma = 1,
+    dt = 0.002, FP64 forces."""
+    R = math.sqrt(n_mol * area_per_mol / (4.0 * math.pi))
+    s = capsomeres(n_mol, R, seed)
+    return s, dict(dt=0.002, kT=1.0, gamma=1.0, rc=4.0, pair="lj", force_fp64=1, seed=seed, R=R)
 
 
 def serving_job(jid: int, seed: int = 5, nmin: int = 64, nmax: int = 16384, smin: float = 1e3,
