@@ -134,7 +134,9 @@ def extra_benches(skin: float):
                   membrane (periodic box);
       capsid      the bead model of the SI's capsid example at scale: 500,000
                   four-bead capsomeres (2M beads) on one spherical template,
-                  FP64 forces."""
+                  FP64 forces;
+      rods_20k    the simplified capsid workload: 20,000 three-bead rods with
+                  one bead on a sphere of radius 50."""
     from workloads import gen
     out = {}
     s, run = gen.torus_lj_2m(250_000)
@@ -156,21 +158,40 @@ def extra_benches(skin: float):
                            skin=skin, **timed_steps(s, run, skin, 2000, 300))
     log(f"[bench] membrane: {out['membrane']}")
     out["capsid"] = capsid_bench(skin)
+    out["rods_20k"] = rods_bench(skin)
     return out
 
 
-def capsid_bench(skin: float, steps: int = 1000, warmup: int = 200):
+def bead_model(mp: dict, R: float):
+    """md.Model from a parameter set of workloads.gen (wall radius: the given
+    inset inside the template radius R)."""
     from paper_1411_3019_amd import md
+    return md.Model(sigma=mp["sigma"], eps=mp["eps"], eps_pairs=mp.get("eps_pairs", {}), rc=mp["rc"],
+                    r0=mp.get("r0", {}), beads_per_molecule=mp["beads_per_molecule"], kb=mp["kb"], ka=mp["ka"],
+                    theta0=mp["theta0"], wall_eps=mp["wall_eps"], wall_sigma=mp["wall_sigma"],
+                    wall_radius=R - mp["wall_inset"])
+
+
+def capsid_bench(skin: float, steps: int = 1000, warmup: int = 200):
     from workloads import gen
     s, run = gen.capsid_2m()
-    mp = gen.capsid_model()
-    model = md.Model(sigma=mp["sigma"], eps=mp["eps"], rc=mp["rc"], beads_per_molecule=mp["beads_per_molecule"],
-                     kb=mp["kb"], ka=mp["ka"], theta0=mp["theta0"], wall_eps=mp["wall_eps"],
-                     wall_sigma=mp["wall_sigma"], wall_radius=run["R"] - mp["wall_inset"])
+    model = bead_model(gen.capsid_model(), run["R"])
     res = dict(workload=f"capsid bead model: {s.n // 4} four-bead capsomeres ({s.n} beads) on a sphere "
                         f"R={run['R']:.1f}, typed LJ (eps 4, attractive like pairs to 4 sigma_0), bonds, bends, "
                         "wall, fp64 forces", skin=skin, **timed_steps(s, run, skin, steps, warmup, model=model))
     log(f"[bench] capsid: {res}")
+    return res
+
+
+def rods_bench(skin: float, steps: int = 2000, warmup: int = 300):
+    from workloads import gen
+    s, run = gen.capsid_rods_20k()
+    model = bead_model(gen.capsid_rods_model(), run["R"])
+    res = dict(workload=f"{s.n // 3} three-bead rods ({s.n} beads), bead 0 on a sphere R={run['R']:.0f}; "
+                        "bonds kb 500 r0 1, bends ka 200, LJ eps 1.5 rc 2.5 between tip beads, WCA otherwise, "
+                        "gamma 0.5, dt 0.001, fp64 forces", skin=skin,
+               **timed_steps(s, run, skin, steps, warmup, model=model))
+    log(f"[bench] rods 20k: {res}")
     return res
 
 

@@ -478,28 +478,50 @@ __device__ __forceinline__ void pair_forces_model(const JobDev& J, const ModelDe
   const int64_t C = B.C;
   const int cnt = (int)B.NCNT[i];
   const uint4* __restrict__ nl = reinterpret_cast<const uint4*>(B.NL) + i;
-  const uint8_t* __restrict__ T = B.TYPE[J.scur];
+  const double* __restrict__ row_rc2 = M.rc2 + ti * kMaxTypes;
+  const double* __restrict__ row_sig2 = M.sig2 + ti * kMaxTypes;
+  const double* __restrict__ row_eps24 = M.eps24 + ti * kMaxTypes;
   double fx = 0.0, fy = 0.0, fz = 0.0;
-  for (int k = 0; k < cnt; k += 4) {
+  // entry: slot in the low bits, partner type in the top two; the partner's
+  // position and the pair's table entries are loaded side by side
+  auto add = [&](uint32_t e, double ax, double ay, double az) {
+    const uint32_t tj = e >> kTypeShift;
+    double dx = xi - ax, dy = yi - ay, dz = zi - az;
+    if (kPer) min_image(J, dx, dy, dz);
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    if (!(r2 < row_rc2[tj])) return;
+    const double inv = 1.0 / r2;
+    const double s2 = row_sig2[tj] * inv;
+    const double s6 = s2 * s2 * s2;
+    const double c = row_eps24[tj] * inv * s6 * (2.0 * s6 - 1.0);
+    fx += c * dx;
+    fy += c * dy;
+    fz += c * dz;
+  };
+  int k = 0;
+  for (; k + 4 <= cnt; k += 4) {
     const uint4 q = nl[(int64_t)(k >> 2) * C];
-    const uint32_t jq[4] = {q.x, q.y, q.z, q.w};
+    const uint32_t e[4] = {q.x, q.y, q.z, q.w};
+    double ax[4], ay[4], az[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      if (k + u >= cnt) break;
-      const int64_t j = jq[u];
-      const int p = ti * kMaxTypes + T[j];
-      double dx = xi - X[3 * j], dy = yi - X[3 * j + 1], dz = zi - X[3 * j + 2];
-      if (kPer) min_image(J, dx, dy, dz);
-      const double r2 = dx * dx + dy * dy + dz * dz;
-      if (!(r2 < M.rc2[p])) continue;
-      const double inv = 1.0 / r2;
-      const double s2 = M.sig2[p] * inv;
-      const double s6 = s2 * s2 * s2;
-      const double c = M.eps24[p] * inv * s6 * (2.0 * s6 - 1.0);
-      fx += c * dx;
-      fy += c * dy;
-      fz += c * dz;
+      const int64_t j = e[u] & kIdMask;
+      ax[u] = X[3 * j];
+      ay[u] = X[3 * j + 1];
+      az[u] = X[3 * j + 2];
     }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) add(e[u], ax[u], ay[u], az[u]);
+  }
+  if (k < cnt) {
+    const uint4 q = nl[(int64_t)(k >> 2) * C];
+    const uint32_t e[3] = {q.x, q.y, q.z};
+#pragma unroll
+    for (int u = 0; u < 3; ++u)
+      if (k + u < cnt) {
+        const int64_t j = e[u] & kIdMask;
+        add(e[u], X[3 * j], X[3 * j + 1], X[3 * j + 2]);
+      }
   }
   Fx = fx;
   Fy = fy;
@@ -512,12 +534,12 @@ __device__ __forceinline__ double pair_energy_model(const JobDev& J, const Model
                                                     double yi, double zi) {
   const int64_t C = B.C;
   const int cnt = (int)B.NCNT[i];
-  const uint8_t* __restrict__ T = B.TYPE[J.scur];
   const bool anyper = J.periodic[0] | J.periodic[1] | J.periodic[2];
   double u = 0.0;
   for (int k = 0; k < cnt; ++k) {
-    const int64_t j = B.NL[(((int64_t)(k >> 2) * C + i) << 2) + (k & 3)];
-    const int p = ti * kMaxTypes + T[j];
+    const uint32_t e = B.NL[(((int64_t)(k >> 2) * C + i) << 2) + (k & 3)];
+    const int64_t j = e & kIdMask;
+    const int p = ti * kMaxTypes + (int)(e >> kTypeShift);
     double dx = xi - X[3 * j], dy = yi - X[3 * j + 1], dz = zi - X[3 * j + 2];
     if (anyper) min_image(J, dx, dy, dz);
     const double r2 = dx * dx + dy * dy + dz * dz;

@@ -314,10 +314,12 @@ struct Engine {
   std::vector<HostJob> jobs;
   FirstFit slots, words;
   // device scratch for launch descriptors
-  int* step_tiles_job = nullptr;       // [2][tile_cap]: fp64-force tiles, then fp32-force tiles
+  // step tile classes, one step kernel each: FP64 forces, FP32 forces, bead model (FP64)
+  static constexpr int kClasses = 3;
+  int* step_tiles_job = nullptr;       // [kClasses][tile_cap]
   int64_t* step_tiles_first = nullptr;
-  int* step_counts = nullptr;          // [2]: tiles in each list (read by the step kernel)
-  int grid64 = 0, grid32 = 0;          // grid sizes baked into the cached graphs
+  int* step_counts = nullptr;          // [kClasses]: tiles in each list (read by the step kernels)
+  int grid[kClasses] = {0, 0, 0};      // grid sizes baked into the cached graphs
   int* aux_tiles_job = nullptr;        // rebuild / finish lists
   int64_t* aux_tiles_first = nullptr;
   int64_t tile_cap = 0;
@@ -341,8 +343,8 @@ struct Engine {
   static constexpr int kSubEvents = 16;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   hipEvent_t ev_sub[kSubEvents] = {};
-  std::vector<int> last_tj[2];
-  std::vector<int64_t> last_tf[2];
+  std::vector<int> last_tj[kClasses];
+  std::vector<int64_t> last_tf[kClasses];
   size_t nl_bytes = 0;
 
   ~Engine() { release(); }
@@ -461,10 +463,10 @@ struct Engine {
     tile_cap = C / kTile + max_jobs + 8;
     MDCHK(dalloc(&B.NLSTAT, 2 * (C / kGroup + 1)));
     HIPCHK(hipMemsetAsync(B.NLSTAT, 0, sizeof(uint32_t) * 2 * (C / kGroup + 1), stream));
-    MDCHK(dalloc(&step_tiles_job, 2 * tile_cap));
-    MDCHK(dalloc(&step_tiles_first, 2 * tile_cap));
-    MDCHK(dalloc(&step_counts, 2));
-    HIPCHK(hipMemsetAsync(step_counts, 0, 2 * sizeof(int), stream));
+    MDCHK(dalloc(&step_tiles_job, kClasses * tile_cap));
+    MDCHK(dalloc(&step_tiles_first, kClasses * tile_cap));
+    MDCHK(dalloc(&step_counts, kClasses));
+    HIPCHK(hipMemsetAsync(step_counts, 0, kClasses * sizeof(int), stream));
     MDCHK(dalloc(&aux_tiles_job, tile_cap));
     MDCHK(dalloc(&aux_tiles_first, tile_cap));
     chunk_cap = (C + max_jobs) / kScanChunk + BMW / kScanChunk + 4 * max_jobs + 16;
@@ -633,7 +635,8 @@ struct Engine {
             const double* p, const double* mass, const uint8_t* cons, const double* fcomb, int64_t step0,
             int64_t target, int* job_id, const ModelDev* model = nullptr, const uint8_t* types = nullptr) {
     MDCHK(validate_params(prm));
-    if (model && (prm.pair_kind != MD_PAIR_LJ || !prm.force_fp64 || (n > 0 && !types) || n > (int64_t)kIdMask))
+    // bead-model lists carry the partner type in the top two bits of a slot index
+    if (model && (prm.pair_kind != MD_PAIR_LJ || !prm.force_fp64 || (n > 0 && !types) || C > (int64_t)kIdMask))
       return MD_EINVAL;
     if (n < 0 || (n > 0 && (!x || !p)) || n > 0xFFFFFFF0LL) return MD_EINVAL;
     int j = -1;
@@ -923,20 +926,23 @@ struct Engine {
   // much smaller than it.
   int prepare_step_tiles() {
     if (step_tiles_valid) return MD_OK;
-    std::vector<int> tj[2];
-    std::vector<int64_t> tf[2];
+    std::vector<int> tj[kClasses];
+    std::vector<int64_t> tf[kClasses];
     for (int j = 0; j < max_jobs; ++j) {
       const HostJob& h = jobs[j];
       if (!h.used || h.done || h.status != MD_OK) continue;
-      const int c = h.dev.force_fp64 ? 0 : 1;
+      const int c = h.model ? 2 : (h.dev.force_fp64 ? 0 : 1);
       tiles_of(h, j, tj[c], tf[c]);
     }
-    for (int c = 0; c < 2; ++c)
+    bool same = true;
+    for (int c = 0; c < kClasses; ++c) {
       if ((int64_t)tj[c].size() > tile_cap) return MD_ENOMEM;
+      same = same && tj[c] == last_tj[c] && tf[c] == last_tf[c];
+    }
     step_tiles_valid = true;
-    if (tj[0] == last_tj[0] && tf[0] == last_tf[0] && tj[1] == last_tj[1] && tf[1] == last_tf[1]) return MD_OK;
-    int counts[2];
-    for (int c = 0; c < 2; ++c) {
+    if (same) return MD_OK;
+    int counts[kClasses];
+    for (int c = 0; c < kClasses; ++c) {
       counts[c] = (int)tj[c].size();
       if (!tj[c].empty()) {
         MDCHK(upload(step_tiles_job + c * tile_cap, tj[c].data(), sizeof(int) * tj[c].size()));
@@ -946,14 +952,14 @@ struct Engine {
       last_tf[c].swap(tf[c]);
     }
     MDCHK(upload(step_counts, counts, sizeof(counts)));
-    const int want64 = grid_for(counts[0]), want32 = grid_for(counts[1]);
-    auto fits = [](int grid, int count, int want) {
-      if (count == 0) return grid == 0;
-      return grid >= count && grid <= 4 * want;
+    auto fits = [](int g, int count, int want) {
+      if (count == 0) return g == 0;
+      return g >= count && g <= 4 * want;
     };
-    if (!fits(grid64, counts[0], want64) || !fits(grid32, counts[1], want32)) {
-      grid64 = want64;
-      grid32 = want32;
+    bool refit = false;
+    for (int c = 0; c < kClasses; ++c) refit = refit || !fits(grid[c], counts[c], grid_for(counts[c]));
+    if (refit) {
+      for (int c = 0; c < kClasses; ++c) grid[c] = grid_for(counts[c]);
       drop_graphs();
     }
     return MD_OK;
@@ -961,12 +967,15 @@ struct Engine {
 
   void enqueue_steps(int t0, int k) {
     for (int t = t0; t < t0 + k; ++t) {
-      if (grid64 > 0)
-        hipLaunchKernelGGL(k_step_f64, dim3(grid64), dim3(kTile), 0, stream, B, step_tiles_job, step_tiles_first,
+      if (grid[0] > 0)
+        hipLaunchKernelGGL(k_step_f64, dim3(grid[0]), dim3(kTile), 0, stream, B, step_tiles_job, step_tiles_first,
                            step_counts, t);
-      if (grid32 > 0)
-        hipLaunchKernelGGL(k_step_f32, dim3(grid32), dim3(kTile), 0, stream, B, step_tiles_job + tile_cap,
+      if (grid[1] > 0)
+        hipLaunchKernelGGL(k_step_f32, dim3(grid[1]), dim3(kTile), 0, stream, B, step_tiles_job + tile_cap,
                            step_tiles_first + tile_cap, step_counts + 1, t);
+      if (grid[2] > 0)
+        hipLaunchKernelGGL(k_step_model, dim3(grid[2]), dim3(kTile), 0, stream, B, step_tiles_job + 2 * tile_cap,
+                           step_tiles_first + 2 * tile_cap, step_counts + 2, t);
     }
   }
 
@@ -1072,7 +1081,7 @@ struct Engine {
     MDCHK(read_book());
     for (int q = 0; q < nsub; ++q) stats.step_kernel_ms += elapsed_ms(ev_sub[2 * q], ev_sub[2 * q + 1]);
     stats.chunks += 1;
-    stats.step_launches += (int64_t)kk * ((grid64 > 0) + (grid32 > 0));
+    stats.step_launches += (int64_t)kk * ((grid[0] > 0) + (grid[1] > 0) + (grid[2] > 0));
     const int longest = collect_build_stats();
     int64_t adv = 0;
     for (int j = 0; j < max_jobs; ++j) {

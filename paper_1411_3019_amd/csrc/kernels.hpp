@@ -120,7 +120,7 @@ __device__ __forceinline__ void combined_force(const JobDev& J, const DevBufs& B
 // tile and shares no barrier with the others, so it leaves as soon as its own
 // particles are done.  (Workgroups of one wavefront would be capped by the
 // per-CU workgroup limit well below the register-bound occupancy.)
-template <bool kF64>
+template <bool kF64, bool kModel>
 __device__ __forceinline__ void step_body(const DevBufs& B, const int* __restrict__ tile_job,
                                           const int64_t* __restrict__ tile_first, const int* __restrict__ ntiles_ptr,
                                           int t) {
@@ -157,7 +157,7 @@ __device__ __forceinline__ void step_body(const DevBufs& B, const int* __restric
     langevin_kick<kF64>(J, id, m, s, start, rx, ry, rz);
     double Fx = 0.0, Fy = 0.0, Fz = 0.0;
     if (J.pair_kind != kPairNone) {
-      if (kF64 && J.model)
+      if (kModel)
         model_forces<false>(J, B.models[job], B, X, i, id, xi, yi, zi, Fx, Fy, Fz);
       else
         pair_forces<kF64>(J, B, X, i, xi, yi, zi, Fx, Fy, Fz);
@@ -238,14 +238,28 @@ __device__ __forceinline__ void step_body(const DevBufs& B, const int* __restric
 __global__ void __launch_bounds__(kTile) __attribute__((amdgpu_waves_per_eu(MDK_STEP32_WAVES, 8)))
 k_step_f32(DevBufs B, const int* __restrict__ tile_job, const int64_t* __restrict__ tile_first,
            const int* __restrict__ ntiles_ptr, int t) {
-  step_body<false>(B, tile_job, tile_first, ntiles_ptr, t);
+  step_body<false, false>(B, tile_job, tile_first, ntiles_ptr, t);
 }
 
 // FP64 pair forces and FP64 Box-Muller.
 __global__ void __launch_bounds__(kTile) k_step_f64(DevBufs B, const int* __restrict__ tile_job,
                                                     const int64_t* __restrict__ tile_first,
                                                     const int* __restrict__ ntiles_ptr, int t) {
-  step_body<true>(B, tile_job, tile_first, ntiles_ptr, t);
+  step_body<true, false>(B, tile_job, tile_first, ntiles_ptr, t);
+}
+
+#ifndef MDK_STEPMODEL_WAVES
+#define MDK_STEPMODEL_WAVES 5
+#endif
+
+// Bead-model jobs (FP64 forces): typed pairs, bonds, bends and the wall;
+// occupancy target MDK_STEPMODEL_WAVES wavefronts per SIMD (5 fits without
+// spilling).
+__global__ void __launch_bounds__(kTile) __attribute__((amdgpu_waves_per_eu(MDK_STEPMODEL_WAVES, 8)))
+k_step_model(DevBufs B, const int* __restrict__ tile_job,
+                                                      const int64_t* __restrict__ tile_first,
+                                                      const int* __restrict__ ntiles_ptr, int t) {
+  step_body<true, true>(B, tile_job, tile_first, ntiles_ptr, t);
 }
 
 // Finish: state at the current step m (x^m, p^m, f^m) and per-particle
@@ -682,12 +696,17 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const int* __r
       else
         nlist_lane<true, false>(B, J, i, xi, yi, zi, cx, cy, cz, kid, lane, kmax, cnt, 0u, nullptr, 0);
       stored = cnt < kmax ? cnt : kmax;
+      // bead model: the partner's type rides in the top two bits of the entry
+      const uint8_t* __restrict__ T = B.TYPE[J.scur ^ 1];
+      const bool typed = kWithModel && J.model;
       for (int k = 0; k < stored; k += 4) {
         uint32_t v[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const uint32_t q = k + u < stored ? kid[(k + u) * kNlistBlock + lane] : 0u;  // 0: a valid index
-          v[u] = k + u < stored ? (uint32_t)base + B.INV[base + q] : 0u;
+          const uint32_t sl = (uint32_t)base + B.INV[base + q];
+          v[u] = k + u < stored ? sl : 0u;
+          if (typed && k + u < stored) v[u] |= (uint32_t)T[sl] << kTypeShift;
         }
         reinterpret_cast<uint4*>(B.NL)[(int64_t)(k >> 2) * C + i] = make_uint4(v[0], v[1], v[2], v[3]);
       }

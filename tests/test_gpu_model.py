@@ -184,17 +184,30 @@ def test_model_argument_checks():
     g.close()
 
 
-def test_full_size_capsid_2m_one_step():
-    """The 2,000,000-bead capsid workload in the benchmark's launch
-    configuration (skin 0.5): one step, every bead compared with the oracle."""
+def _bead_models(mp, R):
     from paper_1411_3019_amd import md
-    s, run = gen.capsid_2m()
-    mp = gen.capsid_model()
-    common = dict(sigma=mp["sigma"], eps=mp["eps"], rc=mp["rc"], kb=mp["kb"], ka=mp["ka"], theta0=mp["theta0"],
-                  wall_eps=mp["wall_eps"], wall_sigma=mp["wall_sigma"], wall_radius=run["R"] - mp["wall_inset"])
-    om = o.Model(bpm=mp["beads_per_molecule"], **common)
-    gm = md.Model(beads_per_molecule=mp["beads_per_molecule"], **common)
-    print(f"[gpu] full-size capsid one step n={s.n}", flush=True)
+    kw = dict(sigma=mp["sigma"], eps=mp["eps"], eps_pairs=mp.get("eps_pairs", {}), rc=mp["rc"], r0=mp.get("r0", {}),
+              kb=mp["kb"], ka=mp["ka"], theta0=mp["theta0"], wall_eps=mp["wall_eps"], wall_sigma=mp["wall_sigma"],
+              wall_radius=R - mp["wall_inset"])
+    return o.Model(bpm=mp["beads_per_molecule"], **kw), md.Model(beads_per_molecule=mp["beads_per_molecule"], **kw)
+
+
+FULL = {
+    "capsid_2m": lambda: (gen.capsid_2m(), gen.capsid_model()),
+    "rods_20k": lambda: (gen.capsid_rods_20k(), gen.capsid_rods_model()),
+    "rods_2k": lambda: (gen.capsid_rods_20k(n_mol=2000, R=15.8), gen.capsid_rods_model()),
+}
+
+
+@pytest.mark.parametrize("case", list(FULL))
+def test_full_size_bead_workloads_one_step(case):
+    """The bead-model workloads the benchmark times, at full size and in its
+    launch configuration (skin 0.5): one step, every bead compared with the
+    oracle (rods_2k: the rod workload at a tenth of the molecules)."""
+    from paper_1411_3019_amd import md
+    (s, run), mp = FULL[case]()
+    om, gm = _bead_models(mp, run["R"])
+    print(f"[gpu] full-size {case} one step n={s.n}", flush=True)
     P = o.Params(dt=run["dt"], surface=s.surface, surf=s.surf, rc=run["rc"], pair="lj", gamma=run["gamma"],
                  kT=run["kT"], seed=run["seed"], model=om, types=s.types)
     ref = o.State(P, s.x, s.p, mass=s.mass, cons=s.cons)
@@ -210,10 +223,37 @@ def test_full_size_capsid_2m_one_step():
     st = g.get_state()
     g.close()
     ex, ep, ef = rel_pos_err(st["x"], ref.x), rel_err(st["p"], ref.p), rel_err(st["f"], ref.f)
-    report("capsid2m 1-step", x=ex, p=ep, f=ef, f0=rel_err(st0["f"], f0))
+    report(f"{case} 1-step", x=ex, p=ep, f=ef, f0=rel_err(st0["f"], f0))
     assert ex < 1e-12
     assert ep < 1e-9
     assert ef < 1e-9
     d = ref.diag()
     assert abs(st["diag"]["U"] / d["U"] - 1) < 1e-9
-    assert st["diag"]["gdist_max"] < 1e-13 * 600.0
+    assert st["diag"]["gdist_max"] < 1e-13 * max(1.0, np.abs(st["x"]).max())
+
+
+def test_rods_short_trajectory():
+    """The rod workload's parameters (kb 500, ka 200, tip attraction) at 2,000
+    molecules: 200 steps against the oracle."""
+    from paper_1411_3019_amd import md
+    (s, run), mp = FULL["rods_2k"]()
+    om, gm = _bead_models(mp, run["R"])
+    print(f"[gpu] rods 200-step n={s.n}", flush=True)
+    P = o.Params(dt=run["dt"], surface=s.surface, surf=s.surf, rc=run["rc"], pair="lj", gamma=run["gamma"],
+                 kT=run["kT"], seed=run["seed"], model=om, types=s.types)
+    ref = o.State(P, s.x, s.p, mass=s.mass, cons=s.cons)
+    ref.run(200)
+    prm = md.Params(dt=run["dt"], kT=run["kT"], gamma=run["gamma"], seed=run["seed"], rc=run["rc"], pair="lj",
+                    force_fp64=1, skin=0.3)
+    g = md.System(prm, s.surface, s.surf)
+    g.set_model(gm, s.types)
+    g.set_particles(s.x, s.p, mass=s.mass, cons=s.cons)
+    g.step(200)
+    st = g.get_state()
+    g.close()
+    d = ref.diag()
+    ex, ep = rel_pos_err(st["x"], ref.x), rel_err(st["p"], ref.p)
+    report("rods_2k 200-step", x=ex, p=ep, dK=abs(st["diag"]["K"] / d["K"] - 1), dU=abs(st["diag"]["U"] - d["U"]))
+    assert ex < 1e-6
+    assert abs(st["diag"]["K"] - d["K"]) <= 1e-6 * abs(d["K"])
+    assert abs(st["diag"]["U"] - d["U"]) <= 1e-6 * max(1.0, abs(d["U"]))

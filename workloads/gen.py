@@ -426,6 +426,25 @@ def capsid_2m(seed: int = 21, n_mol: int = 500_000, area_per_mol: float = 6.0) -
     return s, dict(dt=0.002, kT=1.0, gamma=1.0, rc=4.0, pair="lj", force_fp64=1, seed=seed, R=R)
 
 
+def capsid_rods_model() -> dict:
+    """Bead-model parameters of the three-bead rod workload: equal sizes 1,
+    bonds kb = 500 with rest length 1, bends ka = 200 about pi, LJ well depth
+    1.5 with cut-off 2.5 between type-2 (tip) beads, purely repulsive LJ
+    (eps 1) otherwise, no wall."""
+    return dict(sigma=(1.0, 1.0, 1.0), eps=1.0, eps_pairs={(2, 2): 1.5}, rc={(2, 2): 2.5},
+                r0={(0, 1): 1.0, (1, 2): 1.0}, beads_per_molecule=3, kb=500.0, ka=200.0, theta0=math.pi,
+                wall_eps=0.0, wall_sigma=1.0, wall_inset=0.0)
+
+
+def capsid_rods_20k(seed: int = 11, n_mol: int = 20_000, R: float = 50.0) -> tuple[System, dict]:
+    """20,000 three-bead rods with bead 0 on a sphere of radius 50 (template
+    area fraction 0.5 of unit disks; at radius 25 the same count would need
+    twice the template's area), random tilts up to 0.3 rad, unit masses;
+    Langevin kT = 1, gamma = 0.5, dt = 0.001, FP64 forces."""
+    s = capsomeres(n_mol, R, seed, sizes=(1.0, 1.0, 1.0), bonds=(1.0, 1.0), dmin=0.9)
+    return s, dict(dt=0.001, kT=1.0, gamma=0.5, rc=2.5, pair="lj", force_fp64=1, seed=seed, R=R)
+
+
 def serving_job(jid: int, seed: int = 5, nmin: int = 64, nmax: int = 16384, smin: float = 1e3,
                 smax: float = 1e4) -> tuple[System, dict]:
     """Job jid of the serving stream: N log-uniform in [nmin, nmax], surface
