@@ -136,7 +136,9 @@ def extra_benches(skin: float):
                   four-bead capsomeres (2M beads) on one spherical template,
                   FP64 forces;
       rods_20k    the simplified capsid workload: 20,000 three-bead rods with
-                  one bead on a sphere of radius 50."""
+                  one bead on a sphere of radius 50;
+      bridge      the piecewise thylakoid bridge surface at the size of the
+                  paper's crowding study (4000 particles)."""
     from workloads import gen
     out = {}
     s, run = gen.torus_lj_2m(250_000)
@@ -159,6 +161,12 @@ def extra_benches(skin: float):
     log(f"[bench] membrane: {out['membrane']}")
     out["capsid"] = capsid_bench(skin)
     out["rods_20k"] = rods_bench(skin)
+    s = gen.bridge(4000, 10.0, 1.5, 3.0, 70.0, 13)
+    run = dict(dt=0.002, kT=1.0, gamma=1.0, rc=2.0 ** (1.0 / 6.0), pair="lj", force_fp64=1, seed=13)
+    out["bridge"] = dict(workload="piecewise bridge surface (cylinder Rb 1.5, length 10, connectors R 3, two "
+                                  "70x70 periodic planes), 4000 WCA particles, fp64 forces", skin=skin,
+                         **timed_steps(s, run, skin, 4000, 500))
+    log(f"[bench] bridge: {out['bridge']}")
     return out
 
 

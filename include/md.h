@@ -69,7 +69,17 @@ extern "C" {
  *   MD_SURF_CYLINDER   x0 y0 z0 a b c R   g = a(x-x0)^2 + b(y-y0)^2 + c(z-z0)^2 - R^2,
  *                                         one of a, b, c zero            (SI S3.1)
  *   MD_SURF_HEIGHT     z0 A Lx Ly         g = z - z0 - A sin(2 pi x/Lx) sin(2 pi y/Ly);
- *                                         needs a box periodic in x and y   */
+ *                                         needs a box periodic in x and y
+ *   MD_SURF_BRIDGE     x0 y0 z0 Lb Rb R   piecewise (SI S3.1, the thylakoid bridge): with
+ *                                         u = x-x0, r = |(y-y0, z-z0)|, h = Lb/2:
+ *                                         |u| <= h:        cylinder (R/Rb)(Rb^2 - r^2);
+ *                                         else r < Rb+R:   connector (|u|-h)^2 + (r-Rb-R)^2 - R^2;
+ *                                         else:            plane 2R(|u| - h - R).
+ *                                         The piece is chosen by the position g is
+ *                                         evaluated at; the factors make n continuous
+ *                                         where pieces meet (|n| = 2R there).  Lb >= 0,
+ *                                         Rb, R > 0; along periodic y or z the box side
+ *                                         must be at least 2(Rb + R).  */
 #define MD_SURF_NONE 0
 #define MD_SURF_PLANE 1
 #define MD_SURF_SPHERE 2
@@ -77,6 +87,7 @@ extern "C" {
 #define MD_SURF_TORUS 4
 #define MD_SURF_CYLINDER 5
 #define MD_SURF_HEIGHT 6
+#define MD_SURF_BRIDGE 7
 #define MD_SURF_MAXPRM 8
 
 /* ---- pair potentials (Eq. S1) ---------------------------------------------- */

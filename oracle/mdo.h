@@ -43,7 +43,11 @@ enum {
   MDO_SURF_ELLIPSOID = 3, /* prm: cx cy cz a b c       g = sum (x_k-c_k)^2/a_k^2 - 1     */
   MDO_SURF_TORUS = 4,     /* prm: cx cy cz Rt r        g = (rho-Rt)^2 + (z-cz)^2 - r^2   */
   MDO_SURF_CYLINDER = 5,  /* prm: x0 y0 z0 a b c R     g = a(x-x0)^2+b(y-y0)^2+c(z-z0)^2-R^2 */
-  MDO_SURF_HEIGHT = 6     /* prm: z0 A Lx Ly           g = z - z0 - A sin(2pi x/Lx) sin(2pi y/Ly) */
+  MDO_SURF_HEIGHT = 6,    /* prm: z0 A Lx Ly           g = z - z0 - A sin(2pi x/Lx) sin(2pi y/Ly) */
+  MDO_SURF_BRIDGE = 7     /* prm: x0 y0 z0 Lb Rb R     piecewise (SI S3.1): a cylinder of radius Rb
+                           * along x over |x-x0| <= Lb/2, connectors (R0 = Rb, tube radius R) at
+                           * each end, and the planes x = x0 +- (Lb/2 + R) beyond them; each
+                           * piece is scaled so that n is continuous across the joins */
 };
 
 enum {

@@ -154,6 +154,43 @@ double mdo_surface_g(const mdo_params* P, const double x[3], double grad[3]) {
       grad[2] = 1.0;
       break;
     }
+    case MDO_SURF_BRIDGE: {
+      /* SI Section S3.1: the bridge between two blocks is a cylinder along x
+       * (a = 0, b = c = 1, radius Rb), joined at each end by a connector
+       * (distance to a circle of radius R in the (x, r) plane, centred at
+       * x = x0 +- Lb/2, r = R0 + R with R0 = Rb) to a plane perpendicular to x.
+       * The piece is chosen by position: |x - x0| <= Lb/2 the cylinder, else
+       * r < Rb + R the connector, else the plane.  RATTLE is unchanged under
+       * g -> alpha g, so each piece is multiplied by the constant that makes
+       * n continuous where the pieces meet on the surface (|n| = 2R there):
+       * the cylinder by -R/Rb, the plane's coefficient a = +-2R. */
+      const double u = x[0] - q[0], dy = x[1] - q[1], dz = x[2] - q[2];
+      const double half = 0.5 * q[3], Rb = q[4], R = q[5], rc = Rb + R;
+      const double r = sqrt(dy * dy + dz * dz);
+      if (fabs(u) <= half) {
+        const double s = -R / Rb;
+        g = s * (dy * dy + dz * dz - Rb * Rb);
+        grad[0] = 0.0;
+        grad[1] = 2.0 * s * dy;
+        grad[2] = 2.0 * s * dz;
+      } else if (r < rc) {
+        const double x0 = u > 0.0 ? half : -half;
+        const double e = r - rc;
+        g = (u - x0) * (u - x0) + e * e - R * R;
+        const double f = 2.0 * (1.0 - rc / r);
+        grad[0] = 2.0 * (u - x0);
+        grad[1] = f * dy;
+        grad[2] = f * dz;
+      } else {
+        const double a = u > 0.0 ? 2.0 * R : -2.0 * R;
+        const double xp = u > 0.0 ? half + R : -(half + R);
+        g = a * (u - xp);
+        grad[0] = a;
+        grad[1] = 0.0;
+        grad[2] = 0.0;
+      }
+      break;
+    }
     default:
       grad[0] = grad[1] = grad[2] = 0.0;
       return 0.0;

@@ -19,7 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 SRC_PATH = os.path.join(HERE, "oracle.c")
 
-SURF = {"none": 0, "plane": 1, "sphere": 2, "ellipsoid": 3, "torus": 4, "cylinder": 5, "height": 6}
+SURF = {"none": 0, "plane": 1, "sphere": 2, "ellipsoid": 3, "torus": 4, "cylinder": 5, "height": 6, "bridge": 7}
 PAIR = {"none": 0, "lj": 1, "lj_smooth": 2}
 
 

@@ -21,7 +21,7 @@ constexpr int kNlistBlock = kTile;  // threads per workgroup in the list build
 constexpr int kNlistPerTile = kTile / kNlistBlock;
 
 enum : int { kSurfNone = 0, kSurfPlane = 1, kSurfSphere = 2, kSurfEllipsoid = 3, kSurfTorus = 4,
-             kSurfCylinder = 5, kSurfHeight = 6 };
+             kSurfCylinder = 5, kSurfHeight = 6, kSurfBridge = 7 };
 enum : int { kPairNone = 0, kPairLJ = 1, kPairLJSmooth = 2 };
 enum : int { kModeSteady = 0, kModeStart = 1, kModeStartGiven = 2 };
 enum : int { kErrNewton = 1, kErrNaN = 2 };
@@ -248,6 +248,32 @@ __device__ __forceinline__ double surf_eval(const JobDev& J, double x, double y,
       ny = -q[1] * ky * sx * cy;
       nz = 1.0;
       return z - q[0] - q[1] * sx * sy;
+    }
+    case kSurfBridge: {
+      // piecewise (SI S3.1): q[3..7] hold Lb/2, Rb, R, Rb + R, R/Rb on the device;
+      // the piece is chosen by the evaluation point
+      const double u = x - q[0], dy = y - q[1], dz = z - q[2];
+      const double r2 = dy * dy + dz * dz;
+      if (fabs(u) <= q[3]) {  // bridge cylinder, scaled by -R/Rb
+        nx = 0.0;
+        ny = -2.0 * q[7] * dy;
+        nz = -2.0 * q[7] * dz;
+        return q[7] * (q[4] * q[4] - r2);
+      }
+      const double r = sqrt(r2);
+      const double ue = u > 0.0 ? u - q[3] : u + q[3];  // from the connector's end of the bridge
+      if (r < q[6]) {  // connector: distance to the circle of radius R about r = Rb + R
+        const double f = 2.0 * (1.0 - q[6] / r);
+        nx = 2.0 * ue;
+        ny = f * dy;
+        nz = f * dz;
+        const double e = r - q[6];
+        return ue * ue + e * e - q[5] * q[5];
+      }
+      const double a = u > 0.0 ? 2.0 * q[5] : -2.0 * q[5];  // plane x = x0 +- (Lb/2 + R)
+      nx = a;
+      ny = nz = 0.0;
+      return a * (ue - (u > 0.0 ? q[5] : -q[5]));
     }
     default:
       nx = ny = nz = 0.0;

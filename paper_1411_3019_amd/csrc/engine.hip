@@ -113,8 +113,27 @@ int surf_nprm(int kind) {
     case MD_SURF_TORUS: return 5;
     case MD_SURF_CYLINDER: return 7;
     case MD_SURF_HEIGHT: return 4;
+    case MD_SURF_BRIDGE: return 6;
     default: return -1;
   }
+}
+
+// Parameter checks of a surface (shared by single systems and pool jobs).
+int validate_surface(int kind, const double* prm, const md_params& p) {
+  const int need = surf_nprm(kind);
+  if (need < 0 || (need > 0 && !prm)) return MD_EINVAL;
+  for (int k = 0; k < need; ++k)
+    if (!std::isfinite(prm[k])) return MD_EINVAL;
+  if (kind == MD_SURF_SPHERE && !(prm[3] > 0)) return MD_EINVAL;
+  if (kind == MD_SURF_ELLIPSOID && !(prm[3] > 0 && prm[4] > 0 && prm[5] > 0)) return MD_EINVAL;
+  if (kind == MD_SURF_TORUS && !(prm[3] > prm[4] && prm[4] > 0)) return MD_EINVAL;
+  if (kind == MD_SURF_HEIGHT && (!(prm[2] > 0 && prm[3] > 0) || !p.periodic[0] || !p.periodic[1])) return MD_EINVAL;
+  if (kind == MD_SURF_BRIDGE) {
+    if (!(prm[3] >= 0 && prm[4] > 0 && prm[5] > 0)) return MD_EINVAL;
+    for (int k = 1; k < 3; ++k)
+      if (p.periodic[k] && p.box_hi[k] - p.box_lo[k] < 2.0 * (prm[4] + prm[5])) return MD_EINVAL;
+  }
+  return MD_OK;
 }
 
 double host_g(int kind, const double* q, const double* x, double* n) {
@@ -140,6 +159,23 @@ double host_g(int kind, const double* q, const double* x, double* n) {
     case MD_SURF_CYLINDER:
       n[0] = 2 * q[3] * d0, n[1] = 2 * q[4] * d1, n[2] = 2 * q[5] * d2;
       return q[3] * d0 * d0 + q[4] * d1 * d1 + q[5] * d2 * d2 - q[6] * q[6];
+    case MD_SURF_BRIDGE: {
+      const double h = 0.5 * q[3], Rb = q[4], R = q[5], c = Rb + R;
+      const double r = std::sqrt(d1 * d1 + d2 * d2);
+      if (std::fabs(d0) <= h) {
+        const double s = R / Rb;
+        n[0] = 0, n[1] = -2 * s * d1, n[2] = -2 * s * d2;
+        return s * (Rb * Rb - r * r);
+      }
+      const double sg = d0 > 0 ? 1.0 : -1.0;
+      if (r < c) {
+        const double f = 2 * (1 - c / r);
+        n[0] = 2 * (d0 - sg * h), n[1] = f * d1, n[2] = f * d2;
+        return (d0 - sg * h) * (d0 - sg * h) + (r - c) * (r - c) - R * R;
+      }
+      n[0] = sg * 2 * R, n[1] = 0, n[2] = 0;
+      return 2 * R * (std::fabs(d0) - h - R);
+    }
     case MD_SURF_HEIGHT: {
       const double kx = 2 * M_PI / q[2], ky = 2 * M_PI / q[3];
       n[0] = -q[1] * kx * std::cos(kx * x[0]) * std::sin(ky * x[1]);
@@ -603,6 +639,12 @@ struct Engine {
     if (h.surf_kind == MD_SURF_HEIGHT) {
       d.surf[2] = 2.0 / h.surf[2];
       d.surf[3] = 2.0 / h.surf[3];
+    }
+    if (h.surf_kind == MD_SURF_BRIDGE) {
+      // device layout: x0 y0 z0, Lb/2, Rb, R, Rb + R, R/Rb
+      d.surf[3] = 0.5 * h.surf[3];
+      d.surf[6] = h.surf[4] + h.surf[5];
+      d.surf[7] = h.surf[5] / h.surf[4];
     }
   }
 
@@ -1322,14 +1364,8 @@ int md_create(const md_params* params, md_ctx** out) {
 int md_set_surface(md_ctx* ctx, int kind, const double* prm, int nprm) {
   if (!ctx) return MD_EINVAL;
   const int need = surf_nprm(kind);
-  if (need < 0 || nprm < need || (need > 0 && !prm)) return MD_EINVAL;
-  for (int k = 0; k < need; ++k)
-    if (!std::isfinite(prm[k])) return MD_EINVAL;
-  if (kind == MD_SURF_SPHERE && !(prm[3] > 0)) return MD_EINVAL;
-  if (kind == MD_SURF_ELLIPSOID && !(prm[3] > 0 && prm[4] > 0 && prm[5] > 0)) return MD_EINVAL;
-  if (kind == MD_SURF_TORUS && !(prm[3] > prm[4] && prm[4] > 0)) return MD_EINVAL;
-  if (kind == MD_SURF_HEIGHT && (!(prm[2] > 0 && prm[3] > 0) || !ctx->prm.periodic[0] || !ctx->prm.periodic[1]))
-    return MD_EINVAL;
+  if (need < 0 || nprm < need) return MD_EINVAL;
+  MDCHK(validate_surface(kind, prm, ctx->prm));
   ctx->surf_kind = kind;
   for (int k = 0; k < MD_SURF_MAXPRM; ++k) ctx->surf[k] = k < need ? prm[k] : 0.0;
   return MD_OK;
@@ -1513,8 +1549,8 @@ int md_pool_create(size_t hbm_budget_bytes, int max_jobs, int device, void* stre
 
 int md_pool_admit(md_pool* pool, const md_job_desc* job, int* job_id) {
   if (!pool || !job || !job_id) return MD_EINVAL;
-  const int need = surf_nprm(job->surface_kind);
-  if (need < 0 || job->nsteps < 0 || job->step0 < 0) return MD_EINVAL;
+  if (job->nsteps < 0 || job->step0 < 0) return MD_EINVAL;
+  MDCHK(validate_surface(job->surface_kind, job->surface_prm, job->params));
   return pool->eng.admit(job->params, job->surface_kind, job->surface_prm, job->n, job->x, job->p, job->mass,
                          job->constrained, nullptr, job->step0, job->step0 + job->nsteps, job_id);
 }

@@ -15,7 +15,7 @@ import numpy as np
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libmd.so")
 
-SURF = {"none": 0, "plane": 1, "sphere": 2, "ellipsoid": 3, "torus": 4, "cylinder": 5, "height": 6}
+SURF = {"none": 0, "plane": 1, "sphere": 2, "ellipsoid": 3, "torus": 4, "cylinder": 5, "height": 6, "bridge": 7}
 PAIR = {"none": 0, "lj": 1, "lj_smooth": 2}
 
 MD_OK, MD_EINVAL, MD_ESTATE, MD_EOFFSURF, MD_ENEWTON, MD_ENAN, MD_ENOMEM, MD_EAGAIN, MD_EHIP, MD_ENOTFOUND = (

@@ -46,6 +46,9 @@ CASES = {
     "cylinder_lj": lambda: (gen.cylinder(1500, 8.0, 60.0, 7), dict(dt=0.002, rc=2.5, seed=2, force_fp64=0)),
     "sphere_nve": lambda: (gen.sphere(800, 12.0, 9), dict(dt=0.001, rc=WCA, gamma=0.0)),
     "sphere_eta": lambda: (gen.sphere(800, 12.0, 10), dict(dt=0.002, rc=WCA, seed=4, newton_tol=1e-6)),
+    "bridge_wca": lambda: (gen.bridge(1000, 10.0, 1.5, 3.0, 30.0, 6), dict(dt=0.002, rc=WCA, seed=21)),
+    "bridge_lj_mixed": lambda: (gen.bridge(1200, 10.0, 2.5, 3.0, 28.0, 7, n_free=800),
+                                dict(dt=0.002, rc=2.5, seed=22, force_fp64=0)),
 }
 
 
@@ -68,7 +71,7 @@ def test_one_step_map(case):
 
 
 @pytest.mark.parametrize("case", ["sphere_wca_fp64", "torus_lj_fp32", "height_mixed", "ellipsoid_wca",
-                                  "sphere_eta", "torus_frozen"])
+                                  "sphere_eta", "torus_frozen", "bridge_wca", "bridge_lj_mixed"])
 def test_short_trajectory(case):
     """50 steps: trajectories still agree point-wise (chaos has not amplified the
     round-off yet); constraint residuals at round-off on both sides."""

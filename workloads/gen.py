@@ -232,6 +232,87 @@ def capsomeres(n_mol: int, R: float, seed: int, sizes=(1.0, 1.35, 1.75, 1.0), bo
                   meta=dict(R=R, bpm=B, sizes=tuple(sizes), bonds=tuple(bonds)))
 
 
+def bridge_area(Lb: float, Rb: float, R: float, L: float) -> dict:
+    """Areas of the bridge surface's pieces: the cylinder, one connector (the
+    inner quarter of a circle of radius R about r = Rb + R, revolved about the
+    x axis) and one plane (an L x L square less the connector's disk)."""
+    c = Rb + R
+    return dict(cylinder=2.0 * math.pi * Rb * Lb, connector=2.0 * math.pi * R * (0.5 * math.pi * c - R),
+                plane=L * L - math.pi * c * c)
+
+
+def bridge(n: int, Lb: float, Rb: float, R: float, L: float, seed: int, dmin: float = 0.9, kT: float = 1.0,
+           n_free: int = 0) -> System:
+    """Two parallel planes x = +-(Lb/2 + R), periodic in y and z with side L,
+    joined by a cylindrical bridge of radius Rb and length Lb along x through
+    connectors of tube radius R (the thylakoid bridge of SI S3.1).  n points
+    area-uniform over the pieces, random sequential adsorption at dmin,
+    tangential Maxwell-Boltzmann momenta; n_free unconstrained particles in
+    the slab between the planes (outside the bridge) are appended."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    h, c = 0.5 * Lb, Rb + R
+    A = bridge_area(Lb, Rb, R, L)
+    w = np.array([A["cylinder"], A["connector"], A["connector"], A["plane"], A["plane"]])
+    xw = h + R
+    lo, hi, per = (-xw - 2.0, -0.5 * L, -0.5 * L), (xw + 2.0, 0.5 * L, 0.5 * L), (0, 1, 1)
+
+    def sampler(rng, m):
+        piece = rng.choice(5, size=m, p=w / w.sum())
+        th = rng.uniform(0.0, 2.0 * math.pi, size=m)
+        out = np.zeros((m, 3))
+        k = piece == 0
+        out[k, 0] = rng.uniform(-h, h, size=k.sum())
+        out[k, 1], out[k, 2] = Rb * np.cos(th[k]), Rb * np.sin(th[k])
+        for side, pc in ((1.0, 1), (-1.0, 2)):
+            k = np.flatnonzero(piece == pc)
+            phi = np.zeros(k.size)
+            todo = np.arange(k.size)
+            while todo.size:  # density of phi proportional to the revolved radius c - R cos(phi)
+                f = rng.uniform(0.0, 0.5 * math.pi, size=todo.size)
+                ok = rng.uniform(0.0, c, size=todo.size) < c - R * np.cos(f)
+                phi[todo[ok]] = f[ok]
+                todo = todo[~ok]
+            r = c - R * np.cos(phi)
+            out[k, 0] = side * (h + R * np.sin(phi))
+            out[k, 1], out[k, 2] = r * np.cos(th[k]), r * np.sin(th[k])
+        for side, pc in ((1.0, 3), (-1.0, 4)):
+            k = np.flatnonzero(piece == pc)
+            yz = rng.uniform(-0.5 * L, 0.5 * L, size=(k.size, 2))
+            bad = np.hypot(yz[:, 0], yz[:, 1]) < c
+            while bad.any():
+                yz[bad] = rng.uniform(-0.5 * L, 0.5 * L, size=(int(bad.sum()), 2))
+                bad = np.hypot(yz[:, 0], yz[:, 1]) < c
+            out[k, 0] = side * xw
+            out[k, 1:] = yz
+        return out
+
+    x = _fill(sampler, n, dmin, rng, lo, hi, per)
+    # unit normals by piece
+    r = np.hypot(x[:, 1], x[:, 2])
+    nh = np.zeros_like(x)
+    cyl = np.abs(x[:, 0]) <= h
+    con = ~cyl & (r < c)
+    pla = ~cyl & ~con
+    nh[cyl, 1:] = x[cyl, 1:] / r[cyl, None]
+    x0 = np.where(x[:, 0] > 0.0, h, -h)
+    nh[con, 0] = x[con, 0] - x0[con]
+    nh[con, 1:] = (r[con] - c)[:, None] * x[con, 1:] / r[con, None]
+    nh[pla, 0] = np.sign(x[pla, 0])
+    nh = _unit(nh)
+    p = _tangent_momenta(rng, nh, kT, None)
+    cons = np.ones(n, dtype=np.uint8)
+    if n_free:
+        def free_sampler(rng, m):
+            q = np.column_stack([rng.uniform(-xw + 1.0, xw - 1.0, size=m), rng.uniform(-0.5 * L, 0.5 * L, size=(m, 2))])
+            return q[np.hypot(q[:, 1], q[:, 2]) > c + 1.0]
+        xf = _fill(free_sampler, n + n_free, dmin, rng, lo, hi, per, prefix=x)[n:]
+        pf = rng.standard_normal((n_free, 3)) * math.sqrt(kT)
+        x, p = np.concatenate([x, xf]), np.concatenate([p, pf])
+        cons = np.concatenate([cons, np.zeros(n_free, dtype=np.uint8)])
+    return System(x, p, "bridge", (0.0, 0.0, 0.0, Lb, Rb, R), lo, hi, per, cons=cons,
+                  meta=dict(Lb=Lb, Rb=Rb, R=R, L=L, area=A))
+
+
 def rods_box(n_mol: int, L: float, seed: int, sizes=(1.0, 1.35, 1.75, 1.0), dmin: float = 4.0,
              kT: float = 1.0) -> System:
     """n_mol free linear molecules (no surface, nothing constrained) in a
