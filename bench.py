@@ -103,7 +103,8 @@ def timed_steps(s, run, skin: float, steps: int, warmup: int, model=None):
     from paper_1411_3019_amd import md
     prm = md.Params(dt=run["dt"], kT=run["kT"], gamma=run["gamma"], eps=run.get("eps", 1.0),
                     sigma=run.get("sigma", 1.0), rc=run["rc"], pair=run["pair"], force_fp64=run["force_fp64"],
-                    skin=skin, seed=run["seed"], box_lo=s.box_lo, box_hi=s.box_hi, periodic=s.periodic)
+                    skin=skin, seed=run["seed"], box_lo=s.box_lo, box_hi=s.box_hi, periodic=s.periodic,
+                    newton_frozen=run.get("newton_frozen", 0))
     sysm = md.System(prm, s.surface, s.surf)
     if model is not None:
         sysm.set_model(model, s.types)
@@ -145,6 +146,13 @@ def extra_benches(skin: float):
     out["shard_250k"] = dict(workload="torus, 250000 LJ particles, area fraction 0.4", skin=skin,
                              **timed_steps(s, run, skin, 2000, 300))
     log(f"[bench] shard 250k: {out['shard_250k']}")
+    # the SI's frozen-normal Newton (chord iteration) against full Newton, same system
+    fz = timed_steps(s, dict(run, newton_frozen=1), skin, 2000, 300)
+    out["frozen_newton"] = {"workload": "torus, 250000 LJ particles: frozen-normal vs full Newton",
+                            "frozen": fz, "full": out["shard_250k"],
+                            "step_kernel_ratio_frozen_over_full": fz["step_kernel_us"] /
+                            out["shard_250k"]["step_kernel_us"]}
+    log(f"[bench] frozen newton: {out['frozen_newton']['step_kernel_ratio_frozen_over_full']:.3f}")
     n = 1_000_000
     run = dict(dt=0.002, kT=1.0, gamma=1.0, rc=2.5, pair="lj", force_fp64=0, seed=11)
     sph = gen.sphere(n, gen.sphere_radius_for(n, 0.4), 11)
@@ -272,15 +280,21 @@ def main():
     ap.add_argument("--serving-plain-jobs", type=int, default=40)
     ap.add_argument("--serving-rate", type=float, default=200.0)
     ap.add_argument("--serving-budget-gb", type=float, default=16.0)
-    ap.add_argument("--no-extra", action="store_true", help="skip the 250k-shard and sphere-vs-plane measurements")
+    ap.add_argument("--no-extra", action="store_true", help="skip the secondary measurements")
+    ap.add_argument("--only", choices=["capsid", "rods"], help="run only this secondary measurement")
     args = ap.parse_args()
     if args.no_graph:
         os.environ["MD_NO_GRAPH"] = "1"
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the single-system step would shard as described in DESIGN.md).", file=sys.stderr)
+        print("bench.py runs on one GPU only: there is no multi-GPU path (a single system would be split "
+              "into spatial domains with halo exchange between GPUs; that is not implemented).", file=sys.stderr)
         sys.exit(2)
+    if args.only:
+        # one secondary measurement alone (for profiling its kernels)
+        res = {"capsid": capsid_bench, "rods": rods_bench}[args.only](args.skin)
+        print(json.dumps(res), flush=True)
+        return
 
     from paper_1411_3019_amd import md
     from workloads import gen

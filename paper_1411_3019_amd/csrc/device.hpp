@@ -631,7 +631,8 @@ __device__ __forceinline__ double bonded_forces(const JobDev& J, const ModelDev&
       const double uu = uu_[0] * uu_[0] + uu_[1] * uu_[1] + uu_[2] * uu_[2];
       const double vv = vv_[0] * vv_[0] + vv_[1] * vv_[1] + vv_[2] * vv_[2];
       const double nu = sqrt(uu), nv = sqrt(vv);
-      double cs = (uu_[0] * vv_[0] + uu_[1] * vv_[1] + uu_[2] * vv_[2]) / (nu * nv);
+      const double inn = 1.0 / (nu * nv);
+      double cs = (uu_[0] * vv_[0] + uu_[1] * vv_[1] + uu_[2] * vv_[2]) * inn;
       cs = fmin(1.0, fmax(-1.0, cs));
       const double th = acos(cs), sn = sqrt(1.0 - cs * cs);
       const double dth = th - M.theta0;
@@ -641,11 +642,12 @@ __device__ __forceinline__ double bonded_forces(const JobDev& J, const ModelDev&
       else
         ratio = fabs(dth) < 1e-6 ? (th > 1.5 ? -1.0 : 1.0) : dth / 1e-12;
       const double k2 = 2.0 * M.ka * ratio;
+      const double cu = cs / uu, cv = cs / vv;
       // this bead is the first end (cb = 3), the middle (cb = 2) or the second end (cb = 1)
       double g[3];
       for (int k = 0; k < 3; ++k) {
-        const double ga = vv_[k] / (nu * nv) - cs * uu_[k] / uu;
-        const double gc = uu_[k] / (nu * nv) - cs * vv_[k] / vv;
+        const double ga = vv_[k] * inn - cu * uu_[k];
+        const double gc = uu_[k] * inn - cv * vv_[k];
         g[k] = cb == 3 ? ga : (cb == 1 ? gc : -(ga + gc));
       }
       Fx += k2 * g[0];
