@@ -51,12 +51,13 @@ def kernel_source_hash() -> str:
 
 
 def device_sync():
-    try:
-        import torch
-        if torch.cuda.is_available():
-            torch.cuda.synchronize()
-    except Exception:
-        pass
+    """hipDeviceSynchronize of the HIP runtime the library runs on (md_step has
+    already waited for its own work; this is the barrier around the timed
+    region)."""
+    from paper_1411_3019_amd import md
+    rc = md.hip_runtime().hipDeviceSynchronize()
+    if rc != 0:
+        raise RuntimeError(f"hipDeviceSynchronize failed ({rc})")
 
 
 def step_kernel_bytes(nl_mean: float) -> float:

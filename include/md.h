@@ -239,10 +239,23 @@ int md_set_particles(md_ctx* ctx, int64_t n, const double* x, const double* p,
  * happened (the state is then undefined). */
 int md_step(md_ctx* ctx, int64_t nsteps);
 
+/* md_set_particles with device pointers (e.g. PyTorch tensors on the same
+ * device): the arrays have the host variant's layouts, are read on the
+ * context's stream (params.stream) before the call returns, and are not
+ * retained; the caller owns them.  Same checks and errors as md_set_particles;
+ * MD_EHIP if a copy fails. */
+int md_set_particles_dev(md_ctx* ctx, int64_t n, const double* x, const double* p, const double* mass,
+                         const uint8_t* constrained, const double* fcomb, int64_t step0);
+
 /* Copy the state at the current step m: positions x^m, momenta p^m (tangent),
  * optionally the combined force f^m (fcomb, n*3), the step index and
  * diagnostics.  Any pointer may be NULL. */
 int md_get_state(md_ctx* ctx, double* x, double* p, double* fcomb, int64_t* step, md_diag* diag);
+
+/* md_get_state into device pointers (x, p, fcomb: n*3 doubles each, caller
+ * owned, any may be NULL): filled by device-to-device copies on the context's
+ * stream, complete when the call returns; step and diag are host pointers. */
+int md_get_state_dev(md_ctx* ctx, double* x, double* p, double* fcomb, int64_t* step, md_diag* diag);
 
 /* Counters and event-timed GPU work of this context (see md_stats). */
 int md_get_stats(md_ctx* ctx, md_stats* stats);

@@ -361,6 +361,7 @@ struct Engine {
   int64_t tile_cap = 0;
   Chunk* chunks_d = nullptr;
   uint32_t* chunk_sums = nullptr;
+  double* diag_d = nullptr;  // [4 kDiagBlocks] partials, then [4] results
   int64_t chunk_cap = 0;
   Range* ranges_d = nullptr;
   int64_t range_cap = 0;
@@ -400,7 +401,7 @@ struct Engine {
     void* ptrs[] = {B.X[0], B.X[1], B.P[0], B.P[1], B.ID[0], B.ID[1], B.FLG[0], B.FLG[1], B.MASS[0], B.MASS[1],
                     B.FC, B.OX, B.OP, B.OF, B.OD, B.NL, B.NCNT, B.BM, B.WOFF, B.CCNT, B.CSTART, B.RASTER,
                     B.CID, B.RANK, B.INV, B.SRC, B.PK, B.TYPE[0], B.TYPE[1], (void*)B.models, B.TACC, B.NLSTAT, B.jobs, B.book, step_tiles_job, step_tiles_first, step_counts, aux_tiles_job,
-                    aux_tiles_first, chunks_d, chunk_sums, ranges_d};
+                    aux_tiles_first, chunks_d, chunk_sums, ranges_d, diag_d};
     for (void* p : ptrs)
       if (p) (void)hipFree(p);
     std::memset(&B, 0, sizeof(B));
@@ -411,6 +412,7 @@ struct Engine {
     chunks_d = nullptr;
     chunk_sums = nullptr;
     ranges_d = nullptr;
+    diag_d = nullptr;
     if (book_h) (void)hipHostFree(book_h);
     if (stage) (void)hipHostFree(stage);
     if (arena) (void)hipHostFree(arena);
@@ -508,6 +510,7 @@ struct Engine {
     chunk_cap = (C + max_jobs) / kScanChunk + BMW / kScanChunk + 4 * max_jobs + 16;
     MDCHK(dalloc(&chunks_d, chunk_cap));
     MDCHK(dalloc(&chunk_sums, chunk_cap));
+    MDCHK(dalloc(&diag_d, 4 * kDiagBlocks + 4));
     range_cap = 3 * max_jobs + 4;
     MDCHK(dalloc(&ranges_d, range_cap));
     HIPCHK(hipHostMalloc((void**)&book_h, sizeof(JobBook) * max_jobs, hipHostMallocDefault));
@@ -1160,7 +1163,10 @@ struct Engine {
   }
 
   // ------------------------------------------------------------------ finish
-  int finish(int j, double* x, double* p, double* f, md_diag* diag) {
+  // State at the current step by particle index.  dev: x, p, f are device
+  // pointers (filled by device-to-device copies on the library's stream),
+  // else host pointers; any may be NULL.
+  int finish(int j, double* x, double* p, double* f, md_diag* diag, bool dev = false) {
     HostJob& h = jobs[j];
     if (!h.used) return MD_ENOTFOUND;
     if (h.n == 0) {
@@ -1186,29 +1192,30 @@ struct Engine {
     else
       hipLaunchKernelGGL(k_finish<false>, dim3((unsigned)tj.size()), dim3(kTile), 0, stream, B, aux_tiles_job,
                          aux_tiles_first);
-    HIPCHK(hipGetLastError());
     const int64_t n = h.n;
-    MDCHK(ensure_stage(sizeof(double) * 13 * n));
+    const int nb = (int)std::min<int64_t>(kDiagBlocks, (n + kDiagThreads - 1) / kDiagThreads);
+    hipLaunchKernelGGL(k_diag_partial, dim3(nb), dim3(kDiagThreads), 0, stream, B.OD, (int64_t)C, h.off, n, diag_d);
+    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(kDiagThreads), 0, stream, diag_d, nb, diag_d + 4 * kDiagBlocks);
+    HIPCHK(hipGetLastError());
+    const size_t vb = sizeof(double) * 3 * n;
+    MDCHK(ensure_stage(3 * vb + 4 * sizeof(double)));
     double* st = (double*)stage;
-    HIPCHK(hipMemcpyAsync(st, B.OX + 3 * h.off, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, stream));
-    HIPCHK(hipMemcpyAsync(st + 3 * n, B.OP + 3 * h.off, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, stream));
-    HIPCHK(hipMemcpyAsync(st + 6 * n, B.OF + 3 * h.off, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, stream));
-    for (int k = 0; k < 4; ++k)
-      HIPCHK(hipMemcpyAsync(st + (9 + k) * n, B.OD + k * C + h.off, sizeof(double) * n, hipMemcpyDeviceToHost,
-                            stream));
+    const hipMemcpyKind kind = dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    double* dst[3] = {dev ? x : st, dev ? p : st + 3 * n, dev ? f : st + 6 * n};
+    const double* src[3] = {B.OX + 3 * h.off, B.OP + 3 * h.off, B.OF + 3 * h.off};
+    const bool want[3] = {x != nullptr, p != nullptr, f != nullptr};
+    for (int k = 0; k < 3; ++k)
+      if (want[k]) HIPCHK(hipMemcpyAsync(dst[k], src[k], vb, kind, stream));
+    HIPCHK(hipMemcpyAsync(st + 9 * n, diag_d + 4 * kDiagBlocks, 4 * sizeof(double), hipMemcpyDeviceToHost, stream));
     MDCHK(sync());
-    if (x) std::memcpy(x, st, sizeof(double) * 3 * n);
-    if (p) std::memcpy(p, st + 3 * n, sizeof(double) * 3 * n);
-    if (f) std::memcpy(f, st + 6 * n, sizeof(double) * 3 * n);
+    if (!dev) {
+      if (x) std::memcpy(x, st, vb);
+      if (p) std::memcpy(p, st + 3 * n, vb);
+      if (f) std::memcpy(f, st + 6 * n, vb);
+    }
     if (diag) {
-      double K = 0.0, U = 0.0, gd = 0.0, nv = 0.0, ndof = 0.0;
-      for (int64_t i = 0; i < n; ++i) {
-        K += st[9 * n + i];
-        U += st[10 * n + i];
-        gd = std::max(gd, st[11 * n + i]);
-        nv = std::max(nv, st[12 * n + i]);
-      }
-      ndof = h.ndof;
+      const double* red = st + 9 * n;
+      const double K = red[0], U = red[1], gd = red[2], nv = red[3], ndof = h.ndof;
       std::memset(diag, 0, sizeof(*diag));
       diag->K = K;
       diag->U = U;
@@ -1467,6 +1474,45 @@ int md_get_state(md_ctx* ctx, double* x, double* p, double* fcomb, int64_t* step
   Engine* e = ctx->eng;
   if (step) *step = e->jobs[ctx->job].step;
   return e->finish(ctx->job, x, p, fcomb, diag);
+}
+
+int md_get_state_dev(md_ctx* ctx, double* x, double* p, double* fcomb, int64_t* step, md_diag* diag) {
+  if (!ctx) return MD_EINVAL;
+  if (!ctx->have_particles) return MD_ESTATE;
+  Engine* e = ctx->eng;
+  if (step) *step = e->jobs[ctx->job].step;
+  return e->finish(ctx->job, x, p, fcomb, diag, true);
+}
+
+int md_set_particles_dev(md_ctx* ctx, int64_t n, const double* x, const double* p, const double* mass,
+                         const uint8_t* constrained, const double* fcomb, int64_t step0) {
+  if (!ctx || n < 0 || step0 < 0) return MD_EINVAL;
+  if (n > 0 && (!x || !p)) return MD_EINVAL;
+  if (n == 0) return md_set_particles(ctx, 0, nullptr, nullptr, nullptr, nullptr, nullptr, step0);
+  // the inputs are read once, on the context's stream, into host memory: the
+  // admission checks (every particle on its surface, momenta tangent) and the
+  // cell-grid plan run on the host, as for md_set_particles
+  HIPCHK(hipSetDevice(ctx->prm.device));
+  hipStream_t s = (hipStream_t)ctx->prm.stream;
+  std::vector<double> hx, hp, hm, hf;
+  std::vector<uint8_t> hc;
+  try {
+    hx.resize(3 * n);
+    hp.resize(3 * n);
+    if (mass) hm.resize(n);
+    if (fcomb) hf.resize(3 * n);
+    if (constrained) hc.resize(n);
+  } catch (...) {
+    return MD_ENOMEM;
+  }
+  HIPCHK(hipMemcpyAsync(hx.data(), x, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(hp.data(), p, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, s));
+  if (mass) HIPCHK(hipMemcpyAsync(hm.data(), mass, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+  if (fcomb) HIPCHK(hipMemcpyAsync(hf.data(), fcomb, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, s));
+  if (constrained) HIPCHK(hipMemcpyAsync(hc.data(), constrained, n, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return md_set_particles(ctx, n, hx.data(), hp.data(), mass ? hm.data() : nullptr,
+                          constrained ? hc.data() : nullptr, fcomb ? hf.data() : nullptr, step0);
 }
 
 int md_tune(md_ctx* ctx, int trial_steps, const double* skins, int nskins, double* best_skin,

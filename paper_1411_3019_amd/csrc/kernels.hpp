@@ -738,6 +738,65 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const int* __r
   }
 }
 
+// Diagnostics of one job from the finish kernel's per-particle values (Section
+// 3.1: K and U summed, constraint residuals maximised), in two passes with a
+// fixed reduction tree, so the result depends only on n, not on scheduling.
+// Pass 1: workgroup b reduces its contiguous chunk into part[4 b .. 4 b + 3];
+// pass 2: one workgroup reduces the partials into out[0..3] = K, U, gdist_max,
+// nv_max.
+constexpr int kDiagThreads = 256;
+constexpr int kDiagBlocks = 256;
+
+__device__ __forceinline__ void diag_tree(double* sk, double* su, double* sg, double* sv, int tid) {
+  for (int w = kDiagThreads / 2; w > 0; w >>= 1) {
+    __syncthreads();
+    if (tid < w) {
+      sk[tid] += sk[tid + w];
+      su[tid] += su[tid + w];
+      sg[tid] = fmax(sg[tid], sg[tid + w]);
+      sv[tid] = fmax(sv[tid], sv[tid + w]);
+    }
+  }
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(kDiagThreads) k_diag_partial(const double* __restrict__ OD, int64_t C, int64_t off,
+                                                               int64_t n, double* __restrict__ part) {
+  __shared__ double sk[kDiagThreads], su[kDiagThreads], sg[kDiagThreads], sv[kDiagThreads];
+  const int tid = threadIdx.x;
+  const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t b0 = (int64_t)blockIdx.x * chunk, b1 = min(b0 + chunk, n);
+  double k = 0.0, u = 0.0, g = 0.0, v = 0.0;
+  for (int64_t i = b0 + tid; i < b1; i += kDiagThreads) {
+    k += OD[off + i];
+    u += OD[C + off + i];
+    g = fmax(g, OD[2 * C + off + i]);
+    v = fmax(v, OD[3 * C + off + i]);
+  }
+  sk[tid] = k, su[tid] = u, sg[tid] = g, sv[tid] = v;
+  diag_tree(sk, su, sg, sv, tid);
+  if (tid == 0) {
+    double* o = part + 4 * blockIdx.x;
+    o[0] = sk[0], o[1] = su[0], o[2] = sg[0], o[3] = sv[0];
+  }
+}
+
+__global__ void __launch_bounds__(kDiagThreads) k_diag_final(const double* __restrict__ part, int nb,
+                                                             double* __restrict__ out) {
+  __shared__ double sk[kDiagThreads], su[kDiagThreads], sg[kDiagThreads], sv[kDiagThreads];
+  const int tid = threadIdx.x;
+  double k = 0.0, u = 0.0, g = 0.0, v = 0.0;
+  for (int b = tid; b < nb; b += kDiagThreads) {
+    k += part[4 * b];
+    u += part[4 * b + 1];
+    g = fmax(g, part[4 * b + 2]);
+    v = fmax(v, part[4 * b + 3]);
+  }
+  sk[tid] = k, su[tid] = u, sg[tid] = g, sv[tid] = v;
+  diag_tree(sk, su, sg, sv, tid);
+  if (tid == 0) out[0] = sk[0], out[1] = su[0], out[2] = sg[0], out[3] = sv[0];
+}
+
 // Per-job reductions read by the host after a chunk of steps: the largest
 // per-tile displacement bound and, after list builds, the list statistics.
 // One workgroup per job record.

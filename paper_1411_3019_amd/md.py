@@ -23,7 +23,7 @@ MD_OK, MD_EINVAL, MD_ESTATE, MD_EOFFSURF, MD_ENEWTON, MD_ENAN, MD_ENOMEM, MD_EAG
 SYMBOLS = ["md_create", "md_set_surface", "md_set_particles", "md_step", "md_get_state", "md_destroy",
            "md_strerror", "md_job_footprint", "md_pool_create", "md_pool_admit", "md_pool_run", "md_pool_poll",
            "md_pool_fetch", "md_pool_release", "md_pool_usage", "md_pool_destroy", "md_get_stats",
-           "md_pool_get_stats", "md_tune", "md_set_model"]
+           "md_pool_get_stats", "md_tune", "md_set_model", "md_set_particles_dev", "md_get_state_dev"]
 MD_MAX_TYPES = 4
 
 
@@ -181,6 +181,8 @@ def lib():
         L.md_set_surface.argtypes = [vp, C.c_int, dp, C.c_int]
         L.md_set_particles.argtypes = [vp, C.c_int64, dp, dp, dp, u8, dp, C.c_int64]
         L.md_set_model.argtypes = [vp, C.POINTER(_Model), u8, C.c_int64]
+        L.md_set_particles_dev.argtypes = [vp, C.c_int64, vp, vp, vp, vp, vp, C.c_int64]
+        L.md_get_state_dev.argtypes = [vp, vp, vp, vp, C.POINTER(C.c_int64), C.POINTER(_Diag)]
         L.md_step.argtypes = [vp, C.c_int64]
         L.md_get_state.argtypes = [vp, dp, dp, dp, C.POINTER(C.c_int64), C.POINTER(_Diag)]
         L.md_destroy.argtypes = [vp]
@@ -200,11 +202,19 @@ def lib():
         L.md_pool_destroy.argtypes = [vp]
         L.md_pool_destroy.restype = None
         for name in ("md_create", "md_set_surface", "md_set_particles", "md_set_model", "md_step", "md_get_state",
+                     "md_set_particles_dev", "md_get_state_dev",
                      "md_pool_create", "md_pool_admit", "md_pool_run", "md_pool_poll", "md_pool_fetch",
                      "md_pool_release", "md_pool_usage", "md_get_stats", "md_pool_get_stats", "md_tune"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
+
+
+def hip_runtime():
+    """The HIP runtime libmd.so runs on (the already loaded library of that
+    soname), for device buffers and synchronisation that must share it."""
+    lib()
+    return C.CDLL("libamdhip64.so.7")
 
 
 def strerror(code: int) -> str:
@@ -270,6 +280,22 @@ class System:
         _check(lib().md_set_particles(self._h, n, _dp(x), _dp(p), _dp(m), _u8(c), _dp(f), int(step0)),
                "md_set_particles")
         self.n = n
+
+    def set_particles_dev(self, n: int, x_ptr: int, p_ptr: int, mass_ptr: int | None = None,
+                          cons_ptr: int | None = None, fcomb_ptr: int | None = None, step0: int = 0):
+        """md_set_particles_dev: device addresses (e.g. tensor.data_ptr()) of
+        contiguous arrays with the host layouts (x, p, fcomb: n*3 float64;
+        mass: n float64; cons: n uint8)."""
+        _check(lib().md_set_particles_dev(self._h, int(n), x_ptr, p_ptr, mass_ptr, cons_ptr, fcomb_ptr, int(step0)),
+               "md_set_particles_dev")
+        self.n = int(n)
+
+    def get_state_dev(self, x_ptr: int | None, p_ptr: int | None, fcomb_ptr: int | None = None):
+        """md_get_state_dev into device addresses; returns step and diagnostics."""
+        step = C.c_int64(0)
+        d = _Diag()
+        _check(lib().md_get_state_dev(self._h, x_ptr, p_ptr, fcomb_ptr, C.byref(step), C.byref(d)), "md_get_state_dev")
+        return dict(step=step.value, diag=d.to_dict())
 
     def step(self, nsteps: int):
         _check(lib().md_step(self._h, int(nsteps)), "md_step")
