@@ -75,3 +75,44 @@ def test_projected_noise_is_planar_normal():
     for t in (0.5, 1.0, 2.0, 4.0):
         assert abs(np.mean(q < t) - (1.0 - np.exp(-t / 2.0))) < 0.012
     assert np.max(np.abs(np.sum(zt * nh, axis=1))) < 1e-12
+
+
+def test_philox_matches_rocrand_header(tmp_path):
+    """The oracle's Philox4x32-10 against ROCm's open-source rocRAND engine
+    (its header, compiled for the host here): rocRAND's engine seeded with key
+    k and moved to subsequence (c2 | c3 << 32) and offset 4 (c0 | c1 << 32)
+    sits at counter (c0, c1, c2, c3), so its first four words are the block
+    function of that counter and key.  Includes the counter layout the method
+    uses, (particle index, step lo, step hi, 0)."""
+    import shutil
+    import subprocess
+    hipcc = shutil.which("hipcc")
+    if hipcc is None or not os.path.exists("/opt/rocm/include/rocrand/rocrand_philox4x32_10.h"):
+        pytest.skip("no hipcc / rocRAND headers")
+    src = tmp_path / "ph.cpp"
+    src.write_text(
+        "#include <cstdio>\n#include <rocrand/rocrand_philox4x32_10.h>\n"
+        "int main() {\n  unsigned long long k; unsigned c[4];\n"
+        "  while (std::scanf(\"%llx %x %x %x %x\", &k, &c[0], &c[1], &c[2], &c[3]) == 5) {\n"
+        "    unsigned long long sub = (unsigned long long)c[2] | ((unsigned long long)c[3] << 32);\n"
+        "    unsigned long long off = 4ull * ((unsigned long long)c[0] | ((unsigned long long)c[1] << 32));\n"
+        "    rocrand_device::philox4x32_10_engine e(k, sub, off);\n"
+        "    uint4 r = e.next4();\n"
+        "    std::printf(\"%08x %08x %08x %08x\\n\", r.x, r.y, r.z, r.w);\n  }\n  return 0;\n}\n")
+    exe = tmp_path / "ph"
+    subprocess.run([hipcc, "--offload-arch=gfx950", "-O1", "-o", str(exe), str(src)], check=True,
+                   capture_output=True)
+    rng = np.random.default_rng(77)
+    cases = []
+    for _ in range(200):
+        key = int(rng.integers(0, 2 ** 63))
+        ctr = [int(rng.integers(0, 2 ** 32)), int(rng.integers(0, 2 ** 30)), int(rng.integers(0, 2 ** 32)),
+               int(rng.integers(0, 2 ** 32))]
+        cases.append((key, ctr))
+    for pid, step in [(0, 0), (1, 1), (999, 12345), (2_000_000 - 1, 10_299)]:  # (index, step lo, step hi, 0)
+        cases.append((42, [pid, step & 0xFFFFFFFF, step >> 32, 0]))
+    inp = "".join(f"{k:x} {c[0]:x} {c[1]:x} {c[2]:x} {c[3]:x}\n" for k, c in cases)
+    out = subprocess.run([str(exe)], input=inp, capture_output=True, text=True, check=True).stdout.split("\n")
+    for (key, ctr), line in zip(cases, out):
+        want = [int(t, 16) for t in line.split()]
+        assert o.philox(ctr, [key & 0xFFFFFFFF, key >> 32]) == want
