@@ -92,10 +92,17 @@ def cpu_baseline(s, run, budget_s: float = 12.0):
         st.run(1)
         t += time.perf_counter() - t0
         steps += 1
-    cores = int(os.environ.get("OMP_NUM_THREADS") or len(os.sched_getaffinity(0)))
+    cores = o.threads()
+    # the same step on one thread
+    o.set_threads(1)
+    t0 = time.perf_counter()
+    st.run(1)
+    t1 = time.perf_counter() - t0
+    o.set_threads(cores)
     return {"value": s.n * steps / t, "unit": "particle-steps/s", "cores": cores, "kind": "oracle",
             "sample": f"{steps} full time step(s) of the same {s.n}-particle torus system, FP64, "
-                      f"linked cells, OpenMP; {t:.1f} s"}
+                      f"linked cells, OpenMP; {t:.1f} s",
+            "one_thread": {"value": s.n / t1, "unit": "particle-steps/s", "sample": f"1 step, {t1:.1f} s"}}
 
 
 def timed_steps(s, run, skin: float, steps: int, warmup: int, model=None):
@@ -353,6 +360,7 @@ def main():
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "traffic_GBps": None if traffic is None else traffic / per_launch_s / 1e9,
             "kernel": "k_step<fp32 forces>", "mean_launch_us": per_launch_s * 1e6,
             "alg_bytes_per_particle_step": step_kernel_bytes(st1["nl_mean"]), "nl_mean": st1["nl_mean"],
         },

@@ -110,6 +110,10 @@ typedef struct {
 /* Philox4x32-10 block function: out = Philox(ctr, key). */
 void mdo_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 
+/* OpenMP threads the oracle's loops use (for reporting its timing), and a setter. */
+int mdo_threads(void);
+void mdo_set_threads(int n);
+
 /* Three standard normals for particle id at step `step` (counter
  * (id, step lo, step hi, 0), key (seed lo, seed hi)), by Box-Muller. */
 void mdo_normals(uint64_t seed, uint32_t id, int64_t step, double z[3]);

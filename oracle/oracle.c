@@ -61,6 +61,12 @@ static void philox_round(uint32_t c[4], const uint32_t k[2]) {
   c[3] = lo0;
 }
 
+int mdo_threads(void) { return omp_get_max_threads(); }
+
+void mdo_set_threads(int n) {
+  if (n > 0) omp_set_num_threads(n);
+}
+
 void mdo_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
   uint32_t c[4] = {ctr[0], ctr[1], ctr[2], ctr[3]};
   uint32_t k[2] = {key[0], key[1]};

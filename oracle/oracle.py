@@ -164,6 +164,9 @@ def lib():
         i64p = C.POINTER(C.c_int64)
         pp = C.POINTER(_Params)
         L.mdo_philox4x32_10.argtypes = [u32p, u32p, u32p]
+        L.mdo_threads.restype = C.c_int
+        L.mdo_set_threads.argtypes = [C.c_int]
+        L.mdo_set_threads.restype = None
         L.mdo_philox4x32_10.restype = None
         L.mdo_normals.argtypes = [C.c_uint64, C.c_uint32, C.c_int64, dp]
         L.mdo_normals.restype = None
@@ -200,6 +203,15 @@ class OracleError(RuntimeError):
 def _check(rc, what):
     if rc != 0:
         raise OracleError(f"{what} failed with code {rc}")
+
+
+def threads() -> int:
+    """OpenMP threads of the oracle's parallel loops."""
+    return int(lib().mdo_threads())
+
+
+def set_threads(n: int):
+    lib().mdo_set_threads(int(n))
 
 
 def philox(ctr, key):
