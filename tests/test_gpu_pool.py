@@ -87,3 +87,52 @@ def test_pool_usage_and_release():
     with pytest.raises(md.MDError):
         pool.release(ids[0])
     pool.close()
+
+
+def test_every_surface_kind_in_one_pool():
+    """One job per surface kind (periodic boxes, free particles beside
+    constrained ones, both force classes, the smoothed potential) resident in
+    one pool: each job's state equals the same job run alone in its own
+    context bit for bit, and agrees with the oracle."""
+    from paper_1411_3019_amd import md
+    from _common import WCA, gpu_params, gpu_system
+    cases = [
+        (gen.sphere(300, 8.0, 1), dict(rc=2.5, force_fp64=0)),
+        (gen.ellipsoid(300, 8.0, 8.0, 12.0, 2), dict(rc=WCA, force_fp64=1)),
+        (gen.torus(400, 12.0, 4.0, 3), dict(rc=2.5, force_fp64=0)),
+        (gen.cylinder(300, 5.0, 30.0, 4), dict(rc=2.5, force_fp64=1)),
+        (gen.plane(300, 25.0, 5), dict(rc=2.5, pair="lj_smooth", force_fp64=0)),
+        (gen.height_membrane(200, 300, 20.0, 20.0, 16.0, 2.0, 20.0, 6), dict(rc=WCA, force_fp64=0)),
+        (gen.bridge(400, 10.0, 1.5, 3.0, 24.0, 7, n_free=100), dict(rc=WCA, force_fp64=1)),
+        (gen.box_gas(300, 12.0, 8), dict(rc=2.5, force_fp64=0)),
+    ]
+    steps = [90 + 13 * k for k in range(len(cases))]
+    print("[gpu] pool with one job per surface kind:", [s.surface for s, _ in cases], flush=True)
+    pool = md.Pool(256 << 20, 16)
+    ids = []
+    for (s, kw), n in zip(cases, steps):
+        jid = pool.admit(gpu_params(s, dt=0.002, seed=len(ids) + 3, **kw), s.surface, s.surf, s.x, s.p, n,
+                         mass=s.mass, cons=s.cons)
+        assert jid is not None
+        ids.append(jid)
+    done = set()
+    for _ in range(200):
+        pool.run(32)
+        done |= set(pool.poll())
+        if done >= set(ids):
+            break
+    assert done >= set(ids)
+    for k, ((s, kw), n, jid) in enumerate(zip(cases, steps, ids)):
+        rc, mix = pool.fetch(jid)
+        assert rc == 0, (s.surface, rc)
+        g = gpu_system(s, dt=0.002, seed=k + 3, **kw)
+        g.step(n)
+        alone = g.get_state()
+        g.close()
+        assert np.array_equal(mix["x"], alone["x"]) and np.array_equal(mix["p"], alone["p"]), s.surface
+        assert mix["diag"]["step"] == n
+        ref = o.State(oracle_params(s, dt=0.002, seed=k + 3, **kw), s.x, s.p, mass=s.mass, cons=s.cons).run(n)
+        e = rel_pos_err(mix["x"], ref.x)
+        report(f"pool {s.surface} n={s.n} {n} steps", x=e)
+        assert e < 1e-6
+    pool.close()
