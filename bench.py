@@ -176,6 +176,7 @@ def extra_benches(skin: float):
                            skin=skin, **timed_steps(s, run, skin, 2000, 300))
     log(f"[bench] membrane: {out['membrane']}")
     out["capsid"] = capsid_bench(skin)
+    out["capsid_fp32"] = capsid_bench(skin, force_fp64=0)
     out["rods_20k"] = rods_bench(skin)
     s = gen.bridge(4000, 10.0, 1.5, 3.0, 70.0, 13)
     run = dict(dt=0.002, kT=1.0, gamma=1.0, rc=2.0 ** (1.0 / 6.0), pair="lj", force_fp64=1, seed=13)
@@ -196,13 +197,15 @@ def bead_model(mp: dict, R: float):
                     wall_radius=R - mp["wall_inset"])
 
 
-def capsid_bench(skin: float, steps: int = 1000, warmup: int = 200):
+def capsid_bench(skin: float, steps: int = 1000, warmup: int = 200, force_fp64: int = 1):
     from workloads import gen
     s, run = gen.capsid_2m()
+    run = dict(run, force_fp64=force_fp64)
     model = bead_model(gen.capsid_model(), run["R"])
     res = dict(workload=f"capsid bead model: {s.n // 4} four-bead capsomeres ({s.n} beads) on a sphere "
                         f"R={run['R']:.1f}, typed LJ (eps 4, attractive like pairs to 4 sigma_0), bonds, bends, "
-                        "wall, fp64 forces", skin=skin, **timed_steps(s, run, skin, steps, warmup, model=model))
+                        f"wall, {'fp64' if force_fp64 else 'fp32'} pair forces", skin=skin,
+               **timed_steps(s, run, skin, steps, warmup, model=model))
     log(f"[bench] capsid: {res}")
     return res
 
@@ -289,7 +292,7 @@ def main():
     ap.add_argument("--serving-rate", type=float, default=200.0)
     ap.add_argument("--serving-budget-gb", type=float, default=16.0)
     ap.add_argument("--no-extra", action="store_true", help="skip the secondary measurements")
-    ap.add_argument("--only", choices=["capsid", "rods"], help="run only this secondary measurement")
+    ap.add_argument("--only", choices=["capsid", "capsid_fp32", "rods"], help="run only this secondary measurement")
     args = ap.parse_args()
     if args.no_graph:
         os.environ["MD_NO_GRAPH"] = "1"
@@ -300,7 +303,8 @@ def main():
         sys.exit(2)
     if args.only:
         # one secondary measurement alone (for profiling its kernels)
-        res = {"capsid": capsid_bench, "rods": rods_bench}[args.only](args.skin)
+        res = {"capsid": capsid_bench, "rods": rods_bench,
+               "capsid_fp32": lambda sk: capsid_bench(sk, force_fp64=0)}[args.only](args.skin)
         print(json.dumps(res), flush=True)
         return
 

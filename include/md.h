@@ -151,9 +151,10 @@ typedef struct md_params {
  *  - a repulsive wall about the surface centre c, for d = |x - c| - wall_radius
  *    below 2^(1/6) wall_sigma: V = 4 wall_eps [(s/d)^12 - (s/d)^6 + 1/4],
  *    s = wall_sigma; wall_eps = 0: no wall.
- * Requires pair_kind MD_PAIR_LJ and force_fp64 = 1; params.rc is not used (the
- * cell grid and lists use the largest rc_ab).  Tables are symmetric: entry
- * [a][b] is used for a <= b. */
+ * Requires pair_kind MD_PAIR_LJ; force_fp64 selects the pair terms' class as
+ * for plain systems (bonds, bends and the wall are always FP64).  params.rc is
+ * not used (the cell grid and lists use the largest rc_ab).  Tables are
+ * symmetric: entry [a][b] is used for a <= b. */
 #define MD_MAX_TYPES 4
 typedef struct md_model {
   int ntypes;                              /* 1 .. MD_MAX_TYPES                     */

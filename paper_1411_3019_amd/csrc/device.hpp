@@ -491,13 +491,14 @@ __device__ __forceinline__ double pair_energy(const JobDev& J, const DevBufs& B,
 }
 
 // ---------------------------------------------------------------------------
-// Bead model (SI, Virus capsid self-assembly), FP64 class only.
+// Bead model (SI, Virus capsid self-assembly).  Pair terms in either force
+// class (FP64: summed in particle-index order; FP32: FP32 terms from FP64
+// separations on the exact-sum grid); bonded terms always FP64.
 // ---------------------------------------------------------------------------
 
 // Pair forces on slot i (type ti) from its list, typed truncated-shifted LJ;
-// pairs inside a molecule are not in the list.  Summed in list order (sorted
-// by particle index).
-template <bool kPer>
+// pairs inside a molecule are not in the list.
+template <bool kPer, bool kF64>
 __device__ __forceinline__ void pair_forces_model(const JobDev& J, const ModelDev& M, const DevBufs& B,
                                                   const double* __restrict__ X, int64_t i, int ti, double xi,
                                                   double yi, double zi, double& Fx, double& Fy, double& Fz) {
@@ -516,13 +517,23 @@ __device__ __forceinline__ void pair_forces_model(const JobDev& J, const ModelDe
     if (kPer) min_image(J, dx, dy, dz);
     const double r2 = dx * dx + dy * dy + dz * dz;
     if (!(r2 < row_rc2[tj])) return;
-    const double inv = 1.0 / r2;
-    const double s2 = row_sig2[tj] * inv;
-    const double s6 = s2 * s2 * s2;
-    const double c = row_eps24[tj] * inv * s6 * (2.0 * s6 - 1.0);
-    fx += c * dx;
-    fy += c * dy;
-    fz += c * dz;
+    if (kF64) {
+      const double inv = 1.0 / r2;
+      const double s2 = row_sig2[tj] * inv;
+      const double s6 = s2 * s2 * s2;
+      const double c = row_eps24[tj] * inv * s6 * (2.0 * s6 - 1.0);
+      fx += c * dx;
+      fy += c * dy;
+      fz += c * dz;
+    } else {
+      const float inv = __builtin_amdgcn_rcpf((float)r2);
+      const float s2 = (float)row_sig2[tj] * inv;
+      const float s6 = s2 * s2 * s2;
+      const float c = (float)row_eps24[tj] * inv * s6 * (2.0f * s6 - 1.0f);
+      fx += on_grid((double)(c * (float)dx));
+      fy += on_grid((double)(c * (float)dy));
+      fz += on_grid((double)(c * (float)dz));
+    }
   };
   int k = 0;
   for (; k + 4 <= cnt; k += 4) {
@@ -572,7 +583,8 @@ __device__ __forceinline__ double pair_energy_model(const JobDev& J, const Model
     if (!(r2 < M.rc2[p])) continue;
     const double s2 = M.sig2[p] / r2;
     const double s6 = s2 * s2 * s2;
-    u += 0.5 * (M.eps4[p] * s6 * (s6 - 1.0) - M.phic[p]);
+    const double v = 0.5 * (M.eps4[p] * s6 * (s6 - 1.0) - M.phic[p]);
+    u += J.force_fp64 ? v : on_grid(v);  // FP32 class: slot-ordered lists, exact-sum grid
   }
   return u;
 }

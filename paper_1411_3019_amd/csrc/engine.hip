@@ -210,7 +210,7 @@ int validate_params(const md_params& p) {
 // Bytes of device state per particle slot (excluding the neighbour list).
 constexpr int64_t kSlotBytes = 2 * 24 /*X*/ + 2 * 24 /*P*/ + 2 * 4 /*ID*/ + 2 * 1 /*FLG*/ + 2 * 8 /*MASS*/ +
                                24 /*FC*/ + 3 * 24 /*OX,OP,OF*/ + 32 /*OD*/ + 4 /*NCNT*/ + 4 * 7 /*rebuild*/ +
-                               16 /*PK*/;
+                               16 /*PK*/ + 2 * 1 /*TYPE*/;
 
 struct HostJob {
   bool used = false;
@@ -350,12 +350,13 @@ struct Engine {
   std::vector<HostJob> jobs;
   FirstFit slots, words;
   // device scratch for launch descriptors
-  // step tile classes, one step kernel each: FP64 forces, FP32 forces, bead model (FP64)
-  static constexpr int kClasses = 3;
+  // step tile classes, one step kernel each: FP64 forces, FP32 forces, bead
+  // model with FP64 forces, bead model with FP32 forces
+  static constexpr int kClasses = 4;
   int* step_tiles_job = nullptr;       // [kClasses][tile_cap]
   int64_t* step_tiles_first = nullptr;
   int* step_counts = nullptr;          // [kClasses]: tiles in each list (read by the step kernels)
-  int grid[kClasses] = {0, 0, 0};      // grid sizes baked into the cached graphs
+  int grid[kClasses] = {0, 0, 0, 0};   // grid sizes baked into the cached graphs
   int* aux_tiles_job = nullptr;        // rebuild / finish lists
   int64_t* aux_tiles_first = nullptr;
   int64_t tile_cap = 0;
@@ -681,7 +682,7 @@ struct Engine {
             int64_t target, int* job_id, const ModelDev* model = nullptr, const uint8_t* types = nullptr) {
     MDCHK(validate_params(prm));
     // bead-model lists carry the partner type in the top two bits of a slot index
-    if (model && (prm.pair_kind != MD_PAIR_LJ || !prm.force_fp64 || (n > 0 && !types) || C > (int64_t)kIdMask))
+    if (model && (prm.pair_kind != MD_PAIR_LJ || (n > 0 && !types) || C > (int64_t)kIdMask))
       return MD_EINVAL;
     if (n < 0 || (n > 0 && (!x || !p)) || n > 0xFFFFFFF0LL) return MD_EINVAL;
     int j = -1;
@@ -976,7 +977,7 @@ struct Engine {
     for (int j = 0; j < max_jobs; ++j) {
       const HostJob& h = jobs[j];
       if (!h.used || h.done || h.status != MD_OK) continue;
-      const int c = h.model ? 2 : (h.dev.force_fp64 ? 0 : 1);
+      const int c = (h.model ? 2 : 0) + (h.dev.force_fp64 ? 0 : 1);
       tiles_of(h, j, tj[c], tf[c]);
     }
     bool same = true;
@@ -1021,6 +1022,9 @@ struct Engine {
       if (grid[2] > 0)
         hipLaunchKernelGGL(k_step_model, dim3(grid[2]), dim3(kTile), 0, stream, B, step_tiles_job + 2 * tile_cap,
                            step_tiles_first + 2 * tile_cap, step_counts + 2, t);
+      if (grid[3] > 0)
+        hipLaunchKernelGGL(k_step_model_f32, dim3(grid[3]), dim3(kTile), 0, stream, B,
+                           step_tiles_job + 3 * tile_cap, step_tiles_first + 3 * tile_cap, step_counts + 3, t);
     }
   }
 
@@ -1126,7 +1130,7 @@ struct Engine {
     MDCHK(read_book());
     for (int q = 0; q < nsub; ++q) stats.step_kernel_ms += elapsed_ms(ev_sub[2 * q], ev_sub[2 * q + 1]);
     stats.chunks += 1;
-    stats.step_launches += (int64_t)kk * ((grid[0] > 0) + (grid[1] > 0) + (grid[2] > 0));
+    stats.step_launches += (int64_t)kk * ((grid[0] > 0) + (grid[1] > 0) + (grid[2] > 0) + (grid[3] > 0));
     const int longest = collect_build_stats();
     int64_t adv = 0;
     for (int j = 0; j < max_jobs; ++j) {
@@ -1386,7 +1390,7 @@ int md_set_model(md_ctx* ctx, const md_model* model, const uint8_t* types, int64
     return MD_OK;
   }
   if (n < 0 || (n > 0 && !types)) return MD_EINVAL;
-  if (ctx->prm.pair_kind != MD_PAIR_LJ || !ctx->prm.force_fp64) return MD_EINVAL;
+  if (ctx->prm.pair_kind != MD_PAIR_LJ) return MD_EINVAL;
   ModelDev d;
   double rc_max = 0.0;
   MDCHK(build_model(*model, d, rc_max));

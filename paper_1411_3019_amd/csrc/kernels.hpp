@@ -50,15 +50,15 @@ __device__ __forceinline__ void record_error(JobBook& K, int code, uint32_t id, 
 
 // Bead-model forces on slot i (particle index id): typed pairs, then bonds,
 // bends and the wall; returns the particle's energy share (kEnergy).
-template <bool kEnergy>
+template <bool kEnergy, bool kF64>
 __device__ __forceinline__ double model_forces(const JobDev& J, const ModelDev& M, const DevBufs& B,
                                                const double* __restrict__ X, int64_t i, uint32_t id, double xi,
                                                double yi, double zi, double& Fx, double& Fy, double& Fz) {
   const int ti = B.TYPE[J.scur][i];
   if (J.periodic[0] | J.periodic[1] | J.periodic[2])
-    pair_forces_model<true>(J, M, B, X, i, ti, xi, yi, zi, Fx, Fy, Fz);
+    pair_forces_model<true, kF64>(J, M, B, X, i, ti, xi, yi, zi, Fx, Fy, Fz);
   else
-    pair_forces_model<false>(J, M, B, X, i, ti, xi, yi, zi, Fx, Fy, Fz);
+    pair_forces_model<false, kF64>(J, M, B, X, i, ti, xi, yi, zi, Fx, Fy, Fz);
   double u = kEnergy ? pair_energy_model(J, M, B, X, i, ti, xi, yi, zi) : 0.0;
   double xs[15];
   int tid[5];
@@ -158,7 +158,7 @@ __device__ __forceinline__ void step_body(const DevBufs& B, const int* __restric
     double Fx = 0.0, Fy = 0.0, Fz = 0.0;
     if (J.pair_kind != kPairNone) {
       if (kModel)
-        model_forces<false>(J, B.models[job], B, X, i, id, xi, yi, zi, Fx, Fy, Fz);
+        model_forces<false, kF64>(J, B.models[job], B, X, i, id, xi, yi, zi, Fx, Fy, Fz);
       else
         pair_forces<kF64>(J, B, X, i, xi, yi, zi, Fx, Fy, Fz);
     }
@@ -252,14 +252,20 @@ __global__ void __launch_bounds__(kTile) k_step_f64(DevBufs B, const int* __rest
 #define MDK_STEPMODEL_WAVES 5
 #endif
 
-// Bead-model jobs (FP64 forces): typed pairs, bonds, bends and the wall;
+// Bead-model jobs: typed pairs, bonds, bends and the wall (FP64 force class);
 // occupancy target MDK_STEPMODEL_WAVES wavefronts per SIMD (5 fits without
 // spilling).
 __global__ void __launch_bounds__(kTile) __attribute__((amdgpu_waves_per_eu(MDK_STEPMODEL_WAVES, 8)))
-k_step_model(DevBufs B, const int* __restrict__ tile_job,
-                                                      const int64_t* __restrict__ tile_first,
-                                                      const int* __restrict__ ntiles_ptr, int t) {
+k_step_model(DevBufs B, const int* __restrict__ tile_job, const int64_t* __restrict__ tile_first,
+             const int* __restrict__ ntiles_ptr, int t) {
   step_body<true, true>(B, tile_job, tile_first, ntiles_ptr, t);
+}
+
+// The same with FP32 pair terms (and the FP32 Box-Muller transform).
+__global__ void __launch_bounds__(kTile) __attribute__((amdgpu_waves_per_eu(MDK_STEPMODEL_WAVES, 8)))
+k_step_model_f32(DevBufs B, const int* __restrict__ tile_job, const int64_t* __restrict__ tile_first,
+                 const int* __restrict__ ntiles_ptr, int t) {
+  step_body<false, true>(B, tile_job, tile_first, ntiles_ptr, t);
 }
 
 // Finish: state at the current step m (x^m, p^m, f^m) and per-particle
@@ -284,8 +290,8 @@ __global__ void __launch_bounds__(kTile) k_finish(DevBufs B, const int* __restri
   const long long s = J.step0;
   double Fx = 0.0, Fy = 0.0, Fz = 0.0, Ui = 0.0;
   if (J.pair_kind != kPairNone) {
-    if (kF64 && J.model) {
-      Ui = model_forces<true>(J, B.models[job], B, X, i, id, xi, yi, zi, Fx, Fy, Fz);
+    if (J.model) {
+      Ui = model_forces<true, kF64>(J, B.models[job], B, X, i, id, xi, yi, zi, Fx, Fy, Fz);
     } else {
       pair_forces<kF64>(J, B, X, i, xi, yi, zi, Fx, Fy, Fz);
       Ui = pair_energy(J, B, X, i, xi, yi, zi);
@@ -644,8 +650,8 @@ __device__ __forceinline__ void nlist_lane(const DevBufs& B, const JobDev& J, in
         if (j + u < end && j + u != i && take) {
           if (kSorted)
             list_insert(kid, lane, kmax, cnt, q);
-          else
-            list_append(kid, lane, kmax, cnt, (uint32_t)(j + u - base));
+          else  // job-local slot (bead model: partner type in the top bits)
+            list_append(kid, lane, kmax, cnt, (uint32_t)(j + u - base) | (kModel ? w & ~kIdMask : 0u));
         }
       }
     }
@@ -712,12 +718,22 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const int* __r
       }
     } else {
       // FP32 class: slot order, as found
-      nlist_lane<false, false>(B, J, i, xi, yi, zi, cx, cy, cz, kid, lane, kmax, cnt, 0u, nullptr, 0);
+      if (kWithModel && J.model)
+        nlist_lane<false, kWithModel>(B, J, i, xi, yi, zi, cx, cy, cz, kid, lane, kmax, cnt, B.ID[J.scur ^ 1][i],
+                                      B.models + job, B.TYPE[J.scur ^ 1][i]);
+      else
+        nlist_lane<false, false>(B, J, i, xi, yi, zi, cx, cy, cz, kid, lane, kmax, cnt, 0u, nullptr, 0);
       stored = cnt < kmax ? cnt : kmax;
       for (int k = 0; k < stored; k += 4) {
         uint32_t v[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) v[u] = k + u < stored ? (uint32_t)base + kid[(k + u) * kNlistBlock + lane] : 0u;
+        for (int u = 0; u < 4; ++u) {
+          // job-local slot, with the bead model's partner type in the top bits
+          const uint32_t q = kid[(k + u) * kNlistBlock + lane];
+          const uint32_t sl = kWithModel && J.model ? ((uint32_t)base + (q & kIdMask)) | (q & ~kIdMask)
+                                                    : (uint32_t)base + q;
+          v[u] = k + u < stored ? sl : 0u;
+        }
         reinterpret_cast<uint4*>(B.NL)[(int64_t)(k >> 2) * C + i] = make_uint4(v[0], v[1], v[2], v[3]);
       }
     }
