@@ -184,7 +184,40 @@ def extra_benches(skin: float):
                                   "70x70 periodic planes), 4000 WCA particles, fp64 forces", skin=skin,
                          **timed_steps(s, run, skin, 4000, 500))
     log(f"[bench] bridge: {out['bridge']}")
+    out["bridge_pool"] = bridge_pool_bench(skin)
     return out
+
+
+def bridge_pool_bench(skin: float, jobs: int = 128, steps: int = 2000):
+    """Many small systems on the piecewise bridge resident in one pool (the
+    batched form): jobs x 4000 WCA particles, each its own seed and initial
+    state, all advanced by shared launches until every job is done."""
+    from paper_1411_3019_amd import md
+    from workloads import gen
+    systems = [gen.bridge(4000, 10.0, 1.5, 3.0, 70.0, 100 + k) for k in range(jobs)]
+    pool = md.Pool(16 << 30, jobs)
+    ids = []
+    for k, s in enumerate(systems):
+        prm = md.Params(dt=0.002, kT=1.0, gamma=1.0, rc=2.0 ** (1.0 / 6.0), pair="lj", force_fp64=1, skin=skin,
+                        seed=100 + k, box_lo=s.box_lo, box_hi=s.box_hi, periodic=s.periodic)
+        jid = pool.admit(prm, s.surface, s.surf, s.x, s.p, steps)
+        if jid is None:
+            raise RuntimeError("bridge pool: no room")
+        ids.append(jid)
+    device_sync()
+    t0 = time.perf_counter()
+    done = set()
+    while not done >= set(ids):
+        pool.run(64)
+        done |= set(pool.poll())
+    device_sync()
+    wall = time.perf_counter() - t0
+    pool.close()
+    n = sum(s.n for s in systems)
+    res = {"workload": f"{jobs} independent bridge systems x 4000 WCA particles in one pool, {steps} steps each, "
+                       "fp64 forces", "particle_steps_per_s": n * steps / wall, "wall_s": wall}
+    log(f"[bench] bridge pool: {res}")
+    return res
 
 
 def bead_model(mp: dict, R: float):

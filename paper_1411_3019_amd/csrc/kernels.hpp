@@ -825,13 +825,28 @@ __global__ void __launch_bounds__(kStatsThreads) k_job_stats(DevBufs B, int with
   if (J.n <= 0) return;
   double a = 0.0, sm = 0.0;
   uint32_t mx = 0u;
-  const int64_t t1 = (J.off + J.n + kGroup - 1) / kGroup;
-  for (int64_t t = J.off / kGroup + threadIdx.x; t < t1; t += kStatsThreads) a = fmax(a, B.TACC[t]);
+  const int64_t g0 = J.off / kGroup, g1 = (J.off + J.n + kGroup - 1) / kGroup;
+  // four independent loads in flight per thread (one workgroup serves a job)
+  constexpr int64_t kStride = kStatsThreads;
+  int64_t g = g0 + threadIdx.x;
+  for (; g + 3 * kStride < g1; g += 4 * kStride) {
+    const double t0 = B.TACC[g], t1 = B.TACC[g + kStride], t2 = B.TACC[g + 2 * kStride], t3 = B.TACC[g + 3 * kStride];
+    a = fmax(fmax(a, fmax(t0, t1)), fmax(t2, t3));
+  }
+  for (; g < g1; g += kStride) a = fmax(a, B.TACC[g]);
   if (with_lists) {
-    const int64_t g1 = (J.off + J.n + kGroup - 1) / kGroup;
-    for (int64_t g = J.off / kGroup + threadIdx.x; g < g1; g += kStatsThreads) {
-      mx = max(mx, B.NLSTAT[2 * g]);
-      sm += (double)B.NLSTAT[2 * g + 1];
+    // list-length sums are integers: exact in FP64 in any order
+    const uint2* __restrict__ st = reinterpret_cast<const uint2*>(B.NLSTAT);
+    g = g0 + threadIdx.x;
+    for (; g + 3 * kStride < g1; g += 4 * kStride) {
+      const uint2 q0 = st[g], q1 = st[g + kStride], q2 = st[g + 2 * kStride], q3 = st[g + 3 * kStride];
+      mx = max(mx, max(max(q0.x, q1.x), max(q2.x, q3.x)));
+      sm += (double)q0.y + (double)q1.y + (double)q2.y + (double)q3.y;
+    }
+    for (; g < g1; g += kStride) {
+      const uint2 q = st[g];
+      mx = max(mx, q.x);
+      sm += (double)q.y;
     }
   }
   for (int o = 32; o > 0; o >>= 1) {
