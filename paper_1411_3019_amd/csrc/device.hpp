@@ -384,10 +384,7 @@ __device__ __forceinline__ double on_grid(double t) {
 // the list order (the lists of this class are in slot order).  The loop issues
 // the gathers of kForceBatch neighbours before using them.  Specialised on the
 // potential's form and on periodicity so the loop carries no dead work.
-#ifndef MDK_FORCE_BATCH
-#define MDK_FORCE_BATCH 4
-#endif
-constexpr int kForceBatch = MDK_FORCE_BATCH;  // neighbour gathers in flight per force-loop iteration
+constexpr int kForceBatch = 4;  // neighbour gathers in flight per force-loop iteration: one uint4 list row
 
 template <bool kF64, bool kSmooth, bool kPer>
 __device__ __forceinline__ void pair_forces_impl(const JobDev& J, const DevBufs& B, const double* __restrict__ X,

@@ -2,7 +2,7 @@
 // hot path on MI355X.
 //
 // An Engine holds the device state of one or more jobs (systems) in
-// concatenated SoA arrays, a job table, and the tile lists that let one
+// concatenated per-slot arrays, a job table, and the tile lists that let one
 // launch cover every resident job.  md_ctx is an Engine with one job; md_pool
 // is an Engine with many.
 //

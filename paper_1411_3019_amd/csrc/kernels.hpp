@@ -6,7 +6,7 @@
 //
 // Step kernel (one launch per time step), for particle i of a job at step s:
 //   input  x^s (buffer parity xin), p^{s-1/2} (or p^s at a start), neighbour list
-//   force  F_i(x^s) from the list (sorted by particle index)
+//   force  F_i(x^s) from the list (and, for bead models, bonds, bends, wall)
 //   f^s    = b [F - gamma p^{s-1/2} + 1/2 sqrt(m) k (xi^s + xi^{s-1})]   (Algorithm S1)
 //   p^s    = q - (n.q / n.n) n,   q = p^{s-1/2} + dt/2 f^s,  n = n(x^s)  (Algorithm 1, 2nd loop)
 //   x^{s+1}, p^{s+1/2} from the scalar-Newton position stage          (Algorithm 1, 1st loop)
@@ -19,28 +19,6 @@
 #include "device.hpp"
 
 namespace mdk {
-
-// Maximum over the workgroup (result valid in thread 0).
-__device__ __forceinline__ double block_max(double v, double* red) {
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (lane == 0) red[wave] = v;
-  __syncthreads();
-  double m = red[0];
-  for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = fmax(m, red[w]);
-  return m;
-}
-
-__device__ __forceinline__ int block_max_int(int v, int* red) {
-  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) red[wave] = v;
-  __syncthreads();
-  int m = red[0];
-  for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = max(m, red[w]);
-  return m;
-}
 
 // An error at step s stops the job from step s + 1 on.
 __device__ __forceinline__ void record_error(JobBook& K, int code, uint32_t id, long long s) {
