@@ -185,7 +185,56 @@ def extra_benches(skin: float):
                          **timed_steps(s, run, skin, 4000, 500))
     log(f"[bench] bridge: {out['bridge']}")
     out["bridge_pool"] = bridge_pool_bench(skin)
+    out["capsid_pool"] = capsid_pool_bench(skin)
     return out
+
+
+def capsid_pool_bench(skin: float, jobs: int = 256, steps: int = 1000):
+    """Many small capsid systems (the bead model at the size of one template:
+    200 four-bead capsomeres on R = 11.5) in one pool, against one such system
+    alone."""
+    from paper_1411_3019_amd import md
+    from workloads import gen
+    mp = gen.capsid_model()
+    R = 11.5
+    model = bead_model(mp, R)
+    systems = [gen.capsomeres(200, R, 300 + k) for k in range(jobs)]
+
+    def params(s, k):
+        return md.Params(dt=0.002, kT=1.0, gamma=1.0, rc=4.0, pair="lj", force_fp64=1, skin=skin, seed=300 + k,
+                         box_lo=s.box_lo, box_hi=s.box_hi, periodic=s.periodic)
+
+    pool = md.Pool(16 << 30, jobs)
+    ids = [pool.admit(params(s, k), s.surface, s.surf, s.x, s.p, steps, mass=s.mass, cons=s.cons, model=model,
+                      types=s.types) for k, s in enumerate(systems)]
+    if None in ids:
+        raise RuntimeError("capsid pool: no room")
+    device_sync()
+    t0 = time.perf_counter()
+    done = set()
+    while not done >= set(ids):
+        pool.run(64)
+        done |= set(pool.poll())
+    device_sync()
+    wall = time.perf_counter() - t0
+    pool.close()
+    n = sum(s.n for s in systems)
+    s = systems[0]
+    g = md.System(params(s, 0), s.surface, s.surf)
+    g.set_model(model, s.types)
+    g.set_particles(s.x, s.p, mass=s.mass, cons=s.cons)
+    g.step(100)
+    device_sync()
+    t0 = time.perf_counter()
+    g.step(steps)
+    device_sync()
+    one = s.n * steps / (time.perf_counter() - t0)
+    g.close()
+    res = {"workload": f"{jobs} capsid systems x 200 four-bead capsomeres on R={R} (800 beads each) in one pool, "
+                       f"{steps} steps each, fp64 pair forces",
+           "particle_steps_per_s": n * steps / wall, "wall_s": wall, "one_system_alone_particle_steps_per_s": one}
+    log(f"[bench] capsid pool: {res}")
+    return res
 
 
 def bridge_pool_bench(skin: float, jobs: int = 128, steps: int = 2000):

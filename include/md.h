@@ -134,8 +134,8 @@ typedef struct md_params {
 } md_params;
 
 /* ---- bead model ----------------------------------------------------------------
- * The bead model of the capsid example (SI, Virus capsid self-assembly), for
- * one system (md_create contexts; pools run plain pair potentials only):
+ * The bead model of the capsid example (SI, Virus capsid self-assembly), for a
+ * system (md_set_model) or a pool job (md_job_desc.model):
  *  - bead types 0..ntypes-1 with sizes sigma[a]; sigma_ab = (sigma_a + sigma_b)/2
  *    (additive mixing);
  *  - truncated-shifted LJ per type pair, V = phi(r) - phi(rc_ab) for r < rc_ab,
@@ -296,6 +296,8 @@ typedef struct md_job_desc {
   const uint8_t* constrained; /* host, n or NULL */
   int64_t step0;
   int64_t nsteps;         /* steps to run before the job is done */
+  const md_model* model;  /* bead model (see md_model) or NULL; params.rc is then not used */
+  const uint8_t* types;   /* host, n bead types when model is set */
 } md_job_desc;
 
 /* Device bytes one job of n particles needs (for admission by HBM budget). */

@@ -1601,8 +1601,19 @@ int md_pool_admit(md_pool* pool, const md_job_desc* job, int* job_id) {
   if (!pool || !job || !job_id) return MD_EINVAL;
   if (job->nsteps < 0 || job->step0 < 0) return MD_EINVAL;
   MDCHK(validate_surface(job->surface_kind, job->surface_prm, job->params));
-  return pool->eng.admit(job->params, job->surface_kind, job->surface_prm, job->n, job->x, job->p, job->mass,
-                         job->constrained, nullptr, job->step0, job->step0 + job->nsteps, job_id);
+  md_params prm = job->params;
+  ModelDev md;
+  if (job->model) {
+    double rc_max = 0.0;
+    MDCHK(build_model(*job->model, md, rc_max));
+    if (job->n > 0 && !job->types) return MD_EINVAL;
+    for (int64_t i = 0; i < job->n; ++i)
+      if (job->types[i] >= job->model->ntypes) return MD_EINVAL;
+    prm.rc = rc_max;  // the cell grid and the lists cover the largest pair cut-off
+  }
+  return pool->eng.admit(prm, job->surface_kind, job->surface_prm, job->n, job->x, job->p, job->mass,
+                         job->constrained, nullptr, job->step0, job->step0 + job->nsteps, job_id,
+                         job->model ? &md : nullptr, job->model ? job->types : nullptr);
 }
 
 int md_pool_run(md_pool* pool, int steps_chunk) {

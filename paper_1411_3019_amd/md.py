@@ -118,6 +118,7 @@ class _JobDesc(C.Structure):
         ("n", C.c_int64), ("x", C.POINTER(C.c_double)), ("p", C.POINTER(C.c_double)),
         ("mass", C.POINTER(C.c_double)), ("constrained", C.POINTER(C.c_uint8)),
         ("step0", C.c_int64), ("nsteps", C.c_int64),
+        ("model", C.c_void_p), ("types", C.POINTER(C.c_uint8)),
     ]
 
 
@@ -351,7 +352,8 @@ class Pool:
                "md_pool_create")
         self._keep = {}
 
-    def admit(self, params: Params, surface: str, surf, x, p, nsteps: int, step0: int = 0, mass=None, cons=None):
+    def admit(self, params: Params, surface: str, surf, x, p, nsteps: int, step0: int = 0, mass=None, cons=None,
+              model: "Model | None" = None, types=None):
         """Returns the job id, or None when the pool has no room (MD_EAGAIN)."""
         x = np.asarray(x)
         n = x.shape[0]
@@ -365,8 +367,16 @@ class Pool:
         d.n = n
         d.x, d.p, d.mass, d.constrained = _dp(xs), _dp(ps), _dp(m), _u8(c)
         d.step0, d.nsteps = int(step0), int(nsteps)
+        keep = None
+        if model is not None:
+            mc = model.to_c()
+            t = np.ascontiguousarray(types, dtype=np.uint8).reshape(n)
+            d.model = C.cast(C.pointer(mc), C.c_void_p)
+            d.types = _u8(t)
+            keep = (mc, t)  # alive until md_pool_admit has copied them
         jid = C.c_int(-1)
         rc = lib().md_pool_admit(self._h, C.byref(d), C.byref(jid))
+        del keep
         if rc == MD_EAGAIN:
             return None
         _check(rc, "md_pool_admit")

@@ -136,3 +136,59 @@ def test_every_surface_kind_in_one_pool():
         report(f"pool {s.surface} n={s.n} {n} steps", x=e)
         assert e < 1e-6
     pool.close()
+
+
+def test_bead_model_jobs_in_a_pool():
+    """Small capsid systems (bead model) beside plain jobs in one pool, in both
+    force classes: each equals the same system run alone bit for bit, and the
+    bead-model jobs agree with the oracle."""
+    import math
+    from paper_1411_3019_amd import md
+    from _common import gpu_params, gpu_system
+    kw = dict(sigma=(1.0, 1.35, 1.75, 1.0), eps=4.0, rc={(1, 1): 4.0, (2, 2): 4.0}, kb=50.0, ka=250.0,
+              theta0=math.pi, wall_eps=1.0, wall_sigma=1.0)
+    jobs = []
+    for k, (nm, R) in enumerate([(120, 9.0), (200, 11.5), (80, 7.5), (150, 10.0)]):
+        s = gen.capsomeres(nm, R, 40 + k)
+        jobs.append((s, dict(rc=4.0, force_fp64=1 - (k % 2), seed=7 + k), R - 2.0))
+    plain = gen.sphere(500, 10.0, 9)
+    print("[gpu] pool with bead-model jobs", [(s.n, c["force_fp64"]) for s, c, _ in jobs], flush=True)
+    pool = md.Pool(256 << 20, 8)
+    ids = []
+    for s, c, rw in jobs:
+        m = md.Model(beads_per_molecule=4, wall_radius=rw, **kw)
+        ids.append(pool.admit(gpu_params(s, dt=0.002, **c), s.surface, s.surf, s.x, s.p, 150, mass=s.mass,
+                              cons=s.cons, model=m, types=s.types))
+    pid = pool.admit(gpu_params(plain, dt=0.002, rc=2.5, force_fp64=0, seed=3), plain.surface, plain.surf, plain.x,
+                     plain.p, 150)
+    assert None not in ids and pid is not None
+    done = set()
+    for _ in range(100):
+        pool.run(32)
+        done |= set(pool.poll())
+        if done >= set(ids + [pid]):
+            break
+    for (s, c, rw), jid in zip(jobs, ids):
+        rc, mix = pool.fetch(jid)
+        assert rc == 0
+        g = md.System(gpu_params(s, dt=0.002, **c), s.surface, s.surf)
+        g.set_model(md.Model(beads_per_molecule=4, wall_radius=rw, **kw), s.types)
+        g.set_particles(s.x, s.p, mass=s.mass, cons=s.cons)
+        g.step(150)
+        alone = g.get_state()
+        g.close()
+        assert np.array_equal(mix["x"], alone["x"]) and np.array_equal(mix["p"], alone["p"])
+        om = o.Model(bpm=4, wall_radius=rw, **kw)
+        P = o.Params(dt=0.002, surface=s.surface, surf=s.surf, rc=4.0, pair="lj", seed=c["seed"], model=om,
+                     types=s.types)
+        ref = o.State(P, s.x, s.p, mass=s.mass, cons=s.cons).run(150)
+        e = rel_pos_err(mix["x"], ref.x)
+        report(f"pool bead model n={s.n} fp64={c['force_fp64']} 150 steps", x=e)
+        assert e < (1e-10 if c["force_fp64"] else 1e-6)
+    rc, mix = pool.fetch(pid)
+    g = gpu_system(plain, dt=0.002, rc=2.5, force_fp64=0, seed=3)
+    g.step(150)
+    alone = g.get_state()
+    g.close()
+    assert np.array_equal(mix["x"], alone["x"])
+    pool.close()
