@@ -208,6 +208,8 @@ int validate_params(const md_params& p) {
 }
 
 // Bytes of device state per particle slot (excluding the neighbour list).
+constexpr double kInfinityCacheBytes = 256.0 * 1024.0 * 1024.0;  // MI355X last-level (memory-side) cache
+
 constexpr int64_t kSlotBytes = 2 * 24 /*X*/ + 2 * 24 /*P*/ + 2 * 4 /*ID*/ + 2 * 1 /*FLG*/ + 2 * 8 /*MASS*/ +
                                24 /*FC*/ + 3 * 24 /*OX,OP,OF*/ + 32 /*OD*/ + 4 /*NCNT*/ + 4 * 7 /*rebuild*/ +
                                16 /*PK*/ + 2 * 1 /*TYPE*/;
@@ -357,6 +359,7 @@ struct Engine {
   int64_t* step_tiles_first = nullptr;
   int* step_counts = nullptr;          // [kClasses]: tiles in each list (read by the step kernels)
   int grid[kClasses] = {0, 0, 0, 0};   // grid sizes baked into the cached graphs
+  bool stream_stores = false;          // store policy of the step and list kernels (set_store_policy)
   int* aux_tiles_job = nullptr;        // rebuild / finish lists
   int64_t* aux_tiles_first = nullptr;
   int64_t tile_cap = 0;
@@ -586,6 +589,36 @@ struct Engine {
       stage_cap = bytes;
     }
     return MD_OK;
+  }
+
+  // Bytes one step moves for the resident jobs: x read and written, p read
+  // and written, index, flag, count, the lists (mean length of the last
+  // build; a guess of 12 before the first), masses when they differ, and for
+  // bead models the type and the inverse-permutation entries of the bonded
+  // partners.
+  double step_working_set() const {
+    double ws = 0.0;
+    for (int j = 0; j < max_jobs; ++j) {
+      const HostJob& h = jobs[j];
+      if (!h.used || h.n == 0) continue;
+      const double kbar = h.nl_sum > 0.0 ? h.nl_sum / (double)h.n : 12.0;
+      double per = 105.0 + 4.0 * kbar;
+      if (!h.dev.uniform_mass) per += 8.0;
+      if (h.model) per += 1.0 + 16.0;
+      ws += (double)h.n * per;
+    }
+    return ws;
+  }
+
+  // Streaming stores for the new state (and list rows) when a step's data
+  // exceed the 256 MB Infinity Cache of the MI355X (see the step kernel); the
+  // kernel instances are chosen at launch, so cached graphs go when it flips.
+  void set_store_policy() {
+    const bool s = step_working_set() > kInfinityCacheBytes;
+    if (s != stream_stores) {
+      stream_stores = s;
+      drop_graphs();
+    }
   }
 
   int upload_jobs() {
@@ -892,12 +925,16 @@ struct Engine {
     hipLaunchKernelGGL(k_gather, dim3(ntiles), dim3(kTile), 0, stream, B, aux_tiles_job, aux_tiles_first);
     bool any_model = false;
     for (int j : set) any_model = any_model || jobs[j].model;
-    if (any_model)
-      hipLaunchKernelGGL(k_nlist<true>, dim3(kNlistPerTile * ntiles), dim3(kNlistBlock), lds, stream, B,
-                         aux_tiles_job, aux_tiles_first);
+    set_store_policy();
+    const dim3 ng(kNlistPerTile * ntiles), nb_(kNlistBlock);
+    if (any_model && stream_stores)
+      hipLaunchKernelGGL((k_nlist<true, true>), ng, nb_, lds, stream, B, aux_tiles_job, aux_tiles_first);
+    else if (any_model)
+      hipLaunchKernelGGL((k_nlist<true, false>), ng, nb_, lds, stream, B, aux_tiles_job, aux_tiles_first);
+    else if (stream_stores)
+      hipLaunchKernelGGL((k_nlist<false, true>), ng, nb_, lds, stream, B, aux_tiles_job, aux_tiles_first);
     else
-      hipLaunchKernelGGL(k_nlist<false>, dim3(kNlistPerTile * ntiles), dim3(kNlistBlock), lds, stream, B,
-                         aux_tiles_job, aux_tiles_first);
+      hipLaunchKernelGGL((k_nlist<false, false>), ng, nb_, lds, stream, B, aux_tiles_job, aux_tiles_first);
     hipLaunchKernelGGL(k_job_stats, dim3(max_jobs), dim3(kStatsThreads), 0, stream, B, 1);
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(ev[3], stream));
@@ -1011,21 +1048,29 @@ struct Engine {
     return MD_OK;
   }
 
-  void enqueue_steps(int t0, int k) {
+  template <bool kStream>
+  void enqueue_steps_as(int t0, int k) {
     for (int t = t0; t < t0 + k; ++t) {
       if (grid[0] > 0)
-        hipLaunchKernelGGL(k_step_f64, dim3(grid[0]), dim3(kTile), 0, stream, B, step_tiles_job, step_tiles_first,
-                           step_counts, t);
+        hipLaunchKernelGGL(k_step_f64<kStream>, dim3(grid[0]), dim3(kTile), 0, stream, B, step_tiles_job,
+                           step_tiles_first, step_counts, t);
       if (grid[1] > 0)
-        hipLaunchKernelGGL(k_step_f32, dim3(grid[1]), dim3(kTile), 0, stream, B, step_tiles_job + tile_cap,
+        hipLaunchKernelGGL(k_step_f32<kStream>, dim3(grid[1]), dim3(kTile), 0, stream, B, step_tiles_job + tile_cap,
                            step_tiles_first + tile_cap, step_counts + 1, t);
       if (grid[2] > 0)
-        hipLaunchKernelGGL(k_step_model, dim3(grid[2]), dim3(kTile), 0, stream, B, step_tiles_job + 2 * tile_cap,
-                           step_tiles_first + 2 * tile_cap, step_counts + 2, t);
+        hipLaunchKernelGGL(k_step_model<kStream>, dim3(grid[2]), dim3(kTile), 0, stream, B,
+                           step_tiles_job + 2 * tile_cap, step_tiles_first + 2 * tile_cap, step_counts + 2, t);
       if (grid[3] > 0)
-        hipLaunchKernelGGL(k_step_model_f32, dim3(grid[3]), dim3(kTile), 0, stream, B,
+        hipLaunchKernelGGL(k_step_model_f32<kStream>, dim3(grid[3]), dim3(kTile), 0, stream, B,
                            step_tiles_job + 3 * tile_cap, step_tiles_first + 3 * tile_cap, step_counts + 3, t);
     }
+  }
+
+  void enqueue_steps(int t0, int k) {
+    if (stream_stores)
+      enqueue_steps_as<true>(t0, k);
+    else
+      enqueue_steps_as<false>(t0, k);
   }
 
   int launch_chunk(int k, bool use_graph) {
@@ -1105,6 +1150,7 @@ struct Engine {
       h.dev.remaining = cap[j];
     }
     MDCHK(prepare_step_tiles());
+    set_store_policy();
     std::vector<JobDev> tab(max_jobs);
     int t0 = 0, nsub = 0;
     for (int len = kMaxChunk; len >= 1; len >>= 1) {

@@ -98,7 +98,7 @@ __device__ __forceinline__ void combined_force(const JobDev& J, const DevBufs& B
 // tile and shares no barrier with the others, so it leaves as soon as its own
 // particles are done.  (Workgroups of one wavefront would be capped by the
 // per-CU workgroup limit well below the register-bound occupancy.)
-template <bool kF64, bool kModel>
+template <bool kF64, bool kModel, bool kStream>
 __device__ __forceinline__ void step_body(const DevBufs& B, const int* __restrict__ tile_job,
                                           const int64_t* __restrict__ tile_first, const int* __restrict__ ntiles_ptr,
                                           int t) {
@@ -177,15 +177,28 @@ __device__ __forceinline__ void step_body(const DevBufs& B, const int* __restric
       y1 = yi + dtm * py;
       z1 = zi + dtm * pz;
     }
-    // streaming stores: the new state is not read again in this launch, so it
-    // should not displace the neighbour positions the other waves are
-    // gathering from L2 (measured: step kernel 119 -> 108 us on the 2M torus)
-    __builtin_nontemporal_store(x1, Xo + 3 * i);
-    __builtin_nontemporal_store(y1, Xo + 3 * i + 1);
-    __builtin_nontemporal_store(z1, Xo + 3 * i + 2);
-    __builtin_nontemporal_store(px, P + 3 * i);
-    __builtin_nontemporal_store(py, P + 3 * i + 1);
-    __builtin_nontemporal_store(pz, P + 3 * i + 2);
+    if (kStream) {
+      // streaming stores: the new state is not read again in this launch, so
+      // it should not displace the neighbour positions the other waves are
+      // gathering from L2 (2M torus: step kernel 119 -> 107 us).  Used when the
+      // step's data exceed the Infinity Cache; when they fit, ordinary stores
+      // leave the new state there for the next step (1M particles: 5 % faster).
+      // A template parameter, not a runtime flag: with both forms in one
+      // kernel the compiler merges part of them into ordinary stores.
+      __builtin_nontemporal_store(x1, Xo + 3 * i);
+      __builtin_nontemporal_store(y1, Xo + 3 * i + 1);
+      __builtin_nontemporal_store(z1, Xo + 3 * i + 2);
+      __builtin_nontemporal_store(px, P + 3 * i);
+      __builtin_nontemporal_store(py, P + 3 * i + 1);
+      __builtin_nontemporal_store(pz, P + 3 * i + 2);
+    } else {
+      Xo[3 * i] = x1;
+      Xo[3 * i + 1] = y1;
+      Xo[3 * i + 2] = z1;
+      P[3 * i] = px;
+      P[3 * i + 1] = py;
+      P[3 * i + 2] = pz;
+    }
     const double dx = x1 - xi, dy = y1 - yi, dz = z1 - zi;
     disp2 = dx * dx + dy * dy + dz * dz;
     if (!(disp2 <= 1e300) || !(fabs(px) + fabs(py) + fabs(pz) <= 1e300)) {
@@ -216,17 +229,19 @@ __device__ __forceinline__ void step_body(const DevBufs& B, const int* __restric
 
 // FP32 pair forces (and FP32 Box-Muller): occupancy target MDK_STEP32_WAVES
 // wavefronts per SIMD.
+template <bool kStream>
 __global__ void __launch_bounds__(kTile) __attribute__((amdgpu_waves_per_eu(MDK_STEP32_WAVES, 8)))
 k_step_f32(DevBufs B, const int* __restrict__ tile_job, const int64_t* __restrict__ tile_first,
            const int* __restrict__ ntiles_ptr, int t) {
-  step_body<false, false>(B, tile_job, tile_first, ntiles_ptr, t);
+  step_body<false, false, kStream>(B, tile_job, tile_first, ntiles_ptr, t);
 }
 
 // FP64 pair forces and FP64 Box-Muller.
+template <bool kStream>
 __global__ void __launch_bounds__(kTile) k_step_f64(DevBufs B, const int* __restrict__ tile_job,
                                                     const int64_t* __restrict__ tile_first,
                                                     const int* __restrict__ ntiles_ptr, int t) {
-  step_body<true, false>(B, tile_job, tile_first, ntiles_ptr, t);
+  step_body<true, false, kStream>(B, tile_job, tile_first, ntiles_ptr, t);
 }
 
 #ifndef MDK_STEPMODEL_WAVES
@@ -236,17 +251,19 @@ __global__ void __launch_bounds__(kTile) k_step_f64(DevBufs B, const int* __rest
 // Bead-model jobs: typed pairs, bonds, bends and the wall (FP64 force class);
 // occupancy target MDK_STEPMODEL_WAVES wavefronts per SIMD (5 fits without
 // spilling).
+template <bool kStream>
 __global__ void __launch_bounds__(kTile) __attribute__((amdgpu_waves_per_eu(MDK_STEPMODEL_WAVES, 8)))
 k_step_model(DevBufs B, const int* __restrict__ tile_job, const int64_t* __restrict__ tile_first,
              const int* __restrict__ ntiles_ptr, int t) {
-  step_body<true, true>(B, tile_job, tile_first, ntiles_ptr, t);
+  step_body<true, true, kStream>(B, tile_job, tile_first, ntiles_ptr, t);
 }
 
 // The same with FP32 pair terms (and the FP32 Box-Muller transform).
+template <bool kStream>
 __global__ void __launch_bounds__(kTile) __attribute__((amdgpu_waves_per_eu(MDK_STEPMODEL_WAVES, 8)))
 k_step_model_f32(DevBufs B, const int* __restrict__ tile_job, const int64_t* __restrict__ tile_first,
                  const int* __restrict__ ntiles_ptr, int t) {
-  step_body<false, true>(B, tile_job, tile_first, ntiles_ptr, t);
+  step_body<false, true, kStream>(B, tile_job, tile_first, ntiles_ptr, t);
 }
 
 // Finish: state at the current step m (x^m, p^m, f^m) and per-particle
@@ -647,13 +664,19 @@ __device__ __forceinline__ void nlist_lane(const DevBufs& B, const JobDev& J, in
   }
 }
 
-// One uint4 row of a list (entries k .. k+3 of slot i) with a streaming store:
-// the lists are read in the next step, not in this launch, and would
-// otherwise displace the candidate records the build is reading from L2.
-__device__ __forceinline__ void store_row_nt(uint32_t* NL, int64_t C, int k, int64_t i, const uint32_t* v) {
+// One uint4 row of a list (entries k .. k+3 of slot i).  Streaming (as the
+// step's state stores, when the data exceed the Infinity Cache): the lists
+// are read in the next step, not in this launch, and would otherwise
+// displace the candidate records the build is reading from L2.
+template <bool kStream>
+__device__ __forceinline__ void store_row(uint32_t* NL, int64_t C, int k, int64_t i, const uint32_t* v) {
   typedef unsigned int v4u __attribute__((ext_vector_type(4)));
   const v4u row = {v[0], v[1], v[2], v[3]};
-  __builtin_nontemporal_store(row, reinterpret_cast<v4u*>(NL) + (int64_t)(k >> 2) * C + i);
+  v4u* dst = reinterpret_cast<v4u*>(NL) + (int64_t)(k >> 2) * C + i;
+  if (kStream)
+    __builtin_nontemporal_store(row, dst);
+  else
+    *dst = row;
 }
 
 // Neighbour-list build, one lane per slot of the freshly sorted (raster cell)
@@ -665,7 +688,7 @@ __device__ __forceinline__ void store_row_nt(uint32_t* NL, int64_t C, int k, int
 // neighbouring lanes then read neighbouring memory in the force loop.
 // kWithModel: the instance launched when a bead-model job is among those built
 // (the plain instance keeps the model path out of its register budget).
-template <bool kWithModel>
+template <bool kWithModel, bool kStream>
 __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const int* __restrict__ tile_job,
                                                        const int64_t* __restrict__ tile_first) {
   extern __shared__ uint32_t kid[];  // lists [kmax][kNlistBlock]
@@ -704,7 +727,7 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const int* __r
           v[u] = k + u < stored ? sl : 0u;
           if (typed && k + u < stored) v[u] |= (uint32_t)T[sl] << kTypeShift;
         }
-        store_row_nt(B.NL, C, k, i, v);
+        store_row<kStream>(B.NL, C, k, i, v);
       }
     } else {
       // FP32 class: slot order, as found
@@ -724,7 +747,7 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const int* __r
                                                     : (uint32_t)base + q;
           v[u] = k + u < stored ? sl : 0u;
         }
-        store_row_nt(B.NL, C, k, i, v);
+        store_row<kStream>(B.NL, C, k, i, v);
       }
     }
     B.NCNT[i] = (uint32_t)stored;
