@@ -20,6 +20,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <limits>
 #include <map>
 #include <new>
 #include <vector>
@@ -656,7 +657,8 @@ struct Engine {
     d.rc2 = rc * rc;
     const double rl = (rc > 0.0 ? rc : 1.0) + skin;
     d.rlist2 = rl * rl;
-    d.half_skin = 0.5 * skin;
+    // without a pair potential there are no lists to keep valid: no rebuilds
+    d.half_skin = p.pair_kind != MD_PAIR_NONE ? 0.5 * skin : std::numeric_limits<double>::infinity();
     if (p.pair_kind != MD_PAIR_NONE) {
       double dphic;
       d.phic = lj_phi(p.eps, p.sigma, p.rc, &dphic);

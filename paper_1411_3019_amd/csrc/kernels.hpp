@@ -700,7 +700,9 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const int* __r
   const int64_t i = uniform_i64(tile_first[tile]) + ((int)blockIdx.x % kNlistPerTile) * kNlistBlock + lane;
   const int64_t base = J.off;
   int cnt = 0;
-  if (i < J.off + J.n) {
+  if (i < J.off + J.n && J.pair_kind == kPairNone) {
+    B.NCNT[i] = 0u;  // no pair potential: empty lists (the build only sorts)
+  } else if (i < J.off + J.n) {
     const double* __restrict__ X = B.X[J.xcur ^ 1];  // the sorted copies written by k_gather
     const double xi = X[3 * i], yi = X[3 * i + 1], zi = X[3 * i + 2];
     const int cx = cell_coord(J, 0, xi), cy = cell_coord(J, 1, yi), cz = cell_coord(J, 2, zi);
