@@ -1,7 +1,8 @@
 """GPU edge cases against the oracle: an empty system, a single particle,
 sizes that leave ragged tiles and wavefronts, non-uniform masses, free
-particles with no surface in a periodic box, and pools holding empty and
-one-particle jobs beside ordinary ones."""
+particles with no surface in a periodic box, pools holding empty and
+one-particle jobs beside ordinary ones, lists outgrowing their capacity
+mid-run, and the device-pointer entry points."""
 import numpy as np
 import pytest
 
@@ -129,6 +130,54 @@ def test_pool_with_degenerate_jobs():
     alone = g.get_state()
     g.close()
     assert np.array_equal(alone["x"], r_one["x"]) and np.array_equal(alone["p"], r_one["p"])
+
+
+@pytest.mark.parametrize("force_fp64", [1, 0])
+def test_list_capacity_grows_mid_run(force_fp64):
+    """A gas converging on the pole of a sphere: its neighbour counts rise from
+    at most 12 (the lists start with room for 16) to above 20 within one
+    md_step call.  The build that overflows stops the system before its first
+    step on the new lists, the capacity grows and the lists are built again, so
+    the trajectory is bitwise that of a context whose capacity was large from the
+    start (grown by a dense system evaluated beforehand), and follows the oracle.
+    Tolerances: the trajectory is chaotic; in the oracle a 1e-15 relative
+    perturbation of the start grows to ~5e-12 in x and ~2e-10 in p over the 900
+    steps, so per-step differences of ~1e-15 (FP64 class) and ~1e-10 (FP32
+    class) bound the differences at the end well inside the limits below."""
+    from paper_1411_3019_amd import md
+    steps = 900
+    s = gen.converging_cap(150, 12.0, 6.0, 3)
+    kw = dict(dt=0.002, kT=0.0, gamma=0.0, pair="lj", rc=2.5, force_fp64=force_fp64)
+    print(f"[gpu] list capacity grows mid-run force_fp64={force_fp64}", flush=True)
+    g = gpu_system(s, **kw)
+    start_max = g.get_state(want_force=False)["diag"]["nlist_max"]
+    g.step(steps)
+    grown = g.get_state()
+    builds_grown = g.stats()["builds"]
+    g.close()
+    assert start_max <= 12 and grown["diag"]["nlist_max"] > 20
+
+    primed = md.System(gpu_params(s, **kw), s.surface, s.surf)
+    dense = gen.sphere(2900, 12.0, 8, dmin=0.5)
+    primed.set_particles(dense.x, dense.p)
+    cap = primed.get_state(want_force=False)["diag"]["nlist_max"]
+    assert cap > grown["diag"]["nlist_max"] + 10
+    builds_primer = primed.stats()["builds"]
+    primed.set_particles(s.x, s.p)
+    primed.step(steps)
+    wide = primed.get_state()
+    builds_wide = primed.stats()["builds"] - builds_primer
+    primed.close()
+    for k in ("x", "p", "f"):
+        assert np.array_equal(grown[k], wide[k]), k
+    # the same build schedule, plus the builds that overflowed and were redone
+    assert builds_grown > builds_wide
+
+    ref = o.State(oracle_params(s, **kw), s.x, s.p).run(steps)
+    ex, ep = rel_pos_err(grown["x"], ref.x), rel_err(grown["p"], ref.p)
+    report(f"capacity growth fp64={force_fp64} {steps} steps", x=ex, p=ep)
+    assert ex < (1e-9 if force_fp64 else 1e-5)
+    assert ep < (1e-7 if force_fp64 else 1e-3)
 
 
 class _Dev:

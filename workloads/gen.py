@@ -127,6 +127,27 @@ def sphere(n: int, R: float, seed: int, dmin: float = 0.9, kT: float = 1.0) -> S
     return System(x, p, "sphere", (0.0, 0.0, 0.0, R), meta=dict(R=R))
 
 
+def converging_cap(n: int, R: float, speed: float, seed: int, lat_max: float = math.radians(35.0),
+                   dmin: float = 1.2) -> System:
+    """A dilute gas on a band of the sphere (latitudes 0..lat_max) whose particles
+    all move north at one speed: they pile up at the pole, so the neighbour counts
+    rise several-fold during the run (a test of list capacity growing mid-run)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+
+    def sampler(rng, m):
+        z = R * rng.uniform(0.0, math.sin(lat_max), size=m)  # uniform in area on the band
+        ph = rng.uniform(0.0, 2.0 * np.pi, size=m)
+        rho = np.sqrt(R * R - z * z)
+        return np.stack([rho * np.cos(ph), rho * np.sin(ph), z], axis=1)
+
+    x = _fill(sampler, n, dmin, rng)
+    u = _unit(x)
+    north = np.array([0.0, 0.0, 1.0]) - u[:, 2:3] * u
+    p = speed * _unit(north)
+    p -= np.sum(p * u, axis=1, keepdims=True) * u
+    return System(x, p, "sphere", (0.0, 0.0, 0.0, R), meta=dict(R=R))
+
+
 def torus(n: int, Rt: float, r: float, seed: int, dmin: float = 0.9, kT: float = 1.0) -> System:
     """Torus about the z axis: tube angle accepted with probability (Rt + r cos t)/(Rt + r)."""
     rng = np.random.Generator(np.random.PCG64(seed))
