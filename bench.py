@@ -408,7 +408,15 @@ def main():
     device_sync()
     wall = time.perf_counter() - t0
     st1 = sysm.stats()
+    t0 = time.perf_counter()
     state = sysm.get_state(want_force=False)
+    get_ms = (time.perf_counter() - t0) * 1e3
+    # the host side of the boundary: state back to the host above, and the
+    # same arrays handed in again (copy, checks, admission and list build)
+    t0 = time.perf_counter()
+    sysm.set_particles(s.x, s.p)
+    device_sync()
+    set_ms = (time.perf_counter() - t0) * 1e3
     sysm.close()
     d = state["diag"]
     log(f"[bench] {args.steps} steps in {wall:.3f} s; kT={d['kT']:.4f} gdist={d['gdist_max']:.2e} "
@@ -453,6 +461,11 @@ def main():
         "breakdown": {
             "step_kernel_ms": kern_ms, "launches": launches, "builds": builds, "build_ms": rebuild_ms,
             "wall_ms": wall * 1e3,
+        },
+        "host_boundary": {
+            "set_particles_ms": set_ms, "get_state_ms": get_ms,
+            "value_incl_host_io": s.n * args.steps / (wall + (set_ms + get_ms) * 1e-3),
+            "note": "the same steps with the state handed in from and back to host memory (not the metric)",
         },
     }
     if not args.no_extra:
