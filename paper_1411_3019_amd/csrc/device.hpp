@@ -377,11 +377,21 @@ __device__ __forceinline__ double on_grid(double t) {
   return (t + kM) - kM;
 }
 
+// The product c x rounded onto the same grid with a single rounding: the fused
+// multiply-add rounds c x + kM to a multiple of 2^-32, and removing kM is
+// exact.  One instruction fewer per component than rounding the product first,
+// and without its double rounding.
+__device__ __forceinline__ double grid_product(double c, double x) {
+  constexpr double kM = 0x1.8p20;
+  return __builtin_fma(c, x, kM) - kM;
+}
+
 // Pair forces on slot i from its neighbour list.  FP64 class: FP64 terms
 // summed in list order, the list being sorted by particle index.  FP32 class:
-// separations and the cut-off test in FP64, the term in FP32, rounded onto the
-// 2^-32 grid and summed in FP64, which makes the sum exact and independent of
-// the list order (the lists of this class are in slot order).  The loop issues
+// separations and the cut-off test in FP64, the force coefficient in FP32, its
+// product with the separation rounded onto the 2^-32 grid and summed in FP64,
+// which makes the sum exact and independent of the list order (the lists of
+// this class are in slot order).  The loop issues
 // the gathers of kForceBatch neighbours before using them.  Specialised on the
 // potential's form and on periodicity so the loop carries no dead work.
 constexpr int kForceBatch = 4;  // neighbour gathers in flight per force-loop iteration: one uint4 list row
@@ -407,9 +417,10 @@ __device__ __forceinline__ void pair_forces_impl(const JobDev& J, const DevBufs&
       fy += c * dy;
       fz += c * dz;
     } else {
-      fx += on_grid((double)(c * (real)dx));
-      fy += on_grid((double)(c * (real)dy));
-      fz += on_grid((double)(c * (real)dz));
+      const double c64 = (double)c;
+      fx += grid_product(c64, dx);
+      fy += grid_product(c64, dy);
+      fz += grid_product(c64, dz);
     }
   };
   static_assert(kForceBatch == 4, "one uint4 row of the list per batch");
@@ -489,7 +500,7 @@ __device__ __forceinline__ double pair_energy(const JobDev& J, const DevBufs& B,
 
 // ---------------------------------------------------------------------------
 // Bead model (SI, Virus capsid self-assembly).  Pair terms in either force
-// class (FP64: summed in particle-index order; FP32: FP32 terms from FP64
+// class (FP64: summed in particle-index order; FP32: FP32 coefficients times FP64
 // separations on the exact-sum grid); bonded terms always FP64.
 // ---------------------------------------------------------------------------
 
@@ -527,9 +538,10 @@ __device__ __forceinline__ void pair_forces_model(const JobDev& J, const ModelDe
       const float s2 = (float)row_sig2[tj] * inv;
       const float s6 = s2 * s2 * s2;
       const float c = (float)row_eps24[tj] * inv * s6 * (2.0f * s6 - 1.0f);
-      fx += on_grid((double)(c * (float)dx));
-      fy += on_grid((double)(c * (float)dy));
-      fz += on_grid((double)(c * (float)dz));
+      const double c64 = (double)c;
+      fx += grid_product(c64, dx);
+      fy += grid_product(c64, dy);
+      fz += grid_product(c64, dz);
     }
   };
   int k = 0;

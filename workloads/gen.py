@@ -148,6 +148,47 @@ def converging_cap(n: int, R: float, speed: float, seed: int, lat_max: float = m
     return System(x, p, "sphere", (0.0, 0.0, 0.0, R), meta=dict(R=R))
 
 
+def cutoff_pairs(rc: float, rel, seed: int, periodic: bool = False, L: float = 800.0) -> System:
+    """Isolated pairs at rest on the plane z = 0, pair k at separation
+    rc (1 + rel[k]) (the FP64 distance checked to lie on the side of rc the
+    sign of rel[k] says), for tests of the cut-off decision.  Non-periodic: the
+    pair centres spread over a square of side L, so positions have magnitudes
+    up to L/2.  Periodic (x and y, period L): every pair straddles the x = 0
+    boundary and its separation is the minimum image."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    k = len(rel)
+    side = int(math.ceil(math.sqrt(k)))
+    spacing = L / max(side, 1) if not periodic else L / max(k, 1)
+    if spacing < 4.0 * rc:
+        raise ValueError("pairs would interact")
+    xs = []
+    for q, d in enumerate(rel):
+        sep = rc * (1.0 + d)
+        th = rng.uniform(-0.4, 0.4)
+        u = np.array([math.cos(th), math.sin(th), 0.0])
+        if periodic:
+            c = np.array([0.0, (q + 0.5) * spacing, 0.0])
+        else:
+            c = np.array([(q % side + 0.5) * spacing - 0.5 * L, (q // side + 0.5) * spacing - 0.5 * L, 0.0])
+        a, b = c - 0.5 * sep * u, c + 0.5 * sep * u
+        if periodic:
+            a[:2] -= L * np.floor(a[:2] / L)
+            b[:2] -= L * np.floor(b[:2] / L)
+        dx = a - b
+        if periodic:
+            dx[:2] -= L * np.rint(dx[:2] / L)
+        r2 = float(dx @ dx)
+        if (r2 < rc * rc) != (d < 0.0):
+            raise ValueError(f"separation {sep!r} rounds to the other side of rc")
+        xs += [a, b]
+    x = np.array(xs)
+    p = np.zeros_like(x)
+    if periodic:
+        return System(x, p, "plane", (0.0, 0.0, 0.0, 0.0, 0.0, 1.0), (0.0, 0.0, -0.5 * L), (L, L, 0.5 * L),
+                      (1, 1, 0))
+    return System(x, p, "plane", (0.0, 0.0, 0.0, 0.0, 0.0, 1.0))
+
+
 def torus(n: int, Rt: float, r: float, seed: int, dmin: float = 0.9, kT: float = 1.0) -> System:
     """Torus about the z axis: tube angle accepted with probability (Rt + r cos t)/(Rt + r)."""
     rng = np.random.Generator(np.random.PCG64(seed))
