@@ -338,16 +338,15 @@ __global__ void __launch_bounds__(kTile) k_finish(DevBufs B, const int* __restri
 // prefix -> counting sort of particles into raster cell order -> lists.
 // ---------------------------------------------------------------------------
 
+// Cell coordinate along dimension k: wrapped into the grid when periodic (in
+// FP64, exact for the integers involved; no 64-bit integer division), clamped
+// to the edge cells otherwise.  The final clamp also keeps a wrap rounded far
+// from the box, or a NaN, inside the grid.
 __device__ __forceinline__ int cell_coord(const JobDev& J, int k, double v) {
-  long long c = (long long)floor((v - J.glo[k]) * J.inv_cs[k]);
-  const long long nc = J.nc[k];
-  if (J.periodic[k]) {
-    c %= nc;
-    if (c < 0) c += nc;
-  } else {
-    c = c < 0 ? 0 : (c >= nc ? nc - 1 : c);
-  }
-  return (int)c;
+  double c = floor((v - J.glo[k]) * J.inv_cs[k]);
+  const double nc = (double)J.nc[k];
+  if (J.periodic[k]) c -= nc * floor(c / nc);
+  return (int)fmin(fmax(c, 0.0), nc - 1.0);
 }
 
 __device__ __forceinline__ uint32_t raster_of(const JobDev& J, int cx, int cy, int cz) {
@@ -392,13 +391,11 @@ __global__ void __launch_bounds__(kTile) k_mark(DevBufs B, const int* __restrict
   const JobDev& J = B.jobs[job];
   const int64_t i = uniform_i64(tile_first[blockIdx.x]) + threadIdx.x;
   const bool valid = i < J.off + J.n;
-  // a list build starts the job's bookkeeping afresh
-  if (i == J.off) B.book[job] = fresh_book();
   uint32_t key = kNoKey, bits = 0u;
   if (valid) {
     const double* X = B.X[J.xcur];
-    const int cx = cell_coord(J, 0, X[3 * i]), cy = cell_coord(J, 1, X[3 * i + 1]),
-              cz = cell_coord(J, 2, X[3 * i + 2]);
+    const double px = X[3 * i], py = X[3 * i + 1], pz = X[3 * i + 2];
+    const int cx = cell_coord(J, 0, px), cy = cell_coord(J, 1, py), cz = cell_coord(J, 2, pz);
     const uint32_t r = raster_of(J, cx, cy, cz);
     B.RASTER[i] = r;
     key = r >> 5;
@@ -415,6 +412,9 @@ __global__ void __launch_bounds__(kTile) k_mark(DevBufs B, const int* __restrict
   }
   const bool tail = lane == 63 || ((heads >> (lane + 1)) & 1ull);
   if (tail && key != kNoKey) atomicOr(&B.BM[J.bm_off + key], v);
+  // a list build starts the job's bookkeeping afresh (stored last, so that no
+  // read of the job record has to wait behind it)
+  if (i == J.off) B.book[job] = fresh_book();
 }
 
 __global__ void __launch_bounds__(kTile) k_count(DevBufs B, const int* __restrict__ tile_job,
@@ -450,10 +450,13 @@ __global__ void __launch_bounds__(kTile) k_perm(DevBufs B, const int* __restrict
   const int job = uniform_int(tile_job[blockIdx.x]);
   const JobDev& J = B.jobs[job];
   const int64_t i = uniform_i64(tile_first[blockIdx.x]) + threadIdx.x;
-  if (i >= J.off + J.n) return;
-  const int64_t d = J.off + B.CSTART[J.off + B.CID[i]] + B.RANK[i];
-  B.SRC[d] = (uint32_t)(i - J.off);
-  B.INV[J.off + B.ID[J.scur][i]] = (uint32_t)(d - J.off);
+  const int64_t off = J.off;
+  if (i >= off + J.n) return;
+  // the independent loads first, together
+  const uint32_t cid = B.CID[i], rank = B.RANK[i], id = B.ID[J.scur][i];
+  const int64_t d = off + B.CSTART[off + cid] + rank;
+  B.SRC[d] = (uint32_t)(i - off);
+  B.INV[off + id] = (uint32_t)(d - off);
 }
 
 // Gather the state into the new order: consecutive threads write consecutive
@@ -465,27 +468,40 @@ __global__ void __launch_bounds__(kTile) k_gather(DevBufs B, const int* __restri
   const int64_t d = uniform_i64(tile_first[blockIdx.x]) + threadIdx.x;
   if (d >= J.off + J.n) return;
   const int64_t i = J.off + B.SRC[d];
-  const double* Xs = B.X[J.xcur];
-  double* Xd = B.X[J.xcur ^ 1];
-  const double* Ps = B.P[J.pcur];
-  double* Pd = B.P[J.pcur ^ 1];
+  const double* __restrict__ Xs = B.X[J.xcur];
+  double* __restrict__ Xd = B.X[J.xcur ^ 1];
+  const double* __restrict__ Ps = B.P[J.pcur];
+  double* __restrict__ Pd = B.P[J.pcur ^ 1];
+  // every load before the first store: source and destination are different
+  // buffers, and this way the loads are in flight together instead of each
+  // waiting for the store before it
+  double x[3], p[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    Xd[3 * d + k] = Xs[3 * i + k];
-    Pd[3 * d + k] = Ps[3 * i + k];
+    x[k] = Xs[3 * i + k];
+    p[k] = Ps[3 * i + k];
   }
-  const uint32_t id = B.ID[J.scur][i];
-  B.ID[J.scur ^ 1][d] = id;
-  B.FLG[J.scur ^ 1][d] = B.FLG[J.scur][i];
-  if (!J.uniform_mass) B.MASS[J.scur ^ 1][d] = B.MASS[J.scur][i];
+  const int sc = J.scur;
+  const bool per_mass = !J.uniform_mass, model = J.model != 0;
+  const uint32_t id = B.ID[sc][i];
+  const uint8_t flag = B.FLG[sc][i];
+  const double mass = per_mass ? B.MASS[sc][i] : 0.0;
+  const uint8_t type = model ? B.TYPE[sc][i] : (uint8_t)0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    Xd[3 * d + k] = x[k];
+    Pd[3 * d + k] = p[k];
+  }
+  B.ID[sc ^ 1][d] = id;
+  B.FLG[sc ^ 1][d] = flag;
+  if (per_mass) B.MASS[sc ^ 1][d] = mass;
   uint32_t w = id;
-  if (J.model) {
+  if (model) {
     // bead model: the type rides in the top two bits of the record's index
-    const uint8_t t = B.TYPE[J.scur][i];
-    B.TYPE[J.scur ^ 1][d] = t;
-    w |= (uint32_t)t << kTypeShift;
+    B.TYPE[sc ^ 1][d] = type;
+    w |= (uint32_t)type << kTypeShift;
   }
-  B.PK[d] = make_float4((float)Xs[3 * i], (float)Xs[3 * i + 1], (float)Xs[3 * i + 2], __uint_as_float(w));
+  B.PK[d] = make_float4((float)x[0], (float)x[1], (float)x[2], __uint_as_float(w));
 }
 
 // Occupied cells with raster index below r, for the compact cell index.
