@@ -640,10 +640,20 @@ __device__ __forceinline__ void nlist_lane(const DevBufs& B, const JobDev& J, in
   const uint32_t bpm = (uint32_t)J.bpm, mstart = bpm != 0u ? (myid / bpm) * bpm : 0u;  // bpm = 0: no molecules
   auto scan = [&](uint32_t b, uint32_t e) {
     const int64_t end = base + e;
+    if (b >= e) return;
+    // software-pipelined: the next batch's records are loaded while this one is
+    // tested (past the end the loads repeat the last record and are not used)
+    float4 nxt[kListBatch];
+#pragma unroll
+    for (int u = 0; u < kListBatch; ++u) nxt[u] = PK[base + b + u < end ? base + b + u : end - 1];
     for (int64_t j = base + b; j < end; j += kListBatch) {
       float4 r[kListBatch];
 #pragma unroll
-      for (int u = 0; u < kListBatch; ++u) r[u] = PK[j + u < end ? j + u : end - 1];
+      for (int u = 0; u < kListBatch; ++u) {
+        r[u] = nxt[u];
+        const int64_t jn = j + kListBatch + u;
+        nxt[u] = PK[jn < end ? jn : end - 1];
+      }
 #pragma unroll
       for (int u = 0; u < kListBatch; ++u) {
         float dx = xf - r[u].x, dy = yf - r[u].y, dz = zf - r[u].z;
