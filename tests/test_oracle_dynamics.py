@@ -168,6 +168,26 @@ def test_p9_thermostat_stationary_variances_and_diffusion():
     assert abs(msd / expect - 1) < 0.03
 
 
+def test_p9b_first_step_from_rest_is_the_gjf_first_step():
+    """At a start there is no previous random force, and the combined force
+    takes the whole f_r^0 (Algorithm S1 at m = 0).  From rest and without
+    forces, x^1 - x^0 = (dt^2 / 2m) b f_r^0, so each component has variance
+    b^2 dt^3 kT / (2 m tau): the first position update of the GJF scheme,
+    x^1 = x^0 + (b dt / 2m) beta^1 with Var beta^1 = 2 (m / tau) kT dt.
+    Half of f_r^0 (the average with a missing f_r^-1 taken as zero) would give
+    a quarter of it."""
+    n, dt, tau, kT, m = 60000, 0.05, 0.5, 1.3, 2.0
+    b = 1.0 / (1.0 + dt / (2 * tau))
+    rng = np.random.default_rng(9)
+    x = rng.uniform(-100, 100, (n, 3))
+    P = o.Params(dt=dt, kT=kT, gamma=1.0 / tau, pair="none", surface="none", seed=5)
+    st = o.State(P, x, np.zeros((n, 3)), mass=np.full(n, m)).run(1)
+    var = float(np.mean((st.x - x) ** 2))
+    expect = b * b * dt ** 3 * kT / (2 * m * tau)
+    se = math.sqrt(2.0 / (3 * n))
+    assert abs(var / expect - 1) < 5 * se
+
+
 @pytest.fixture(scope="module")
 def sphere_diffusion():
     R, tau, dt, n = 3.0, 0.1, 0.01, 10000
