@@ -505,17 +505,22 @@ __device__ __forceinline__ double pair_energy(const JobDev& J, const DevBufs& B,
 // ---------------------------------------------------------------------------
 
 // Pair forces on slot i (type ti) from its list, typed truncated-shifted LJ;
-// pairs inside a molecule are not in the list.
+// pairs inside a molecule are not in the list.  tab: the job's rc^2, sigma^2
+// and 24 eps tables staged in LDS by the caller (kModelTab doubles), or
+// nullptr to read them from the model record.
+constexpr int kModelTab = 3 * kMaxTypes * kMaxTypes;
+
 template <bool kPer, bool kF64>
 __device__ __forceinline__ void pair_forces_model(const JobDev& J, const ModelDev& M, const DevBufs& B,
                                                   const double* __restrict__ X, int64_t i, int ti, double xi,
-                                                  double yi, double zi, double& Fx, double& Fy, double& Fz) {
+                                                  double yi, double zi, double& Fx, double& Fy, double& Fz,
+                                                  const double* tab) {
   const int64_t C = B.C;
   const int cnt = (int)B.NCNT[i];
   const uint4* __restrict__ nl = reinterpret_cast<const uint4*>(B.NL) + i;
-  const double* __restrict__ row_rc2 = M.rc2 + ti * kMaxTypes;
-  const double* __restrict__ row_sig2 = M.sig2 + ti * kMaxTypes;
-  const double* __restrict__ row_eps24 = M.eps24 + ti * kMaxTypes;
+  const double* row_rc2 = (tab ? tab : M.rc2) + ti * kMaxTypes;
+  const double* row_sig2 = (tab ? tab + kMaxTypes * kMaxTypes : M.sig2) + ti * kMaxTypes;
+  const double* row_eps24 = (tab ? tab + 2 * kMaxTypes * kMaxTypes : M.eps24) + ti * kMaxTypes;
   double fx = 0.0, fy = 0.0, fz = 0.0;
   // entry: slot in the low bits, partner type in the top two; the partner's
   // position and the pair's table entries are loaded side by side

@@ -31,12 +31,13 @@ __device__ __forceinline__ void record_error(JobBook& K, int code, uint32_t id, 
 template <bool kEnergy, bool kF64>
 __device__ __forceinline__ double model_forces(const JobDev& J, const ModelDev& M, const DevBufs& B,
                                                const double* __restrict__ X, int64_t i, uint32_t id, double xi,
-                                               double yi, double zi, double& Fx, double& Fy, double& Fz) {
+                                               double yi, double zi, double& Fx, double& Fy, double& Fz,
+                                               const double* tab = nullptr) {
   const int ti = B.TYPE[J.scur][i];
   if (J.periodic[0] | J.periodic[1] | J.periodic[2])
-    pair_forces_model<true, kF64>(J, M, B, X, i, ti, xi, yi, zi, Fx, Fy, Fz);
+    pair_forces_model<true, kF64>(J, M, B, X, i, ti, xi, yi, zi, Fx, Fy, Fz, tab);
   else
-    pair_forces_model<false, kF64>(J, M, B, X, i, ti, xi, yi, zi, Fx, Fy, Fz);
+    pair_forces_model<false, kF64>(J, M, B, X, i, ti, xi, yi, zi, Fx, Fy, Fz, tab);
   double u = kEnergy ? pair_energy_model(J, M, B, X, i, ti, xi, yi, zi) : 0.0;
   double xs[15];
   int tid[5];
@@ -111,6 +112,22 @@ __device__ __forceinline__ void step_body(const DevBufs& B, const int* __restric
   const int64_t first = uniform_i64(tile_first[b]) + (int64_t)uniform_int((int)threadIdx.x / kGroup) * kGroup;
   const JobDev& J = B.jobs[job];
   JobBook& K = B.book[job];
+  // bead model: the pair tables of this tile's job in LDS, so that the typed
+  // lookups of the force loop are LDS reads instead of vector-memory loads
+  // (every wavefront of the workgroup reaches this barrier: the job is the
+  // tile's, and the per-wavefront exits come after it)
+  __shared__ double mtab[kModel ? kModelTab : 1];
+  if (kModel) {
+    const ModelDev& M = B.models[job];
+    const int q = (int)threadIdx.x;
+    constexpr int kP = kMaxTypes * kMaxTypes;
+    if (q < kP) {
+      mtab[q] = M.rc2[q];
+      mtab[kP + q] = M.sig2[q];
+      mtab[2 * kP + q] = M.eps24[q];
+    }
+    __syncthreads();
+  }
   if (t >= J.remaining || first >= J.off + J.n) return;
   const long long s = J.step0 + t;
   // a tile whose accumulated displacement passed skin/2 during step s-1 (or an
@@ -136,7 +153,7 @@ __device__ __forceinline__ void step_body(const DevBufs& B, const int* __restric
     double Fx = 0.0, Fy = 0.0, Fz = 0.0;
     if (J.pair_kind != kPairNone) {
       if (kModel)
-        model_forces<false, kF64>(J, B.models[job], B, X, i, id, xi, yi, zi, Fx, Fy, Fz);
+        model_forces<false, kF64>(J, B.models[job], B, X, i, id, xi, yi, zi, Fx, Fy, Fz, mtab);
       else
         pair_forces<kF64>(J, B, X, i, xi, yi, zi, Fx, Fy, Fz);
     }
