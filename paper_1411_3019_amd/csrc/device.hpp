@@ -505,10 +505,10 @@ __device__ __forceinline__ double pair_energy(const JobDev& J, const DevBufs& B,
 // ---------------------------------------------------------------------------
 
 // Pair forces on slot i (type ti) from its list, typed truncated-shifted LJ;
-// pairs inside a molecule are not in the list.  tab: the job's rc^2, sigma^2
-// and 24 eps tables staged in LDS by the caller (kModelTab doubles), or
-// nullptr to read them from the model record.
-constexpr int kModelTab = 3 * kMaxTypes * kMaxTypes;
+// pairs inside a molecule are not in the list.  tab: the job's rc^2, sigma^2,
+// 24 eps and bond rest-length tables staged in LDS by the caller (kModelTab
+// doubles), or nullptr to read them from the model record.
+constexpr int kModelTab = 4 * kMaxTypes * kMaxTypes;
 
 template <bool kPer, bool kF64>
 __device__ __forceinline__ void pair_forces_model(const JobDev& J, const ModelDev& M, const DevBufs& B,
@@ -621,7 +621,9 @@ __device__ __forceinline__ void pos_of(const JobDev& J, const DevBufs& B, const 
 // theta = theta0 = pi).
 __device__ __forceinline__ double bonded_forces(const JobDev& J, const ModelDev& M, const DevBufs& B,
                                                 const double* __restrict__ X, int64_t id, const int* tid,
-                                                const double* xs, double& Fx, double& Fy, double& Fz) {
+                                                const double* xs, double& Fx, double& Fy, double& Fz,
+                                                const double* tab) {
+  const double* r0_tab = tab ? tab + 3 * kMaxTypes * kMaxTypes : M.r0;
   // xs: positions of beads id-2 .. id+2 (3 doubles each; those outside the
   // molecule unused); tid: their types
   double u = 0.0;
@@ -632,7 +634,7 @@ __device__ __forceinline__ double bonded_forces(const JobDev& J, const ModelDev&
     double d[3] = {xi[0] - xs[3 * q], xi[1] - xs[3 * q + 1], xi[2] - xs[3 * q + 2]};
     if (J.periodic[0] | J.periodic[1] | J.periodic[2]) min_image(J, d[0], d[1], d[2]);
     const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-    const double r0 = M.r0[tid[2] * kMaxTypes + tid[q]];
+    const double r0 = r0_tab[tid[2] * kMaxTypes + tid[q]];
     const double c = -2.0 * M.kb * (r - r0) / r;
     Fx += c * d[0];
     Fy += c * d[1];

@@ -42,7 +42,7 @@ __device__ __forceinline__ double model_forces(const JobDev& J, const ModelDev& 
   double xs[15];
   int tid[5];
   molecule_window(J, M, B, X, id, xi, yi, zi, ti, xs, tid);
-  u += bonded_forces(J, M, B, X, id, tid, xs, Fx, Fy, Fz);
+  u += bonded_forces(J, M, B, X, id, tid, xs, Fx, Fy, Fz, tab);
   return u;
 }
 
@@ -112,8 +112,9 @@ __device__ __forceinline__ void step_body(const DevBufs& B, const int* __restric
   const int64_t first = uniform_i64(tile_first[b]) + (int64_t)uniform_int((int)threadIdx.x / kGroup) * kGroup;
   const JobDev& J = B.jobs[job];
   JobBook& K = B.book[job];
-  // bead model: the pair tables of this tile's job in LDS, so that the typed
-  // lookups of the force loop are LDS reads instead of vector-memory loads
+  // bead model: the type-pair tables of this tile's job in LDS, so that the
+  // typed lookups of the force loop and the bonds are LDS reads instead of
+  // vector-memory loads
   // (every wavefront of the workgroup reaches this barrier: the job is the
   // tile's, and the per-wavefront exits come after it)
   __shared__ double mtab[kModel ? kModelTab : 1];
@@ -125,6 +126,7 @@ __device__ __forceinline__ void step_body(const DevBufs& B, const int* __restric
       mtab[q] = M.rc2[q];
       mtab[kP + q] = M.sig2[q];
       mtab[2 * kP + q] = M.eps24[q];
+      mtab[3 * kP + q] = M.r0[q];
     }
     __syncthreads();
   }
