@@ -99,10 +99,12 @@ extern "C" {
  * gamma is the rate 1/tau of Algorithm S1 (friction m gamma, noise
  * sqrt(2 m kT gamma / dt)); gamma = 0 gives plain constant-energy dynamics.
  * force_fp64 = 1 computes pair forces in FP64, summed in particle-index order;
- * 0 computes each pair term in FP32 from the FP64 separation and sums the terms
- * exactly (each rounded to a 2^-32 grid, accumulated in FP64), so the result
- * does not depend on the order of the terms.  Positions, momenta, the RATTLE
- * solves and the tangent projection are always FP64.
+ * 0 computes each pair coefficient in FP32 from the FP64 separation and sums
+ * the terms exactly (each rounded once to a 2^-32 grid, summed without
+ * rounding), so the result does not depend on the order of the terms while
+ * every term stays below 2^19 (md_diag.exact_sum_breaches counts the
+ * exceptions).  Positions, momenta, the RATTLE solves and the tangent
+ * projection are always FP64.
  * newton_tol is the paper's eta on ||r||_inf (Section 2.2); 0 iterates to
  * round-off (stop when the Newton update is within 16 ulp of the position).
  * skin: neighbour-list skin (0 selects 0.3 sigma); lists are rebuilt before
@@ -173,7 +175,9 @@ typedef struct md_model {
 
 /* Diagnostics of the current state (computed by md_get_state / md_pool_fetch).
  * K = sum p^2/2m, U = sum_{i<j} V_ij, kT = 2K/N_dof (Section 3.1),
- * gdist_max = max |g|/|n| over constrained particles, nv_max = max |n.p|/(|n| m). */
+ * gdist_max = max |g|/|n| over constrained particles, nv_max = max |n.p|/(|n| m).
+ * After a device error (MD_ENEWTON, MD_ENAN) the state is the one after the
+ * failing step (undefined for the failing particle): step = error_step + 1. */
 typedef struct md_diag {
   double K;
   double U;
@@ -186,7 +190,11 @@ typedef struct md_diag {
   int newton_iter_max;    /* largest Newton iteration count seen                */
   int nlist_max;          /* largest neighbour count at the last build          */
   int error_index;        /* particle index of the last device error, or -1     */
-  int reserved;
+  int exact_sum_breaches; /* FP32 class: particle-steps whose pair terms left the
+                             exact-sum range (a pair closer than about sigma/2);
+                             those forces were summed in FP64 in list order, so
+                             they may depend on the order of the terms         */
+  int64_t error_step;     /* step whose launch found the device error, or -1   */
 } md_diag;
 
 /* Counters and GPU times of the work done so far.  step_kernel_ms and
@@ -236,8 +244,8 @@ int md_set_particles(md_ctx* ctx, int64_t n, const double* x, const double* p,
                      int64_t step0);
 
 /* Advance nsteps time steps (Algorithm S1 around Algorithm 1).  Returns after
- * the work is done; MD_ENEWTON / MD_ENAN report a failure at the step where it
- * happened (the state is then undefined). */
+ * the work is done; MD_ENEWTON / MD_ENAN report a failure, and md_get_state's
+ * diagnostics then name the failing step (error_step) and particle. */
 int md_step(md_ctx* ctx, int64_t nsteps);
 
 /* md_set_particles with device pointers (e.g. PyTorch tensors on the same

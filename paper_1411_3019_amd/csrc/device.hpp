@@ -1,11 +1,18 @@
 // device.hpp -- per-particle device math for the RATTLE + Langevin step.
 //
-// Everything here is FP64 except the optional FP32 pair-force path.  The
-// constants of the Philox4x32-10 generator are those published by Salmon et
-// al. (SC'11).  The RATTLE position stage is the scalar form of the Newton
-// iteration of Algorithm 1: because the first three rows of its Jacobian are
-// -I, J^{-1} r reduces to one scalar update of lambda per iteration, which is
-// the analytic solve the paper reports as fastest (SI Section S2).
+// Positions, momenta, the RATTLE solves and the tangent projection are FP64;
+// pair forces are FP64 or FP32 (force class).  The constants of the
+// Philox4x32-10 generator are those published by Salmon et al. (SC'11).  The
+// RATTLE position stage is the scalar form of the Newton iteration of
+// Algorithm 1: because the first three rows of its Jacobian are -I, J^{-1} r
+// reduces to one scalar update of lambda per iteration, which is the analytic
+// solve the paper reports as fastest (SI Section S2).
+//
+// Neighbour lists index a per-tile "window": the tile's own 256 slots
+// (entries 0..255, slot = tile start + entry) followed by the tile's halo, the
+// sorted list of other slots any of its particles has as a neighbour (entry
+// 256 + h is halo[h]).  The step kernel stages the window's positions in LDS
+// once per step, so the force loop reads neighbours from LDS.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -16,9 +23,9 @@
 namespace mdk {
 
 constexpr int kGroup = 64;          // slots per wavefront; per displacement accumulator and list statistic
-constexpr int kTile = 256;          // particles per workgroup in per-particle kernels
+constexpr int kTile = 256;          // particles per workgroup in per-particle kernels; one list window
 constexpr int kNlistBlock = kTile;  // threads per workgroup in the list build
-constexpr int kNlistPerTile = kTile / kNlistBlock;
+constexpr int kRow = 8;             // list entries per 16-byte row (16-bit entries)
 
 enum : int { kSurfNone = 0, kSurfPlane = 1, kSurfSphere = 2, kSurfEllipsoid = 3, kSurfTorus = 4,
              kSurfCylinder = 5, kSurfHeight = 6, kSurfBridge = 7 };
@@ -31,10 +38,15 @@ struct JobDev {
   double dt, half_dt, gamma, b;     // b = 1 / (1 + dt gamma / 2)        (Algorithm S1)
   double noise_k;                   // sqrt(2 kT gamma / dt); times sqrt(m) per particle
   double mass, inv_mass;            // used when uniform_mass
+  double noise_km;                  // noise_k sqrt(mass) (uniform mass)
+  double dtm, cpos, inv_cpos;       // dt/m, c = dt^2/(2m), 1/c (uniform mass)
   double eps, sig2, rc2, rlist2;    // pair parameters; rlist = rc + skin
   double phic, dphic;               // phi(rc) and phi'(rc)              (Eq. S1)
   double half_skin;
   double newton_tol;
+  double grid_bias;                 // 1.5 2^20: FP32-class terms are rounded onto the 2^-32 grid of [2^20, 2^21)
+  float grid_cmax;                  // FP32-class sums are exact while every pair coefficient is below this
+  int pad0;
   double surf[8];
   double box_len[3], inv_box_len[3];
   double glo[3], inv_cs[3];
@@ -55,21 +67,29 @@ struct JobDev {
 constexpr long long kNever = 0x7FFFFFFFFFFFFFFFLL;
 struct JobBook {
   long long stop_at;                // first step that must not run: stale list, list overflow or error (kNever if none)
+  long long err_step;               // step whose launch found the error (-1 if none)
   int err_code;
   int err_id;
   int newton_max;
   int nl_max;                       // largest neighbour count of the last list build (above kmax: overflow)
   double nl_sum;                    // sum of the stored neighbour counts of the last list build
   double a_now;                     // largest per-tile displacement bound since the last list build
+  int halo_max;                     // largest tile halo of the last build (above the capacity: overflow)
+  int build_fail;                   // the last build could not stage a tile's candidates (see k_nlist)
+  int sum_breaches;                 // particles whose FP32-class force terms left the exact-sum range
+  int sum_breach_id;                // particle index of the first such particle
 };
-__host__ __device__ constexpr JobBook fresh_book() { return JobBook{kNever, 0, 0, 0, 0, 0.0, 0.0}; }
+__host__ __device__ constexpr JobBook fresh_book() {
+  return JobBook{kNever, -1, 0, 0, 0, 0, 0.0, 0.0, 0, 0, 0, -1};
+}
 
 // Bead model of one job (SI, Virus capsid self-assembly), tables by type pair
 // a * kMaxTypes + b (symmetric).
 constexpr int kMaxTypes = 4;
-// Bead-model jobs carry the bead type in the top two bits of the candidate
-// record's particle index (such jobs hold fewer than 2^30 particles).
-constexpr int kTypeShift = 30;
+// Bead-model list entries carry the partner's type in their top two bits.
+constexpr int kEntryTypeShift = 14;
+constexpr uint32_t kEntryMask = (1u << kEntryTypeShift) - 1u;
+constexpr int kTypeShift = 30;      // type bits of a 32-bit index (candidate records of the list build)
 constexpr uint32_t kIdMask = (1u << kTypeShift) - 1u;
 
 struct ModelDev {
@@ -91,14 +111,18 @@ struct DevBufs {
   uint32_t* ID[2];     // particle index within its job; parity flips at rebuilds
   uint8_t* FLG[2];     // 1 = constrained
   double* MASS[2];     // per-particle mass (jobs with non-uniform mass)
+  double* NZD[2];      // normals of the last step's Langevin draw, FP64 class, AoS [C][3]; parity as P
+  float* NZF[2];       // the same for the FP32 class (FP32 normals), AoS [C][3]
   double* FC;          // combined force handed in by the caller, AoS [C][3], by job offset + id
   double* OX;          // outputs of the finish kernel (AoS [C][3]), by job offset + id
   double* OP;
   double* OF;
   double* OD;          // [4][C]: kinetic energy, potential energy share, |g|/|n|, |n.v|/|n|
-  uint32_t* NL;        // neighbour slots: entry k of slot i at ((k/4) C + i) 4 + k%4, i.e. rows of uint4
-                       // [kmax/4][C] (kmax is a multiple of 4), four entries per load
+  uint16_t* NL;        // window entries: entry k of slot i at ((k/8) C + i) 8 + k%8, i.e. rows of
+                       // 8 entries [kmax/8][C] (kmax a multiple of 8), one 16-byte load per row
   uint32_t* NCNT;      // neighbour count per slot
+  uint32_t* HALO;      // per tile (slot / 256): hcap slots (absolute), sorted; the window's entries 256..
+  uint32_t* HCNT;      // per tile: halo length
   uint32_t* BM;        // occupied-cell bitmap words (per job segment)
   uint32_t* WOFF;      // exclusive popcount prefix per bitmap word (job-local)
   uint32_t* CCNT;      // particles per occupied cell, at job offset + compact cell
@@ -108,7 +132,6 @@ struct DevBufs {
   uint32_t* RANK;      // rank within the cell per slot
   uint32_t* INV;       // slot of each particle index after the last sort, by job offset + index
   uint32_t* SRC;       // old slot (job-relative) of each new slot during a sort
-  float4* PK;          // list-build candidates in the sorted order: FP32 position, particle index bits
   uint8_t* TYPE[2];    // bead type (jobs with a bead model); parity as ID
   const ModelDev* models;  // per job
   double* TACC;        // per group of 64 slots: accumulated max displacement since the last build
@@ -117,7 +140,7 @@ struct DevBufs {
   JobBook* book;
   int64_t C;           // slot capacity (SoA stride)
   int kmax;
-  int pad2;
+  int hcap;            // halo capacity per tile
 };
 
 // ---------------------------------------------------------------------------
@@ -168,8 +191,8 @@ __device__ __forceinline__ void normals3(uint64_t seed, uint32_t id, long long s
 // transcendental units (v_log_f32; v_sin_f32 / v_cos_f32 take their argument in
 // revolutions, so sin(2 pi u) is one instruction).  Used with FP32 pair forces;
 // the normals differ from the FP64 transform by ~1e-6 relative.
-__device__ __forceinline__ void normals3_fast(uint64_t seed, uint32_t id, long long step, double& z0, double& z1,
-                                              double& z2) {
+__device__ __forceinline__ void normals3_f32(uint64_t seed, uint32_t id, long long step, float& z0, float& z1,
+                                             float& z2) {
   uint32_t c0 = id, c1 = (uint32_t)(unsigned long long)step, c2 = (uint32_t)((unsigned long long)step >> 32),
            c3 = 0u;
   philox4x32_10(c0, c1, c2, c3, (uint32_t)seed, (uint32_t)(seed >> 32));
@@ -180,9 +203,18 @@ __device__ __forceinline__ void normals3_fast(uint64_t seed, uint32_t id, long l
   const float u3 = (float)(((double)c3 + 0.5) * inv32);
   const float r0 = sqrtf(-2.0f * __logf(u0));
   const float r1 = sqrtf(-2.0f * __logf(u2));
-  z0 = (double)(r0 * __builtin_amdgcn_cosf(u1));
-  z1 = (double)(r0 * __builtin_amdgcn_sinf(u1));
-  z2 = (double)(r1 * __builtin_amdgcn_cosf(u3));
+  z0 = r0 * __builtin_amdgcn_cosf(u1);
+  z1 = r0 * __builtin_amdgcn_sinf(u1);
+  z2 = r1 * __builtin_amdgcn_cosf(u3);
+}
+
+__device__ __forceinline__ void normals3_fast(uint64_t seed, uint32_t id, long long step, double& z0, double& z1,
+                                              double& z2) {
+  float a, b, c;
+  normals3_f32(seed, id, step, a, b, c);
+  z0 = (double)a;
+  z1 = (double)b;
+  z2 = (double)c;
 }
 
 template <bool kF64>
@@ -195,11 +227,44 @@ __device__ __forceinline__ void langevin_normals(uint64_t seed, uint32_t id, lon
 }
 
 // ---------------------------------------------------------------------------
-// Surfaces: g(x) and n = dg/dx (un-normalised, Eq. 4).
+// FP64 reciprocal and reciprocal square root: the hardware estimates refined
+// by two Newton steps each (about one ulp; the step kernel and the finish
+// kernel use the same routines, so they agree bit for bit).
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ double rcp64(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  double e = __builtin_fma(-d, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-d, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+
+__device__ __forceinline__ double rsqrt64(double a) {
+  double y = __builtin_amdgcn_rsq(a);
+  double h = a * y;
+  double r = __builtin_fma(-h, y, 1.0);
+  y = __builtin_fma(0.5 * y, r, y);
+  h = a * y;
+  r = __builtin_fma(-h, y, 1.0);
+  return __builtin_fma(0.5 * y, r, y);
+}
+
+// ---------------------------------------------------------------------------
+// Surfaces: g(x) and n = dg/dx (un-normalised, Eq. 4).  kAll: every kind; the
+// step kernels of jobs on the quadric surfaces (and the plane) are built
+// without the height field and the bridge, whose transcendentals and pieces
+// would otherwise set their register budget.
+// ---------------------------------------------------------------------------
+constexpr bool heavy_surface(int kind) { return kind == kSurfHeight || kind == kSurfBridge; }
+
+template <bool kAll = true>
 __device__ __forceinline__ double surf_eval(const JobDev& J, double x, double y, double z, double& nx, double& ny,
                                             double& nz) {
   const double* q = J.surf;
+  if (!kAll && heavy_surface(J.surf_kind)) {
+    nx = ny = nz = 0.0;
+    return 0.0;
+  }
   switch (J.surf_kind) {
     case kSurfPlane:
       nx = q[3];
@@ -222,10 +287,12 @@ __device__ __forceinline__ double surf_eval(const JobDev& J, double x, double y,
       return d0 * d0 * q[3] + d1 * d1 * q[4] + d2 * d2 * q[5] - 1.0;
     }
     case kSurfTorus: {
+      // rho and 1/rho from one reciprocal square root
       const double d0 = x - q[0], d1 = y - q[1], d2 = z - q[2];
-      const double rho = sqrt(d0 * d0 + d1 * d1);
-      const double e = rho - q[3];
-      const double s = 2.0 * (1.0 - q[3] / rho);
+      const double rho2 = d0 * d0 + d1 * d1;
+      const double ir = rsqrt64(rho2);
+      const double e = rho2 * ir - q[3];
+      const double s = 2.0 - 2.0 * q[3] * ir;
       nx = s * d0;
       ny = s * d1;
       nz = 2.0 * d2;
@@ -260,10 +327,11 @@ __device__ __forceinline__ double surf_eval(const JobDev& J, double x, double y,
         nz = -2.0 * q[7] * dz;
         return q[7] * (q[4] * q[4] - r2);
       }
-      const double r = sqrt(r2);
+      const double ir = rsqrt64(r2);
+      const double r = r2 > 0.0 ? r2 * ir : 0.0;
       const double ue = u > 0.0 ? u - q[3] : u + q[3];  // from the connector's end of the bridge
       if (r < q[6]) {  // connector: distance to the circle of radius R about r = Rb + R
-        const double f = 2.0 * (1.0 - q[6] / r);
+        const double f = 2.0 - 2.0 * q[6] * ir;
         nx = 2.0 * ue;
         ny = f * dy;
         nz = f * dz;
@@ -285,11 +353,22 @@ __device__ __forceinline__ double maxabs3(double a, double b, double c) {
   return fmax(fabs(a), fmax(fabs(b), fabs(c)));
 }
 
+// Mass-dependent constants of one particle: dt/m, c = dt^2/(2m) and 1/c.
+struct MassTerms {
+  double dtm, c, ic;
+};
+__device__ __forceinline__ MassTerms mass_terms(const JobDev& J, double m) {
+  if (J.uniform_mass) return MassTerms{J.dtm, J.cpos, J.inv_cpos};
+  const double im = rcp64(m);
+  const double dtm = J.dt * im;
+  return MassTerms{dtm, 0.5 * J.dt * dtm, 2.0 * m / (J.dt * J.dt)};
+}
+
 // ---------------------------------------------------------------------------
 // RATTLE position stage (Algorithm 1, first loop) for one particle.
-// Input: x^m, the half-kicked momentum pt = p^m + dt/2 f^m, n^m = n(x^m) and
-// g(x^m).  Output: x^{m+1} = x~ - c lambda n^m and p^{m+1/2} = pt - dt/2 lambda n^m
-// with x~ = x^m + dt/m pt and c = dt^2/(2m).
+// Input: x^m, the half-kicked momentum pt = p^m + dt/2 f^m, n^m = n(x^m),
+// g(x^m) and 1/(n^m.n^m).  Output: x^{m+1} = x~ - c lambda n^m and
+// p^{m+1/2} = pt - dt/2 lambda n^m with x~ = x^m + dt/m pt and c = dt^2/(2m).
 // Newton iterates (identical to Algorithm 1's 4x4 iteration):
 //   first:  lambda = [g(x^m) + n^m.(x~ - x^m)] / (c n^m.n^m)
 //   then:   lambda += g(x') / (c n(x').n^m),  x' = x~ - c lambda n^m
@@ -297,17 +376,17 @@ __device__ __forceinline__ double maxabs3(double a, double b, double c) {
 //       eta = 0: position update within 16 ulp of max(1, |x'|_inf).
 // Returns the iteration count, or -count when the cap was hit.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int rattle_position(const JobDev& J, double m, double x0, double y0, double z0,
-                                               double g0, double nx, double ny, double nz, double& px,
-                                               double& py, double& pz, double& x1, double& y1, double& z1) {
-  const double dtm = J.dt / m;
-  const double c = J.dt * dtm * 0.5;
+template <bool kAll = true>
+__device__ __forceinline__ int rattle_position(const JobDev& J, const MassTerms& mt, double x0, double y0, double z0,
+                                               double g0, double nx, double ny, double nz, double inv_nn,
+                                               double& px, double& py, double& pz, double& x1, double& y1,
+                                               double& z1) {
+  const double dtm = mt.dtm, c = mt.c;
   const double xt = x0 + dtm * px, yt = y0 + dtm * py, zt = z0 + dtm * pz;
   const double eps16 = 16.0 * 2.220446049250313e-16;
   // iteration 1: linearisation at x^m (the start x' = x^m, lambda = 0 of Algorithm 1)
   const double rx = xt - x0, ry = yt - y0, rz = zt - z0;
-  const double nn = nx * nx + ny * ny + nz * nz;
-  double lam = (g0 + nx * rx + ny * ry + nz * rz) / (c * nn);
+  double lam = (g0 + nx * rx + ny * ry + nz * rz) * (mt.ic * inv_nn);
   double xc = xt - c * lam * nx, yc = yt - c * lam * ny, zc = zt - c * lam * nz;
   bool done;
   if (J.newton_tol > 0.0) {
@@ -320,9 +399,9 @@ __device__ __forceinline__ int rattle_position(const JobDev& J, double m, double
   while (!done && it < J.newton_cap) {
     ++it;
     double mx, my, mz;
-    const double g = surf_eval(J, xc, yc, zc, mx, my, mz);
+    const double g = surf_eval<kAll>(J, xc, yc, zc, mx, my, mz);
     // full Newton: dg/dx at the iterate; frozen normal: at x^m (SI, Performance)
-    const double dl = g / (c * (J.newton_frozen ? nn : mx * nx + my * ny + mz * nz));
+    const double dl = g * mt.ic * (J.newton_frozen ? inv_nn : rcp64(mx * nx + my * ny + mz * nz));
     lam += dl;
     const double xn = xt - c * lam * nx, yn = yt - c * lam * ny, zn = zt - c * lam * nz;
     if (J.newton_tol > 0.0) {
@@ -351,139 +430,192 @@ __device__ __forceinline__ void min_image(const JobDev& J, double& dx, double& d
   if (J.periodic[2]) dz -= J.box_len[2] * rint(dz * J.inv_box_len[2]);
 }
 
-// Force coefficient c of one pair, F_i += c (x_i - x_j), for r^2 < rc^2
-// (Eq. S1: -dV/dr / r); zero beyond the cut-off.
-template <typename real, bool kSmooth>
-__device__ __forceinline__ real pair_coef(const JobDev& J, double r2, real eps24, real sig2, real dphic) {
-  if (!(r2 < J.rc2)) return (real)0;
-  const real r2r = (real)r2;
-  // FP32: the hardware reciprocal (1 ulp); FP64: a correctly rounded division
-  const real inv = sizeof(real) == 8 ? (real)(1.0 / (double)r2r) : (real)__builtin_amdgcn_rcpf((float)r2r);
-  const real s2 = sig2 * inv;
-  const real s6 = s2 * s2 * s2;
-  real coef = eps24 * inv * s6 * ((real)2 * s6 - (real)1);
-  if (kSmooth) {
-    const real rinv = sizeof(real) == 8 ? (real)(1.0 / sqrt((double)r2r)) : (real)rsqrtf((float)r2r);
-    coef += dphic * rinv;
+// ---------------------------------------------------------------------------
+// Pair terms (Eq. S1).  The force on i from j is c (x_i - x_j) with
+// c = -V'(r)/r for r < rc, 0 beyond.
+//
+// FP64 class: c in FP64, the terms summed in list order (lists of this class
+// are sorted by particle index).
+// FP32 class: c in FP32 from the FP64 r^2; each term c dx rounded once onto
+// the grid of multiples of 2^-32 (a fused multiply-add with 1.5 2^20, whose
+// result then lies in [2^20, 2^21) with an ulp of 2^-32 while |c dx| < 2^19).
+// The bit pattern of such a double is an affine function of its value, so the
+// terms are summed exactly as 64-bit integers of their bit patterns: the sum
+// does not depend on the order of the terms, which lets these lists stay in
+// any order.  Each particle checks that its largest coefficient kept every term
+// inside that range; a particle that fails (a pair closer than about half a
+// sigma) is summed again in FP64 and reported (JobBook::sum_breaches).
+// ---------------------------------------------------------------------------
+// Exact sum of FP32-class terms (see above).
+struct GridSum {
+  uint64_t x, y, z;
+  int cmax;  // largest coefficient as integer bits (positive floats order as integers)
+  __device__ __forceinline__ void clear() {
+    x = y = z = 0;
+    cmax = 0;
   }
-  return coef;
-}
-
-// Rounds t to a multiple of 2^-32 (for |t| < 2^19).  Sums of such values are
-// exact in FP64 while their magnitude stays below 2^21, so they do not depend
-// on the order of the terms.
-__device__ __forceinline__ double on_grid(double t) {
-  constexpr double kM = 0x1.8p20;  // 1.5 * 2^20: t + kM has an ulp of 2^-32
-  return (t + kM) - kM;
-}
-
-// The product c x rounded onto the same grid with a single rounding: the fused
-// multiply-add rounds c x + kM to a multiple of 2^-32, and removing kM is
-// exact.  One instruction fewer per component than rounding the product first,
-// and without its double rounding.
-__device__ __forceinline__ double grid_product(double c, double x) {
-  constexpr double kM = 0x1.8p20;
-  return __builtin_fma(c, x, kM) - kM;
-}
-
-// Pair forces on slot i from its neighbour list.  FP64 class: FP64 terms
-// summed in list order, the list being sorted by particle index.  FP32 class:
-// separations and the cut-off test in FP64, the force coefficient in FP32, its
-// product with the separation rounded onto the 2^-32 grid and summed in FP64,
-// which makes the sum exact and independent of the list order (the lists of
-// this class are in slot order).  The loop issues
-// the gathers of kForceBatch neighbours before using them.  Specialised on the
-// potential's form and on periodicity so the loop carries no dead work.
-constexpr int kForceBatch = 4;  // neighbour gathers in flight per force-loop iteration: one uint4 list row
-
-template <bool kF64, bool kSmooth, bool kPer>
-__device__ __forceinline__ void pair_forces_impl(const JobDev& J, const DevBufs& B, const double* __restrict__ X,
-                                                 int64_t i, double xi, double yi, double zi, double& Fx,
-                                                 double& Fy, double& Fz) {
-  using real = typename std::conditional<kF64, double, float>::type;
-  const int64_t C = B.C;
-  const int cnt = (int)B.NCNT[i];
-  const uint4* __restrict__ nl = reinterpret_cast<const uint4*>(B.NL) + i;
-  double fx = 0.0, fy = 0.0, fz = 0.0;
-  const real eps24 = (real)(24.0 * J.eps);
-  const real sig2 = (real)J.sig2;
-  const real dphic = (real)J.dphic;
-  auto add = [&](double dx, double dy, double dz) {
-    if (kPer) min_image(J, dx, dy, dz);
-    const double r2 = dx * dx + dy * dy + dz * dz;
-    const real c = pair_coef<real, kSmooth>(J, r2, eps24, sig2, dphic);
-    if (kF64) {
-      fx += c * dx;
-      fy += c * dy;
-      fz += c * dz;
-    } else {
-      const double c64 = (double)c;
-      fx += grid_product(c64, dx);
-      fy += grid_product(c64, dy);
-      fz += grid_product(c64, dz);
-    }
-  };
-  static_assert(kForceBatch == 4, "one uint4 row of the list per batch");
-  int k = 0;
-  for (; k + kForceBatch <= cnt; k += kForceBatch) {
-    const uint4 q = nl[(int64_t)(k >> 2) * C];
-    const int64_t j[kForceBatch] = {(int64_t)q.x, (int64_t)q.y, (int64_t)q.z, (int64_t)q.w};
-    double ax[kForceBatch], ay[kForceBatch], az[kForceBatch];
-#pragma unroll
-    for (int u = 0; u < kForceBatch; ++u) {
-      ax[u] = X[3 * j[u]];
-      ay[u] = X[3 * j[u] + 1];
-      az[u] = X[3 * j[u] + 2];
-    }
-#pragma unroll
-    for (int u = 0; u < kForceBatch; ++u) add(xi - ax[u], yi - ay[u], zi - az[u]);
+  __device__ __forceinline__ void add(float c, double dx, double dy, double dz, double bias) {
+    const double c64 = (double)c;
+    x += (uint64_t)__double_as_longlong(__builtin_fma(c64, dx, bias));
+    y += (uint64_t)__double_as_longlong(__builtin_fma(c64, dy, bias));
+    z += (uint64_t)__double_as_longlong(__builtin_fma(c64, dz, bias));
+    cmax = max(cmax, __float_as_int(c));
   }
-  if (k < cnt) {
-    const uint4 q = nl[(int64_t)(k >> 2) * C];
-    const uint32_t jt[3] = {q.x, q.y, q.z};
-#pragma unroll
-    for (int u = 0; u < 3; ++u)
-      if (k + u < cnt) {
-        const int64_t j = jt[u];
-        add(xi - X[3 * j], yi - X[3 * j + 1], zi - X[3 * j + 2]);
-      }
+  // F from n terms; false when a term may have left [2^20, 2^21)
+  __device__ __forceinline__ bool get(int n, float guard, double& Fx, double& Fy, double& Fz) const {
+    const uint64_t base = (uint64_t)n * (uint64_t)__double_as_longlong(0x1.8p20);
+    Fx = (double)(int64_t)(x - base) * 0x1p-32;
+    Fy = (double)(int64_t)(y - base) * 0x1p-32;
+    Fz = (double)(int64_t)(z - base) * 0x1p-32;
+    return cmax < __float_as_int(guard);
   }
-  Fx = fx;
-  Fy = fy;
-  Fz = fz;
+};
+
+// Slot (absolute) of window entry e of the tile starting at slot first.
+__device__ __forceinline__ int64_t window_slot(const DevBufs& B, int64_t first, uint32_t e) {
+  if (e < (uint32_t)kTile) return first + e;
+  const int64_t h = min((int64_t)(e - kTile), (int64_t)B.hcap - 1);
+  return (int64_t)B.HALO[(first / kTile) * (int64_t)B.hcap + h];
 }
 
-template <bool kF64>
-__device__ __forceinline__ void pair_forces(const JobDev& J, const DevBufs& B, const double* __restrict__ X,
-                                            int64_t i, double xi, double yi, double zi, double& Fx, double& Fy,
-                                            double& Fz) {
+// One 16-byte row (8 entries) of slot i's list.
+__device__ __forceinline__ uint4 list_row(const DevBufs& B, int64_t i, int r) {
+  return reinterpret_cast<const uint4*>(B.NL)[(int64_t)r * B.C + i];
+}
+
+__device__ __forceinline__ uint32_t row_entry(const uint4& q, int u) {
+  const uint32_t w = u < 2 ? q.x : (u < 4 ? q.y : (u < 6 ? q.z : q.w));
+  return (w >> ((u & 1) * 16)) & 0xFFFFu;
+}
+
+// The same for an index u known only at run time.
+__device__ __forceinline__ uint32_t row_entry_dyn(uint4 q, int u) { return row_entry(q, u); }
+
+// The first two rows of a list (16 entries), loaded ahead of the force loop.
+struct Rows3 {
+  uint4 r0, r1;
+};
+__device__ __forceinline__ Rows3 load_rows3(const DevBufs& B, int64_t i, int cnt) {
+  Rows3 q;
+  q.r0 = q.r1 = make_uint4(0u, 0u, 0u, 0u);
+  if (cnt > 0) q.r0 = list_row(B, i, 0);
+  if (cnt > kRow) q.r1 = list_row(B, i, 1);
+  return q;
+}
+
+// Calls f(entry) for the cnt entries of slot i's list, in list order: one
+// row of eight entries at a time, the next row loading while one is processed
+// (the first two come in q).
+template <class F>
+__device__ __forceinline__ void for_entries(const DevBufs& B, int64_t i, int cnt, const Rows3& q, F f) {
+  uint4 cur = q.r0, nxt = q.r1;
+  for (int k0 = 0; k0 < cnt; k0 += kRow) {
+    const uint4 r = cur;
+    cur = nxt;
+    if (k0 + 2 * kRow < cnt) nxt = list_row(B, i, k0 / kRow + 2);
+#pragma unroll
+    for (int u = 0; u < kRow; ++u)
+      if (k0 + u < cnt) f(row_entry(r, u));
+  }
+}
+
+// Pair forces of slot i (list of cnt window entries, first rows q) from
+// positions fetched by pos(e, ax, ay, az).  Plain or smoothed LJ, minimum
+// image where periodic (uniform flags: one copy of the loop).  exact: false
+// when an FP32-class term left the exact range (the forces are then the FP64
+// sum of the same terms in list order).
+template <bool kF64, class Pos>
+__device__ __forceinline__ void pair_forces(const JobDev& J, const DevBufs& B, int64_t i, int cnt, const Rows3& q,
+                                            double xi, double yi, double zi, Pos pos, double& Fx, double& Fy,
+                                            double& Fz, bool& exact) {
+  const double rc2 = J.rc2;
   const bool smooth = J.pair_kind == kPairLJSmooth;
   const bool per = J.periodic[0] | J.periodic[1] | J.periodic[2];
-  if (smooth) {
-    if (per)
-      pair_forces_impl<kF64, true, true>(J, B, X, i, xi, yi, zi, Fx, Fy, Fz);
-    else
-      pair_forces_impl<kF64, true, false>(J, B, X, i, xi, yi, zi, Fx, Fy, Fz);
+  exact = true;
+  auto sep = [&](uint32_t e, double& dx, double& dy, double& dz) {
+    double ax, ay, az;
+    pos(e, ax, ay, az);
+    dx = xi - ax;
+    dy = yi - ay;
+    dz = zi - az;
+    if (per) min_image(J, dx, dy, dz);
+    return dx * dx + dy * dy + dz * dz;
+  };
+  if (kF64) {
+    const double eps24 = 24.0 * J.eps, sig2 = J.sig2, dphic = J.dphic;
+    double fx = 0.0, fy = 0.0, fz = 0.0;
+    for_entries(B, i, cnt, q, [&](uint32_t e) {
+      double dx, dy, dz;
+      const double r2 = sep(e, dx, dy, dz);
+      if (r2 < rc2) {
+        const double inv = 1.0 / r2;
+        const double s2 = sig2 * inv;
+        const double s6 = s2 * s2 * s2;
+        double c = eps24 * inv * s6 * (2.0 * s6 - 1.0);
+        if (smooth) c += dphic / sqrt(r2);
+        fx += c * dx;
+        fy += c * dy;
+        fz += c * dz;
+      }
+    });
+    Fx = fx;
+    Fy = fy;
+    Fz = fz;
   } else {
-    if (per)
-      pair_forces_impl<kF64, false, true>(J, B, X, i, xi, yi, zi, Fx, Fy, Fz);
-    else
-      pair_forces_impl<kF64, false, false>(J, B, X, i, xi, yi, zi, Fx, Fy, Fz);
+    const float eps24 = (float)(24.0 * J.eps), sig2 = (float)J.sig2, dphic = (float)J.dphic;
+    const double bias = J.grid_bias;
+    auto coef = [&](double r2) {
+      const float r2f = (float)r2;
+      const float inv = __builtin_amdgcn_rcpf(r2f);
+      const float s2 = sig2 * inv;
+      const float s6 = s2 * s2 * s2;
+      float c = eps24 * inv * s6 * (2.0f * s6 - 1.0f);
+      if (smooth) c += dphic * __builtin_amdgcn_rsqf(r2f);
+      return c;
+    };
+    GridSum s;
+    s.clear();
+    for_entries(B, i, cnt, q, [&](uint32_t e) {
+      double dx, dy, dz;
+      const double r2 = sep(e, dx, dy, dz);
+      float c = coef(r2);
+      c = r2 < rc2 ? c : 0.0f;
+      s.add(c, dx, dy, dz, bias);
+    });
+    exact = s.get(cnt, J.grid_cmax, Fx, Fy, Fz);
+    if (!exact) {
+      // (rare: a plain loop, kept out of the unrolled code)
+      double fx = 0.0, fy = 0.0, fz = 0.0;
+#pragma nounroll
+      for (int k = 0; k < cnt; ++k) {
+        double dx, dy, dz;
+        const double r2 = sep(row_entry_dyn(list_row(B, i, k / kRow), k % kRow), dx, dy, dz);
+        if (r2 < rc2) {
+          const double c = (double)coef(r2);
+          fx += c * dx;
+          fy += c * dy;
+          fz += c * dz;
+        }
+      }
+      Fx = fx;
+      Fy = fy;
+      Fz = fz;
+    }
   }
 }
 
 // Energy share U_i = 1/2 sum_j V_ij (Eq. S1), FP64, for diagnostics; for the
-// FP32 class the terms go on the exact-sum grid like the forces.
+// FP32 class the terms go on the 2^-32 grid (summed in FP64: exact while the
+// partial sums stay below 2^21).
 __device__ __forceinline__ double pair_energy(const JobDev& J, const DevBufs& B, const double* __restrict__ X,
-                                              int64_t i, double xi, double yi, double zi) {
-  const int64_t C = B.C;
+                                              int64_t first, int64_t i, double xi, double yi, double zi) {
   const int cnt = (int)B.NCNT[i];
   const bool smooth = J.pair_kind == kPairLJSmooth;
   const bool anyper = J.periodic[0] | J.periodic[1] | J.periodic[2];
   const double rc = sqrt(J.rc2);
   double u = 0.0;
   for (int k = 0; k < cnt; ++k) {
-    const int64_t j = B.NL[(((int64_t)(k >> 2) * C + i) << 2) + (k & 3)];
+    const int64_t j = window_slot(B, first, row_entry(list_row(B, i, k / kRow), k % kRow));
     double dx = xi - X[3 * j], dy = yi - X[3 * j + 1], dz = zi - X[3 * j + 2];
     if (anyper) min_image(J, dx, dy, dz);
     const double r2 = dx * dx + dy * dy + dz * dz;
@@ -492,105 +624,109 @@ __device__ __forceinline__ double pair_energy(const JobDev& J, const DevBufs& B,
     const double s6 = s2 * s2 * s2;
     double v = 4.0 * J.eps * s6 * (s6 - 1.0) - J.phic;
     if (smooth) v -= (sqrt(r2) - rc) * J.dphic;
-    // FP32 class: lists in slot order, terms on the exact-sum grid
-    u += J.force_fp64 ? 0.5 * v : on_grid(0.5 * v);
+    u += J.force_fp64 ? 0.5 * v : (__builtin_fma(0.5, v, 0x1.8p20) - 0x1.8p20);
   }
   return u;
 }
 
 // ---------------------------------------------------------------------------
 // Bead model (SI, Virus capsid self-assembly).  Pair terms in either force
-// class (FP64: summed in particle-index order; FP32: FP32 coefficients times FP64
-// separations on the exact-sum grid); bonded terms always FP64.
+// class; bonded terms always FP64.  List entries carry the partner's type in
+// their top two bits; pairs inside a molecule are not in the list.  tab: the
+// job's rc^2, sigma^2, 24 eps and bond rest-length tables (kModelTab doubles,
+// staged in LDS by the step kernel), or nullptr to read the model record.
 // ---------------------------------------------------------------------------
-
-// Pair forces on slot i (type ti) from its list, typed truncated-shifted LJ;
-// pairs inside a molecule are not in the list.  tab: the job's rc^2, sigma^2,
-// 24 eps and bond rest-length tables staged in LDS by the caller (kModelTab
-// doubles), or nullptr to read them from the model record.
 constexpr int kModelTab = 4 * kMaxTypes * kMaxTypes;
 
-template <bool kPer, bool kF64>
-__device__ __forceinline__ void pair_forces_model(const JobDev& J, const ModelDev& M, const DevBufs& B,
-                                                  const double* __restrict__ X, int64_t i, int ti, double xi,
-                                                  double yi, double zi, double& Fx, double& Fy, double& Fz,
+template <bool kPer, bool kF64, class Pos>
+__device__ __forceinline__ void pair_forces_model(const JobDev& J, const ModelDev& M, const DevBufs& B, int64_t i,
+                                                  int cnt, const Rows3& q, int ti, double xi, double yi, double zi,
+                                                  Pos pos, double& Fx, double& Fy, double& Fz, bool& exact,
                                                   const double* tab) {
-  const int64_t C = B.C;
-  const int cnt = (int)B.NCNT[i];
-  const uint4* __restrict__ nl = reinterpret_cast<const uint4*>(B.NL) + i;
   const double* row_rc2 = (tab ? tab : M.rc2) + ti * kMaxTypes;
   const double* row_sig2 = (tab ? tab + kMaxTypes * kMaxTypes : M.sig2) + ti * kMaxTypes;
   const double* row_eps24 = (tab ? tab + 2 * kMaxTypes * kMaxTypes : M.eps24) + ti * kMaxTypes;
-  double fx = 0.0, fy = 0.0, fz = 0.0;
-  // entry: slot in the low bits, partner type in the top two; the partner's
-  // position and the pair's table entries are loaded side by side
-  auto add = [&](uint32_t e, double ax, double ay, double az) {
-    const uint32_t tj = e >> kTypeShift;
-    double dx = xi - ax, dy = yi - ay, dz = zi - az;
+  exact = true;
+  auto sep = [&](uint32_t e, double& dx, double& dy, double& dz) {
+    double ax, ay, az;
+    pos(e & kEntryMask, ax, ay, az);
+    dx = xi - ax;
+    dy = yi - ay;
+    dz = zi - az;
     if (kPer) min_image(J, dx, dy, dz);
-    const double r2 = dx * dx + dy * dy + dz * dz;
-    if (!(r2 < row_rc2[tj])) return;
-    if (kF64) {
-      const double inv = 1.0 / r2;
-      const double s2 = row_sig2[tj] * inv;
-      const double s6 = s2 * s2 * s2;
-      const double c = row_eps24[tj] * inv * s6 * (2.0 * s6 - 1.0);
-      fx += c * dx;
-      fy += c * dy;
-      fz += c * dz;
-    } else {
-      const float inv = __builtin_amdgcn_rcpf((float)r2);
-      const float s2 = (float)row_sig2[tj] * inv;
-      const float s6 = s2 * s2 * s2;
-      const float c = (float)row_eps24[tj] * inv * s6 * (2.0f * s6 - 1.0f);
-      const double c64 = (double)c;
-      fx += grid_product(c64, dx);
-      fy += grid_product(c64, dy);
-      fz += grid_product(c64, dz);
-    }
+    return dx * dx + dy * dy + dz * dz;
   };
-  int k = 0;
-  for (; k + 4 <= cnt; k += 4) {
-    const uint4 q = nl[(int64_t)(k >> 2) * C];
-    const uint32_t e[4] = {q.x, q.y, q.z, q.w};
-    double ax[4], ay[4], az[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int64_t j = e[u] & kIdMask;
-      ax[u] = X[3 * j];
-      ay[u] = X[3 * j + 1];
-      az[u] = X[3 * j + 2];
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) add(e[u], ax[u], ay[u], az[u]);
-  }
-  if (k < cnt) {
-    const uint4 q = nl[(int64_t)(k >> 2) * C];
-    const uint32_t e[3] = {q.x, q.y, q.z};
-#pragma unroll
-    for (int u = 0; u < 3; ++u)
-      if (k + u < cnt) {
-        const int64_t j = e[u] & kIdMask;
-        add(e[u], X[3 * j], X[3 * j + 1], X[3 * j + 2]);
+  auto coef_f = [&](uint32_t tj, double r2) -> float {
+    const float inv = __builtin_amdgcn_rcpf((float)r2);
+    const float s2 = (float)row_sig2[tj] * inv;
+    const float s6 = s2 * s2 * s2;
+    return (float)row_eps24[tj] * inv * s6 * (2.0f * s6 - 1.0f);
+  };
+  if (kF64) {
+    double fx = 0.0, fy = 0.0, fz = 0.0;
+    for_entries(B, i, cnt, q, [&](uint32_t e) {
+      const uint32_t tj = e >> kEntryTypeShift;
+      double dx, dy, dz;
+      const double r2 = sep(e, dx, dy, dz);
+      if (r2 < row_rc2[tj]) {
+        const double inv = 1.0 / r2;
+        const double s2 = row_sig2[tj] * inv;
+        const double s6 = s2 * s2 * s2;
+        const double c = row_eps24[tj] * inv * s6 * (2.0 * s6 - 1.0);
+        fx += c * dx;
+        fy += c * dy;
+        fz += c * dz;
       }
+    });
+    Fx = fx;
+    Fy = fy;
+    Fz = fz;
+  } else {
+    const double bias = J.grid_bias;
+    GridSum s;
+    s.clear();
+    for_entries(B, i, cnt, q, [&](uint32_t e) {
+      const uint32_t tj = e >> kEntryTypeShift;
+      double dx, dy, dz;
+      const double r2 = sep(e, dx, dy, dz);
+      float c = coef_f(tj, r2);
+      c = r2 < row_rc2[tj] ? c : 0.0f;
+      s.add(c, dx, dy, dz, bias);
+    });
+    exact = s.get(cnt, J.grid_cmax, Fx, Fy, Fz);
+    if (!exact) {
+      double fx = 0.0, fy = 0.0, fz = 0.0;
+#pragma nounroll
+      for (int k = 0; k < cnt; ++k) {
+        const uint32_t e = row_entry_dyn(list_row(B, i, k / kRow), k % kRow);
+        const uint32_t tj = e >> kEntryTypeShift;
+        double dx, dy, dz;
+        const double r2 = sep(e, dx, dy, dz);
+        if (r2 < row_rc2[tj]) {
+          const double c = (double)coef_f(tj, r2);
+          fx += c * dx;
+          fy += c * dy;
+          fz += c * dz;
+        }
+      }
+      Fx = fx;
+      Fy = fy;
+      Fz = fz;
+    }
   }
-  Fx = fx;
-  Fy = fy;
-  Fz = fz;
 }
 
 // Energy share of slot i from the typed pairs (half of each pair).
 __device__ __forceinline__ double pair_energy_model(const JobDev& J, const ModelDev& M, const DevBufs& B,
-                                                    const double* __restrict__ X, int64_t i, int ti, double xi,
-                                                    double yi, double zi) {
-  const int64_t C = B.C;
+                                                    const double* __restrict__ X, int64_t first, int64_t i, int ti,
+                                                    double xi, double yi, double zi) {
   const int cnt = (int)B.NCNT[i];
   const bool anyper = J.periodic[0] | J.periodic[1] | J.periodic[2];
   double u = 0.0;
   for (int k = 0; k < cnt; ++k) {
-    const uint32_t e = B.NL[(((int64_t)(k >> 2) * C + i) << 2) + (k & 3)];
-    const int64_t j = e & kIdMask;
-    const int p = ti * kMaxTypes + (int)(e >> kTypeShift);
+    const uint32_t e = row_entry(list_row(B, i, k / kRow), k % kRow);
+    const int64_t j = window_slot(B, first, e & kEntryMask);
+    const int p = ti * kMaxTypes + (int)(e >> kEntryTypeShift);
     double dx = xi - X[3 * j], dy = yi - X[3 * j + 1], dz = zi - X[3 * j + 2];
     if (anyper) min_image(J, dx, dy, dz);
     const double r2 = dx * dx + dy * dy + dz * dz;
@@ -598,7 +734,7 @@ __device__ __forceinline__ double pair_energy_model(const JobDev& J, const Model
     const double s2 = M.sig2[p] / r2;
     const double s6 = s2 * s2 * s2;
     const double v = 0.5 * (M.eps4[p] * s6 * (s6 - 1.0) - M.phic[p]);
-    u += J.force_fp64 ? v : on_grid(v);  // FP32 class: slot-ordered lists, exact-sum grid
+    u += J.force_fp64 ? v : (__builtin_fma(1.0, v, 0x1.8p20) - 0x1.8p20);
   }
   return u;
 }

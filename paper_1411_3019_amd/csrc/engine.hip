@@ -27,12 +27,15 @@
 
 #include "../../include/md.h"
 #include "kernels.hpp"
+#include "launch.hpp"
 
 using namespace mdk;
 
 namespace {
 
-constexpr int kDefaultKmax = 16;
+constexpr int kDefaultKmax = 16;   // list capacity (a multiple of kRow)
+constexpr int kDefaultHcap = 640;  // halo capacity per tile
+constexpr int kMaxHcap = 16128;    // window entries are 14-bit (bead-model entries carry a type)
 constexpr int kMaxChunk = 64;
 constexpr int kPoolChunk = 32;
 constexpr size_t kArenaBytes = (size_t)4 << 20;  // pinned staging for small uploads
@@ -211,9 +214,15 @@ int validate_params(const md_params& p) {
 // Bytes of device state per particle slot (excluding the neighbour list).
 constexpr double kInfinityCacheBytes = 256.0 * 1024.0 * 1024.0;  // MI355X last-level (memory-side) cache
 
-constexpr int64_t kSlotBytes = 2 * 24 /*X*/ + 2 * 24 /*P*/ + 2 * 4 /*ID*/ + 2 * 1 /*FLG*/ + 2 * 8 /*MASS*/ +
-                               24 /*FC*/ + 3 * 24 /*OX,OP,OF*/ + 32 /*OD*/ + 4 /*NCNT*/ + 4 * 7 /*rebuild*/ +
-                               16 /*PK*/ + 2 * 1 /*TYPE*/;
+constexpr int64_t kSlotBytes = 2 * 24 /*X*/ + 2 * 24 /*P*/ + 2 * 36 /*NZD, NZF*/ + 2 * 4 /*ID*/ + 2 * 1 /*FLG*/ +
+                               2 * 8 /*MASS*/ + 24 /*FC*/ + 3 * 24 /*OX,OP,OF*/ + 32 /*OD*/ + 4 /*NCNT*/ +
+                               4 * 7 /*rebuild*/ + 2 * 1 /*TYPE*/;
+
+// Device bytes per slot with list capacity kmax (16-bit entries) and halo
+// capacity hcap (per tile of kTile slots).
+constexpr double slot_bytes(int kmax, int hcap) {
+  return (double)kSlotBytes + 2.0 * kmax + (4.0 * hcap + 4.0) / kTile;
+}
 
 struct HostJob {
   bool used = false;
@@ -226,7 +235,9 @@ struct HostJob {
   int64_t last_build = 0, rebuilds = 0;
   bool built = false, done = false, reported = false;
   int status = MD_OK;
-  int newton_max = 0, nl_max = 0, err_id = -1;
+  int newton_max = 0, nl_max = 0, halo_max = 0, err_id = -1;
+  int64_t err_step = -1;
+  int sum_breaches = 0, breach_base = 0;  // breaches so far; those of earlier list epochs
   double nl_sum = 0.0;
   bool lists_pending = false;  // list statistics of the last build not read back yet
   double A_now = 0.0;
@@ -349,17 +360,21 @@ struct Engine {
   int64_t BMW = 0;      // bitmap word capacity
   int max_jobs = 0;
   int kmax = kDefaultKmax;
+  int hcap = kDefaultHcap;
+  int lds_max = 65536;  // LDS bytes one workgroup may use on this device
   DevBufs B{};
   std::vector<HostJob> jobs;
   FirstFit slots, words;
   // device scratch for launch descriptors
   // step tile classes, one step kernel each: FP64 forces, FP32 forces, bead
-  // model with FP64 forces, bead model with FP32 forces
-  static constexpr int kClasses = 4;
+  // model with FP64 forces, bead model with FP32 forces; + 4: the same for jobs
+  // on the height field or the bridge (kernels built with every surface)
+  static constexpr int kClasses = 8;
   int* step_tiles_job = nullptr;       // [kClasses][tile_cap]
   int64_t* step_tiles_first = nullptr;
   int* step_counts = nullptr;          // [kClasses]: tiles in each list (read by the step kernels)
-  int grid[kClasses] = {0, 0, 0, 0};   // grid sizes baked into the cached graphs
+  int grid[kClasses] = {};             // grid sizes baked into the cached graphs
+  int f32_variant = 0;                 // FP32-class step-kernel instance (kStepVariants; md_tune)
   bool stream_stores = false;          // store policy of the step and list kernels (set_store_policy)
   int* aux_tiles_job = nullptr;        // rebuild / finish lists
   int64_t* aux_tiles_first = nullptr;
@@ -404,9 +419,10 @@ struct Engine {
     for (auto& e : ev_sub)
       if (e) (void)hipEventDestroy(e), e = nullptr;
     void* ptrs[] = {B.X[0], B.X[1], B.P[0], B.P[1], B.ID[0], B.ID[1], B.FLG[0], B.FLG[1], B.MASS[0], B.MASS[1],
-                    B.FC, B.OX, B.OP, B.OF, B.OD, B.NL, B.NCNT, B.BM, B.WOFF, B.CCNT, B.CSTART, B.RASTER,
-                    B.CID, B.RANK, B.INV, B.SRC, B.PK, B.TYPE[0], B.TYPE[1], (void*)B.models, B.TACC, B.NLSTAT, B.jobs, B.book, step_tiles_job, step_tiles_first, step_counts, aux_tiles_job,
-                    aux_tiles_first, chunks_d, chunk_sums, ranges_d, diag_d};
+                    B.NZD[0], B.NZD[1], B.NZF[0], B.NZF[1], B.FC, B.OX, B.OP, B.OF, B.OD, B.NL, B.NCNT, B.HALO, B.HCNT, B.BM, B.WOFF,
+                    B.CCNT, B.CSTART, B.RASTER, B.CID, B.RANK, B.INV, B.SRC, B.TYPE[0], B.TYPE[1],
+                    (void*)B.models, B.TACC, B.NLSTAT, B.jobs, B.book, step_tiles_job, step_tiles_first,
+                    step_counts, aux_tiles_job, aux_tiles_first, chunks_d, chunk_sums, ranges_d, diag_d};
     for (void* p : ptrs)
       if (p) (void)hipFree(p);
     std::memset(&B, 0, sizeof(B));
@@ -462,21 +478,35 @@ struct Engine {
     words.reset(BMW);
     B.C = C;
     B.kmax = kmax;
+    B.hcap = hcap;
+    if (const char* v = std::getenv("MD_STEP_VARIANT")) f32_variant = std::max(0, std::min(kNumStepVariants - 1, std::atoi(v)));
+    {
+      int v = 0;
+      if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
+        lds_max = v;
+      else
+        (void)hipGetLastError();
+    }
     for (int q = 0; q < 2; ++q) {
       MDCHK(dalloc(&B.X[q], 3 * C));
       MDCHK(dalloc(&B.P[q], 3 * C));
       MDCHK(dalloc(&B.ID[q], C));
       MDCHK(dalloc(&B.FLG[q], C));
       MDCHK(dalloc(&B.MASS[q], C));
+      MDCHK(dalloc(&B.NZD[q], 3 * C));
+      MDCHK(dalloc(&B.NZF[q], 3 * C));
     }
     MDCHK(dalloc(&B.FC, 3 * C));
     MDCHK(dalloc(&B.OX, 3 * C));
     MDCHK(dalloc(&B.OP, 3 * C));
     MDCHK(dalloc(&B.OF, 3 * C));
     MDCHK(dalloc(&B.OD, 4 * C));
-    nl_bytes = (size_t)kmax * C * 4;
+    nl_bytes = (size_t)kmax * C * 2;
     MDCHK(dalloc(&B.NL, (size_t)kmax * C));
     MDCHK(dalloc(&B.NCNT, C));
+    MDCHK(dalloc(&B.HALO, (size_t)(C / kTile + 1) * hcap));
+    MDCHK(dalloc(&B.HCNT, C / kTile + 1));
+    HIPCHK(hipMemsetAsync(B.HCNT, 0, sizeof(uint32_t) * (C / kTile + 1), stream));
     MDCHK(dalloc(&B.BM, BMW));
     MDCHK(dalloc(&B.WOFF, BMW));
     MDCHK(dalloc(&B.CCNT, C));
@@ -486,7 +516,6 @@ struct Engine {
     MDCHK(dalloc(&B.RANK, C));
     MDCHK(dalloc(&B.INV, C));
     MDCHK(dalloc(&B.SRC, C));
-    MDCHK(dalloc(&B.PK, C));
     MDCHK(dalloc(&B.TYPE[0], C));
     MDCHK(dalloc(&B.TYPE[1], C));
     MDCHK(dalloc(&B.TACC, C / kGroup + 1));
@@ -592,20 +621,28 @@ struct Engine {
     return MD_OK;
   }
 
-  // Bytes one step moves for the resident jobs: x read and written, p read
-  // and written, index, flag, count, the lists (mean length of the last
-  // build; a guess of 12 before the first), masses when they differ, and for
-  // bead models the type and the inverse-permutation entries of the bonded
-  // partners.
+  // Bytes one step moves per particle of job h: x read and written, p read
+  // and written, index, flag, count, the list (16-bit entries, kbar of them),
+  // the tile's halo list, the noise cache read and written (FP32 class 12 +
+  // 12, FP64 class 24 + 24), masses when they differ, and for bead models the
+  // type and the inverse-permutation entries of the bonded partners.
+  static double step_bytes_per_particle(const HostJob& h, double kbar) {
+    double per = 105.0 + 2.0 * kbar + 6.0;
+    if (h.dev.gamma > 0.0) per += h.dev.force_fp64 ? 48.0 : 24.0;
+    if (!h.dev.uniform_mass) per += 8.0;
+    if (h.model) per += 1.0 + 16.0;
+    return per;
+  }
+
+  // Bytes one step moves for the resident jobs (the mean list length of the
+  // last build; a guess of 12 before the first).
   double step_working_set() const {
     double ws = 0.0;
     for (int j = 0; j < max_jobs; ++j) {
       const HostJob& h = jobs[j];
       if (!h.used || h.n == 0) continue;
       const double kbar = h.nl_sum > 0.0 ? h.nl_sum / (double)h.n : 12.0;
-      double per = 105.0 + 4.0 * kbar;
-      if (!h.dev.uniform_mass) per += 8.0;
-      if (h.model) per += 1.0 + 16.0;
+      double per = step_bytes_per_particle(h, kbar);
       ws += (double)h.n * per;
     }
     return ws;
@@ -641,6 +678,15 @@ struct Engine {
   }
 
   // ------------------------------------------------------------------ admission
+  // Constants of a job with uniform mass d.mass (used when d.uniform_mass).
+  static void mass_constants(JobDev& d) {
+    const double m = d.mass > 0.0 ? d.mass : 1.0;
+    d.noise_km = std::sqrt(m) * d.noise_k;
+    d.dtm = d.dt / m;
+    d.cpos = d.dt * d.dtm * 0.5;
+    d.inv_cpos = 2.0 * m / (d.dt * d.dt);
+  }
+
   static void fill_constants(HostJob& h) {
     const md_params& p = h.prm;
     JobDev& d = h.dev;
@@ -666,6 +712,10 @@ struct Engine {
     }
     d.force_fp64 = p.force_fp64 ? 1 : 0;
     d.newton_tol = p.newton_tol;
+    // FP32-class exact sums: terms c dx stay below 2^19 while c < 2^19 / rc
+    d.grid_bias = 0x1.8p20;
+    d.grid_cmax = (float)(0x1p19 / (rc > 0.0 ? rc : 1.0) * (1.0 - 0x1p-10));
+    mass_constants(d);
     d.newton_cap = p.newton_max_iter > 0 ? p.newton_max_iter : 32;
     d.newton_frozen = p.newton_frozen;
     d.model = h.model ? 1 : 0;
@@ -764,6 +814,7 @@ struct Engine {
     d.uniform_mass = uniform ? 1 : 0;
     d.mass = m0;
     d.inv_mass = 1.0 / m0;
+    mass_constants(d);
     h.step = step0;
     h.target = target;
     h.last_build = step0;
@@ -828,18 +879,35 @@ struct Engine {
 
   // ------------------------------------------------------------------ rebuild
   int grow_kmax(int need) {
-    int nk = kmax;
-    while (nk < need) nk = nk + nk / 2 + 4;
-    nk = (nk + 3) & ~3;  // whole uint4 rows
-    uint32_t* nl = nullptr;
+    // whole rows, and only as large as needed: the list build holds the
+    // lists of a tile in LDS
+    const int nk = (std::max(need, kmax + kRow) + kRow - 1) / kRow * kRow;
+    uint16_t* nl = nullptr;
     MDCHK(dalloc(&nl, (size_t)nk * C));
-    HIPCHK(hipMemcpyAsync(nl, B.NL, sizeof(uint32_t) * (size_t)kmax * C, hipMemcpyDeviceToDevice, stream));
+    // rows of entries k/8 do not move when rows are added
+    HIPCHK(hipMemcpyAsync(nl, B.NL, sizeof(uint16_t) * (size_t)kmax * C, hipMemcpyDeviceToDevice, stream));
     MDCHK(sync());
     (void)hipFree(B.NL);
     B.NL = nl;
     kmax = nk;
     B.kmax = nk;
-    nl_bytes = (size_t)nk * C * 4;
+    nl_bytes = (size_t)nk * C * 2;
+    drop_graphs();
+    return MD_OK;
+  }
+
+  // A larger halo capacity per tile (the lists are built again afterwards).
+  int grow_hcap(int need) {
+    if (need > kMaxHcap) return MD_ENOMEM;
+    int nh = std::min(kMaxHcap, std::max(need + need / 4, hcap + 64));
+    nh = std::min(kMaxHcap, (nh + 63) / 64 * 64);
+    uint32_t* hl = nullptr;
+    MDCHK(sync());
+    MDCHK(dalloc(&hl, (size_t)(C / kTile + 1) * nh));
+    (void)hipFree(B.HALO);
+    B.HALO = hl;
+    hcap = nh;
+    B.hcap = nh;
     drop_graphs();
     return MD_OK;
   }
@@ -883,8 +951,10 @@ struct Engine {
     if ((int64_t)(cb.size() + cc.size()) > chunk_cap || (int64_t)tj.size() > tile_cap ||
         (int64_t)(rb.size() + rcnt.size() + rtacc.size()) > range_cap)
       return MD_ENOMEM;
-    const size_t lds = nlist_lds_bytes(kmax);
-    if (lds > 160 * 1024) return MD_ENOMEM;
+    bool wide = false;  // FP64-class or bead-model jobs among those built
+    for (int j : set) wide = wide || jobs[j].dev.force_fp64 || jobs[j].model;
+    const size_t lds = nlist_lds_bytes(kmax, wide);
+    if ((int64_t)lds + nlist_static_lds(wide) > (int64_t)lds_max) return MD_ENOMEM;
     MDCHK(upload_jobs());
     MDCHK(upload_cached(aux_tiles_job, tj.data(), sizeof(int) * tj.size()));
     MDCHK(upload_cached(aux_tiles_first, tf.data(), sizeof(int64_t) * tf.size()));
@@ -925,18 +995,16 @@ struct Engine {
     hipLaunchKernelGGL(k_scan_c, dim3(nc), dim3(kScanThreads), 0, stream, B.CSTART, chunks_d + nb, chunk_sums + nb);
     hipLaunchKernelGGL(k_perm, dim3(ntiles), dim3(kTile), 0, stream, B, aux_tiles_job, aux_tiles_first);
     hipLaunchKernelGGL(k_gather, dim3(ntiles), dim3(kTile), 0, stream, B, aux_tiles_job, aux_tiles_first);
-    bool any_model = false;
-    for (int j : set) any_model = any_model || jobs[j].model;
     set_store_policy();
-    const dim3 ng(kNlistPerTile * ntiles), nb_(kNlistBlock);
-    if (any_model && stream_stores)
-      hipLaunchKernelGGL((k_nlist<true, true>), ng, nb_, lds, stream, B, aux_tiles_job, aux_tiles_first);
-    else if (any_model)
-      hipLaunchKernelGGL((k_nlist<true, false>), ng, nb_, lds, stream, B, aux_tiles_job, aux_tiles_first);
+    const dim3 ng(ntiles), nb_(kNlistBlock);
+    if (wide && stream_stores)
+      hipLaunchKernelGGL((k_nlist<true, true>), ng, nb_, lds, stream, B, B.jobs, B.models, aux_tiles_job, aux_tiles_first);
+    else if (wide)
+      hipLaunchKernelGGL((k_nlist<true, false>), ng, nb_, lds, stream, B, B.jobs, B.models, aux_tiles_job, aux_tiles_first);
     else if (stream_stores)
-      hipLaunchKernelGGL((k_nlist<false, true>), ng, nb_, lds, stream, B, aux_tiles_job, aux_tiles_first);
+      hipLaunchKernelGGL((k_nlist<false, true>), ng, nb_, lds, stream, B, B.jobs, B.models, aux_tiles_job, aux_tiles_first);
     else
-      hipLaunchKernelGGL((k_nlist<false, false>), ng, nb_, lds, stream, B, aux_tiles_job, aux_tiles_first);
+      hipLaunchKernelGGL((k_nlist<false, false>), ng, nb_, lds, stream, B, B.jobs, B.models, aux_tiles_job, aux_tiles_first);
     hipLaunchKernelGGL(k_job_stats, dim3(max_jobs), dim3(kStatsThreads), 0, stream, B, 1);
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(ev[3], stream));
@@ -948,6 +1016,7 @@ struct Engine {
       h.dev.pcur ^= 1;
       h.dev.scur ^= 1;
       h.built = true;
+      h.breach_base = h.sum_breaches;  // the build starts the device counter afresh
       h.lists_pending = true;
       if (h.step > h.last_build && h.A_now > 0.0) h.rate_prev = h.A_now / (double)(h.step - h.last_build);
       h.A_now = 0.0;
@@ -960,12 +1029,15 @@ struct Engine {
   // After a drained stream: take the list statistics of the last builds from
   // the job records in book_h, and the build time.  Returns the largest list
   // length found (for a capacity check).
-  int collect_build_stats() {
+  // Also grows the halo capacity when a tile's halo did not fit (the jobs
+  // concerned were stopped before their first step and are built again), and
+  // fails the jobs whose neighbourhoods the staged build could not hold.
+  int collect_build_stats(int* halo_need = nullptr) {
     if (build_timing_pending) {
       stats.rebuild_ms += elapsed_ms(ev[2], ev[3]);
       build_timing_pending = false;
     }
-    int need = 0;
+    int need = 0, hneed = 0;
     double sum = 0.0, cnt = 0.0;
     for (int j = 0; j < max_jobs; ++j) {
       HostJob& h = jobs[j];
@@ -974,23 +1046,34 @@ struct Engine {
       if (h.n == 0) continue;
       h.nl_max = book_h[j].nl_max;
       h.nl_sum = book_h[j].nl_sum;
+      h.halo_max = book_h[j].halo_max;
+      if (book_h[j].build_fail) {
+        h.status = MD_ENOMEM;
+        h.done = true;
+        step_tiles_valid = false;
+        continue;
+      }
       need = std::max(need, h.nl_max);
+      hneed = std::max(hneed, h.halo_max);
       sum += h.nl_sum;
       cnt += (double)h.n;
     }
     if (cnt > 0) stats.nl_mean = sum / cnt;
+    if (halo_need) *halo_need = hneed;
     return need;
   }
 
   // Build the lists of `set` and wait for them; on a capacity overflow grow the
   // capacity and build again (for callers that use the lists at once).
   int rebuild_now(const std::vector<int>& set) {
-    for (int attempt = 0; attempt < 4; ++attempt) {
+    for (int attempt = 0; attempt < 6; ++attempt) {
       MDCHK(rebuild(set));
       MDCHK(read_book());
-      const int need = collect_build_stats();
-      if (need <= kmax) return MD_OK;
-      MDCHK(grow_kmax(need + need / 8 + 2));
+      int hneed = 0;
+      const int need = collect_build_stats(&hneed);
+      if (need <= kmax && hneed <= hcap) return MD_OK;
+      if (need > kmax) MDCHK(grow_kmax(need + need / 8 + 2));
+      if (hneed > hcap) MDCHK(grow_hcap(hneed));
       for (int j : set) jobs[j].built = false;
     }
     return MD_ENOMEM;
@@ -1006,6 +1089,10 @@ struct Engine {
     return g;
   }
 
+  static int class_of(const HostJob& h) {
+    return (h.model ? 2 : 0) + (h.dev.force_fp64 ? 0 : 1) + (heavy_surface(h.surf_kind) ? 4 : 0);
+  }
+
   // Upload the tile lists of the steppable jobs.  Graphs bake the grid size,
   // not the lists: they stay valid while each list fits its grid and is not
   // much smaller than it.
@@ -1016,8 +1103,7 @@ struct Engine {
     for (int j = 0; j < max_jobs; ++j) {
       const HostJob& h = jobs[j];
       if (!h.used || h.done || h.status != MD_OK) continue;
-      const int c = (h.model ? 2 : 0) + (h.dev.force_fp64 ? 0 : 1);
-      tiles_of(h, j, tj[c], tf[c]);
+      tiles_of(h, j, tj[class_of(h)], tf[class_of(h)]);
     }
     bool same = true;
     for (int c = 0; c < kClasses; ++c) {
@@ -1050,30 +1136,26 @@ struct Engine {
     return MD_OK;
   }
 
-  template <bool kStream>
-  void enqueue_steps_as(int t0, int k) {
-    for (int t = t0; t < t0 + k; ++t) {
-      if (grid[0] > 0)
-        hipLaunchKernelGGL(k_step_f64<kStream>, dim3(grid[0]), dim3(kTile), 0, stream, B, step_tiles_job,
-                           step_tiles_first, step_counts, t);
-      if (grid[1] > 0)
-        hipLaunchKernelGGL(k_step_f32<kStream>, dim3(grid[1]), dim3(kTile), 0, stream, B, step_tiles_job + tile_cap,
-                           step_tiles_first + tile_cap, step_counts + 1, t);
-      if (grid[2] > 0)
-        hipLaunchKernelGGL(k_step_model<kStream>, dim3(grid[2]), dim3(kTile), 0, stream, B,
-                           step_tiles_job + 2 * tile_cap, step_tiles_first + 2 * tile_cap, step_counts + 2, t);
-      if (grid[3] > 0)
-        hipLaunchKernelGGL(k_step_model_f32<kStream>, dim3(grid[3]), dim3(kTile), 0, stream, B,
-                           step_tiles_job + 3 * tile_cap, step_tiles_first + 3 * tile_cap, step_counts + 3, t);
+  // One step launch of tile class c (see class_of).
+  void launch_class(int c, int t, bool stream_st) {
+    const StepLaunch L{dim3(grid[c]), stream, &B, step_tiles_job + c * tile_cap, step_tiles_first + c * tile_cap,
+                       step_counts + c, t};
+    const bool all = c >= 4;
+    switch (c & 3) {
+      case 0: launch_step_f64(L, all, stream_st); break;
+      case 1: launch_step_f32(L, f32_variant, all, stream_st); break;
+      case 2: launch_step_model(L, true, all, stream_st); break;
+      default: launch_step_model(L, false, all, stream_st); break;
     }
   }
 
-  void enqueue_steps(int t0, int k) {
-    if (stream_stores)
-      enqueue_steps_as<true>(t0, k);
-    else
-      enqueue_steps_as<false>(t0, k);
+  void enqueue_steps_as(int t0, int k, bool stream_st) {
+    for (int t = t0; t < t0 + k; ++t)
+      for (int c = 0; c < kClasses; ++c)
+        if (grid[c] > 0) launch_class(c, t, stream_st);
   }
+
+  void enqueue_steps(int t0, int k) { enqueue_steps_as(t0, k, stream_stores); }
 
   int launch_chunk(int k, bool use_graph) {
     if (!use_graph) {
@@ -1178,8 +1260,11 @@ struct Engine {
     MDCHK(read_book());
     for (int q = 0; q < nsub; ++q) stats.step_kernel_ms += elapsed_ms(ev_sub[2 * q], ev_sub[2 * q + 1]);
     stats.chunks += 1;
-    stats.step_launches += (int64_t)kk * ((grid[0] > 0) + (grid[1] > 0) + (grid[2] > 0) + (grid[3] > 0));
-    const int longest = collect_build_stats();
+    int classes = 0;
+    for (int c = 0; c < kClasses; ++c) classes += grid[c] > 0;
+    stats.step_launches += (int64_t)kk * classes;
+    int halo_need = 0;
+    const int longest = collect_build_stats(&halo_need);
     int64_t adv = 0;
     for (int j = 0; j < max_jobs; ++j) {
       HostJob& h = jobs[j];
@@ -1188,11 +1273,19 @@ struct Engine {
       int64_t done = cap[j];
       if (K.stop_at < h.step + done) done = std::max<int64_t>(0, K.stop_at - h.step);
       h.newton_max = std::max(h.newton_max, K.newton_max);
+      h.sum_breaches = h.breach_base + K.sum_breaches;
       if (K.err_code != 0) {
+        // the launch of step err_step failed: the state is that after it (its
+        // position stage ran), undefined for the failing particle
         h.status = K.err_code == kErrNewton ? MD_ENEWTON : MD_ENAN;
         h.err_id = K.err_id;
+        h.err_step = K.err_step;
+        if (done & 1) h.dev.xcur ^= 1;
+        h.step += done;
         h.done = true;
         step_tiles_valid = false;
+        stats.steps += done;
+        stats.particle_steps += done * h.n;
         continue;
       }
       h.step += done;
@@ -1210,6 +1303,7 @@ struct Engine {
       stats.particle_steps += done * h.n;
     }
     if (longest > kmax) MDCHK(grow_kmax(longest + longest / 8 + 2));
+    if (halo_need > hcap) MDCHK(grow_hcap(halo_need));
     *advanced = adv;
     return MD_OK;
   }
@@ -1226,6 +1320,7 @@ struct Engine {
         std::memset(diag, 0, sizeof(*diag));
         diag->step = h.step;
         diag->error_index = -1;
+        diag->error_step = -1;
       }
       return h.status;
     }
@@ -1280,6 +1375,8 @@ struct Engine {
       diag->newton_iter_max = h.newton_max;
       diag->nlist_max = h.nl_max;
       diag->error_index = h.err_id;
+      diag->error_step = h.err_step;
+      diag->exact_sum_breaches = h.sum_breaches;
     }
     return h.status;
   }
@@ -1624,7 +1721,7 @@ size_t md_job_footprint(int64_t n, int surface_kind, const double* surface_prm, 
   } else if (plan_job(*params, surface_kind, surface_prm, n, nullptr, &nslots, &nwords) != MD_OK) {
     return 0;
   }
-  return (size_t)nslots * (size_t)(kSlotBytes + 4 * (kDefaultKmax + kDefaultKmax / 2)) + (size_t)nwords * 8;
+  return (size_t)((double)nslots * slot_bytes(kDefaultKmax + kDefaultKmax / 2, kDefaultHcap)) + (size_t)nwords * 8;
 }
 
 int md_pool_create(size_t hbm_budget_bytes, int max_jobs, int device, void* stream, md_pool** out) {
@@ -1633,7 +1730,7 @@ int md_pool_create(size_t hbm_budget_bytes, int max_jobs, int device, void* stre
   MDCHK(check_device(device));
   md_pool* pl = new (std::nothrow) md_pool();
   if (!pl) return MD_ENOMEM;
-  const double per_slot = (double)(kSlotBytes + 4 * (kDefaultKmax + kDefaultKmax / 2));
+  const double per_slot = slot_bytes(kDefaultKmax + kDefaultKmax / 2, kDefaultHcap);
   const int64_t slots = (int64_t)(0.75 * (double)hbm_budget_bytes / per_slot);
   const int64_t words = (int64_t)(0.25 * (double)hbm_budget_bytes / 8.0);
   const int r = pl->eng.init(device, stream, slots, words, max_jobs);
@@ -1725,7 +1822,7 @@ int md_pool_usage(md_pool* pool, int* jobs, int64_t* particles, size_t* bytes) {
     }
   if (jobs) *jobs = nj;
   if (particles) *particles = np;
-  if (bytes) *bytes = (size_t)slots * (size_t)(kSlotBytes + 4 * pool->eng.kmax) + (size_t)words * 8;
+  if (bytes) *bytes = (size_t)((double)slots * slot_bytes(pool->eng.kmax, pool->eng.hcap)) + (size_t)words * 8;
   return MD_OK;
 }
 

@@ -1,356 +1,10 @@
-// kernels.hpp -- HIP kernels of the RATTLE + Langevin hot path (gfx950).
-//
-// Per-particle kernels run one thread per particle over "tiles": 256
-// consecutive slots of one job.  A launch covers the tiles of many jobs
-// (tile -> job table), so one launch advances every resident system.
-//
-// Step kernel (one launch per time step), for particle i of a job at step s:
-//   input  x^s (buffer parity xin), p^{s-1/2} (or p^s at a start), neighbour list
-//   force  F_i(x^s) from the list (and, for bead models, bonds, bends, wall)
-//   f^s    = b [F - gamma p^{s-1/2} + 1/2 sqrt(m) k (xi^s + xi^{s-1})]   (Algorithm S1)
-//   p^s    = q - (n.q / n.n) n,   q = p^{s-1/2} + dt/2 f^s,  n = n(x^s)  (Algorithm 1, 2nd loop)
-//   x^{s+1}, p^{s+1/2} from the scalar-Newton position stage          (Algorithm 1, 1st loop)
-// so that one kernel does the force stage and momentum stage of step s-1 -> s
-// and the position stage of s -> s+1.  The state between launches is
-// (x^s, p^{s-1/2}); no force array is stored and the previous random force is
-// regenerated from the Philox counter.
+// kernels.hpp -- the list build, sort, diagnostics and bookkeeping kernels of
+// the RATTLE + Langevin hot path (gfx950); the step kernels are in step.hpp.
 #pragma once
 
-#include "device.hpp"
+#include "step.hpp"
 
 namespace mdk {
-
-// An error at step s stops the job from step s + 1 on.
-__device__ __forceinline__ void record_error(JobBook& K, int code, uint32_t id, long long s) {
-  if (atomicCAS(&K.err_code, 0, code) == 0) K.err_id = (int)id;
-  atomicMin(&K.stop_at, s + 1);
-}
-
-// Bead-model forces on slot i (particle index id): typed pairs, then bonds,
-// bends and the wall; returns the particle's energy share (kEnergy).
-template <bool kEnergy, bool kF64>
-__device__ __forceinline__ double model_forces(const JobDev& J, const ModelDev& M, const DevBufs& B,
-                                               const double* __restrict__ X, int64_t i, uint32_t id, double xi,
-                                               double yi, double zi, double& Fx, double& Fy, double& Fz,
-                                               const double* tab = nullptr) {
-  const int ti = B.TYPE[J.scur][i];
-  if (J.periodic[0] | J.periodic[1] | J.periodic[2])
-    pair_forces_model<true, kF64>(J, M, B, X, i, ti, xi, yi, zi, Fx, Fy, Fz, tab);
-  else
-    pair_forces_model<false, kF64>(J, M, B, X, i, ti, xi, yi, zi, Fx, Fy, Fz, tab);
-  double u = kEnergy ? pair_energy_model(J, M, B, X, i, ti, xi, yi, zi) : 0.0;
-  double xs[15];
-  int tid[5];
-  molecule_window(J, M, B, X, id, xi, yi, zi, ti, xs, tid);
-  u += bonded_forces(J, M, B, X, id, tid, xs, Fx, Fy, Fz, tab);
-  return u;
-}
-
-// Random part of the combined force of Algorithm S1 for one particle:
-// 1/2 sqrt(m) k (xi^s + xi^{s-1}) (at a start: sqrt(m) k xi^s, the previous
-// draw being taken equal to this one).  Independent of the pair forces, so it
-// is computed while the neighbour gathers are in flight.
-template <bool kF64>
-__device__ __forceinline__ void langevin_kick(const JobDev& J, uint32_t id, double m, long long s, bool start,
-                                              double& rx, double& ry, double& rz) {
-  rx = ry = rz = 0.0;
-  if (!(J.gamma > 0.0) || (J.mode == kModeStartGiven && start)) return;
-  double a0, a1, a2;
-  langevin_normals<kF64>(J.seed, id, s, a0, a1, a2);
-  const double k = sqrt(m) * J.noise_k;
-  if (start) {
-    rx = k * a0;
-    ry = k * a1;
-    rz = k * a2;
-  } else {
-    double r0, r1, r2;
-    langevin_normals<kF64>(J.seed, id, s - 1, r0, r1, r2);
-    const double hk = 0.5 * k;
-    rx = hk * (a0 + r0);
-    ry = hk * (a1 + r1);
-    rz = hk * (a2 + r2);
-  }
-}
-
-// Combined force f^s = b [F - gamma p + random part] (Algorithm S1); at a
-// start with a force handed in by the caller, that force.
-__device__ __forceinline__ void combined_force(const JobDev& J, const DevBufs& B, uint32_t id, bool start, double Fx,
-                                               double Fy, double Fz, double px, double py, double pz, double rx,
-                                               double ry, double rz, double& fx, double& fy, double& fz) {
-  if (J.mode == kModeStartGiven && start) {
-    const int64_t o = J.off + id;
-    fx = B.FC[3 * o];
-    fy = B.FC[3 * o + 1];
-    fz = B.FC[3 * o + 2];
-    return;
-  }
-  if (J.gamma > 0.0) {
-    fx = J.b * (Fx - J.gamma * px + rx);
-    fy = J.b * (Fy - J.gamma * py + ry);
-    fz = J.b * (Fz - J.gamma * pz + rz);
-  } else {
-    fx = Fx;
-    fy = Fy;
-    fz = Fz;
-  }
-}
-
-// One workgroup per tile; each wavefront works on its own 64 slots of the
-// tile and shares no barrier with the others, so it leaves as soon as its own
-// particles are done.  (Workgroups of one wavefront would be capped by the
-// per-CU workgroup limit well below the register-bound occupancy.)
-template <bool kF64, bool kModel, bool kStream>
-__device__ __forceinline__ void step_body(const DevBufs& B, const int* __restrict__ tile_job,
-                                          const int64_t* __restrict__ tile_first, const int* __restrict__ ntiles_ptr,
-                                          int t) {
-  // the grid may be larger than the tile list (it is sized once per graph);
-  // surplus workgroups leave at once
-  const int ntiles = uniform_int(*ntiles_ptr);
-  if ((int)blockIdx.x >= ntiles) return;
-  const int b = xcd_remap((int)blockIdx.x, ntiles);
-  const int job = uniform_int(tile_job[b]);
-  const int64_t first = uniform_i64(tile_first[b]) + (int64_t)uniform_int((int)threadIdx.x / kGroup) * kGroup;
-  const JobDev& J = B.jobs[job];
-  JobBook& K = B.book[job];
-  // bead model: the type-pair tables of this tile's job in LDS, so that the
-  // typed lookups of the force loop and the bonds are LDS reads instead of
-  // vector-memory loads
-  // (every wavefront of the workgroup reaches this barrier: the job is the
-  // tile's, and the per-wavefront exits come after it)
-  __shared__ double mtab[kModel ? kModelTab : 1];
-  if (kModel) {
-    const ModelDev& M = B.models[job];
-    const int q = (int)threadIdx.x;
-    constexpr int kP = kMaxTypes * kMaxTypes;
-    if (q < kP) {
-      mtab[q] = M.rc2[q];
-      mtab[kP + q] = M.sig2[q];
-      mtab[2 * kP + q] = M.eps24[q];
-      mtab[3 * kP + q] = M.r0[q];
-    }
-    __syncthreads();
-  }
-  if (t >= J.remaining || first >= J.off + J.n) return;
-  const long long s = J.step0 + t;
-  // a tile whose accumulated displacement passed skin/2 during step s-1 (or an
-  // error) set stop_at <= s: the lists are no longer valid for forces at x^s
-  if (s >= K.stop_at) return;
-  const bool start = (J.mode != kModeSteady) && (t == 0);
-  const int xin = J.xcur ^ (t & 1);
-  const double* __restrict__ X = B.X[xin];
-  double* __restrict__ Xo = B.X[xin ^ 1];
-  double* __restrict__ P = B.P[J.pcur];
-  const int64_t C = B.C;
-  const int64_t i = first + (threadIdx.x % kGroup);
-  double disp2 = 0.0;
-  int iters = 0;
-  if (i < J.off + J.n) {
-    const double xi = X[3 * i], yi = X[3 * i + 1], zi = X[3 * i + 2];
-    const uint32_t id = B.ID[J.scur][i];
-    const double m = J.uniform_mass ? J.mass : B.MASS[J.scur][i];
-    // noise first: pure arithmetic that overlaps the latency of the list and
-    // neighbour loads issued next
-    double rx, ry, rz;
-    langevin_kick<kF64>(J, id, m, s, start, rx, ry, rz);
-    double Fx = 0.0, Fy = 0.0, Fz = 0.0;
-    if (J.pair_kind != kPairNone) {
-      if (kModel)
-        model_forces<false, kF64>(J, B.models[job], B, X, i, id, xi, yi, zi, Fx, Fy, Fz, mtab);
-      else
-        pair_forces<kF64>(J, B, X, i, xi, yi, zi, Fx, Fy, Fz);
-    }
-    // the particle's own momentum and flag are loaded after the force loop,
-    // which keeps them out of the loop's live registers
-    double px = P[3 * i], py = P[3 * i + 1], pz = P[3 * i + 2];
-    const bool cons = B.FLG[J.scur][i] != 0;
-    double fx, fy, fz;
-    combined_force(J, B, id, start, Fx, Fy, Fz, px, py, pz, rx, ry, rz, fx, fy, fz);
-    double nx = 0.0, ny = 0.0, nz = 0.0, g0 = 0.0;
-    if (cons) g0 = surf_eval(J, xi, yi, zi, nx, ny, nz);
-    // momentum stage of step s-1 -> s: tangent projection (closed form of the linear Newton)
-    if (!start) {
-      px += J.half_dt * fx;
-      py += J.half_dt * fy;
-      pz += J.half_dt * fz;
-      if (cons) {
-        const double a = (nx * px + ny * py + nz * pz) / (nx * nx + ny * ny + nz * nz);
-        px -= a * nx;
-        py -= a * ny;
-        pz -= a * nz;
-      }
-    }
-    // position stage of step s -> s+1
-    px += J.half_dt * fx;
-    py += J.half_dt * fy;
-    pz += J.half_dt * fz;
-    double x1, y1, z1;
-    if (cons) {
-      iters = rattle_position(J, m, xi, yi, zi, g0, nx, ny, nz, px, py, pz, x1, y1, z1);
-      if (iters < 0) {
-        record_error(K, kErrNewton, id, s);
-        iters = -iters;
-      }
-    } else {
-      const double dtm = J.dt / m;
-      x1 = xi + dtm * px;
-      y1 = yi + dtm * py;
-      z1 = zi + dtm * pz;
-    }
-    if (kStream) {
-      // streaming stores: the new state is not read again in this launch, so
-      // it should not displace the neighbour positions the other waves are
-      // gathering from L2 (2M torus: step kernel 119 -> 107 us).  Used when the
-      // step's data exceed the Infinity Cache; when they fit, ordinary stores
-      // leave the new state there for the next step (1M particles: 5 % faster).
-      // A template parameter, not a runtime flag: with both forms in one
-      // kernel the compiler merges part of them into ordinary stores.
-      __builtin_nontemporal_store(x1, Xo + 3 * i);
-      __builtin_nontemporal_store(y1, Xo + 3 * i + 1);
-      __builtin_nontemporal_store(z1, Xo + 3 * i + 2);
-      __builtin_nontemporal_store(px, P + 3 * i);
-      __builtin_nontemporal_store(py, P + 3 * i + 1);
-      __builtin_nontemporal_store(pz, P + 3 * i + 2);
-    } else {
-      Xo[3 * i] = x1;
-      Xo[3 * i + 1] = y1;
-      Xo[3 * i + 2] = z1;
-      P[3 * i] = px;
-      P[3 * i + 1] = py;
-      P[3 * i + 2] = pz;
-    }
-    const double dx = x1 - xi, dy = y1 - yi, dz = z1 - zi;
-    disp2 = dx * dx + dy * dy + dz * dz;
-    if (!(disp2 <= 1e300) || !(fabs(px) + fabs(py) + fabs(pz) <= 1e300)) {
-      record_error(K, kErrNaN, id, s);
-      disp2 = 0.0;
-    }
-  }
-  // per-group bound on the displacement since the last build: sum over steps of
-  // the group's largest displacement; only this wavefront touches its entry
-  double m2 = disp2;
-  int im = iters;
-  for (int o = 32; o > 0; o >>= 1) {
-    m2 = fmax(m2, __shfl_xor(m2, o, 64));
-    im = max(im, __shfl_xor(im, o, 64));
-  }
-  if (threadIdx.x % kGroup == 0) {
-    const int64_t g = first / kGroup;
-    const double a = B.TACC[g] + sqrt(m2);
-    B.TACC[g] = a;
-    if (a > J.half_skin) atomicMin(&K.stop_at, s + 1);
-    if (im > K.newton_max) atomicMax(&K.newton_max, im);
-  }
-}
-
-#ifndef MDK_STEP32_WAVES
-#define MDK_STEP32_WAVES 5
-#endif
-
-// FP32 pair forces (and FP32 Box-Muller): occupancy target MDK_STEP32_WAVES
-// wavefronts per SIMD.
-template <bool kStream>
-__global__ void __launch_bounds__(kTile) __attribute__((amdgpu_waves_per_eu(MDK_STEP32_WAVES, 8)))
-k_step_f32(DevBufs B, const int* __restrict__ tile_job, const int64_t* __restrict__ tile_first,
-           const int* __restrict__ ntiles_ptr, int t) {
-  step_body<false, false, kStream>(B, tile_job, tile_first, ntiles_ptr, t);
-}
-
-// FP64 pair forces and FP64 Box-Muller.
-template <bool kStream>
-__global__ void __launch_bounds__(kTile) k_step_f64(DevBufs B, const int* __restrict__ tile_job,
-                                                    const int64_t* __restrict__ tile_first,
-                                                    const int* __restrict__ ntiles_ptr, int t) {
-  step_body<true, false, kStream>(B, tile_job, tile_first, ntiles_ptr, t);
-}
-
-#ifndef MDK_STEPMODEL_WAVES
-#define MDK_STEPMODEL_WAVES 5
-#endif
-
-// Bead-model jobs: typed pairs, bonds, bends and the wall (FP64 force class);
-// occupancy target MDK_STEPMODEL_WAVES wavefronts per SIMD (5 fits without
-// spilling).
-template <bool kStream>
-__global__ void __launch_bounds__(kTile) __attribute__((amdgpu_waves_per_eu(MDK_STEPMODEL_WAVES, 8)))
-k_step_model(DevBufs B, const int* __restrict__ tile_job, const int64_t* __restrict__ tile_first,
-             const int* __restrict__ ntiles_ptr, int t) {
-  step_body<true, true, kStream>(B, tile_job, tile_first, ntiles_ptr, t);
-}
-
-// The same with FP32 pair terms (and the FP32 Box-Muller transform).
-template <bool kStream>
-__global__ void __launch_bounds__(kTile) __attribute__((amdgpu_waves_per_eu(MDK_STEPMODEL_WAVES, 8)))
-k_step_model_f32(DevBufs B, const int* __restrict__ tile_job, const int64_t* __restrict__ tile_first,
-                 const int* __restrict__ ntiles_ptr, int t) {
-  step_body<false, true, kStream>(B, tile_job, tile_first, ntiles_ptr, t);
-}
-
-// Finish: state at the current step m (x^m, p^m, f^m) and per-particle
-// diagnostics, written by particle index.
-template <bool kF64>
-__global__ void __launch_bounds__(kTile) k_finish(DevBufs B, const int* __restrict__ tile_job,
-                                                  const int64_t* __restrict__ tile_first) {
-  const int job = uniform_int(tile_job[blockIdx.x]);
-  const int64_t first = uniform_i64(tile_first[blockIdx.x]);
-  const JobDev& J = B.jobs[job];
-  const int64_t C = B.C;
-  const int64_t i = first + threadIdx.x;
-  if (i >= J.off + J.n) return;
-  const double* __restrict__ X = B.X[J.xcur];
-  const double* __restrict__ P = B.P[J.pcur];
-  const double xi = X[3 * i], yi = X[3 * i + 1], zi = X[3 * i + 2];
-  double px = P[3 * i], py = P[3 * i + 1], pz = P[3 * i + 2];
-  const uint32_t id = B.ID[J.scur][i];
-  const bool cons = B.FLG[J.scur][i] != 0;
-  const double m = J.uniform_mass ? J.mass : B.MASS[J.scur][i];
-  const bool start = J.mode != kModeSteady;
-  const long long s = J.step0;
-  double Fx = 0.0, Fy = 0.0, Fz = 0.0, Ui = 0.0;
-  if (J.pair_kind != kPairNone) {
-    if (J.model) {
-      Ui = model_forces<true, kF64>(J, B.models[job], B, X, i, id, xi, yi, zi, Fx, Fy, Fz);
-    } else {
-      pair_forces<kF64>(J, B, X, i, xi, yi, zi, Fx, Fy, Fz);
-      Ui = pair_energy(J, B, X, i, xi, yi, zi);
-    }
-  }
-  double rx, ry, rz, fx, fy, fz;
-  langevin_kick<kF64>(J, id, m, s, start, rx, ry, rz);
-  combined_force(J, B, id, start, Fx, Fy, Fz, px, py, pz, rx, ry, rz, fx, fy, fz);
-  double nx = 0.0, ny = 0.0, nz = 0.0, g = 0.0;
-  if (cons) g = surf_eval(J, xi, yi, zi, nx, ny, nz);
-  if (!start) {
-    px += J.half_dt * fx;
-    py += J.half_dt * fy;
-    pz += J.half_dt * fz;
-    if (cons) {
-      const double a = (nx * px + ny * py + nz * pz) / (nx * nx + ny * ny + nz * nz);
-      px -= a * nx;
-      py -= a * ny;
-      pz -= a * nz;
-    }
-  }
-  const int64_t o = J.off + id;
-  B.OX[3 * o] = xi;
-  B.OX[3 * o + 1] = yi;
-  B.OX[3 * o + 2] = zi;
-  B.OP[3 * o] = px;
-  B.OP[3 * o + 1] = py;
-  B.OP[3 * o + 2] = pz;
-  B.OF[3 * o] = fx;
-  B.OF[3 * o + 1] = fy;
-  B.OF[3 * o + 2] = fz;
-  B.OD[o] = 0.5 * (px * px + py * py + pz * pz) / m;
-  B.OD[C + o] = Ui;
-  double gd = 0.0, nv = 0.0;
-  if (cons) {
-    const double nn = sqrt(nx * nx + ny * ny + nz * nz);
-    gd = fabs(g) / nn;
-    nv = fabs(nx * px + ny * py + nz * pz) / (nn * m);
-  }
-  B.OD[2 * C + o] = gd;
-  B.OD[3 * C + o] = nv;
-}
 
 // ---------------------------------------------------------------------------
 // Neighbour-list build: occupied-cell bitmap -> compact cell index by popcount
@@ -479,7 +133,8 @@ __global__ void __launch_bounds__(kTile) k_perm(DevBufs B, const int* __restrict
 }
 
 // Gather the state into the new order: consecutive threads write consecutive
-// slots (whole cache lines), the reads follow the permutation.
+// slots (whole cache lines), the reads follow the permutation.  The noise
+// cache (the last step's normals) moves with the momenta.
 __global__ void __launch_bounds__(kTile) k_gather(DevBufs B, const int* __restrict__ tile_job,
                                                   const int64_t* __restrict__ tile_first) {
   const int job = uniform_int(tile_job[blockIdx.x]);
@@ -501,26 +156,39 @@ __global__ void __launch_bounds__(kTile) k_gather(DevBufs B, const int* __restri
     p[k] = Ps[3 * i + k];
   }
   const int sc = J.scur;
-  const bool per_mass = !J.uniform_mass, model = J.model != 0;
+  const bool per_mass = !J.uniform_mass, model = J.model != 0, f64 = J.force_fp64 != 0;
   const uint32_t id = B.ID[sc][i];
   const uint8_t flag = B.FLG[sc][i];
   const double mass = per_mass ? B.MASS[sc][i] : 0.0;
   const uint8_t type = model ? B.TYPE[sc][i] : (uint8_t)0;
+  double nz[3];
+  if (f64) {
+    const double* zs = B.NZD[J.pcur];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) nz[k] = zs[3 * i + k];
+  } else {
+    const float* zs = B.NZF[J.pcur];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) nz[k] = (double)zs[3 * i + k];
+  }
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     Xd[3 * d + k] = x[k];
     Pd[3 * d + k] = p[k];
   }
+  if (f64) {
+    double* zd = B.NZD[J.pcur ^ 1];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) zd[3 * d + k] = nz[k];
+  } else {
+    float* zd = B.NZF[J.pcur ^ 1];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) zd[3 * d + k] = (float)nz[k];
+  }
   B.ID[sc ^ 1][d] = id;
   B.FLG[sc ^ 1][d] = flag;
   if (per_mass) B.MASS[sc ^ 1][d] = mass;
-  uint32_t w = id;
-  if (model) {
-    // bead model: the type rides in the top two bits of the record's index
-    B.TYPE[sc ^ 1][d] = type;
-    w |= (uint32_t)type << kTypeShift;
-  }
-  B.PK[d] = make_float4((float)x[0], (float)x[1], (float)x[2], __uint_as_float(w));
+  if (model) B.TYPE[sc ^ 1][d] = type;
 }
 
 // Occupied cells with raster index below r, for the compact cell index.
@@ -544,16 +212,18 @@ __device__ __forceinline__ bool stencil_coord(const JobDev& J, int k, int c, int
 }
 
 // Slot ranges (relative to the job) of one stencil column: cells (x, y, z-1..z+1),
-// split in two runs when z wraps.
+// split in two runs when z wraps; key identifies the column (x nc_y + y), or
+// 0xFFFFFFFF when the offset leaves a non-periodic grid.
 struct ColumnRange {
-  uint32_t b0, e0, b1, e1;
+  uint32_t b0, e0, b1, e1, key;
 };
 
 __device__ __forceinline__ ColumnRange column_range(const DevBufs& B, const JobDev& J, int cx, int cy, int col,
                                                     int za0, int zb0, int za1, int zb1) {
-  ColumnRange r{0u, 0u, 0u, 0u};
+  ColumnRange r{0u, 0u, 0u, 0u, 0xFFFFFFFFu};
   int ax, ay;
   if (!stencil_coord(J, 0, cx, col / 3 - 1, ax) || !stencil_coord(J, 1, cy, col % 3 - 1, ay)) return r;
+  r.key = (uint32_t)ax * (uint32_t)J.nc[1] + (uint32_t)ay;
   const int64_t base = J.off;
   const uint32_t c0 = ((uint32_t)ax * (uint32_t)J.nc[1] + (uint32_t)ay) * (uint32_t)J.nc[2];
   r.b0 = B.CSTART[base + cells_before(B, J, c0 + (uint32_t)za0)];
@@ -563,28 +233,6 @@ __device__ __forceinline__ ColumnRange column_range(const DevBufs& B, const JobD
     r.e1 = B.CSTART[base + cells_before(B, J, c0 + (uint32_t)zb1 + 1u)];
   }
   return r;
-}
-
-// Insert particle index q into this lane's list, kept sorted by particle index
-// in LDS ([kmax][kNlistBlock], thread-minor so lanes hit distinct banks).  cnt counts every
-// candidate accepted, stored or not (cnt > kmax signals overflow).
-__device__ __forceinline__ void list_insert(uint32_t* kid, int lane, int kmax, int& cnt, uint32_t q) {
-  if (cnt < kmax) {
-    int k = cnt;
-    while (k > 0 && kid[(k - 1) * kNlistBlock + lane] > q) {
-      kid[k * kNlistBlock + lane] = kid[(k - 1) * kNlistBlock + lane];
-      --k;
-    }
-    kid[k * kNlistBlock + lane] = q;
-  }
-  ++cnt;
-}
-
-// Append slot q to this lane's list in LDS (lists of the FP32 class stay in
-// the order the stencil walk finds them, which is slot order).
-__device__ __forceinline__ void list_append(uint32_t* kid, int lane, int kmax, int& cnt, uint32_t q) {
-  if (cnt < kmax) kid[cnt * kNlistBlock + lane] = q;
-  ++cnt;
 }
 
 // z cells of the stencil around cz: [za0, zb0] and, when z wraps, [za1, zb1].
@@ -607,18 +255,58 @@ __device__ __forceinline__ void z_runs(const JobDev& J, int cz, int& za0, int& z
   }
 }
 
-// One lane walks its own 27-cell stencil: 9 contiguous z-runs of slots, the next
-// column's lookups in flight while the current one is scanned.  Candidates are
-// read from the packed FP32 records (one 16-byte load each), kListBatch at a
-// time; the last batch of a run is padded with repeats of its last record.
+// Exclusive scan over the 256 threads of a workgroup (every thread calls it);
+// *total receives the sum.  sh: 4 words of LDS.
+__device__ __forceinline__ uint32_t block_scan(uint32_t v, uint32_t* sh, uint32_t& total) {
+  const int lane = (int)threadIdx.x & 63, w = (int)threadIdx.x >> 6;
+  uint32_t x = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) sh[w] = x;
+  __syncthreads();
+  uint32_t before = 0u, tot = 0u;
+#pragma unroll
+  for (int q = 0; q < kNlistBlock / 64; ++q) {
+    const uint32_t s = sh[q];
+    if (q < w) before += s;
+    tot += s;
+  }
+  total = tot;
+  __syncthreads();
+  return before + x - v;
+}
+
+// Neighbour-list build.  One workgroup per tile (256 slots of the freshly
+// sorted raster cell order), one lane per slot:
+//  1. cells: the tile's lanes of one cell are consecutive; the first lane of
+//     each cell (within a wavefront) finds the cell's 27-cell stencil as 9
+//     column pieces (runs of slots, cells (x, y, z-1..z+1) of a column) and
+//     puts their hulls into an LDS table of the tile's columns;
+//  2. the hulls' slots are numbered consecutively ("candidates") and staged
+//     in LDS as FP32 records, kStageCap at a time;
+//  3. each wavefront tests the candidates of its own cells: a cell's
+//     candidates are spread over the lanes, and the cell's particles take
+//     turns, so lanes rarely idle; kept pairs are appended to the particle's
+//     list (one wavefront owns each list, so no atomics), and a bitmap over
+//     candidate numbers marks the kept ones outside the tile (the halo);
+//  4. the halo is the marked candidates in candidate order; list entries
+//     become window indices (own slots 0..255, halo 256 + rank) and are
+//     written as 16-bit entries, with the halo list of the tile.
+// FP64 class: lists sorted by particle index (the order of the FP64 sums).
+// FP32 class: lists in the order found.
 // The FP32 distance test uses the list radius widened by a bound on the FP32
-// rounding of both positions and of the separation (times eight), so it accepts
-// every pair closer than the list radius; the few extra pairs it may accept lie
-// beyond the cut-off and add nothing to the forces.
-#ifndef MDK_LIST_BATCH
-#define MDK_LIST_BATCH 4
-#endif
-constexpr int kListBatch = MDK_LIST_BATCH;
+// rounding of both positions and of the separation (times eight), so it
+// accepts every pair closer than the list radius; the few extra pairs it may
+// accept lie beyond the cut-off and add nothing to the forces.
+constexpr int kColCap = 256;     // distinct stencil columns of one tile
+constexpr int kCandCap = 16384;  // candidates of one tile
+constexpr uint32_t kNoCol = 0xFFFFFFFFu;
+template <bool kWide>
+constexpr int stage_cap() {  // candidate records staged at a time (the wide instance keeps LDS for its lists)
+  return kWide ? 768 : 1024;
+}
 
 __device__ __forceinline__ void min_image_f(const JobDev& J, float& dx, float& dy, float& dz) {
   if (J.periodic[0]) dx -= (float)J.box_len[0] * rintf(dx * (float)J.inv_box_len[0]);
@@ -626,182 +314,393 @@ __device__ __forceinline__ void min_image_f(const JobDev& J, float& dx, float& d
   if (J.periodic[2]) dz -= (float)J.box_len[2] * rintf(dz * (float)J.inv_box_len[2]);
 }
 
-// kModel: bead model (FP64 class): each candidate is tested against the list
-// radius of its type pair, rc_ab + skin, and pairs inside a molecule are left out.
-template <bool kSorted, bool kModel>
-__device__ __forceinline__ void nlist_lane(const DevBufs& B, const JobDev& J, int64_t i, double xi, double yi,
-                                           double zi, int cx, int cy, int cz, uint32_t* kid, int lane, int kmax,
-                                           int& cnt, uint32_t myid, const ModelDev* M, int ti) {
-  int za0, zb0, za1, zb1;
-  z_runs(J, cz, za0, zb0, za1, zb1);
-  const int64_t base = J.off;
-  const bool anyper = J.periodic[0] | J.periodic[1] | J.periodic[2];
-  const float4* __restrict__ PK = B.PK;
-  double lper = 0.0;
-  for (int k = 0; k < 3; ++k)
-    if (J.periodic[k]) lper = fmax(lper, J.box_len[k]);
-  const double rl = sqrt(J.rlist2);
-  const double delta = 0x1p-21 * (2.0 * fmax(fabs(xi), fmax(fabs(yi), fabs(zi))) + 3.0 * rl + lper);
-  const float thr = (float)((rl + delta) * (rl + delta) * (1.0 + 0x1p-20));
-  const float xf = (float)xi, yf = (float)yi, zf = (float)zi;
-  // bead model: list radius per partner type (rounding bound as above, which
-  // covers the shorter radii too); candidates with particle index in
-  // [mstart, mstart + bpm) share this molecule
-  float tthr[kMaxTypes];
-  if (kModel) {
-    const double skin = 2.0 * J.half_skin;
-#pragma unroll
-    for (int b = 0; b < kMaxTypes; ++b) {
-      const double r = sqrt(M->rc2[ti * kMaxTypes + b]) + skin;
-      tthr[b] = (float)((r + delta) * (r + delta) * (1.0 + 0x1p-20));
-    }
-  }
-  const uint32_t bpm = (uint32_t)J.bpm, mstart = bpm != 0u ? (myid / bpm) * bpm : 0u;  // bpm = 0: no molecules
-  auto scan = [&](uint32_t b, uint32_t e) {
-    const int64_t end = base + e;
-    if (b >= e) return;
-    // software-pipelined: the next batch's records are loaded while this one is
-    // tested (past the end the loads repeat the last record and are not used)
-    float4 nxt[kListBatch];
-#pragma unroll
-    for (int u = 0; u < kListBatch; ++u) nxt[u] = PK[base + b + u < end ? base + b + u : end - 1];
-    for (int64_t j = base + b; j < end; j += kListBatch) {
-      float4 r[kListBatch];
-#pragma unroll
-      for (int u = 0; u < kListBatch; ++u) {
-        r[u] = nxt[u];
-        const int64_t jn = j + kListBatch + u;
-        nxt[u] = PK[jn < end ? jn : end - 1];
-      }
-#pragma unroll
-      for (int u = 0; u < kListBatch; ++u) {
-        float dx = xf - r[u].x, dy = yf - r[u].y, dz = zf - r[u].z;
-        if (anyper) min_image_f(J, dx, dy, dz);
-        const float d2 = dx * dx + dy * dy + dz * dz;
-        const uint32_t w = __float_as_uint(r[u].w);
-        uint32_t q;
-        bool take;
-        if (kModel) {
-          const uint32_t tj = w >> kTypeShift;
-          q = w & kIdMask;
-          const float t = tj == 0u ? tthr[0] : (tj == 1u ? tthr[1] : (tj == 2u ? tthr[2] : tthr[3]));
-          take = d2 < t && q - mstart >= bpm;
-        } else {
-          q = w;
-          take = d2 < thr && w - mstart >= bpm;
-        }
-        if (j + u < end && j + u != i && take) {
-          if (kSorted)
-            list_insert(kid, lane, kmax, cnt, q);
-          else  // job-local slot (bead model: partner type in the top bits)
-            list_append(kid, lane, kmax, cnt, (uint32_t)(j + u - base) | (kModel ? w & ~kIdMask : 0u));
-        }
-      }
-    }
-  };
-  ColumnRange cur = column_range(B, J, cx, cy, 0, za0, zb0, za1, zb1);
-  for (int col = 0; col < 9; ++col) {
-    ColumnRange nxt{0u, 0u, 0u, 0u};
-    if (col + 1 < 9) nxt = column_range(B, J, cx, cy, col + 1, za0, zb0, za1, zb1);
-    scan(cur.b0, cur.e0);
-    scan(cur.b1, cur.e1);
-    cur = nxt;
-  }
-}
-
-// One uint4 row of a list (entries k .. k+3 of slot i).  Streaming (as the
-// step's state stores, when the data exceed the Infinity Cache): the lists
-// are read in the next step, not in this launch, and would otherwise
-// displace the candidate records the build is reading from L2.
+// One row of a list (entries k .. k+7 of slot i).  Streaming (as the step's
+// state stores, when the data exceed the Infinity Cache): the lists are read
+// in the next step, not in this launch.
 template <bool kStream>
-__device__ __forceinline__ void store_row(uint32_t* NL, int64_t C, int k, int64_t i, const uint32_t* v) {
+__device__ __forceinline__ void store_row(uint16_t* NL, int64_t C, int k, int64_t i, const uint32_t* e) {
   typedef unsigned int v4u __attribute__((ext_vector_type(4)));
-  const v4u row = {v[0], v[1], v[2], v[3]};
-  v4u* dst = reinterpret_cast<v4u*>(NL) + (int64_t)(k >> 2) * C + i;
+  const v4u row = {e[0] | (e[1] << 16), e[2] | (e[3] << 16), e[4] | (e[5] << 16), e[6] | (e[7] << 16)};
+  v4u* dst = reinterpret_cast<v4u*>(NL) + (int64_t)(k / kRow) * C + i;
   if (kStream)
     __builtin_nontemporal_store(row, dst);
   else
     *dst = row;
 }
 
-// Neighbour-list build, one lane per slot of the freshly sorted (raster cell)
-// order, one workgroup per tile.  Each lane walks its own stencil and
-// stages its list in LDS.  FP64 class: kept sorted by particle index and mapped
-// back to slots through the inverse permutation of the sort, so that the FP64
-// force sums run in particle-index order.  FP32 class: slots in the order the
-// walk finds them (ascending), since its force sums do not depend on the order;
-// neighbouring lanes then read neighbouring memory in the force loop.
-// kWithModel: the instance launched when a bead-model job is among those built
-// (the plain instance keeps the model path out of its register budget).
-template <bool kWithModel, bool kStream>
-__global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const int* __restrict__ tile_job,
+// The table entry of column key (read only), or -1.
+__device__ __forceinline__ int column_slot(const uint32_t* ckey, uint32_t key) {
+  uint32_t h = (key * 0x9E3779B1u) >> 24;
+  for (int probe = 0; probe < kColCap; ++probe) {
+    const uint32_t k = ckey[h];
+    if (k == key) return (int)h;
+    if (k == kNoCol) return -1;
+    h = (h + 1u) & (kColCap - 1);
+  }
+  return -1;
+}
+
+// kWide: the instance for builds that include FP64-class or bead-model jobs
+// (32-bit codes; particle indices and types of the candidates staged too).
+// jobs, models: B.jobs and B.models as no-alias arguments (scalar loads).
+template <bool kWide, bool kStream>
+__global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const JobDev* __restrict__ jobs,
+                                                       const ModelDev* __restrict__ models,
+                                                       const int* __restrict__ tile_job,
                                                        const int64_t* __restrict__ tile_first) {
-  extern __shared__ uint32_t kid[];  // lists [kmax][kNlistBlock]
+  // codes of kept neighbours: own-tile slots as kOwn | local index, others as
+  // their candidate number; bead model: the partner's type in the top bits
+  using code_t = typename std::conditional<kWide, uint32_t, uint16_t>::type;
+  constexpr uint32_t kOwn = kWide ? 0x10000u : 0x8000u;
+  constexpr int kStageCap = stage_cap<kWide>();
+  extern __shared__ uint32_t dyn[];  // codes [kmax][256]; FP64 class: then particle indices [kmax][256]
+  __shared__ float4 stg[kStageCap];
+  __shared__ uint32_t stid[kWide ? kStageCap : 1];  // particle index | type << 30 of staged candidates
+  __shared__ float4 ownp[kNlistBlock];              // the tile's particles: FP32 position, list radius^2 bound
+  __shared__ float ownt[kWide ? kNlistBlock * kMaxTypes : 1];  // bead model: the same per partner type
+  __shared__ uint32_t ownm[kWide ? kNlistBlock : 1];          // first particle index of the particle's molecule
+  __shared__ uint32_t lcnt[kNlistBlock];            // neighbours found per particle
+  __shared__ uint32_t ckey[kColCap], cb[kColCap], ce[kColCap], coff[kColCap + 1];
+  __shared__ uint32_t bits[kCandCap / 32], wpre[kCandCap / 32];
+  __shared__ uint32_t scan_sh[kNlistBlock / 64];
+  __shared__ int fail;
   const int kmax = B.kmax;
-  const int tile = (int)blockIdx.x / kNlistPerTile;
+  code_t* kid = reinterpret_cast<code_t*>(dyn);
+  uint32_t* kkey = dyn + ((size_t)kmax * kNlistBlock * sizeof(code_t) + 3) / 4;
+  const int tile = (int)blockIdx.x;
   const int job = uniform_int(tile_job[tile]);
-  const JobDev& J = B.jobs[job];
-  const int lane = threadIdx.x;
-  const int64_t i = uniform_i64(tile_first[tile]) + ((int)blockIdx.x % kNlistPerTile) * kNlistBlock + lane;
+  const JobDev& J = jobs[job];
+  JobBook& K = B.book[job];
+  const int lane = (int)threadIdx.x;
+  const int wl = lane & 63, wb = lane & ~63;  // lane in the wavefront, first lane of the wavefront
+  const int64_t first = uniform_i64(tile_first[tile]);
+  const int64_t i = first + lane;
   const int64_t base = J.off;
-  int cnt = 0;
-  if (i < J.off + J.n && J.pair_kind == kPairNone) {
-    B.NCNT[i] = 0u;  // no pair potential: empty lists (the build only sorts)
-  } else if (i < J.off + J.n) {
-    const double* __restrict__ X = B.X[J.xcur ^ 1];  // the sorted copies written by k_gather
-    const double xi = X[3 * i], yi = X[3 * i + 1], zi = X[3 * i + 2];
-    const int cx = cell_coord(J, 0, xi), cy = cell_coord(J, 1, yi), cz = cell_coord(J, 2, zi);
-    const int64_t C = B.C;
-    int stored;
-    if (J.force_fp64) {
-      // FP64 class: sorted by particle index, mapped back to slots through the
-      // inverse permutation, four lookups in flight at a time
-      if (kWithModel && J.model)
-        nlist_lane<true, kWithModel>(B, J, i, xi, yi, zi, cx, cy, cz, kid, lane, kmax, cnt, B.ID[J.scur ^ 1][i],
-                               B.models + job, B.TYPE[J.scur ^ 1][i]);
-      else
-        nlist_lane<true, false>(B, J, i, xi, yi, zi, cx, cy, cz, kid, lane, kmax, cnt, 0u, nullptr, 0);
-      stored = cnt < kmax ? cnt : kmax;
-      // bead model: the partner's type rides in the top two bits of the entry
-      const uint8_t* __restrict__ T = B.TYPE[J.scur ^ 1];
-      const bool typed = kWithModel && J.model;
-      for (int k = 0; k < stored; k += 4) {
-        uint32_t v[4];
+  const uint32_t first_local = (uint32_t)(first - base);
+  const int64_t gt = first / kTile;
+  const bool valid = i < J.off + J.n;
+  const int64_t C = B.C;
+  if (J.pair_kind == kPairNone) {
+    // no pair potential: empty lists (the build only sorts)
+    if (valid) B.NCNT[i] = 0u;
+    if (lane == 0) B.HCNT[gt] = 0u;
+    if (lane % kGroup == 0 && valid) {
+      B.NLSTAT[2 * (i / kGroup)] = 0u;
+      B.NLSTAT[2 * (i / kGroup) + 1] = 0u;
+    }
+    return;
+  }
+  const bool sorted = kWide && J.force_fp64;
+  const bool typed = kWide && J.model;
+  ckey[lane] = kNoCol;
+  cb[lane] = 0xFFFFFFFFu;
+  ce[lane] = 0u;
+  lcnt[lane] = 0u;
+  for (int w = lane; w < kCandCap / 32; w += kNlistBlock) bits[w] = 0u;
+  if (lane == 0) fail = 0;
+  // this lane's particle: position, cell, list radius (widened by a bound on
+  // the FP32 rounding of both positions and the separation)
+  const double* __restrict__ X = B.X[J.xcur ^ 1];  // the sorted copies written by k_gather
+  double xi = 0.0, yi = 0.0, zi = 0.0;
+  int cx = 0, cy = 0, cz = 0;
+  if (valid) {
+    xi = X[3 * i];
+    yi = X[3 * i + 1];
+    zi = X[3 * i + 2];
+    cx = cell_coord(J, 0, xi);
+    cy = cell_coord(J, 1, yi);
+    cz = cell_coord(J, 2, zi);
+  }
+  {
+    double lper = 0.0;
+    for (int k = 0; k < 3; ++k)
+      if (J.periodic[k]) lper = fmax(lper, J.box_len[k]);
+    const double rl = sqrt(J.rlist2);
+    const double delta = 0x1p-21 * (2.0 * fmax(fabs(xi), fmax(fabs(yi), fabs(zi))) + 3.0 * rl + lper);
+    ownp[lane] = make_float4((float)xi, (float)yi, (float)zi, (float)((rl + delta) * (rl + delta) * (1.0 + 0x1p-20)));
+    if (kWide) {
+      // bead model: list radius per partner type, rc_ab + skin (the rounding
+      // bound above covers the shorter radii too); partners of the same
+      // molecule are left out
+      const uint32_t myid = valid ? B.ID[J.scur ^ 1][i] : 0u;
+      const int ti = typed && valid ? (int)B.TYPE[J.scur ^ 1][i] : 0;
+      const double skin = 2.0 * J.half_skin;
+      const ModelDev& M = models[job];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const uint32_t q = k + u < stored ? kid[(k + u) * kNlistBlock + lane] : 0u;  // 0: a valid index
-          const uint32_t sl = (uint32_t)base + B.INV[base + q];
-          v[u] = k + u < stored ? sl : 0u;
-          if (typed && k + u < stored) v[u] |= (uint32_t)T[sl] << kTypeShift;
-        }
-        store_row<kStream>(B.NL, C, k, i, v);
+      for (int b = 0; b < kMaxTypes; ++b) {
+        const double r = typed ? sqrt(M.rc2[ti * kMaxTypes + b]) + skin : rl;
+        ownt[lane * kMaxTypes + b] = (float)((r + delta) * (r + delta) * (1.0 + 0x1p-20));
       }
-    } else {
-      // FP32 class: slot order, as found
-      if (kWithModel && J.model)
-        nlist_lane<false, kWithModel>(B, J, i, xi, yi, zi, cx, cy, cz, kid, lane, kmax, cnt, B.ID[J.scur ^ 1][i],
-                                      B.models + job, B.TYPE[J.scur ^ 1][i]);
-      else
-        nlist_lane<false, false>(B, J, i, xi, yi, zi, cx, cy, cz, kid, lane, kmax, cnt, 0u, nullptr, 0);
-      stored = cnt < kmax ? cnt : kmax;
-      for (int k = 0; k < stored; k += 4) {
-        uint32_t v[4];
+      const uint32_t bpm = (uint32_t)J.bpm;
+      ownm[lane] = bpm != 0u ? (myid / bpm) * bpm : 0u;
+    }
+  }
+  __syncthreads();
+  // 1. cells: runs of equal cells within the wavefront; the first lane of each
+  // run finds the cell's 9 stencil column pieces and puts their hulls in the table
+  const uint32_t rkey = valid ? raster_of(J, cx, cy, cz) : kNoKey;
+  unsigned long long heads;
+  const int rs = run_start(rkey, wl, &heads);
+  const bool is_head = valid && rs == wl;
+  uint32_t pb0[9], pe0[9], pb1[9], pe1[9], pkey[9];
+  {
+    int za0, zb0, za1, zb1;
+    z_runs(J, cz, za0, zb0, za1, zb1);
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          // job-local slot, with the bead model's partner type in the top bits
-          const uint32_t q = kid[(k + u) * kNlistBlock + lane];
-          const uint32_t sl = kWithModel && J.model ? ((uint32_t)base + (q & kIdMask)) | (q & ~kIdMask)
-                                                    : (uint32_t)base + q;
-          v[u] = k + u < stored ? sl : 0u;
+    for (int col = 0; col < 9; ++col) {
+      pb0[col] = pe0[col] = pb1[col] = pe1[col] = 0u;
+      pkey[col] = kNoCol;
+      if (!is_head) continue;
+      const ColumnRange r = column_range(B, J, cx, cy, col, za0, zb0, za1, zb1);
+      const bool has0 = r.e0 > r.b0, has1 = r.e1 > r.b1;
+      if (r.key == kNoCol || !(has0 || has1)) continue;
+      pb0[col] = r.b0;
+      pe0[col] = r.e0;
+      pb1[col] = r.b1;
+      pe1[col] = r.e1;
+      pkey[col] = r.key;
+      uint32_t h = (r.key * 0x9E3779B1u) >> 24;
+      int found = -1;
+      for (int probe = 0; probe < kColCap; ++probe) {
+        const uint32_t old = atomicCAS(&ckey[h], kNoCol, r.key);
+        if (old == kNoCol || old == r.key) {
+          found = (int)h;
+          break;
         }
-        store_row<kStream>(B.NL, C, k, i, v);
+        h = (h + 1u) & (kColCap - 1);
       }
+      if (found < 0) {
+        fail = 1;
+        continue;
+      }
+      atomicMin(&cb[found], has0 ? (has1 ? min(r.b0, r.b1) : r.b0) : r.b1);
+      atomicMax(&ce[found], has0 ? (has1 ? max(r.e0, r.e1) : r.e0) : r.e1);
+    }
+  }
+  __syncthreads();
+  // candidate numbering: the columns' hulls one after another in table order
+  uint32_t M = 0u;
+  {
+    const uint32_t len = ckey[lane] != kNoCol ? ce[lane] - cb[lane] : 0u;
+    const uint32_t off = block_scan(len, scan_sh, M);
+    coff[lane] = off;
+    if (lane == 0) coff[kColCap] = M;
+  }
+  // the candidate-number offset of each of the head's columns (candidate = slot + off)
+  int poff[9];
+#pragma unroll
+  for (int col = 0; col < 9; ++col) {
+    poff[col] = 0;
+    if (pkey[col] == kNoCol) continue;
+    const int h = column_slot(ckey, pkey[col]);
+    if (h < 0) {
+      fail = 1;
+      pkey[col] = kNoCol;
+      continue;
+    }
+    poff[col] = (int)coff[h] - (int)cb[h];
+  }
+  __syncthreads();
+  if (M > (uint32_t)kCandCap || fail) {
+    // too dense for the staged build: the job stops with an error
+    if (lane == 0) {
+      atomicOr(&K.build_fail, 1);
+      atomicMin(&K.stop_at, (long long)J.step0);
+      B.HCNT[gt] = 0u;
+    }
+    if (valid) B.NCNT[i] = 0u;
+    if (lane % kGroup == 0 && valid) {
+      B.NLSTAT[2 * (i / kGroup)] = 0u;
+      B.NLSTAT[2 * (i / kGroup) + 1] = 0u;
+    }
+    return;
+  }
+  const bool anyper = J.periodic[0] | J.periodic[1] | J.periodic[2];
+  const uint32_t bpm = (uint32_t)J.bpm;
+  const int* __restrict__ IDs = reinterpret_cast<const int*>(B.ID[J.scur ^ 1]);
+  const uint8_t* __restrict__ TYs = B.TYPE[J.scur ^ 1];
+  const unsigned long long hmask = __ballot(is_head);  // the cells of this wavefront
+  // 2./3. stage the candidates chunk by chunk; each wavefront tests its cells
+  const uint32_t nchunks = (M + kStageCap - 1) / kStageCap;
+  for (uint32_t ch = 0; ch < nchunks; ++ch) {
+    const uint32_t c0 = ch * kStageCap, c1 = min(M, c0 + kStageCap);
+    if (ch > 0) __syncthreads();  // every lane is done with the previous chunk
+    for (uint32_t t = c0 + lane; t < c1; t += kNlistBlock) {
+      // the column holding candidate t: the last table entry with coff <= t
+      int lo = 0, hi = kColCap;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (coff[mid] <= t)
+          lo = mid;
+        else
+          hi = mid;
+      }
+      const uint32_t sl = cb[lo] + (t - coff[lo]);
+      const int64_t g = base + sl;
+      stg[t - c0] = make_float4((float)X[3 * g], (float)X[3 * g + 1], (float)X[3 * g + 2], __uint_as_float(sl));
+      if (kWide) {
+        uint32_t w = (uint32_t)IDs[g];
+        if (typed) w |= (uint32_t)TYs[g] << kTypeShift;
+        stid[t - c0] = w;
+      }
+    }
+    __syncthreads();
+    unsigned long long hm = hmask;
+    while (hm) {
+      const int h = __ffsll((long long)hm) - 1;  // first lane of the cell (wavefront index)
+      hm &= hm - 1ull;
+      const unsigned long long later = heads & ~lanemask_le(h);
+      const int np = (later ? __ffsll((long long)later) - 1 : 64) - h;  // particles of the cell
+      const int p0 = wb + h;                                            // its first lane in the tile
+      // the cell's candidates in this chunk: up to 18 ranges, numbered f = 0 ..
+      uint32_t rb[18], rl_[18];
+      uint32_t ncand = 0u;
+#pragma unroll
+      for (int col = 0; col < 9; ++col) {
+        const uint32_t key = (uint32_t)__builtin_amdgcn_readlane((int)pkey[col], h);
+        const int o = __builtin_amdgcn_readlane(poff[col], h);
+#pragma unroll
+        for (int piece = 0; piece < 2; ++piece) {
+          const uint32_t pb = (uint32_t)__builtin_amdgcn_readlane((int)(piece ? pb1[col] : pb0[col]), h);
+          const uint32_t pe = (uint32_t)__builtin_amdgcn_readlane((int)(piece ? pe1[col] : pe0[col]), h);
+          uint32_t tb = 0u, tl = 0u;
+          if (key != kNoCol && pe > pb) {
+            tb = max((uint32_t)((int)pb + o), c0);
+            const uint32_t te = min((uint32_t)((int)pe + o), c1);
+            tl = te > tb ? te - tb : 0u;
+          }
+          rb[2 * col + piece] = tb;
+          rl_[2 * col + piece] = tl;
+          ncand += tl;
+        }
+      }
+      for (uint32_t f0 = 0; f0 < ncand; f0 += 64) {
+        // this lane's candidate: number t of flat index f
+        const uint32_t f = f0 + (uint32_t)wl;
+        uint32_t t = 0u, acc = 0u;
+#pragma unroll
+        for (int r = 0; r < 18; ++r) {
+          if (f >= acc && f < acc + rl_[r]) t = rb[r] + (f - acc);
+          acc += rl_[r];
+        }
+        const bool have = f < ncand;
+        const float4 cr = have ? stg[t - c0] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const uint32_t cw = kWide && have ? stid[t - c0] : 0u;
+        const uint32_t q = __float_as_uint(cr.w);  // candidate slot (job-local)
+        const uint32_t loc = q - first_local;
+        const bool own = loc < (uint32_t)kTile;
+        const uint32_t qid = cw & kIdMask, tj = cw >> kTypeShift;
+        bool marked = false;
+        for (int pp = 0; pp < np; ++pp) {
+          const int p = p0 + pp;  // tile lane of the particle
+          const float4 pr = ownp[p];
+          float dx = pr.x - cr.x, dy = pr.y - cr.y, dz = pr.z - cr.z;
+          if (anyper) min_image_f(J, dx, dy, dz);
+          const float d2 = dx * dx + dy * dy + dz * dz;
+          bool take;
+          if (kWide) {
+            const float tt = ownt[p * kMaxTypes + (int)tj];
+            take = d2 < tt && qid - ownm[p] >= bpm;
+          } else {
+            take = d2 < pr.w;
+          }
+          take = take && have && q != first_local + (uint32_t)p;
+          const unsigned long long am = __ballot(take);
+          if (am == 0ull) continue;
+          const uint32_t n0 = lcnt[p];
+          if (take) {
+            const uint32_t k = n0 + (uint32_t)__popcll(am & (lanemask_le(wl) >> 1));
+            if (!own) marked = true;
+            uint32_t code = own ? (kOwn | loc) : t;
+            if (kWide) code |= tj << kTypeShift;
+            if (k < (uint32_t)kmax) {
+              kid[k * kNlistBlock + p] = (code_t)code;
+              if (sorted) kkey[k * kNlistBlock + p] = qid;
+            }
+          }
+          if (wl == 0) lcnt[p] = n0 + (uint32_t)__popcll(am);
+        }
+        if (marked) atomicOr(&bits[t >> 5], 1u << (t & 31));
+      }
+    }
+  }
+  __syncthreads();
+  // 4. the halo: rank of each marked candidate
+  uint32_t H = 0u;
+  {
+    const int w0 = 2 * lane;
+    const uint32_t p0 = __popc(bits[w0]), p1 = __popc(bits[w0 + 1]);
+    const uint32_t ex = block_scan(p0 + p1, scan_sh, H);
+    wpre[w0] = ex;
+    wpre[w0 + 1] = ex + p0;
+  }
+  __syncthreads();
+  const uint32_t hcap = (uint32_t)B.hcap;
+  for (uint32_t t = lane; t < M; t += kNlistBlock) {
+    const uint32_t w = bits[t >> 5];
+    if (!((w >> (t & 31)) & 1u)) continue;
+    const uint32_t rank = wpre[t >> 5] + __popc(w & ((1u << (t & 31)) - 1u));
+    if (rank >= hcap) continue;
+    int lo = 0, hi = kColCap;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (coff[mid] <= t)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    B.HALO[gt * (int64_t)hcap + rank] = (uint32_t)(base + cb[lo] + (t - coff[lo]));
+  }
+  if (lane == 0) {
+    B.HCNT[gt] = H;
+    // a halo beyond the capacity stops the job before its first step on these lists
+    if (H > hcap) atomicMin(&K.stop_at, (long long)J.step0);
+  }
+  const int cnt = valid ? (int)lcnt[lane] : 0;
+  int stored = 0;
+  if (valid) {
+    stored = cnt < kmax ? cnt : kmax;
+    if (sorted) {
+      // FP64 class: by particle index (insertion sort of this lane's list)
+      for (int a = 1; a < stored; ++a) {
+        const uint32_t key = kkey[a * kNlistBlock + lane];
+        const code_t code = kid[a * kNlistBlock + lane];
+        int k = a;
+        while (k > 0 && kkey[(k - 1) * kNlistBlock + lane] > key) {
+          kkey[k * kNlistBlock + lane] = kkey[(k - 1) * kNlistBlock + lane];
+          kid[k * kNlistBlock + lane] = kid[(k - 1) * kNlistBlock + lane];
+          --k;
+        }
+        kkey[k * kNlistBlock + lane] = key;
+        kid[k * kNlistBlock + lane] = code;
+      }
+    }
+    for (int k = 0; k < stored; k += kRow) {
+      uint32_t e[kRow];
+#pragma unroll
+      for (int u = 0; u < kRow; ++u) {
+        e[u] = 0u;
+        if (k + u < stored) {
+          const uint32_t code = (uint32_t)kid[(k + u) * kNlistBlock + lane];
+          const uint32_t v = code & 0xFFFFu & ~kOwn;
+          uint32_t en;
+          if (code & kOwn) {
+            en = v;
+          } else {
+            const uint32_t w = bits[v >> 5];
+            en = (uint32_t)kTile + wpre[v >> 5] + __popc(w & ((1u << (v & 31)) - 1u));
+          }
+          if (kWide) en |= (code >> kTypeShift) << kEntryTypeShift;
+          e[u] = en & 0xFFFFu;
+        }
+      }
+      store_row<kStream>(B.NL, C, k, i, e);
     }
     B.NCNT[i] = (uint32_t)stored;
   }
   // list statistics of these 64 slots (no atomics); an overflow stops the job
   // before its first step on these lists
-  uint32_t mx = (uint32_t)cnt, sm = (uint32_t)(cnt < kmax ? cnt : kmax);
+  uint32_t mx = (uint32_t)cnt, sm = (uint32_t)stored;
   for (int o = 32; o > 0; o >>= 1) {
     mx = max(mx, (uint32_t)__shfl_xor((int)mx, o, 64));
     sm += (uint32_t)__shfl_xor((int)sm, o, 64);
@@ -810,8 +709,22 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const int* __r
   if (lane % kGroup == 0 && g0 < J.off + J.n) {
     B.NLSTAT[2 * (g0 / kGroup)] = mx;
     B.NLSTAT[2 * (g0 / kGroup) + 1] = sm;
-    if ((int)mx > kmax) atomicMin(&B.book[job].stop_at, (long long)J.step0);
+    if ((int)mx > kmax) atomicMin(&K.stop_at, (long long)J.step0);
   }
+}
+
+// Dynamic LDS of k_nlist for a list capacity kmax: the kept neighbours' codes
+// (16-bit, or 32-bit plus particle indices in the wide instance).
+constexpr size_t nlist_lds_bytes(int kmax, bool wide) {
+  return (size_t)kmax * kNlistBlock * (wide ? 8 : 2);
+}
+
+// Static LDS of k_nlist (staged candidates, the tile's particles, column
+// table, halo bitmap).
+constexpr int64_t nlist_static_lds(bool wide) {
+  const int64_t staged = wide ? 20 * stage_cap<true>() : 16 * stage_cap<false>() + 4;
+  const int64_t own = 16 * kNlistBlock + (wide ? 20 * kNlistBlock : 8) + 4 * kNlistBlock;
+  return staged + own + 4 * (4 * kColCap + 1) + 8 * (kCandCap / 32) + 4 * (kNlistBlock / 64) + 4;
 }
 
 // Diagnostics of one job from the finish kernel's per-particle values (Section
@@ -874,17 +787,18 @@ __global__ void __launch_bounds__(kDiagThreads) k_diag_final(const double* __res
 }
 
 // Per-job reductions read by the host after a chunk of steps: the largest
-// per-tile displacement bound and, after list builds, the list statistics.
-// One workgroup per job record.
+// per-tile displacement bound and, after list builds, the list statistics
+// (largest list, sum of list lengths, largest tile halo).  One workgroup per
+// job record.
 constexpr int kStatsThreads = 1024;
 __global__ void __launch_bounds__(kStatsThreads) k_job_stats(DevBufs B, int with_lists) {
   __shared__ double ra[kStatsThreads / 64], rs[kStatsThreads / 64];
-  __shared__ uint32_t rm[kStatsThreads / 64];
+  __shared__ uint32_t rm[kStatsThreads / 64], rh[kStatsThreads / 64];
   const int job = blockIdx.x;
   const JobDev& J = B.jobs[job];
   if (J.n <= 0) return;
   double a = 0.0, sm = 0.0;
-  uint32_t mx = 0u;
+  uint32_t mx = 0u, hx = 0u;
   const int64_t g0 = J.off / kGroup, g1 = (J.off + J.n + kGroup - 1) / kGroup;
   // four independent loads in flight per thread (one workgroup serves a job)
   constexpr int64_t kStride = kStatsThreads;
@@ -908,28 +822,29 @@ __global__ void __launch_bounds__(kStatsThreads) k_job_stats(DevBufs B, int with
       mx = max(mx, q.x);
       sm += (double)q.y;
     }
+    const int64_t t0 = J.off / kTile, t1 = (J.off + J.n + kTile - 1) / kTile;
+    for (int64_t t = t0 + threadIdx.x; t < t1; t += kStride) hx = max(hx, B.HCNT[t]);
   }
   for (int o = 32; o > 0; o >>= 1) {
     a = fmax(a, __shfl_xor(a, o, 64));
     sm += __shfl_xor(sm, o, 64);
     mx = max(mx, (uint32_t)__shfl_xor((int)mx, o, 64));
+    hx = max(hx, (uint32_t)__shfl_xor((int)hx, o, 64));
   }
   const int w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) ra[w] = a, rs[w] = sm, rm[w] = mx;
+  if ((threadIdx.x & 63) == 0) ra[w] = a, rs[w] = sm, rm[w] = mx, rh[w] = hx;
   __syncthreads();
   if (threadIdx.x == 0) {
-    for (int q = 1; q < kStatsThreads / 64; ++q) a = fmax(a, ra[q]), sm += rs[q], mx = max(mx, rm[q]);
+    for (int q = 1; q < kStatsThreads / 64; ++q) a = fmax(a, ra[q]), sm += rs[q], mx = max(mx, rm[q]), hx = max(hx, rh[q]);
     JobBook& K = B.book[job];
     K.a_now = a;
     if (with_lists) {
       K.nl_max = (int)mx;
       K.nl_sum = sm;
+      K.halo_max = (int)hx;
     }
   }
 }
-
-// Dynamic LDS of k_nlist for a list capacity kmax.
-constexpr size_t nlist_lds_bytes(int kmax) { return (size_t)kmax * kNlistBlock * sizeof(uint32_t); }
 
 // ---------------------------------------------------------------------------
 // Segmented exclusive scan, three passes, staged in LDS.

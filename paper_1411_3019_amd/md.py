@@ -48,7 +48,8 @@ class _Diag(C.Structure):
     _fields_ = [
         ("K", C.c_double), ("U", C.c_double), ("ndof", C.c_double), ("kT", C.c_double),
         ("gdist_max", C.c_double), ("nv_max", C.c_double), ("step", C.c_int64), ("rebuilds", C.c_int64),
-        ("newton_iter_max", C.c_int), ("nlist_max", C.c_int), ("error_index", C.c_int), ("reserved", C.c_int),
+        ("newton_iter_max", C.c_int), ("nlist_max", C.c_int), ("error_index", C.c_int),
+        ("exact_sum_breaches", C.c_int), ("error_step", C.c_int64),
     ]
 
     def to_dict(self):
