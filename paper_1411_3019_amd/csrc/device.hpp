@@ -132,6 +132,8 @@ struct DevBufs {
   uint32_t* RANK;      // rank within the cell per slot
   uint32_t* INV;       // slot of each particle index after the last sort, by job offset + index
   uint32_t* SRC;       // old slot (job-relative) of each new slot during a sort
+  float4* PK;          // list-build candidates in the sorted order: FP32 position, particle index
+                       // (bead model: type in the top two bits)
   uint8_t* TYPE[2];    // bead type (jobs with a bead model); parity as ID
   const ModelDev* models;  // per job
   double* TACC;        // per group of 64 slots: accumulated max displacement since the last build

@@ -188,7 +188,13 @@ __global__ void __launch_bounds__(kTile) k_gather(DevBufs B, const int* __restri
   B.ID[sc ^ 1][d] = id;
   B.FLG[sc ^ 1][d] = flag;
   if (per_mass) B.MASS[sc ^ 1][d] = mass;
-  if (model) B.TYPE[sc ^ 1][d] = type;
+  uint32_t w = id;
+  if (model) {
+    // bead model: the type rides in the top two bits of the record's index
+    B.TYPE[sc ^ 1][d] = type;
+    w |= (uint32_t)type << kTypeShift;
+  }
+  B.PK[d] = make_float4((float)x[0], (float)x[1], (float)x[2], __uint_as_float(w));
 }
 
 // Occupied cells with raster index below r, for the compact cell index.
@@ -280,18 +286,16 @@ __device__ __forceinline__ uint32_t block_scan(uint32_t v, uint32_t* sh, uint32_
 
 // Neighbour-list build.  One workgroup per tile (256 slots of the freshly
 // sorted raster cell order), one lane per slot:
-//  1. cells: the tile's lanes of one cell are consecutive; the first lane of
-//     each cell (within a wavefront) finds the cell's 27-cell stencil as 9
-//     column pieces (runs of slots, cells (x, y, z-1..z+1) of a column) and
-//     puts their hulls into an LDS table of the tile's columns;
-//  2. the hulls' slots are numbered consecutively ("candidates") and staged
-//     in LDS as FP32 records, kStageCap at a time;
-//  3. each wavefront tests the candidates of its own cells: a cell's
-//     candidates are spread over the lanes, and the cell's particles take
-//     turns, so lanes rarely idle; kept pairs are appended to the particle's
-//     list (one wavefront owns each list, so no atomics), and a bitmap over
+//  1. the first lane of each cell (the tile's lanes of one cell are
+//     consecutive) finds the cell's 9 stencil columns and puts, per column,
+//     the hull of the slots the cell needs into an LDS table of the tile's
+//     columns; the hulls, one after another, number the tile's candidates;
+//  2. each lane walks its own 27-cell stencil (9 runs of slots, the next
+//     column's lookups in flight while the current one is scanned) over the
+//     packed FP32 candidate records, four at a time with the next four
+//     loading, and keeps the candidates inside the list radius; a bitmap over
 //     candidate numbers marks the kept ones outside the tile (the halo);
-//  4. the halo is the marked candidates in candidate order; list entries
+//  3. the halo is the marked candidates in candidate order; list entries
 //     become window indices (own slots 0..255, halo 256 + rank) and are
 //     written as 16-bit entries, with the halo list of the tile.
 // FP64 class: lists sorted by particle index (the order of the FP64 sums).
@@ -303,10 +307,6 @@ __device__ __forceinline__ uint32_t block_scan(uint32_t v, uint32_t* sh, uint32_
 constexpr int kColCap = 256;     // distinct stencil columns of one tile
 constexpr int kCandCap = 16384;  // candidates of one tile
 constexpr uint32_t kNoCol = 0xFFFFFFFFu;
-template <bool kWide>
-constexpr int stage_cap() {  // candidate records staged at a time (the wide instance keeps LDS for its lists)
-  return kWide ? 768 : 1024;
-}
 
 __device__ __forceinline__ void min_image_f(const JobDev& J, float& dx, float& dy, float& dz) {
   if (J.periodic[0]) dx -= (float)J.box_len[0] * rintf(dx * (float)J.inv_box_len[0]);
@@ -341,7 +341,7 @@ __device__ __forceinline__ int column_slot(const uint32_t* ckey, uint32_t key) {
 }
 
 // kWide: the instance for builds that include FP64-class or bead-model jobs
-// (32-bit codes; particle indices and types of the candidates staged too).
+// (32-bit codes, particle indices kept for the sort).
 // jobs, models: B.jobs and B.models as no-alias arguments (scalar loads).
 template <bool kWide, bool kStream>
 __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const JobDev* __restrict__ jobs,
@@ -352,14 +352,7 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const JobDev* 
   // their candidate number; bead model: the partner's type in the top bits
   using code_t = typename std::conditional<kWide, uint32_t, uint16_t>::type;
   constexpr uint32_t kOwn = kWide ? 0x10000u : 0x8000u;
-  constexpr int kStageCap = stage_cap<kWide>();
   extern __shared__ uint32_t dyn[];  // codes [kmax][256]; FP64 class: then particle indices [kmax][256]
-  __shared__ float4 stg[kStageCap];
-  __shared__ uint32_t stid[kWide ? kStageCap : 1];  // particle index | type << 30 of staged candidates
-  __shared__ float4 ownp[kNlistBlock];              // the tile's particles: FP32 position, list radius^2 bound
-  __shared__ float ownt[kWide ? kNlistBlock * kMaxTypes : 1];  // bead model: the same per partner type
-  __shared__ uint32_t ownm[kWide ? kNlistBlock : 1];          // first particle index of the particle's molecule
-  __shared__ uint32_t lcnt[kNlistBlock];            // neighbours found per particle
   __shared__ uint32_t ckey[kColCap], cb[kColCap], ce[kColCap], coff[kColCap + 1];
   __shared__ uint32_t bits[kCandCap / 32], wpre[kCandCap / 32];
   __shared__ uint32_t scan_sh[kNlistBlock / 64];
@@ -372,7 +365,7 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const JobDev* 
   const JobDev& J = jobs[job];
   JobBook& K = B.book[job];
   const int lane = (int)threadIdx.x;
-  const int wl = lane & 63, wb = lane & ~63;  // lane in the wavefront, first lane of the wavefront
+  const int wl = lane & 63;
   const int64_t first = uniform_i64(tile_first[tile]);
   const int64_t i = first + lane;
   const int64_t base = J.off;
@@ -395,11 +388,8 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const JobDev* 
   ckey[lane] = kNoCol;
   cb[lane] = 0xFFFFFFFFu;
   ce[lane] = 0u;
-  lcnt[lane] = 0u;
   for (int w = lane; w < kCandCap / 32; w += kNlistBlock) bits[w] = 0u;
   if (lane == 0) fail = 0;
-  // this lane's particle: position, cell, list radius (widened by a bound on
-  // the FP32 rounding of both positions and the separation)
   const double* __restrict__ X = B.X[J.xcur ^ 1];  // the sorted copies written by k_gather
   double xi = 0.0, yi = 0.0, zi = 0.0;
   int cx = 0, cy = 0, cz = 0;
@@ -411,70 +401,36 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const JobDev* 
     cy = cell_coord(J, 1, yi);
     cz = cell_coord(J, 2, zi);
   }
-  {
-    double lper = 0.0;
-    for (int k = 0; k < 3; ++k)
-      if (J.periodic[k]) lper = fmax(lper, J.box_len[k]);
-    const double rl = sqrt(J.rlist2);
-    const double delta = 0x1p-21 * (2.0 * fmax(fabs(xi), fmax(fabs(yi), fabs(zi))) + 3.0 * rl + lper);
-    ownp[lane] = make_float4((float)xi, (float)yi, (float)zi, (float)((rl + delta) * (rl + delta) * (1.0 + 0x1p-20)));
-    if (kWide) {
-      // bead model: list radius per partner type, rc_ab + skin (the rounding
-      // bound above covers the shorter radii too); partners of the same
-      // molecule are left out
-      const uint32_t myid = valid ? B.ID[J.scur ^ 1][i] : 0u;
-      const int ti = typed && valid ? (int)B.TYPE[J.scur ^ 1][i] : 0;
-      const double skin = 2.0 * J.half_skin;
-      const ModelDev& M = models[job];
-#pragma unroll
-      for (int b = 0; b < kMaxTypes; ++b) {
-        const double r = typed ? sqrt(M.rc2[ti * kMaxTypes + b]) + skin : rl;
-        ownt[lane * kMaxTypes + b] = (float)((r + delta) * (r + delta) * (1.0 + 0x1p-20));
-      }
-      const uint32_t bpm = (uint32_t)J.bpm;
-      ownm[lane] = bpm != 0u ? (myid / bpm) * bpm : 0u;
-    }
-  }
+  int za0, zb0, za1, zb1;
+  z_runs(J, cz, za0, zb0, za1, zb1);
   __syncthreads();
-  // 1. cells: runs of equal cells within the wavefront; the first lane of each
-  // run finds the cell's 9 stencil column pieces and puts their hulls in the table
-  const uint32_t rkey = valid ? raster_of(J, cx, cy, cz) : kNoKey;
-  unsigned long long heads;
-  const int rs = run_start(rkey, wl, &heads);
-  const bool is_head = valid && rs == wl;
-  uint32_t pb0[9], pe0[9], pb1[9], pe1[9], pkey[9];
+  // 1. the tile's columns: the first lane of each cell puts in its columns' hulls
   {
-    int za0, zb0, za1, zb1;
-    z_runs(J, cz, za0, zb0, za1, zb1);
-#pragma unroll
-    for (int col = 0; col < 9; ++col) {
-      pb0[col] = pe0[col] = pb1[col] = pe1[col] = 0u;
-      pkey[col] = kNoCol;
-      if (!is_head) continue;
-      const ColumnRange r = column_range(B, J, cx, cy, col, za0, zb0, za1, zb1);
-      const bool has0 = r.e0 > r.b0, has1 = r.e1 > r.b1;
-      if (r.key == kNoCol || !(has0 || has1)) continue;
-      pb0[col] = r.b0;
-      pe0[col] = r.e0;
-      pb1[col] = r.b1;
-      pe1[col] = r.e1;
-      pkey[col] = r.key;
-      uint32_t h = (r.key * 0x9E3779B1u) >> 24;
-      int found = -1;
-      for (int probe = 0; probe < kColCap; ++probe) {
-        const uint32_t old = atomicCAS(&ckey[h], kNoCol, r.key);
-        if (old == kNoCol || old == r.key) {
-          found = (int)h;
-          break;
+    const uint32_t rkey = valid ? raster_of(J, cx, cy, cz) : kNoKey;
+    unsigned long long heads;
+    const int rs = run_start(rkey, wl, &heads);
+    if (valid && rs == wl) {
+      for (int col = 0; col < 9; ++col) {
+        const ColumnRange r = column_range(B, J, cx, cy, col, za0, zb0, za1, zb1);
+        const bool has0 = r.e0 > r.b0, has1 = r.e1 > r.b1;
+        if (r.key == kNoCol || !(has0 || has1)) continue;
+        uint32_t h = (r.key * 0x9E3779B1u) >> 24;
+        int found = -1;
+        for (int probe = 0; probe < kColCap; ++probe) {
+          const uint32_t old = atomicCAS(&ckey[h], kNoCol, r.key);
+          if (old == kNoCol || old == r.key) {
+            found = (int)h;
+            break;
+          }
+          h = (h + 1u) & (kColCap - 1);
         }
-        h = (h + 1u) & (kColCap - 1);
+        if (found < 0) {
+          fail = 1;
+          continue;
+        }
+        atomicMin(&cb[found], has0 ? (has1 ? min(r.b0, r.b1) : r.b0) : r.b1);
+        atomicMax(&ce[found], has0 ? (has1 ? max(r.e0, r.e1) : r.e0) : r.e1);
       }
-      if (found < 0) {
-        fail = 1;
-        continue;
-      }
-      atomicMin(&cb[found], has0 ? (has1 ? min(r.b0, r.b1) : r.b0) : r.b1);
-      atomicMax(&ce[found], has0 ? (has1 ? max(r.e0, r.e1) : r.e0) : r.e1);
     }
   }
   __syncthreads();
@@ -486,23 +442,9 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const JobDev* 
     coff[lane] = off;
     if (lane == 0) coff[kColCap] = M;
   }
-  // the candidate-number offset of each of the head's columns (candidate = slot + off)
-  int poff[9];
-#pragma unroll
-  for (int col = 0; col < 9; ++col) {
-    poff[col] = 0;
-    if (pkey[col] == kNoCol) continue;
-    const int h = column_slot(ckey, pkey[col]);
-    if (h < 0) {
-      fail = 1;
-      pkey[col] = kNoCol;
-      continue;
-    }
-    poff[col] = (int)coff[h] - (int)cb[h];
-  }
   __syncthreads();
   if (M > (uint32_t)kCandCap || fail) {
-    // too dense for the staged build: the job stops with an error
+    // too dense for the list build: the job stops with an error
     if (lane == 0) {
       atomicOr(&K.build_fail, 1);
       atomicMin(&K.stop_at, (long long)J.step0);
@@ -515,117 +457,113 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const JobDev* 
     }
     return;
   }
-  const bool anyper = J.periodic[0] | J.periodic[1] | J.periodic[2];
-  const uint32_t bpm = (uint32_t)J.bpm;
-  const int* __restrict__ IDs = reinterpret_cast<const int*>(B.ID[J.scur ^ 1]);
-  const uint8_t* __restrict__ TYs = B.TYPE[J.scur ^ 1];
-  const unsigned long long hmask = __ballot(is_head);  // the cells of this wavefront
-  // 2./3. stage the candidates chunk by chunk; each wavefront tests its cells
-  const uint32_t nchunks = (M + kStageCap - 1) / kStageCap;
-  for (uint32_t ch = 0; ch < nchunks; ++ch) {
-    const uint32_t c0 = ch * kStageCap, c1 = min(M, c0 + kStageCap);
-    if (ch > 0) __syncthreads();  // every lane is done with the previous chunk
-    for (uint32_t t = c0 + lane; t < c1; t += kNlistBlock) {
-      // the column holding candidate t: the last table entry with coff <= t
-      int lo = 0, hi = kColCap;
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (coff[mid] <= t)
-          lo = mid;
-        else
-          hi = mid;
-      }
-      const uint32_t sl = cb[lo] + (t - coff[lo]);
-      const int64_t g = base + sl;
-      stg[t - c0] = make_float4((float)X[3 * g], (float)X[3 * g + 1], (float)X[3 * g + 2], __uint_as_float(sl));
-      if (kWide) {
-        uint32_t w = (uint32_t)IDs[g];
-        if (typed) w |= (uint32_t)TYs[g] << kTypeShift;
-        stid[t - c0] = w;
+  // 2. this lane's stencil walk
+  int cnt = 0;
+  if (valid) {
+    const bool anyper = J.periodic[0] | J.periodic[1] | J.periodic[2];
+    double lper = 0.0;
+    for (int k = 0; k < 3; ++k)
+      if (J.periodic[k]) lper = fmax(lper, J.box_len[k]);
+    const double rl = sqrt(J.rlist2);
+    const double delta = 0x1p-21 * (2.0 * fmax(fabs(xi), fmax(fabs(yi), fabs(zi))) + 3.0 * rl + lper);
+    const float thr = (float)((rl + delta) * (rl + delta) * (1.0 + 0x1p-20));
+    const float xf = (float)xi, yf = (float)yi, zf = (float)zi;
+    // bead model: list radius per partner type, rc_ab + skin (the rounding
+    // bound above covers the shorter radii too); partners of the same
+    // molecule are left out
+    float tthr[kMaxTypes];
+    const uint32_t myid = kWide ? B.ID[J.scur ^ 1][i] : 0u;
+    if (kWide) {
+      const int ti = typed ? (int)B.TYPE[J.scur ^ 1][i] : 0;
+      const double skin = 2.0 * J.half_skin;
+      const ModelDev& Mo = models[job];
+#pragma unroll
+      for (int b = 0; b < kMaxTypes; ++b) {
+        const double r = typed ? sqrt(Mo.rc2[ti * kMaxTypes + b]) + skin : rl;
+        tthr[b] = (float)((r + delta) * (r + delta) * (1.0 + 0x1p-20));
       }
     }
-    __syncthreads();
-    unsigned long long hm = hmask;
-    while (hm) {
-      const int h = __ffsll((long long)hm) - 1;  // first lane of the cell (wavefront index)
-      hm &= hm - 1ull;
-      const unsigned long long later = heads & ~lanemask_le(h);
-      const int np = (later ? __ffsll((long long)later) - 1 : 64) - h;  // particles of the cell
-      const int p0 = wb + h;                                            // its first lane in the tile
-      // the cell's candidates in this chunk: up to 18 ranges, numbered f = 0 ..
-      uint32_t rb[18], rl_[18];
-      uint32_t ncand = 0u;
-#pragma unroll
-      for (int col = 0; col < 9; ++col) {
-        const uint32_t key = (uint32_t)__builtin_amdgcn_readlane((int)pkey[col], h);
-        const int o = __builtin_amdgcn_readlane(poff[col], h);
-#pragma unroll
-        for (int piece = 0; piece < 2; ++piece) {
-          const uint32_t pb = (uint32_t)__builtin_amdgcn_readlane((int)(piece ? pb1[col] : pb0[col]), h);
-          const uint32_t pe = (uint32_t)__builtin_amdgcn_readlane((int)(piece ? pe1[col] : pe0[col]), h);
-          uint32_t tb = 0u, tl = 0u;
-          if (key != kNoCol && pe > pb) {
-            tb = max((uint32_t)((int)pb + o), c0);
-            const uint32_t te = min((uint32_t)((int)pe + o), c1);
-            tl = te > tb ? te - tb : 0u;
-          }
-          rb[2 * col + piece] = tb;
-          rl_[2 * col + piece] = tl;
-          ncand += tl;
-        }
+    const uint32_t bpm = (uint32_t)J.bpm, mstart = bpm != 0u ? (myid / bpm) * bpm : 0u;  // bpm = 0: no molecules
+    const uint32_t self = (uint32_t)(i - base);
+    const float4* __restrict__ PK = B.PK + base;
+    // keep candidate j (record r): code and list entry
+    auto keep = [&](uint32_t j, uint32_t t, uint32_t w) {
+      const uint32_t loc = j - first_local;
+      uint32_t code;
+      if (loc < (uint32_t)kTile) {
+        code = kOwn | loc;
+      } else {
+        code = t;
+        atomicOr(&bits[t >> 5], 1u << (t & 31));
       }
-      for (uint32_t f0 = 0; f0 < ncand; f0 += 64) {
-        // this lane's candidate: number t of flat index f
-        const uint32_t f = f0 + (uint32_t)wl;
-        uint32_t t = 0u, acc = 0u;
-#pragma unroll
-        for (int r = 0; r < 18; ++r) {
-          if (f >= acc && f < acc + rl_[r]) t = rb[r] + (f - acc);
-          acc += rl_[r];
+      if (kWide) code |= (w >> kTypeShift) << kTypeShift;
+      if (sorted) {
+        // insertion by particle index (the order of the FP64 sums)
+        const uint32_t qid = w & kIdMask;
+        if (cnt < kmax) {
+          int k = cnt;
+          while (k > 0 && kkey[(k - 1) * kNlistBlock + lane] > qid) {
+            kkey[k * kNlistBlock + lane] = kkey[(k - 1) * kNlistBlock + lane];
+            kid[k * kNlistBlock + lane] = kid[(k - 1) * kNlistBlock + lane];
+            --k;
+          }
+          kkey[k * kNlistBlock + lane] = qid;
+          kid[k * kNlistBlock + lane] = (code_t)code;
         }
-        const bool have = f < ncand;
-        const float4 cr = have ? stg[t - c0] : make_float4(0.f, 0.f, 0.f, 0.f);
-        const uint32_t cw = kWide && have ? stid[t - c0] : 0u;
-        const uint32_t q = __float_as_uint(cr.w);  // candidate slot (job-local)
-        const uint32_t loc = q - first_local;
-        const bool own = loc < (uint32_t)kTile;
-        const uint32_t qid = cw & kIdMask, tj = cw >> kTypeShift;
-        bool marked = false;
-        for (int pp = 0; pp < np; ++pp) {
-          const int p = p0 + pp;  // tile lane of the particle
-          const float4 pr = ownp[p];
-          float dx = pr.x - cr.x, dy = pr.y - cr.y, dz = pr.z - cr.z;
+      } else if (cnt < kmax) {
+        kid[cnt * kNlistBlock + lane] = (code_t)code;
+      }
+      ++cnt;
+    };
+    // slots [b, e) of a column whose candidate numbers are slot + o
+    auto scan = [&](uint32_t b, uint32_t e, uint32_t o) {
+      if (b >= e) return;
+      float4 nxt[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) nxt[u] = PK[min(b + u, e - 1)];
+      for (uint32_t j = b; j < e; j += 4) {
+        float4 r[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          r[u] = nxt[u];
+          nxt[u] = PK[min(j + 4 + u, e - 1)];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          float dx = xf - r[u].x, dy = yf - r[u].y, dz = zf - r[u].z;
           if (anyper) min_image_f(J, dx, dy, dz);
           const float d2 = dx * dx + dy * dy + dz * dz;
+          const uint32_t w = __float_as_uint(r[u].w);
           bool take;
           if (kWide) {
-            const float tt = ownt[p * kMaxTypes + (int)tj];
-            take = d2 < tt && qid - ownm[p] >= bpm;
+            const uint32_t tj = w >> kTypeShift;
+            const float tt = tj == 0u ? tthr[0] : (tj == 1u ? tthr[1] : (tj == 2u ? tthr[2] : tthr[3]));
+            take = d2 < tt && (w & kIdMask) - mstart >= bpm;
           } else {
-            take = d2 < pr.w;
+            take = d2 < thr;
           }
-          take = take && have && q != first_local + (uint32_t)p;
-          const unsigned long long am = __ballot(take);
-          if (am == 0ull) continue;
-          const uint32_t n0 = lcnt[p];
-          if (take) {
-            const uint32_t k = n0 + (uint32_t)__popcll(am & (lanemask_le(wl) >> 1));
-            if (!own) marked = true;
-            uint32_t code = own ? (kOwn | loc) : t;
-            if (kWide) code |= tj << kTypeShift;
-            if (k < (uint32_t)kmax) {
-              kid[k * kNlistBlock + p] = (code_t)code;
-              if (sorted) kkey[k * kNlistBlock + p] = qid;
-            }
-          }
-          if (wl == 0) lcnt[p] = n0 + (uint32_t)__popcll(am);
+          const uint32_t jj = j + u;
+          if (take && jj < e && jj != self) keep(jj, jj + o, w);
         }
-        if (marked) atomicOr(&bits[t >> 5], 1u << (t & 31));
       }
+    };
+    ColumnRange cur = column_range(B, J, cx, cy, 0, za0, zb0, za1, zb1);
+    for (int col = 0; col < 9; ++col) {
+      ColumnRange nx{0u, 0u, 0u, 0u, kNoCol};
+      if (col + 1 < 9) nx = column_range(B, J, cx, cy, col + 1, za0, zb0, za1, zb1);
+      if (cur.key != kNoCol && (cur.e0 > cur.b0 || cur.e1 > cur.b1)) {
+        const int h = column_slot(ckey, cur.key);
+        if (h >= 0) {
+          const uint32_t o = coff[h] - cb[h];  // (mod 2^32)
+          scan(cur.b0, cur.e0, o);
+          scan(cur.b1, cur.e1, o);
+        }
+      }
+      cur = nx;
     }
   }
   __syncthreads();
-  // 4. the halo: rank of each marked candidate
+  // 3. the halo: rank of each marked candidate
   uint32_t H = 0u;
   {
     const int w0 = 2 * lane;
@@ -656,25 +594,9 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const JobDev* 
     // a halo beyond the capacity stops the job before its first step on these lists
     if (H > hcap) atomicMin(&K.stop_at, (long long)J.step0);
   }
-  const int cnt = valid ? (int)lcnt[lane] : 0;
   int stored = 0;
   if (valid) {
     stored = cnt < kmax ? cnt : kmax;
-    if (sorted) {
-      // FP64 class: by particle index (insertion sort of this lane's list)
-      for (int a = 1; a < stored; ++a) {
-        const uint32_t key = kkey[a * kNlistBlock + lane];
-        const code_t code = kid[a * kNlistBlock + lane];
-        int k = a;
-        while (k > 0 && kkey[(k - 1) * kNlistBlock + lane] > key) {
-          kkey[k * kNlistBlock + lane] = kkey[(k - 1) * kNlistBlock + lane];
-          kid[k * kNlistBlock + lane] = kid[(k - 1) * kNlistBlock + lane];
-          --k;
-        }
-        kkey[k * kNlistBlock + lane] = key;
-        kid[k * kNlistBlock + lane] = code;
-      }
-    }
     for (int k = 0; k < stored; k += kRow) {
       uint32_t e[kRow];
 #pragma unroll
@@ -719,12 +641,9 @@ constexpr size_t nlist_lds_bytes(int kmax, bool wide) {
   return (size_t)kmax * kNlistBlock * (wide ? 8 : 2);
 }
 
-// Static LDS of k_nlist (staged candidates, the tile's particles, column
-// table, halo bitmap).
-constexpr int64_t nlist_static_lds(bool wide) {
-  const int64_t staged = wide ? 20 * stage_cap<true>() : 16 * stage_cap<false>() + 4;
-  const int64_t own = 16 * kNlistBlock + (wide ? 20 * kNlistBlock : 8) + 4 * kNlistBlock;
-  return staged + own + 4 * (4 * kColCap + 1) + 8 * (kCandCap / 32) + 4 * (kNlistBlock / 64) + 4;
+// Static LDS of k_nlist (column table, halo bitmap).
+constexpr int64_t nlist_static_lds(bool) {
+  return 4 * (4 * kColCap + 1) + 8 * (kCandCap / 32) + 4 * (kNlistBlock / 64) + 4;
 }
 
 // Diagnostics of one job from the finish kernel's per-particle values (Section
