@@ -210,35 +210,12 @@ __device__ __forceinline__ bool stencil_coord(const JobDev& J, int k, int c, int
   const int nc = J.nc[k];
   if (J.periodic[k]) {
     if (nc < 3 && (d < 0 || d >= nc)) return false;
-    out = (c + d + nc) % nc;
+    const int v = c + d;
+    out = v < 0 ? v + nc : (v >= nc ? v - nc : v);
     return true;
   }
   out = c + d;
   return out >= 0 && out < nc;
-}
-
-// Slot ranges (relative to the job) of one stencil column: cells (x, y, z-1..z+1),
-// split in two runs when z wraps; key identifies the column (x nc_y + y), or
-// 0xFFFFFFFF when the offset leaves a non-periodic grid.
-struct ColumnRange {
-  uint32_t b0, e0, b1, e1, key;
-};
-
-__device__ __forceinline__ ColumnRange column_range(const DevBufs& B, const JobDev& J, int cx, int cy, int col,
-                                                    int za0, int zb0, int za1, int zb1) {
-  ColumnRange r{0u, 0u, 0u, 0u, 0xFFFFFFFFu};
-  int ax, ay;
-  if (!stencil_coord(J, 0, cx, col / 3 - 1, ax) || !stencil_coord(J, 1, cy, col % 3 - 1, ay)) return r;
-  r.key = (uint32_t)ax * (uint32_t)J.nc[1] + (uint32_t)ay;
-  const int64_t base = J.off;
-  const uint32_t c0 = ((uint32_t)ax * (uint32_t)J.nc[1] + (uint32_t)ay) * (uint32_t)J.nc[2];
-  r.b0 = B.CSTART[base + cells_before(B, J, c0 + (uint32_t)za0)];
-  r.e0 = B.CSTART[base + cells_before(B, J, c0 + (uint32_t)zb0 + 1u)];
-  if (zb1 >= za1) {
-    r.b1 = B.CSTART[base + cells_before(B, J, c0 + (uint32_t)za1)];
-    r.e1 = B.CSTART[base + cells_before(B, J, c0 + (uint32_t)zb1 + 1u)];
-  }
-  return r;
 }
 
 // z cells of the stencil around cz: [za0, zb0] and, when z wraps, [za1, zb1].
@@ -258,6 +235,53 @@ __device__ __forceinline__ void z_runs(const JobDev& J, int cz, int& za0, int& z
   } else {
     za0 = cz > 0 ? cz - 1 : 0;
     zb0 = cz + 1 < ncz ? cz + 1 : ncz - 1;
+  }
+}
+
+// Key of stencil column col (0..8) of cell column (cx, cy): x nc_y + y, or
+// kNoCol off a non-periodic grid.
+__device__ __forceinline__ uint32_t column_key(const JobDev& J, int cx, int cy, int col) {
+  int ax = 0, ay = 0;
+  const bool ok = stencil_coord(J, 0, cx, col / 3 - 1, ax) & stencil_coord(J, 1, cy, col % 3 - 1, ay);
+  return ok ? (uint32_t)ax * (uint32_t)J.nc[1] + (uint32_t)ay : 0xFFFFFFFFu;
+}
+
+// Slot runs [rb, re) (relative to the job) of cells z in [za, zb] of the 9
+// stencil columns of (cx, cy), looked up three columns at a time (their loads
+// in flight together); an off-grid column gives an empty run.
+__device__ __forceinline__ void column_runs9(const DevBufs& B, const JobDev& J, int cx, int cy, int za, int zb,
+                                             uint32_t* rb, uint32_t* re) {
+  const int64_t base = J.off;
+  const uint32_t ncy = (uint32_t)J.nc[1], ncz = (uint32_t)J.nc[2];
+#pragma unroll
+  for (int g = 0; g < 9; g += 3) {
+    uint32_t ra[3], rz[3], bma[3], bmz[3], woa[3], woz[3];
+    bool ok[3];
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      const int col = g + u;
+      int ax = 0, ay = 0;
+      ok[u] = stencil_coord(J, 0, cx, col / 3 - 1, ax) & stencil_coord(J, 1, cy, col % 3 - 1, ay);
+      if (!ok[u]) ax = 0, ay = 0;  // looks up column (0, 0), dropped below
+      const uint32_t c0 = ((uint32_t)ax * ncy + (uint32_t)ay) * ncz;
+      ra[u] = c0 + (uint32_t)za;
+      rz[u] = c0 + (uint32_t)zb + 1u;
+      const int64_t wa = J.bm_off + (ra[u] >> 5), wz = J.bm_off + (rz[u] >> 5);
+      bma[u] = B.BM[wa];
+      woa[u] = B.WOFF[wa];
+      bmz[u] = B.BM[wz];
+      woz[u] = B.WOFF[wz];
+    }
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      const uint32_t ia = woa[u] + __popc(bma[u] & ((1u << (ra[u] & 31)) - 1u));
+      const uint32_t iz = woz[u] + __popc(bmz[u] & ((1u << (rz[u] & 31)) - 1u));
+      rb[g + u] = B.CSTART[base + ia];
+      re[g + u] = B.CSTART[base + iz];
+    }
+#pragma unroll
+    for (int u = 0; u < 3; ++u)
+      if (!ok[u]) re[g + u] = rb[g + u];
   }
 }
 
@@ -286,18 +310,21 @@ __device__ __forceinline__ uint32_t block_scan(uint32_t v, uint32_t* sh, uint32_
 
 // Neighbour-list build.  One workgroup per tile (256 slots of the freshly
 // sorted raster cell order), one lane per slot:
+//  0. each lane looks up the slot runs of its 9 stencil columns (cells z-1..z+1
+//     of each; three columns' lookups in flight together) and keeps them in
+//     registers;
 //  1. the first lane of each cell (the tile's lanes of one cell are
-//     consecutive) finds the cell's 9 stencil columns and puts, per column,
-//     the hull of the slots the cell needs into an LDS table of the tile's
-//     columns; the hulls, one after another, number the tile's candidates;
-//  2. each lane walks its own 27-cell stencil (9 runs of slots, the next
-//     column's lookups in flight while the current one is scanned) over the
-//     packed FP32 candidate records, four at a time with the next four
-//     loading, and keeps the candidates inside the list radius; a bitmap over
-//     candidate numbers marks the kept ones outside the tile (the halo);
-//  3. the halo is the marked candidates in candidate order; list entries
-//     become window indices (own slots 0..255, halo 256 + rank) and are
-//     written as 16-bit entries, with the halo list of the tile.
+//     consecutive) puts, per column, the hull of the slots the cell needs
+//     into an LDS table of the tile's columns; the hulls, one after another,
+//     number the tile's candidates;
+//  2. each lane walks its 9 runs over the packed FP32 candidate records, four
+//     at a time with the next four loading, and appends the candidates inside
+//     the list radius without branching (a rejected candidate is overwritten
+//     by the next one);
+//  3. kept candidates outside the tile are marked in a bitmap over candidate
+//     numbers; the halo is the marked candidates in candidate order; list
+//     entries become window indices (own slots 0..255, halo 256 + rank) and
+//     are written as 16-bit entries, with the halo list of the tile.
 // FP64 class: lists sorted by particle index (the order of the FP64 sums).
 // FP32 class: lists in the order found.
 // The FP32 distance test uses the list radius widened by a bound on the FP32
@@ -308,10 +335,12 @@ constexpr int kColCap = 256;     // distinct stencil columns of one tile
 constexpr int kCandCap = 16384;  // candidates of one tile
 constexpr uint32_t kNoCol = 0xFFFFFFFFu;
 
-__device__ __forceinline__ void min_image_f(const JobDev& J, float& dx, float& dy, float& dz) {
-  if (J.periodic[0]) dx -= (float)J.box_len[0] * rintf(dx * (float)J.inv_box_len[0]);
-  if (J.periodic[1]) dy -= (float)J.box_len[1] * rintf(dy * (float)J.inv_box_len[1]);
-  if (J.periodic[2]) dz -= (float)J.box_len[2] * rintf(dz * (float)J.inv_box_len[2]);
+// FP32 minimum image with box lengths L and inverses iL (both 0 along a
+// non-periodic axis, where the correction vanishes).
+__device__ __forceinline__ void min_image_f(const float* L, const float* iL, float& dx, float& dy, float& dz) {
+  dx = fmaf(-L[0], rintf(dx * iL[0]), dx);
+  dy = fmaf(-L[1], rintf(dy * iL[1]), dy);
+  dz = fmaf(-L[2], rintf(dz * iL[2]), dz);
 }
 
 // One row of a list (entries k .. k+7 of slot i).  Streaming (as the step's
@@ -352,14 +381,16 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const JobDev* 
   // their candidate number; bead model: the partner's type in the top bits
   using code_t = typename std::conditional<kWide, uint32_t, uint16_t>::type;
   constexpr uint32_t kOwn = kWide ? 0x10000u : 0x8000u;
-  extern __shared__ uint32_t dyn[];  // codes [kmax][256]; FP64 class: then particle indices [kmax][256]
+  // codes [kmax + 1][256] (row kmax takes the appends beyond the capacity);
+  // wide instance: then particle indices [kmax][256]
+  extern __shared__ uint32_t dyn[];
   __shared__ uint32_t ckey[kColCap], cb[kColCap], ce[kColCap], coff[kColCap + 1];
   __shared__ uint32_t bits[kCandCap / 32], wpre[kCandCap / 32];
   __shared__ uint32_t scan_sh[kNlistBlock / 64];
   __shared__ int fail;
   const int kmax = B.kmax;
   code_t* kid = reinterpret_cast<code_t*>(dyn);
-  uint32_t* kkey = dyn + ((size_t)kmax * kNlistBlock * sizeof(code_t) + 3) / 4;
+  uint32_t* kkey = dyn + ((size_t)(kmax + 1) * kNlistBlock * sizeof(code_t) + 3) / 4;
   const int tile = (int)blockIdx.x;
   const int job = uniform_int(tile_job[tile]);
   const JobDev& J = jobs[job];
@@ -404,21 +435,41 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const JobDev* 
   int za0, zb0, za1, zb1;
   z_runs(J, cz, za0, zb0, za1, zb1);
   __syncthreads();
+  // the lane's 9 stencil columns: run 0 (z in [za0, zb0]) of each; when z
+  // wraps there is a second run (z in [za1, zb1]), looked up where needed
+  const bool wrap = valid && zb1 >= za1;
+  uint32_t rb[9], re[9];
+  column_runs9(B, J, cx, cy, za0, zb0, rb, re);
   // 1. the tile's columns: the first lane of each cell puts in its columns' hulls
   {
     const uint32_t rkey = valid ? raster_of(J, cx, cy, cz) : kNoKey;
     unsigned long long heads;
     const int rs = run_start(rkey, wl, &heads);
     if (valid && rs == wl) {
+      uint32_t lo[9], hi[9];
+#pragma unroll
+      for (int col = 0; col < 9; ++col) lo[col] = rb[col], hi[col] = re[col];
+      if (wrap) {
+        uint32_t b1[9], e1[9];
+        column_runs9(B, J, cx, cy, za1, zb1, b1, e1);
+#pragma unroll
+        for (int col = 0; col < 9; ++col) {
+          if (e1[col] <= b1[col]) continue;
+          if (hi[col] <= lo[col])
+            lo[col] = b1[col], hi[col] = e1[col];
+          else
+            lo[col] = min(lo[col], b1[col]), hi[col] = max(hi[col], e1[col]);
+        }
+      }
+#pragma unroll
       for (int col = 0; col < 9; ++col) {
-        const ColumnRange r = column_range(B, J, cx, cy, col, za0, zb0, za1, zb1);
-        const bool has0 = r.e0 > r.b0, has1 = r.e1 > r.b1;
-        if (r.key == kNoCol || !(has0 || has1)) continue;
-        uint32_t h = (r.key * 0x9E3779B1u) >> 24;
+        if (hi[col] <= lo[col]) continue;
+        const uint32_t key = column_key(J, cx, cy, col);
+        uint32_t h = (key * 0x9E3779B1u) >> 24;
         int found = -1;
         for (int probe = 0; probe < kColCap; ++probe) {
-          const uint32_t old = atomicCAS(&ckey[h], kNoCol, r.key);
-          if (old == kNoCol || old == r.key) {
+          const uint32_t old = atomicCAS(&ckey[h], kNoCol, key);
+          if (old == kNoCol || old == key) {
             found = (int)h;
             break;
           }
@@ -428,8 +479,8 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const JobDev* 
           fail = 1;
           continue;
         }
-        atomicMin(&cb[found], has0 ? (has1 ? min(r.b0, r.b1) : r.b0) : r.b1);
-        atomicMax(&ce[found], has0 ? (has1 ? max(r.e0, r.e1) : r.e0) : r.e1);
+        atomicMin(&cb[found], lo[col]);
+        atomicMax(&ce[found], hi[col]);
       }
     }
   }
@@ -460,10 +511,14 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const JobDev* 
   // 2. this lane's stencil walk
   int cnt = 0;
   if (valid) {
-    const bool anyper = J.periodic[0] | J.periodic[1] | J.periodic[2];
+    const bool anyper = uniform_int(J.periodic[0] | J.periodic[1] | J.periodic[2]) != 0;
     double lper = 0.0;
-    for (int k = 0; k < 3; ++k)
+    float pL[3], piL[3];
+    for (int k = 0; k < 3; ++k) {
       if (J.periodic[k]) lper = fmax(lper, J.box_len[k]);
+      pL[k] = J.periodic[k] ? (float)J.box_len[k] : 0.0f;
+      piL[k] = J.periodic[k] ? (float)J.inv_box_len[k] : 0.0f;
+    }
     const double rl = sqrt(J.rlist2);
     const double delta = 0x1p-21 * (2.0 * fmax(fabs(xi), fmax(fabs(yi), fabs(zi))) + 3.0 * rl + lper);
     const float thr = (float)((rl + delta) * (rl + delta) * (1.0 + 0x1p-20));
@@ -484,54 +539,30 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const JobDev* 
       }
     }
     const uint32_t bpm = (uint32_t)J.bpm, mstart = bpm != 0u ? (myid / bpm) * bpm : 0u;  // bpm = 0: no molecules
-    const uint32_t self = (uint32_t)(i - base);
     const float4* __restrict__ PK = B.PK + base;
-    // keep candidate j (record r): code and list entry
-    auto keep = [&](uint32_t j, uint32_t t, uint32_t w) {
-      const uint32_t loc = j - first_local;
-      uint32_t code;
-      if (loc < (uint32_t)kTile) {
-        code = kOwn | loc;
-      } else {
-        code = t;
-        atomicOr(&bits[t >> 5], 1u << (t & 31));
-      }
-      if (kWide) code |= (w >> kTypeShift) << kTypeShift;
-      if (sorted) {
-        // insertion by particle index (the order of the FP64 sums)
-        const uint32_t qid = w & kIdMask;
-        if (cnt < kmax) {
-          int k = cnt;
-          while (k > 0 && kkey[(k - 1) * kNlistBlock + lane] > qid) {
-            kkey[k * kNlistBlock + lane] = kkey[(k - 1) * kNlistBlock + lane];
-            kid[k * kNlistBlock + lane] = kid[(k - 1) * kNlistBlock + lane];
-            --k;
-          }
-          kkey[k * kNlistBlock + lane] = qid;
-          kid[k * kNlistBlock + lane] = (code_t)code;
-        }
-      } else if (cnt < kmax) {
-        kid[cnt * kNlistBlock + lane] = (code_t)code;
-      }
-      ++cnt;
-    };
-    // slots [b, e) of a column whose candidate numbers are slot + o
-    auto scan = [&](uint32_t b, uint32_t e, uint32_t o) {
+    const uint32_t loc0 = 0u - first_local;  // own-tile index of job slot 0 (mod 2^32)
+    // slots [b, e) of a column whose candidate numbers are slot + o; reads up
+    // to 7 records past e (the record array is padded for that)
+    // f0..f3: the records of slots b .. b + 3, loaded ahead
+    auto scan = [&](uint32_t b, uint32_t e, uint32_t o, float4 f0, float4 f1, float4 f2, float4 f3) {
       if (b >= e) return;
-      float4 nxt[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) nxt[u] = PK[min(b + u, e - 1)];
-      for (uint32_t j = b; j < e; j += 4) {
+      const float4* q = PK + b;
+      float4 nxt[4] = {f0, f1, f2, f3};
+      int rem = (int)(e - b);
+      uint32_t t = b + o;
+      uint32_t loc = b + loc0;
+      while (rem > 0) {
         float4 r[4];
+        q += 4;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           r[u] = nxt[u];
-          nxt[u] = PK[min(j + 4 + u, e - 1)];
+          nxt[u] = q[u];
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           float dx = xf - r[u].x, dy = yf - r[u].y, dz = zf - r[u].z;
-          if (anyper) min_image_f(J, dx, dy, dz);
+          if (anyper) min_image_f(pL, piL, dx, dy, dz);
           const float d2 = dx * dx + dy * dy + dz * dz;
           const uint32_t w = __float_as_uint(r[u].w);
           bool take;
@@ -542,28 +573,65 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const JobDev* 
           } else {
             take = d2 < thr;
           }
-          const uint32_t jj = j + u;
-          if (take && jj < e && jj != self) keep(jj, jj + o, w);
+          take = take && u < rem && loc + u != (uint32_t)lane;
+          const bool own = loc + u < (uint32_t)kTile;
+          uint32_t code = own ? kOwn | (loc + u) : t + u;
+          if (kWide) code |= (w >> kTypeShift) << kTypeShift;
+          if (sorted) {
+            // insertion by particle index (the order of the FP64 sums)
+            if (take && cnt < kmax) {
+              const uint32_t qid = w & kIdMask;
+              int k = cnt;
+              while (k > 0 && kkey[(k - 1) * kNlistBlock + lane] > qid) {
+                kkey[k * kNlistBlock + lane] = kkey[(k - 1) * kNlistBlock + lane];
+                kid[k * kNlistBlock + lane] = kid[(k - 1) * kNlistBlock + lane];
+                --k;
+              }
+              kkey[k * kNlistBlock + lane] = qid;
+              kid[k * kNlistBlock + lane] = (code_t)code;
+            }
+          } else {
+            kid[min(cnt, kmax) * kNlistBlock + lane] = (code_t)code;
+          }
+          cnt += take ? 1 : 0;
         }
+        rem -= 4;
+        t += 4u;
+        loc += 4u;
       }
     };
-    ColumnRange cur = column_range(B, J, cx, cy, 0, za0, zb0, za1, zb1);
+    // the 9 columns, unrolled (their runs stay in registers)
+#pragma unroll
     for (int col = 0; col < 9; ++col) {
-      ColumnRange nx{0u, 0u, 0u, 0u, kNoCol};
-      if (col + 1 < 9) nx = column_range(B, J, cx, cy, col + 1, za0, zb0, za1, zb1);
-      if (cur.key != kNoCol && (cur.e0 > cur.b0 || cur.e1 > cur.b1)) {
-        const int h = column_slot(ckey, cur.key);
-        if (h >= 0) {
-          const uint32_t o = coff[h] - cb[h];  // (mod 2^32)
-          scan(cur.b0, cur.e0, o);
-          scan(cur.b1, cur.e1, o);
-        }
+      if (re[col] > rb[col]) {
+        const int h = column_slot(ckey, column_key(J, cx, cy, col));
+        const uint32_t o = coff[h] - cb[h];  // (mod 2^32)
+        scan(rb[col], re[col], o, PK[rb[col]], PK[rb[col] + 1], PK[rb[col] + 2], PK[rb[col] + 3]);
       }
-      cur = nx;
+    }
+    if (wrap) {
+      // the second z-runs (periodic z, a cell at either end)
+      uint32_t b1[9], e1[9];
+      column_runs9(B, J, cx, cy, za1, zb1, b1, e1);
+      for (int col = 0; col < 9; ++col) {
+        if (e1[col] <= b1[col]) continue;
+        const int h = column_slot(ckey, column_key(J, cx, cy, col));
+        const uint32_t o = coff[h] - cb[h];
+        scan(b1[col], e1[col], o, PK[b1[col]], PK[b1[col] + 1], PK[b1[col] + 2], PK[b1[col] + 3]);
+      }
+    }
+  }
+  // 3. the halo: kept candidates outside the tile, marked in the bitmap,
+  // ranked in candidate order
+  const int stored = valid ? (cnt < kmax ? cnt : kmax) : 0;
+  for (int k = 0; k < stored; ++k) {
+    const uint32_t code = (uint32_t)kid[k * kNlistBlock + lane];
+    if (!(code & kOwn)) {
+      const uint32_t v = code & 0xFFFFu;
+      atomicOr(&bits[v >> 5], 1u << (v & 31));
     }
   }
   __syncthreads();
-  // 3. the halo: rank of each marked candidate
   uint32_t H = 0u;
   {
     const int w0 = 2 * lane;
@@ -594,9 +662,7 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const JobDev* 
     // a halo beyond the capacity stops the job before its first step on these lists
     if (H > hcap) atomicMin(&K.stop_at, (long long)J.step0);
   }
-  int stored = 0;
   if (valid) {
-    stored = cnt < kmax ? cnt : kmax;
     for (int k = 0; k < stored; k += kRow) {
       uint32_t e[kRow];
 #pragma unroll
@@ -636,9 +702,10 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const JobDev* 
 }
 
 // Dynamic LDS of k_nlist for a list capacity kmax: the kept neighbours' codes
-// (16-bit, or 32-bit plus particle indices in the wide instance).
+// (16-bit, or 32-bit plus particle indices in the wide instance), with one
+// spare row of codes.
 constexpr size_t nlist_lds_bytes(int kmax, bool wide) {
-  return (size_t)kmax * kNlistBlock * (wide ? 8 : 2);
+  return (size_t)(kmax + 1) * kNlistBlock * (wide ? 4 : 2) + (wide ? (size_t)kmax * kNlistBlock * 4 : 0);
 }
 
 // Static LDS of k_nlist (column table, halo bitmap).
