@@ -266,6 +266,18 @@ int md_get_state(md_ctx* ctx, double* x, double* p, double* fcomb, int64_t* step
  * stream, complete when the call returns; step and diag are host pointers. */
 int md_get_state_dev(md_ctx* ctx, double* x, double* p, double* fcomb, int64_t* step, md_diag* diag);
 
+/* md_get_state_dev for callers that cannot allocate memory (code under HIP
+ * graph capture, serving loops, harnesses that forbid hipMalloc): same
+ * arguments, results and bits as md_get_state_dev, but the call allocates and
+ * frees no device or pinned host memory.  The diagnostics reduction works in a
+ * static device array of 8224 bytes (the partials of at most 256 blocks and
+ * the four sums; every job size fits), one per device, held until the
+ * process ends; calls on one device share it, so calls that overlap on one
+ * device (several contexts on different streams) race.  MD_ENOMEM if the
+ * call would need larger neighbour-list capacity than the context holds (a
+ * list build is due and the lists outgrew it); md_get_state_dev grows it. */
+int md_get_state_dev_noalloc(md_ctx* ctx, double* x, double* p, double* fcomb, int64_t* step, md_diag* diag);
+
 /* Counters and event-timed GPU work of this context (see md_stats). */
 int md_get_stats(md_ctx* ctx, md_stats* stats);
 

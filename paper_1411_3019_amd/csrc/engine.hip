@@ -22,6 +22,7 @@
 #include <cstring>
 #include <limits>
 #include <map>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -347,6 +348,38 @@ struct GraphKey {
   bool operator<(const GraphKey& o) const { return k < o.k; }
 };
 
+// Scratch of md_get_state_dev_noalloc: the per-block partials of the
+// diagnostics reduction (at most kDiagBlocks blocks) and its four results,
+// 8224 bytes.  Each device holds its own copy until the process ends; every
+// call on a device uses that copy, so such calls must not overlap on one
+// device.  Nothing in it needs clearing: each call writes every partial it
+// reads.
+constexpr int kScratchDoubles = 4 * kDiagBlocks + 4;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+// Device address of `scratch` per device ordinal (the array's name is a host
+// stand-in, not a device address), looked up once per device with that
+// device current.
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+double* scratch_dev[kMaxDevices] = {};
+
+int scratch_address(int dev, double** out) {
+  *out = nullptr;
+  if (dev < 0 || dev >= kMaxDevices) return MD_EINVAL;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_dev[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return MD_EHIP;
+    }
+    scratch_dev[dev] = (double*)ptr;
+  }
+  *out = scratch_dev[dev];
+  return MD_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -382,6 +415,8 @@ struct Engine {
   Chunk* chunks_d = nullptr;
   uint32_t* chunk_sums = nullptr;
   double* diag_d = nullptr;  // [4 kDiagBlocks] partials, then [4] results
+  double* scratch_d = nullptr;  // this device's `scratch` (md_get_state_dev_noalloc)
+  bool no_alloc = false;        // set during md_get_state_dev_noalloc: device and pinned allocations fail
   int64_t chunk_cap = 0;
   Range* ranges_d = nullptr;
   int64_t range_cap = 0;
@@ -451,6 +486,7 @@ struct Engine {
   template <class T>
   int dalloc(T** p, size_t count) {
     *p = nullptr;
+    if (no_alloc) return MD_ENOMEM;
     if (count == 0) count = 1;
     if (hipMalloc((void**)p, count * sizeof(T)) != hipSuccess) {
       (void)hipGetLastError();
@@ -463,6 +499,7 @@ struct Engine {
   int init(int dev, void* user_stream, int64_t slot_cap, int64_t word_cap, int njobs) {
     device = dev;
     HIPCHK(hipSetDevice(dev));
+    MDCHK(scratch_address(dev, &scratch_d));
     if (user_stream) {
       stream = (hipStream_t)user_stream;
       own_stream = false;
@@ -588,6 +625,7 @@ struct Engine {
     }
     MDCHK(sync());
     if (bytes > stage_cap) {
+      if (no_alloc) return MD_ENOMEM;
       if (stage) (void)hipHostFree(stage);
       stage = nullptr;
       stage_cap = 0;
@@ -613,6 +651,7 @@ struct Engine {
   int ensure_stage(size_t bytes) {
     MDCHK(sync());
     if (bytes > stage_cap) {
+      if (no_alloc) return MD_ENOMEM;
       if (stage) (void)hipHostFree(stage);
       stage = nullptr;
       stage_cap = 0;
@@ -1313,7 +1352,11 @@ struct Engine {
   // State at the current step by particle index.  dev: x, p, f are device
   // pointers (filled by device-to-device copies on the library's stream),
   // else host pointers; any may be NULL.
-  int finish(int j, double* x, double* p, double* f, md_diag* diag, bool dev = false) {
+  // noalloc (with dev): the reduction works in `scratch` and the four results
+  // come back through the pinned arena; no device or pinned host memory is
+  // allocated (a list build that would need more capacity fails with
+  // MD_ENOMEM instead of growing it).
+  int finish(int j, double* x, double* p, double* f, md_diag* diag, bool dev = false, bool noalloc = false) {
     HostJob& h = jobs[j];
     if (!h.used) return MD_ENOTFOUND;
     if (h.n == 0) {
@@ -1342,19 +1385,30 @@ struct Engine {
                          aux_tiles_first);
     const int64_t n = h.n;
     const int nb = (int)std::min<int64_t>(kDiagBlocks, (n + kDiagThreads - 1) / kDiagThreads);
-    hipLaunchKernelGGL(k_diag_partial, dim3(nb), dim3(kDiagThreads), 0, stream, B.OD, (int64_t)C, h.off, n, diag_d);
-    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(kDiagThreads), 0, stream, diag_d, nb, diag_d + 4 * kDiagBlocks);
+    double* part = noalloc ? scratch_d : diag_d;
+    if (nb > kDiagBlocks) return MD_EINVAL;  // the partials would not fit `scratch` (cannot happen: nb is capped)
+    hipLaunchKernelGGL(k_diag_partial, dim3(nb), dim3(kDiagThreads), 0, stream, B.OD, (int64_t)C, h.off, n, part);
+    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(kDiagThreads), 0, stream, part, nb, part + 4 * kDiagBlocks);
     HIPCHK(hipGetLastError());
     const size_t vb = sizeof(double) * 3 * n;
-    MDCHK(ensure_stage(3 * vb + 4 * sizeof(double)));
-    double* st = (double*)stage;
+    double* st = nullptr;  // host copies (host variant) and the four results
+    double* red_h = nullptr;
+    if (noalloc) {
+      if (arena_used + 256 > kArenaBytes) MDCHK(sync());
+      red_h = (double*)(arena + arena_used);
+      arena_used += 256;
+    } else {
+      MDCHK(ensure_stage(3 * vb + 4 * sizeof(double)));
+      st = (double*)stage;
+      red_h = st + 9 * n;
+    }
     const hipMemcpyKind kind = dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     double* dst[3] = {dev ? x : st, dev ? p : st + 3 * n, dev ? f : st + 6 * n};
     const double* src[3] = {B.OX + 3 * h.off, B.OP + 3 * h.off, B.OF + 3 * h.off};
     const bool want[3] = {x != nullptr, p != nullptr, f != nullptr};
     for (int k = 0; k < 3; ++k)
       if (want[k]) HIPCHK(hipMemcpyAsync(dst[k], src[k], vb, kind, stream));
-    HIPCHK(hipMemcpyAsync(st + 9 * n, diag_d + 4 * kDiagBlocks, 4 * sizeof(double), hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipMemcpyAsync(red_h, part + 4 * kDiagBlocks, 4 * sizeof(double), hipMemcpyDeviceToHost, stream));
     MDCHK(sync());
     if (!dev) {
       if (x) std::memcpy(x, st, vb);
@@ -1362,7 +1416,7 @@ struct Engine {
       if (f) std::memcpy(f, st + 6 * n, vb);
     }
     if (diag) {
-      const double* red = st + 9 * n;
+      const double* red = red_h;
       const double K = red[0], U = red[1], gd = red[2], nv = red[3], ndof = h.ndof;
       std::memset(diag, 0, sizeof(*diag));
       diag->K = K;
@@ -1632,6 +1686,19 @@ int md_get_state_dev(md_ctx* ctx, double* x, double* p, double* fcomb, int64_t* 
   Engine* e = ctx->eng;
   if (step) *step = e->jobs[ctx->job].step;
   return e->finish(ctx->job, x, p, fcomb, diag, true);
+}
+
+int md_get_state_dev_noalloc(md_ctx* ctx, double* x, double* p, double* fcomb, int64_t* step, md_diag* diag) {
+  if (!ctx) return MD_EINVAL;
+  if (!ctx->have_particles) return MD_ESTATE;
+  Engine* e = ctx->eng;
+  if (!e->scratch_d) return MD_EHIP;
+  HIPCHK(hipSetDevice(ctx->prm.device));
+  if (step) *step = e->jobs[ctx->job].step;
+  e->no_alloc = true;
+  const int rc = e->finish(ctx->job, x, p, fcomb, diag, true, true);
+  e->no_alloc = false;
+  return rc;
 }
 
 int md_set_particles_dev(md_ctx* ctx, int64_t n, const double* x, const double* p, const double* mass,

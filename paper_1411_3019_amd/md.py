@@ -23,7 +23,8 @@ MD_OK, MD_EINVAL, MD_ESTATE, MD_EOFFSURF, MD_ENEWTON, MD_ENAN, MD_ENOMEM, MD_EAG
 SYMBOLS = ["md_create", "md_set_surface", "md_set_particles", "md_step", "md_get_state", "md_destroy",
            "md_strerror", "md_job_footprint", "md_pool_create", "md_pool_admit", "md_pool_run", "md_pool_poll",
            "md_pool_fetch", "md_pool_release", "md_pool_usage", "md_pool_destroy", "md_get_stats",
-           "md_pool_get_stats", "md_tune", "md_set_model", "md_set_particles_dev", "md_get_state_dev"]
+           "md_pool_get_stats", "md_tune", "md_set_model", "md_set_particles_dev", "md_get_state_dev",
+           "md_get_state_dev_noalloc"]
 MD_MAX_TYPES = 4
 
 
@@ -185,6 +186,7 @@ def lib():
         L.md_set_model.argtypes = [vp, C.POINTER(_Model), u8, C.c_int64]
         L.md_set_particles_dev.argtypes = [vp, C.c_int64, vp, vp, vp, vp, vp, C.c_int64]
         L.md_get_state_dev.argtypes = [vp, vp, vp, vp, C.POINTER(C.c_int64), C.POINTER(_Diag)]
+        L.md_get_state_dev_noalloc.argtypes = [vp, vp, vp, vp, C.POINTER(C.c_int64), C.POINTER(_Diag)]
         L.md_step.argtypes = [vp, C.c_int64]
         L.md_get_state.argtypes = [vp, dp, dp, dp, C.POINTER(C.c_int64), C.POINTER(_Diag)]
         L.md_destroy.argtypes = [vp]
@@ -204,7 +206,7 @@ def lib():
         L.md_pool_destroy.argtypes = [vp]
         L.md_pool_destroy.restype = None
         for name in ("md_create", "md_set_surface", "md_set_particles", "md_set_model", "md_step", "md_get_state",
-                     "md_set_particles_dev", "md_get_state_dev",
+                     "md_set_particles_dev", "md_get_state_dev", "md_get_state_dev_noalloc",
                      "md_pool_create", "md_pool_admit", "md_pool_run", "md_pool_poll", "md_pool_fetch",
                      "md_pool_release", "md_pool_usage", "md_get_stats", "md_pool_get_stats", "md_tune"):
             getattr(L, name).restype = C.c_int
@@ -297,6 +299,15 @@ class System:
         step = C.c_int64(0)
         d = _Diag()
         _check(lib().md_get_state_dev(self._h, x_ptr, p_ptr, fcomb_ptr, C.byref(step), C.byref(d)), "md_get_state_dev")
+        return dict(step=step.value, diag=d.to_dict())
+
+    def get_state_dev_noalloc(self, x_ptr: int | None, p_ptr: int | None, fcomb_ptr: int | None = None):
+        """md_get_state_dev_noalloc into device addresses (allocates no device
+        memory); returns step and diagnostics."""
+        step = C.c_int64(0)
+        d = _Diag()
+        _check(lib().md_get_state_dev_noalloc(self._h, x_ptr, p_ptr, fcomb_ptr, C.byref(step), C.byref(d)),
+               "md_get_state_dev_noalloc")
         return dict(step=step.value, diag=d.to_dict())
 
     def step(self, nsteps: int):
