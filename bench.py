@@ -43,8 +43,9 @@ def log(*a):
 
 
 def kernel_source_hash() -> str:
+    """Hash of the step kernel's sources (the counter summary is keyed on it)."""
     h = hashlib.sha256()
-    for f in ("device.hpp", "kernels.hpp"):
+    for f in ("device.hpp", "step.hpp", "launch.hpp", "step_f32.hip", "step_f32_hi.hip"):
         with open(os.path.join(ROOT, "paper_1411_3019_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -61,11 +62,14 @@ def device_sync():
 
 
 def step_kernel_bytes(nl_mean: float) -> float:
-    """Algorithmic bytes per particle-step of the fused step kernel:
-    x^m read + x^{m+1} write (48), p read + write (48), particle index (4),
-    constraint flag (1), neighbour count (4), neighbour indices (4 per entry).
-    Neighbour positions are re-reads of x^m served by the caches (counted 0)."""
-    return 48.0 + 48.0 + 4.0 + 1.0 + 4.0 + 4.0 * nl_mean
+    """Algorithmic bytes per particle-step of the fused FP32-class step kernel
+    (uniform masses, gamma > 0): x^m read + x^{m+1} write (48), p read + write
+    (48), particle index (4), constraint flag (1), neighbour count (4), list
+    entries (2 per entry, 16-bit), the carried random force read and written
+    (FP32, 12 + 12).  Neighbour positions are re-reads of x^m served by LDS and
+    the caches (counted 0); the tile's halo list (about 6 bytes per particle)
+    is overhead of the layout, not counted."""
+    return 48.0 + 48.0 + 4.0 + 1.0 + 4.0 + 2.0 * nl_mean + 24.0
 
 
 def traffic_for(n: int, launches_key: str):
@@ -79,6 +83,78 @@ def traffic_for(n: int, launches_key: str):
     if t.get("kernel_source_sha") != kernel_source_hash() or t.get("n") != n:
         return None
     return t.get("hbm_bytes_per_launch")
+
+
+def cpu_model() -> str:
+    """CPU model name of this host (from /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_timing(s, run, steps: int, budget_s: float = 10.0):
+    """The FP64 oracle on the host: particle-steps/s and microseconds per step
+    over up to `steps` full steps (fewer if the budget runs out)."""
+    from oracle import oracle as o
+    P = o.Params(dt=run["dt"], kT=run["kT"], gamma=run["gamma"], eps=run.get("eps", 1.0),
+                 sigma=run.get("sigma", 1.0), rc=run["rc"], pair=run["pair"], surface=s.surface, surf=s.surf,
+                 seed=run["seed"], use_cells=1)
+    st = o.State(P, s.x, s.p)
+    done, t = 0, 0.0
+    chunk = max(1, min(steps, 50))
+    while done < steps and t < budget_s:
+        k = min(chunk, steps - done)
+        t0 = time.perf_counter()
+        st.run(k)
+        t += time.perf_counter() - t0
+        done += k
+    return {"particle_steps_per_s": s.n * done / t, "us_per_step": t * 1e6 / done, "steps": done,
+            "cores": o.threads()}
+
+
+def config1_bench():
+    """1000 WCA particles on a sphere R = 14.4 (area fraction 0.3), FP64 forces,
+    gamma 1, kT 1, dt 0.001: all 1000 steps on the GPU (one system, the first
+    list build included) and on the FP64 oracle."""
+    from workloads import gen
+    s, run = gen.sphere_wca_1000()
+    g = timed_steps(s, run, 0.3, 1000, 0)
+    cpu = oracle_timing(s, run, 1000, budget_s=20.0)
+    res = {"workload": "1000 WCA particles on a sphere R=14.4, fp64 forces, dt 0.001, 1000 steps, skin 0.3",
+           "gpu_us_per_step": g["ms_per_step"] * 1e3, "gpu_particle_steps_per_s": g["particle_steps_per_s"],
+           "gpu_step_kernel_us": g["step_kernel_us"], "oracle": cpu,
+           "gpu_over_oracle": g["particle_steps_per_s"] / cpu["particle_steps_per_s"]}
+    log(f"[bench] config 1: {res}")
+    return res
+
+
+def serving_median_jobs_bench(steps: int = 1000):
+    """One job per surface kind of the serving stream at its median size
+    (N = 1024; sphere, prolate spheroid 1:1:1.5, torus r = Rt/3 at area
+    fraction 0.3, WCA, FP32 forces, dt 0.001): plain one-job launches on the
+    GPU and the FP64 oracle."""
+    from workloads import gen
+    out = {}
+    n, phi = 1024, 0.3
+    run = dict(dt=0.001, kT=1.0, gamma=1.0, eps=1.0, sigma=1.0, rc=2.0 ** (1.0 / 6.0), pair="lj", force_fp64=0,
+               seed=77)
+    a, b, c = gen.prolate_axes_for(n, phi)
+    Rt, r = gen.torus_radii_for(n, phi)
+    for kind, s in (("sphere", gen.sphere(n, gen.sphere_radius_for(n, phi), 71)),
+                    ("ellipsoid", gen.ellipsoid(n, a, b, c, 72)), ("torus", gen.torus(n, Rt, r, 73))):
+        g = timed_steps(s, run, 0.3, steps, 100)
+        cpu = oracle_timing(s, dict(run, force_fp64=1), steps, budget_s=5.0)
+        out[kind] = {"gpu_us_per_step": g["ms_per_step"] * 1e3, "gpu_particle_steps_per_s": g["particle_steps_per_s"],
+                     "oracle": cpu}
+    res = {"workload": f"one serving job per surface kind at the median N={n}, area fraction {phi}, WCA, "
+                       f"fp32 forces (oracle fp64), {steps} steps", **out}
+    log(f"[bench] serving median jobs: {res}")
+    return res
 
 
 def cpu_baseline(s, run, budget_s: float = 12.0):
@@ -100,6 +176,7 @@ def cpu_baseline(s, run, budget_s: float = 12.0):
     t1 = time.perf_counter() - t0
     o.set_threads(cores)
     return {"value": s.n * steps / t, "unit": "particle-steps/s", "cores": cores, "kind": "oracle",
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(),
             "sample": f"{steps} full time step(s) of the same {s.n}-particle torus system, FP64, "
                       f"linked cells, OpenMP; {t:.1f} s",
             "one_thread": {"value": s.n / t1, "unit": "particle-steps/s", "sample": f"1 step, {t1:.1f} s"}}
@@ -366,7 +443,9 @@ def main():
     ap.add_argument("--steps", type=int, default=10000)
     ap.add_argument("--warmup", type=int, default=300)
     ap.add_argument("--n", type=int, default=2_000_000)
-    ap.add_argument("--skin", type=float, default=0.5)
+    ap.add_argument("--skin", type=float, default=0.5, help="list skin when not tuning (and of the secondary runs)")
+    ap.add_argument("--no-tune", action="store_true", help="skip md_tune (step-kernel instance and skin)")
+    ap.add_argument("--tune-steps", type=int, default=120, help="steps per md_tune candidate")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="launch steps one by one instead of hipGraph chunks")
     ap.add_argument("--serving-jobs", type=int, default=400, help="0 skips the serving measurement")
@@ -400,6 +479,17 @@ def main():
                     rc=run["rc"], pair=run["pair"], force_fp64=run["force_fp64"], skin=args.skin, seed=run["seed"])
     sysm = md.System(prm, s.surface, s.surf)
     sysm.set_particles(s.x, s.p)
+    tuned = None
+    if not args.no_tune:
+        # the autotuner picks the step-kernel instance and the skin on the live
+        # system (it advances the system; results depend on neither choice)
+        t0 = time.perf_counter()
+        best_skin, best_us = sysm.tune(args.tune_steps)
+        tst = sysm.stats()
+        tuned = {"skin": best_skin, "gpu_us_per_step": best_us, "step_variant": tst["step_variant"],
+                 "step_waves": tst["step_waves"], "step_halo_lds": tst["step_halo_lds"],
+                 "tune_s": time.perf_counter() - t0}
+        log(f"[bench] md_tune: {tuned}")
     sysm.step(args.warmup)
     device_sync()
     st0 = sysm.stats()
@@ -449,13 +539,15 @@ def main():
             "n": s.n,
             "surface": f"torus Rt={s.meta['Rt']:.3f} r={s.meta['r']:.3f} (area fraction 0.4)",
             "pair": "LJ truncated-shifted, rc=2.5", "dt": run["dt"], "gamma": run["gamma"], "kT": run["kT"],
-            "forces": "fp32", "state": "fp64", "skin": args.skin, "parallelism": "1 GPU",
+            "forces": "fp32", "state": "fp64", "skin": st1["skin"], "parallelism": "1 GPU",
+            "step_variant": st1["step_variant"], "step_waves": st1["step_waves"],
+            "step_halo_lds": st1["step_halo_lds"], "tuned": tuned,
         },
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "traffic_GBps": None if traffic is None else traffic / per_launch_s / 1e9,
-            "kernel": "k_step<fp32 forces>", "mean_launch_us": per_launch_s * 1e6,
+            "kernel": "k_step_f32 (instance %d)" % st1["step_variant"], "mean_launch_us": per_launch_s * 1e6,
             "alg_bytes_per_particle_step": step_kernel_bytes(st1["nl_mean"]), "nl_mean": st1["nl_mean"],
         },
         "breakdown": {
@@ -468,6 +560,12 @@ def main():
             "note": "the same steps with the state handed in from and back to host memory (not the metric)",
         },
     }
+    # the sustained rate: whole list-rebuild cycles by GPU time (step chunks and
+    # builds), beside the wall-clock window above
+    gpu_ms = kern_ms + rebuild_ms
+    out["sustained_gpu"] = {"particle_steps_per_s": s.n * args.steps / (gpu_ms * 1e-3) if gpu_ms > 0 else None,
+                            "note": "GPU time of the timed steps (step kernels and list builds, HIP events)"}
+    out["config1"] = config1_bench()
     if not args.no_extra:
         out.update(extra_benches(args.skin))
     if args.serving_jobs > 0:
@@ -476,6 +574,7 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on the host (bounded sample)")
         out["cpu_baseline"] = cpu_baseline(s, run)
+        out["serving_median_jobs"] = serving_median_jobs_bench()
     print(json.dumps(out), flush=True)
 
 

@@ -209,7 +209,12 @@ typedef struct md_stats {
   double step_kernel_ms;  /* GPU time of the step chunks                         */
   double rebuild_ms;      /* GPU time of the list builds                         */
   double nl_mean;         /* mean neighbours per particle at the last build      */
-  double reserved[4];
+  int step_variant;       /* FP32-class step-kernel instance in use (md_tune)    */
+  int step_waves;         /* its occupancy target, wavefronts per SIMD           */
+  int step_halo_lds;      /* its halo entries staged in LDS per 256-slot tile    */
+  int list_capacity;      /* neighbour-list capacity, entries per particle       */
+  double skin;            /* neighbour-list skin in use (a context; 0 for a pool) */
+  double reserved;
 } md_stats;
 
 /* ---- one system ------------------------------------------------------------ */
@@ -281,15 +286,20 @@ int md_get_state_dev_noalloc(md_ctx* ctx, double* x, double* p, double* fcomb, i
 /* Counters and event-timed GPU work of this context (see md_stats). */
 int md_get_stats(md_ctx* ctx, md_stats* stats);
 
-/* Autotune the neighbour-list skin on the live system.  For each candidate
- * (skins[0..nskins), or a built-in set {0.2, 0.3, 0.4, 0.5, 0.6, 0.8} sigma
- * when skins is NULL) the lists are rebuilt with that skin and the system is
- * advanced trial_steps steps while the wall time per step is measured; the
- * fastest skin stays in effect.  The system really advances
- * nskins * trial_steps steps: because results do not depend on the skin, the
- * trajectory is the one md_step would have produced.  best_skin and
- * best_us_per_step may be NULL.  Candidates whose cell grid does not fit the
- * context's memory are skipped. */
+/* Autotune the live system: first the FP32-class step-kernel instance (the
+ * compiled variants differ in occupancy target and in how many halo entries
+ * a tile stages in LDS; FP64-class and bead-model jobs have one instance),
+ * then the neighbour-list skin (skins[0..nskins), or a built-in set
+ * {0.2, 0.3, 0.4, 0.5, 0.6, 0.8} sigma when skins is NULL).  Each candidate
+ * runs one step (which takes the list build a new choice may force) and then
+ * trial_steps steps scored by GPU time per step, step kernels and list builds
+ * together (HIP events, so graph capture does not count); the fastest
+ * instance and skin stay in effect and md_get_stats reports them.  The system
+ * really advances (instances + skins) * (trial_steps + 1) steps: results
+ * depend on neither choice, so the trajectory is the one md_step would have
+ * produced.  best_skin and best_us_per_step (GPU microseconds per step) may be
+ * NULL.  Candidate skins whose cell grid does not fit the context's memory are
+ * skipped. */
 int md_tune(md_ctx* ctx, int trial_steps, const double* skins, int nskins, double* best_skin,
             double* best_us_per_step);
 

@@ -892,6 +892,28 @@ struct Engine {
 
   // Change a job's skin: new list radius and cell grid; the list is rebuilt
   // before the next step.
+  // FP32-class step-kernel instance (kStepVariants); cached graphs hold the
+  // old instance.
+  void set_variant(int v) {
+    v = std::max(0, std::min(kNumStepVariants - 1, v));
+    if (v != f32_variant) {
+      f32_variant = v;
+      drop_graphs();
+    }
+  }
+
+  // Counters plus the choices in effect.
+  md_stats report() const {
+    md_stats st = stats;
+    st.step_variant = f32_variant;
+    st.step_waves = kStepVariants[f32_variant].waves;
+    st.step_halo_lds = kStepVariants[f32_variant].halo;
+    st.list_capacity = kmax;
+    st.skin = 0.0;
+    st.reserved = 0.0;
+    return st;
+  }
+
   int set_skin(int j, double skin) {
     HostJob& h = jobs[j];
     HostJob trial = h;
@@ -1745,13 +1767,37 @@ int md_tune(md_ctx* ctx, int trial_steps, const double* skins, int nskins, doubl
     if (!(skins[q] > 0.0)) return MD_EINVAL;
   Engine* e = ctx->eng;
   const int j = ctx->job;
+  // GPU microseconds per step of one trial: step chunks and list builds (one
+  // step first, which takes the list build a new skin forces)
+  auto trial = [&](double* us) -> int {
+    MDCHK(md_step(ctx, 1));
+    const md_stats a = e->stats;
+    MDCHK(md_step(ctx, trial_steps));
+    const md_stats b = e->stats;
+    const int64_t steps = b.steps - a.steps;
+    const double ms = (b.step_kernel_ms - a.step_kernel_ms) + (b.rebuild_ms - a.rebuild_ms);
+    *us = steps > 0 ? 1000.0 * ms / (double)steps : 1e300;
+    return MD_OK;
+  };
+  // 1. the step-kernel instance, at the current skin (FP32-class jobs only)
+  const HostJob& h0 = e->jobs[j];
+  if (!h0.dev.force_fp64 && !h0.model && h0.n > 0) {
+    int best_v = e->f32_variant;
+    double best_v_us = 1e300;
+    for (int v = 0; v < kNumStepVariants; ++v) {
+      e->set_variant(v);
+      double us = 0.0;
+      MDCHK(trial(&us));
+      if (us < best_v_us) best_v_us = us, best_v = v;
+    }
+    e->set_variant(best_v);
+  }
+  // 2. the skin, with that instance
   double best = -1.0, best_us = 1e300;
   for (int q = 0; q < nskins; ++q) {
     if (e->set_skin(j, skins[q]) != MD_OK) continue;
-    const auto t0 = std::chrono::steady_clock::now();
-    MDCHK(md_step(ctx, trial_steps));
-    const double us =
-        std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count() / trial_steps;
+    double us = 0.0;
+    MDCHK(trial(&us));
     if (us < best_us) {
       best_us = us;
       best = skins[q];
@@ -1768,7 +1814,10 @@ int md_tune(md_ctx* ctx, int trial_steps, const double* skins, int nskins, doubl
 int md_get_stats(md_ctx* ctx, md_stats* stats) {
   if (!ctx || !stats) return MD_EINVAL;
   std::memset(stats, 0, sizeof(*stats));
-  if (ctx->eng) *stats = ctx->eng->stats;
+  if (ctx->eng) {
+    *stats = ctx->eng->report();
+    if (ctx->have_particles) stats->skin = 2.0 * ctx->eng->jobs[ctx->job].dev.half_skin;
+  }
   return MD_OK;
 }
 
@@ -1896,7 +1945,7 @@ int md_pool_usage(md_pool* pool, int* jobs, int64_t* particles, size_t* bytes) {
 
 int md_pool_get_stats(md_pool* pool, md_stats* stats) {
   if (!pool || !stats) return MD_EINVAL;
-  *stats = pool->eng.stats;
+  *stats = pool->eng.report();
   return MD_OK;
 }
 

@@ -61,7 +61,8 @@ class _Stats(C.Structure):
     _fields_ = [
         ("steps", C.c_int64), ("particle_steps", C.c_int64), ("step_launches", C.c_int64),
         ("chunks", C.c_int64), ("builds", C.c_int64), ("step_kernel_ms", C.c_double),
-        ("rebuild_ms", C.c_double), ("nl_mean", C.c_double), ("reserved", C.c_double * 4),
+        ("rebuild_ms", C.c_double), ("nl_mean", C.c_double), ("step_variant", C.c_int), ("step_waves", C.c_int),
+        ("step_halo_lds", C.c_int), ("list_capacity", C.c_int), ("skin", C.c_double), ("reserved", C.c_double),
     ]
 
     def to_dict(self):

@@ -233,20 +233,47 @@ def test_msd_statistics_torus():
 
 
 def test_autotune_keeps_trajectory():
-    """md_tune advances the live system while timing candidate skins; the
-    trajectory is the same bits as plain stepping (results do not depend on
-    the skin)."""
+    """md_tune advances the live system while timing the FP32-class step-kernel
+    instances and then candidate skins; the trajectory is the same bits as
+    plain stepping (results depend on neither choice), and md_get_stats
+    reports the choices."""
+    from paper_1411_3019_amd import md
     s = gen.torus(6000, 40.0, 13.3, 31)
     kw = dict(dt=0.002, rc=2.5, seed=12, force_fp64=0)
     print("[gpu] autotune torus 6000", flush=True)
     g = gpu_system(s, **kw)
     best, us = g.tune(40, skins=[0.25, 0.45, 0.7])
+    st = g.stats()
     a = g.get_state()
     g.close()
     assert best in (0.25, 0.45, 0.7) and us > 0.0
+    assert st["skin"] == best and 0 <= st["step_variant"] < 4
+    assert st["step_waves"] > 0 and st["step_halo_lds"] > 0 and st["list_capacity"] > 0
+    steps = 41 * (4 + 3)
     g = gpu_system(s, **kw)
-    g.step(120)
+    g.step(steps)
     b = g.get_state()
     g.close()
-    assert a["step"] == b["step"] == 120
+    assert a["step"] == b["step"] == steps
     assert np.array_equal(a["x"], b["x"]) and np.array_equal(a["p"], b["p"])
+
+
+def test_step_instances_same_bits(monkeypatch):
+    """Every compiled FP32-class step-kernel instance (occupancy target, halo
+    entries staged in LDS; tiles whose halo exceeds the LDS part read the rest
+    from global memory) gives the same bits."""
+    Rt, r = gen.torus_radii_for(20000, 0.5)
+    s = gen.torus(20000, Rt, r, 41)
+    kw = dict(dt=0.002, rc=2.5, seed=3, force_fp64=0, skin=0.5)
+    runs = []
+    for v in range(4):
+        print("[gpu] step instance %d torus 20000" % v, flush=True)
+        monkeypatch.setenv("MD_STEP_VARIANT", str(v))
+        g = gpu_system(s, **kw)
+        g.step(45)
+        assert g.stats()["step_variant"] == v
+        runs.append(g.get_state())
+        g.close()
+    for r in runs[1:]:
+        assert np.array_equal(r["x"], runs[0]["x"]) and np.array_equal(r["p"], runs[0]["p"])
+        assert np.array_equal(r["f"], runs[0]["f"])
