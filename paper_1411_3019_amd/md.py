@@ -321,8 +321,12 @@ class System:
         f = np.zeros((n, 3)) if want_force else None
         step = C.c_int64(0)
         d = _Diag()
-        _check(lib().md_get_state(self._h, _dp(x), _dp(p), _dp(f), C.byref(step), C.byref(d)), "md_get_state")
-        return dict(x=x, p=p, f=f, step=step.value, diag=d.to_dict())
+        rc = lib().md_get_state(self._h, _dp(x), _dp(p), _dp(f), C.byref(step), C.byref(d))
+        # after a device error (Newton cap, non-finite state) the state and the
+        # diagnostics naming the failing step and particle are still returned
+        if rc not in (MD_OK, MD_ENEWTON, MD_ENAN):
+            _check(rc, "md_get_state")
+        return dict(x=x, p=p, f=f, step=step.value, diag=d.to_dict(), status=rc)
 
     def stats(self):
         st = _Stats()
@@ -330,7 +334,8 @@ class System:
         return st.to_dict()
 
     def tune(self, trial_steps: int, skins=None):
-        """Autotune the list skin on the live system (advances len(skins) * trial_steps steps)."""
+        """md_tune: the FP32-class step-kernel instance, then the list skin, on the
+        live system; returns (best skin, GPU microseconds per step)."""
         arr = None if skins is None else np.ascontiguousarray(skins, dtype=np.float64)
         best = C.c_double(0.0)
         us = C.c_double(0.0)

@@ -6,6 +6,8 @@ max_i |dx_i| / max(1, |x_i|).  The FP64-force path is expected to agree to
 round-off (~1e-13); the FP32-force path to the FP32 force error times
 dt^2/2m in positions.  Momenta and forces are reported beside positions.
 """
+import math
+
 import numpy as np
 import pytest
 
@@ -161,15 +163,47 @@ def test_error_paths():
         g.set_particles(s.x, badp)
     assert e.value.code == md.MD_EOFFSURF
     g.close()
-    # a Newton cap of one iteration cannot reach round-off: reported, not silent
+    # a Newton cap of one iteration cannot reach round-off: reported, not
+    # silent, with the failing step and particle; the state is the one after
+    # the failing step
     g = gpu_system(s, newton_max_iter=1)
     with pytest.raises(md.MDError) as e:
         g.step(5)
     assert e.value.code == md.MD_ENEWTON
+    st = g.get_state()
+    assert st["status"] == md.MD_ENEWTON
+    d = st["diag"]
+    assert d["error_step"] >= 0 and st["step"] == d["error_step"] + 1
+    assert 0 <= d["error_index"] < s.n
     g.close()
     with pytest.raises(md.MDError) as e:
         md.System(md.Params(dt=-1.0))
     assert e.value.code == md.MD_EINVAL
+
+
+def test_exact_sum_guard_close_pair():
+    """FP32 class: a pair at r = 0.45 sigma has pair terms beyond the exact-sum
+    range (2^19); the step sums that particle's forces in FP64 instead, says so
+    in md_diag.exact_sum_breaches, and still matches the oracle's FP64 step."""
+    R = 5.0
+    a = 0.45 / R  # arc 0.45; chord 2 R sin(a/2)
+    x = np.array([[0.0, 0.0, R], [R * math.sin(a), 0.0, R * math.cos(a)],
+                  [0.0, R, 0.0], [0.0, -R, 0.0], [-R, 0.0, 0.0]])
+    s = gen.System(x, np.zeros_like(x), "sphere", (0.0, 0.0, 0.0, R))
+    kw = dict(dt=0.0005, rc=2.5, seed=3, force_fp64=0)
+    print("[gpu] exact-sum guard: pair at r = 0.45", flush=True)
+    ref, f0, st0, st = _one_step(s, 1, **kw)
+    assert st0["diag"]["exact_sum_breaches"] > 0 or st["diag"]["exact_sum_breaches"] > 0
+    ex, ep = rel_pos_err(st["x"], ref.x), rel_err(st["p"], ref.p)
+    report("close pair 1-step", x=ex, p=ep, breaches=st["diag"]["exact_sum_breaches"])
+    assert ex < POS_TOL and ep < 1e-6
+    # a pair at 0.9 sigma stays inside the range: no breach
+    b = 0.9 / R
+    x2 = x.copy()
+    x2[1] = [R * math.sin(b), 0.0, R * math.cos(b)]
+    s2 = gen.System(x2, np.zeros_like(x2), "sphere", (0.0, 0.0, 0.0, R))
+    _, _, _, st2 = _one_step(s2, 1, **kw)
+    assert st2["diag"]["exact_sum_breaches"] == 0
 
 
 def test_full_size_torus_2m_one_step():
@@ -230,6 +264,61 @@ def test_msd_statistics_torus():
     g.close()
     report("torus20k MSD", worst_rel=worst)
     assert worst < 0.02
+
+
+def _blocked_se(samples, nblocks):
+    """Standard error of the mean of a series from the means of nblocks
+    consecutive blocks (correlated samples)."""
+    a = np.asarray(samples, dtype=float)
+    m = len(a) // nblocks * nblocks
+    blocks = a[:m].reshape(nblocks, -1).mean(axis=1)
+    return float(blocks.std(ddof=1) / math.sqrt(nblocks))
+
+
+def test_long_horizon_statistics_torus():
+    """Long-horizon statistics of the FP32-class GPU path against the FP64
+    oracle: 20,000 LJ particles (rc 2.5) on a torus at area fraction 0.4,
+    dt 0.002, gamma 1, 10^4 steps (20 tau).  The two trajectories share the
+    noise but part ways (FP32 against FP64 forces), so only statistics are
+    compared: MSD(t) at log-spaced t from 1 tau to 20 tau, and the mean kT
+    from 5 tau on (the random initial packing heats the system first).  Bar: 2 % where the blocked standard error (20 blocks of
+    particles for MSD, 5 blocks of time for kT) is below 0.5 %, else four
+    standard errors."""
+    from workloads.gen import torus_radii_for
+    Rt, r = torus_radii_for(20000, 0.4)
+    s = gen.torus(20000, Rt, r, 23)
+    kw = dict(dt=0.002, rc=2.5, seed=29, force_fp64=0)
+    print(f"[gpu] long-horizon statistics torus n={s.n}, 10000 steps", flush=True)
+    ref = o.State(oracle_params(s, **kw), s.x, s.p)
+    g = gpu_system(s, **kw)
+    msd_at = {500, 1000, 2500, 5000, 10000}
+    kt_ref, kt_gpu, rows = [], [], []
+    for step in range(100, 10001, 100):
+        ref.run(100)
+        g.step(100)
+        st = g.get_state(want_force=False)
+        assert st["step"] == step
+        if step > 2500:
+            kt_ref.append(ref.diag()["kT"])
+            kt_gpu.append(st["diag"]["kT"])
+        if step in msd_at:
+            d_ref = np.sum((ref.x - s.x) ** 2, axis=1)
+            d_gpu = np.sum((st["x"] - s.x) ** 2, axis=1)
+            m_ref, m_gpu = d_ref.mean(), d_gpu.mean()
+            se = max(_blocked_se(d_ref, 20) / m_ref, _blocked_se(d_gpu, 20) / m_gpu)
+            rows.append((step, m_ref, m_gpu, se))
+            print(f"[gpu] step {step}: MSD oracle {m_ref:.4f} gpu {m_gpu:.4f} rel se {se:.4f}", flush=True)
+    g.close()
+    worst = 0.0
+    for step, m_ref, m_gpu, se in rows:
+        rel = abs(m_gpu / m_ref - 1.0)
+        worst = max(worst, rel)
+        assert rel < (0.02 if se < 0.005 else max(0.02, 4.0 * se)), (step, m_ref, m_gpu, se)
+    k_ref, k_gpu = float(np.mean(kt_ref)), float(np.mean(kt_gpu))
+    se_k = max(_blocked_se(kt_ref, 5) / k_ref, _blocked_se(kt_gpu, 5) / k_gpu)
+    report("torus20k long horizon", msd_worst_rel=worst, kT_rel=abs(k_gpu / k_ref - 1.0), kT_se=se_k)
+    assert se_k < 0.005
+    assert abs(k_gpu / k_ref - 1.0) < 0.02
 
 
 def test_autotune_keeps_trajectory():
