@@ -387,53 +387,70 @@ def serving_bench(njobs: int, nplain: int, rate: float, budget_gb: float):
     Jobs: N log-uniform in [64, 16384] on a sphere / prolate spheroid / torus at
     area fraction U[0.1, 0.5], WCA, dt 0.001, steps log-uniform in [1e3, 1e4],
     FP32 forces, per-job Philox key; arrivals Poisson at `rate` jobs/s.
-      closed loop: every job queued at t = 0; throughput in jobs/s and
-        particle-steps/s (batched over all njobs; plain over the first nplain);
-      open loop: arrivals in real time; latency = completion - arrival.
+      closed loop: every job queued at t = 0; jobs/s and particle-steps/s of
+        the whole stream batched, and like for like on its first nplain jobs,
+        batched and plain (the ratio is taken on that same subset);
+      open loop: arrivals in real time; latency = completion - arrival
+        (batched over the whole stream, plain over the subset).
+    gpu_busy is the pool's GPU time (step chunks and list builds, HIP events)
+    over the wall time.
     """
     from paper_1411_3019_amd import serve
     from paper_1411_3019_amd.md import Params
     from workloads import gen
 
     arrivals = gen.poisson_arrivals(njobs, rate)
+    t0 = time.perf_counter()
+    from concurrent.futures import ProcessPoolExecutor
+    with ProcessPoolExecutor(max_workers=max(1, min(16, os.cpu_count() or 1))) as ex:
+        systems = list(ex.map(gen.serving_job, range(njobs), chunksize=64))
+    log(f"[serve] generated {njobs} jobs ({sum(s.n for s, _ in systems)} particles) in "
+        f"{time.perf_counter() - t0:.1f} s")
 
     def jobs(count):
         out = []
         for jid in range(count):
-            s, run = gen.serving_job(jid)
+            s, run = systems[jid]
             prm = Params(dt=run["dt"], kT=run["kT"], gamma=run["gamma"], rc=run["rc"], pair="lj",
                          force_fp64=run["force_fp64"], seed=run["seed"])
             out.append(serve.Job(jid, float(arrivals[jid]), prm, s.surface, s.surf, s.x, s.p, run["steps"]))
         return out
 
-    t0 = time.perf_counter()
-    J = jobs(njobs)
-    log(f"[serve] generated {njobs} jobs ({sum(j.n for j in J)} particles) in {time.perf_counter() - t0:.1f} s")
     budget = int(budget_gb * (1 << 30))
-    t0 = time.perf_counter()
-    serve.serve(J, budget, 1024, realtime=False)
-    closed = serve.summarize(J, time.perf_counter() - t0)
-    log(f"[serve] batched closed loop: {closed}")
-    P = jobs(nplain)
-    t0 = time.perf_counter()
-    serve.run_plain(P, realtime=False)
-    plain = serve.summarize(P, time.perf_counter() - t0)
-    log(f"[serve] plain closed loop ({nplain} jobs): {plain}")
-    J = jobs(njobs)
-    serve.serve(J, budget, 1024, realtime=True)
-    opened = serve.summarize(J)
-    log(f"[serve] batched open loop at {rate}/s: {opened}")
-    P = jobs(nplain)
-    serve.run_plain(P, realtime=True)
-    plain_open = serve.summarize(P)
+
+    def batched(count, realtime):
+        J = jobs(count)
+        t0 = time.perf_counter()
+        _, st = serve.serve(J, budget, 1024, realtime=realtime)
+        wall = time.perf_counter() - t0
+        res = serve.summarize(J, None if realtime else wall)
+        res["gpu_busy"] = (st["step_kernel_ms"] + st["rebuild_ms"]) * 1e-3 / wall
+        return res
+
+    def plain(count, realtime):
+        P = jobs(count)
+        t0 = time.perf_counter()
+        serve.run_plain(P, realtime=realtime)
+        return serve.summarize(P, None if realtime else time.perf_counter() - t0)
+
+    closed = batched(njobs, False)
+    log(f"[serve] batched closed loop ({njobs} jobs): {closed}")
+    sub_b = batched(nplain, False)
+    log(f"[serve] batched closed loop, first {nplain} jobs: {sub_b}")
+    sub_p = plain(nplain, False)
+    log(f"[serve] plain closed loop, first {nplain} jobs: {sub_p}")
+    opened = batched(njobs, True)
+    log(f"[serve] batched open loop at {rate}/s ({njobs} jobs): {opened}")
+    plain_open = plain(nplain, True)
     log(f"[serve] plain open loop ({nplain} jobs): {plain_open}")
     return {
         "workload": f"{njobs} jobs, Poisson {rate:g}/s, N logU[64,16384], steps logU[1e3,1e4], sphere/spheroid/torus, "
                     "WCA, fp32 forces",
-        "batched_closed": closed, "plain_closed": plain,
-        "throughput_ratio_particle_steps": closed["particle_steps_per_s"] / plain["particle_steps_per_s"],
-        "batched_open": opened, "plain_open": plain_open,
-        "plain_queue_stable": plain["jobs_per_s"] > rate,
+        "batched_closed": closed, "batched_closed_subset": sub_b, "plain_closed_subset": sub_p,
+        "throughput_ratio_same_jobs": sub_b["particle_steps_per_s"] / sub_p["particle_steps_per_s"],
+        "jobs_per_s_ratio_same_jobs": sub_b["jobs_per_s"] / sub_p["jobs_per_s"],
+        "batched_open": opened, "plain_open_subset": plain_open,
+        "plain_queue_stable": sub_p["jobs_per_s"] > rate,
     }
 
 
@@ -448,8 +465,8 @@ def main():
     ap.add_argument("--tune-steps", type=int, default=120, help="steps per md_tune candidate")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="launch steps one by one instead of hipGraph chunks")
-    ap.add_argument("--serving-jobs", type=int, default=400, help="0 skips the serving measurement")
-    ap.add_argument("--serving-plain-jobs", type=int, default=40)
+    ap.add_argument("--serving-jobs", type=int, default=10000, help="0 skips the serving measurement")
+    ap.add_argument("--serving-plain-jobs", type=int, default=100)
     ap.add_argument("--serving-rate", type=float, default=200.0)
     ap.add_argument("--serving-budget-gb", type=float, default=16.0)
     ap.add_argument("--no-extra", action="store_true", help="skip the secondary measurements")

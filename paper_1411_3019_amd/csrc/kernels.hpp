@@ -387,6 +387,7 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const JobDev* 
   __shared__ uint32_t ckey[kColCap], cb[kColCap], ce[kColCap], coff[kColCap + 1];
   __shared__ uint32_t bits[kCandCap / 32], wpre[kCandCap / 32];
   __shared__ uint32_t scan_sh[kNlistBlock / 64];
+  __shared__ uint32_t span_lo, span_hi;
   __shared__ int fail;
   const int kmax = B.kmax;
   code_t* kid = reinterpret_cast<code_t*>(dyn);
@@ -420,7 +421,7 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const JobDev* 
   cb[lane] = 0xFFFFFFFFu;
   ce[lane] = 0u;
   for (int w = lane; w < kCandCap / 32; w += kNlistBlock) bits[w] = 0u;
-  if (lane == 0) fail = 0;
+  if (lane == 0) fail = 0, span_lo = 0xFFFFFFFFu, span_hi = 0u;
   const double* __restrict__ X = B.X[J.xcur ^ 1];  // the sorted copies written by k_gather
   double xi = 0.0, yi = 0.0, zi = 0.0;
   int cx = 0, cy = 0, cz = 0;
@@ -440,48 +441,65 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const JobDev* 
   const bool wrap = valid && zb1 >= za1;
   uint32_t rb[9], re[9];
   column_runs9(B, J, cx, cy, za0, zb0, rb, re);
-  // 1. the tile's columns: the first lane of each cell puts in its columns' hulls
-  {
-    const uint32_t rkey = valid ? raster_of(J, cx, cy, cz) : kNoKey;
-    unsigned long long heads;
-    const int rs = run_start(rkey, wl, &heads);
-    if (valid && rs == wl) {
-      uint32_t lo[9], hi[9];
+  // 1. the tile's columns: the first lane of each cell finds the hulls of the
+  // runs its cell needs per column, and their span over the whole tile
+  const uint32_t rkey = valid ? raster_of(J, cx, cy, cz) : kNoKey;
+  unsigned long long heads;
+  const int rs = run_start(rkey, wl, &heads);  // every lane takes part (shuffle, ballot)
+  const bool head = valid && rs == wl;
+  uint32_t lo[9], hi[9];
 #pragma unroll
-      for (int col = 0; col < 9; ++col) lo[col] = rb[col], hi[col] = re[col];
-      if (wrap) {
-        uint32_t b1[9], e1[9];
-        column_runs9(B, J, cx, cy, za1, zb1, b1, e1);
-#pragma unroll
-        for (int col = 0; col < 9; ++col) {
-          if (e1[col] <= b1[col]) continue;
-          if (hi[col] <= lo[col])
-            lo[col] = b1[col], hi[col] = e1[col];
-          else
-            lo[col] = min(lo[col], b1[col]), hi[col] = max(hi[col], e1[col]);
-        }
-      }
+  for (int col = 0; col < 9; ++col) lo[col] = rb[col], hi[col] = re[col];
+  if (head) {
+    if (wrap) {
+      uint32_t b1[9], e1[9];
+      column_runs9(B, J, cx, cy, za1, zb1, b1, e1);
 #pragma unroll
       for (int col = 0; col < 9; ++col) {
-        if (hi[col] <= lo[col]) continue;
-        const uint32_t key = column_key(J, cx, cy, col);
-        uint32_t h = (key * 0x9E3779B1u) >> 24;
-        int found = -1;
-        for (int probe = 0; probe < kColCap; ++probe) {
-          const uint32_t old = atomicCAS(&ckey[h], kNoCol, key);
-          if (old == kNoCol || old == key) {
-            found = (int)h;
-            break;
-          }
-          h = (h + 1u) & (kColCap - 1);
-        }
-        if (found < 0) {
-          fail = 1;
-          continue;
-        }
-        atomicMin(&cb[found], lo[col]);
-        atomicMax(&ce[found], hi[col]);
+        if (e1[col] <= b1[col]) continue;
+        if (hi[col] <= lo[col])
+          lo[col] = b1[col], hi[col] = e1[col];
+        else
+          lo[col] = min(lo[col], b1[col]), hi[col] = max(hi[col], e1[col]);
       }
+    }
+    uint32_t smin = 0xFFFFFFFFu, smax = 0u;
+#pragma unroll
+    for (int col = 0; col < 9; ++col)
+      if (hi[col] > lo[col]) smin = min(smin, lo[col]), smax = max(smax, hi[col]);
+    atomicMin(&span_lo, smin);
+    atomicMax(&span_hi, smax);
+  }
+  __syncthreads();
+  // Candidate numbers: the slot's offset in the span of all the tile's runs
+  // when that span fits the bitmap (always for jobs of at most kCandCap
+  // particles, among them sparse tiles whose stencils cover many columns),
+  // else by columns: the hulls of the tile's distinct stencil columns, one
+  // after another (large dense jobs, whose tiles cover few columns but whose
+  // span reaches over several rows of cells)
+  const uint32_t span = span_hi > span_lo ? span_hi - span_lo : 0u;
+  const bool by_span = span <= (uint32_t)kCandCap;
+  if (!by_span && head) {
+#pragma unroll
+    for (int col = 0; col < 9; ++col) {
+      if (hi[col] <= lo[col]) continue;
+      const uint32_t key = column_key(J, cx, cy, col);
+      uint32_t h = (key * 0x9E3779B1u) >> 24;
+      int found = -1;
+      for (int probe = 0; probe < kColCap; ++probe) {
+        const uint32_t old = atomicCAS(&ckey[h], kNoCol, key);
+        if (old == kNoCol || old == key) {
+          found = (int)h;
+          break;
+        }
+        h = (h + 1u) & (kColCap - 1);
+      }
+      if (found < 0) {
+        fail = 1;
+        break;
+      }
+      atomicMin(&cb[found], lo[col]);
+      atomicMax(&ce[found], hi[col]);
     }
   }
   __syncthreads();
@@ -494,8 +512,10 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const JobDev* 
     if (lane == 0) coff[kColCap] = M;
   }
   __syncthreads();
-  if (M > (uint32_t)kCandCap || fail) {
-    // too dense for the list build: the job stops with an error
+  if (!by_span) M = M > (uint32_t)kCandCap || fail ? 0xFFFFFFFFu : M;
+  else M = span;
+  if (M > (uint32_t)kCandCap) {
+    // neither numbering fits: the job stops with an error
     if (lane == 0) {
       atomicOr(&K.build_fail, 1);
       atomicMin(&K.stop_at, (long long)J.step0);
@@ -604,8 +624,11 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const JobDev* 
 #pragma unroll
     for (int col = 0; col < 9; ++col) {
       if (re[col] > rb[col]) {
-        const int h = column_slot(ckey, column_key(J, cx, cy, col));
-        const uint32_t o = coff[h] - cb[h];  // (mod 2^32)
+        uint32_t o = 0u - span_lo;  // (mod 2^32)
+        if (!by_span) {
+          const int h = column_slot(ckey, column_key(J, cx, cy, col));
+          o = coff[h] - cb[h];
+        }
         scan(rb[col], re[col], o, PK[rb[col]], PK[rb[col] + 1], PK[rb[col] + 2], PK[rb[col] + 3]);
       }
     }
@@ -615,8 +638,11 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const JobDev* 
       column_runs9(B, J, cx, cy, za1, zb1, b1, e1);
       for (int col = 0; col < 9; ++col) {
         if (e1[col] <= b1[col]) continue;
-        const int h = column_slot(ckey, column_key(J, cx, cy, col));
-        const uint32_t o = coff[h] - cb[h];
+        uint32_t o = 0u - span_lo;
+        if (!by_span) {
+          const int h = column_slot(ckey, column_key(J, cx, cy, col));
+          o = coff[h] - cb[h];
+        }
         scan(b1[col], e1[col], o, PK[b1[col]], PK[b1[col] + 1], PK[b1[col] + 2], PK[b1[col] + 3]);
       }
     }
@@ -647,15 +673,19 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const JobDev* 
     if (!((w >> (t & 31)) & 1u)) continue;
     const uint32_t rank = wpre[t >> 5] + __popc(w & ((1u << (t & 31)) - 1u));
     if (rank >= hcap) continue;
-    int lo = 0, hi = kColCap;
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (coff[mid] <= t)
-        lo = mid;
-      else
-        hi = mid;
+    uint32_t slot = span_lo + t;
+    if (!by_span) {
+      int lo = 0, hi = kColCap;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (coff[mid] <= t)
+          lo = mid;
+        else
+          hi = mid;
+      }
+      slot = cb[lo] + (t - coff[lo]);
     }
-    B.HALO[gt * (int64_t)hcap + rank] = (uint32_t)(base + cb[lo] + (t - coff[lo]));
+    B.HALO[gt * (int64_t)hcap + rank] = (uint32_t)(base + slot);
   }
   if (lane == 0) {
     B.HCNT[gt] = H;

@@ -56,6 +56,31 @@ def test_pool_job_matches_oracle():
         assert e < 1e-6
 
 
+def test_sparse_jobs_build_lists():
+    """Jobs of the serving stream at area fraction 0.10-0.15 (a few thousand
+    WCA particles, about one particle per four cells): a tile's stencils then
+    cover more distinct cell columns than a dense tile's, and the list build
+    numbers the tile's candidates by their span instead.  Every job finishes,
+    alone and in a pool, and two of them match the oracle."""
+    from paper_1411_3019_amd import serve
+    ids = [60, 94, 104, 200, 234, 258, 259, 284]
+    jobs = _serving_jobs(ids, lambda j: 60)
+    print("[gpu] sparse serving jobs", [(j.surface, j.n) for j in jobs], flush=True)
+    serve.serve(jobs, 512 << 20, 16, chunk=32, realtime=False, keep_results=True)
+    assert all(j.status == 0 for j in jobs), [(j.jid, j.status) for j in jobs]
+    alone = _serving_jobs(ids[:2], lambda j: 60)
+    serve.run_plain(alone, realtime=False, keep_results=True)
+    for a, b in zip(jobs, alone):
+        assert np.array_equal(a.result["x"], b.result["x"]) and np.array_equal(a.result["p"], b.result["p"])
+    for j in jobs[:2]:
+        s, run = gen.serving_job(j.jid)
+        P = oracle_params(s, dt=run["dt"], rc=run["rc"], seed=run["seed"])
+        ref = o.State(P, s.x, s.p).run(60)
+        e = rel_pos_err(j.result["x"], ref.x)
+        report(f"sparse job {j.jid} ({j.surface}, n={j.n}) 60 steps", x=e)
+        assert e < 1e-6
+
+
 def test_admission_backpressure_small_budget():
     """A budget that holds only a few jobs: MD_EAGAIN keeps the rest waiting;
     all of them finish, and the pool never holds more than the budget."""
