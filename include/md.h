@@ -346,6 +346,16 @@ int md_pool_admit(md_pool* pool, const md_job_desc* job, int* job_id);
 /* Advance every resident, unfinished job by up to steps_chunk steps. */
 int md_pool_run(md_pool* pool, int steps_chunk);
 
+/* Enqueue one chunk of up to steps_chunk steps (at most 32) for every
+ * resident, unfinished job and return without waiting for it, so that the
+ * caller can admit jobs (md_pool_admit) while the chunk runs: their uploads go
+ * to slots the chunk does not touch and follow it on the stream.  The chunk is
+ * completed (waited for, its steps counted) by the next md_pool_launch,
+ * md_pool_run, md_pool_poll, md_pool_fetch, md_pool_release or
+ * md_pool_destroy; md_pool_get_stats and md_pool_usage report completed
+ * chunks only. */
+int md_pool_launch(md_pool* pool, int steps_chunk);
+
 /* List jobs that have finished (or failed) and have not been fetched yet:
  * up to cap ids into done_ids, count into *ndone. */
 int md_pool_poll(md_pool* pool, int* done_ids, int cap, int* ndone);

@@ -435,6 +435,14 @@ struct Engine {
   static constexpr int kSubEvents = 16;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   hipEvent_t ev_sub[kSubEvents] = {};
+  hipEvent_t ev_book = nullptr;  // the job records of the chunk in flight are on the host
+  // the chunk enqueued by launch_chunk and not yet completed (complete_chunk)
+  struct Inflight {
+    bool active = false;
+    std::vector<int64_t> cap;  // steps each job may take in the chunk
+    int kk = 0, nsub = 0;
+    int64_t launches = 0;
+  } inflight;
   std::vector<int> last_tj[kClasses];
   std::vector<int64_t> last_tf[kClasses];
   size_t nl_bytes = 0;
@@ -453,6 +461,7 @@ struct Engine {
       if (e) (void)hipEventDestroy(e), e = nullptr;
     for (auto& e : ev_sub)
       if (e) (void)hipEventDestroy(e), e = nullptr;
+    if (ev_book) (void)hipEventDestroy(ev_book), ev_book = nullptr;
     void* ptrs[] = {B.X[0], B.X[1], B.P[0], B.P[1], B.ID[0], B.ID[1], B.FLG[0], B.FLG[1], B.MASS[0], B.MASS[1],
                     B.NZD[0], B.NZD[1], B.NZF[0], B.NZF[1], B.FC, B.OX, B.OP, B.OF, B.OD, B.NL, B.NCNT, B.HALO, B.HCNT, B.BM, B.WOFF,
                     B.CCNT, B.CSTART, B.RASTER, B.CID, B.RANK, B.INV, B.SRC, B.PK, B.TYPE[0], B.TYPE[1],
@@ -589,6 +598,7 @@ struct Engine {
     HIPCHK(hipHostMalloc((void**)&arena, kArenaBytes, hipHostMallocDefault));
     for (auto& e : ev) HIPCHK(hipEventCreate(&e));
     for (auto& e : ev_sub) HIPCHK(hipEventCreate(&e));
+    HIPCHK(hipEventCreateWithFlags(&ev_book, hipEventDisableTiming));
     return sync();
   }
 
@@ -890,8 +900,6 @@ struct Engine {
     step_tiles_valid = false;
   }
 
-  // Change a job's skin: new list radius and cell grid; the list is rebuilt
-  // before the next step.
   // FP32-class step-kernel instance (kStepVariants); cached graphs hold the
   // old instance.
   void set_variant(int v) {
@@ -914,6 +922,8 @@ struct Engine {
     return st;
   }
 
+  // Change a job's skin: new list radius and cell grid; the list is rebuilt
+  // before the next step.
   int set_skin(int j, double skin) {
     HostJob& h = jobs[j];
     HostJob trial = h;
@@ -1263,6 +1273,16 @@ struct Engine {
   // binary digits of k), with the job records for each uploaded before it; the
   // host waits once, for the job records at the end.
   int run_chunk(int kcap, bool use_graph, int64_t* advanced, bool eager = false) {
+    MDCHK(enqueue_chunk(kcap, use_graph, eager));
+    return complete_chunk(advanced);
+  }
+
+  // The first half of run_chunk: rebuilds, the chunk's graphs and the copy of
+  // the job records to the host are enqueued, and the call returns without
+  // waiting (complete_chunk waits).  Until then the host may admit jobs: their
+  // uploads go to slots the chunk does not touch and follow it on the stream.
+  int enqueue_chunk(int kcap, bool use_graph, bool eager) {
+    inflight.active = false;
     std::vector<int> need;
     const int k = std::min(kcap, kMaxChunk);
     for (int j = 0; j < max_jobs; ++j) {
@@ -1284,11 +1304,9 @@ struct Engine {
       any = true;
       if (!eager) kk = std::min<int64_t>(kk, std::max(1, predict_chunk(h)));
     }
-    if (!any) {
-      *advanced = 0;
-      return MD_OK;
-    }
-    std::vector<int64_t> cap(max_jobs, 0);
+    if (!any) return MD_OK;
+    std::vector<int64_t>& cap = inflight.cap;
+    cap.assign(max_jobs, 0);
     for (int j = 0; j < max_jobs; ++j) {
       HostJob& h = jobs[j];
       cap[j] = steppable(h) ? std::min<int64_t>(h.target - h.step, kk) : 0;
@@ -1319,12 +1337,29 @@ struct Engine {
     }
     hipLaunchKernelGGL(k_job_stats, dim3(max_jobs), dim3(kStatsThreads), 0, stream, B, 0);
     HIPCHK(hipGetLastError());
-    MDCHK(read_book());
-    for (int q = 0; q < nsub; ++q) stats.step_kernel_ms += elapsed_ms(ev_sub[2 * q], ev_sub[2 * q + 1]);
-    stats.chunks += 1;
+    HIPCHK(hipMemcpyAsync(book_h, B.book, sizeof(JobBook) * max_jobs, hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipEventRecord(ev_book, stream));
     int classes = 0;
     for (int c = 0; c < kClasses; ++c) classes += grid[c] > 0;
-    stats.step_launches += (int64_t)kk * classes;
+    inflight.kk = kk;
+    inflight.nsub = nsub;
+    inflight.launches = (int64_t)kk * classes;
+    inflight.active = true;
+    return MD_OK;
+  }
+
+  // The second half: wait for the job records of the chunk in flight and
+  // advance the jobs' steps from them.
+  int complete_chunk(int64_t* advanced) {
+    *advanced = 0;
+    if (!inflight.active) return MD_OK;
+    inflight.active = false;
+    HIPCHK(hipEventSynchronize(ev_book));
+    const std::vector<int64_t>& cap = inflight.cap;
+    const int nsub = inflight.nsub;
+    for (int q = 0; q < nsub; ++q) stats.step_kernel_ms += elapsed_ms(ev_sub[2 * q], ev_sub[2 * q + 1]);
+    stats.chunks += 1;
+    stats.step_launches += inflight.launches;
     int halo_need = 0;
     const int longest = collect_build_stats(&halo_need);
     int64_t adv = 0;
@@ -1368,6 +1403,13 @@ struct Engine {
     if (halo_need > hcap) MDCHK(grow_hcap(halo_need));
     *advanced = adv;
     return MD_OK;
+  }
+
+  // Complete the chunk in flight, if any (before anything that reads or
+  // frees device state of the jobs).
+  int drain() {
+    int64_t adv = 0;
+    return complete_chunk(&adv);
   }
 
   // ------------------------------------------------------------------ finish
@@ -1881,6 +1923,7 @@ int md_pool_admit(md_pool* pool, const md_job_desc* job, int* job_id) {
 int md_pool_run(md_pool* pool, int steps_chunk) {
   if (!pool || steps_chunk < 0) return MD_EINVAL;
   Engine& e = pool->eng;
+  MDCHK(e.drain());
   const bool graph = use_graphs();
   int64_t left = steps_chunk;
   while (left > 0) {
@@ -1897,9 +1940,18 @@ int md_pool_run(md_pool* pool, int steps_chunk) {
   return MD_OK;
 }
 
+int md_pool_launch(md_pool* pool, int steps_chunk) {
+  if (!pool || steps_chunk < 0) return MD_EINVAL;
+  Engine& e = pool->eng;
+  MDCHK(e.drain());
+  if (steps_chunk == 0) return MD_OK;
+  return e.enqueue_chunk((int)std::min<int64_t>(steps_chunk, kPoolChunk), use_graphs(), true);
+}
+
 int md_pool_poll(md_pool* pool, int* done_ids, int cap, int* ndone) {
   if (!pool || !ndone || (cap > 0 && !done_ids)) return MD_EINVAL;
   Engine& e = pool->eng;
+  MDCHK(e.drain());
   int c = 0;
   for (int j = 0; j < e.max_jobs && c < cap; ++j) {
     HostJob& h = e.jobs[j];
@@ -1916,12 +1968,14 @@ int md_pool_poll(md_pool* pool, int* done_ids, int cap, int* ndone) {
 int md_pool_fetch(md_pool* pool, int job_id, double* x, double* p, md_diag* diag) {
   if (!pool || job_id < 0 || job_id >= pool->eng.max_jobs) return MD_ENOTFOUND;
   if (!pool->eng.jobs[job_id].used) return MD_ENOTFOUND;
+  MDCHK(pool->eng.drain());
   return pool->eng.finish(job_id, x, p, nullptr, diag);
 }
 
 int md_pool_release(md_pool* pool, int job_id) {
   if (!pool || job_id < 0 || job_id >= pool->eng.max_jobs) return MD_ENOTFOUND;
   if (!pool->eng.jobs[job_id].used) return MD_ENOTFOUND;
+  MDCHK(pool->eng.drain());
   pool->eng.drop(job_id);
   return MD_OK;
 }
@@ -1949,6 +2003,10 @@ int md_pool_get_stats(md_pool* pool, md_stats* stats) {
   return MD_OK;
 }
 
-void md_pool_destroy(md_pool* pool) { delete pool; }
+void md_pool_destroy(md_pool* pool) {
+  if (!pool) return;
+  (void)pool->eng.drain();
+  delete pool;
+}
 
 }  // extern "C"

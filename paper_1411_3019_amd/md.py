@@ -24,7 +24,7 @@ SYMBOLS = ["md_create", "md_set_surface", "md_set_particles", "md_step", "md_get
            "md_strerror", "md_job_footprint", "md_pool_create", "md_pool_admit", "md_pool_run", "md_pool_poll",
            "md_pool_fetch", "md_pool_release", "md_pool_usage", "md_pool_destroy", "md_get_stats",
            "md_pool_get_stats", "md_tune", "md_set_model", "md_set_particles_dev", "md_get_state_dev",
-           "md_get_state_dev_noalloc"]
+           "md_get_state_dev_noalloc", "md_pool_launch"]
 MD_MAX_TYPES = 4
 
 
@@ -197,6 +197,7 @@ def lib():
         L.md_pool_create.argtypes = [C.c_size_t, C.c_int, C.c_int, vp, C.POINTER(vp)]
         L.md_pool_admit.argtypes = [vp, C.POINTER(_JobDesc), C.POINTER(C.c_int)]
         L.md_pool_run.argtypes = [vp, C.c_int]
+        L.md_pool_launch.argtypes = [vp, C.c_int]
         L.md_pool_poll.argtypes = [vp, C.POINTER(C.c_int), C.c_int, C.POINTER(C.c_int)]
         L.md_pool_fetch.argtypes = [vp, C.c_int, dp, dp, C.POINTER(_Diag)]
         L.md_pool_release.argtypes = [vp, C.c_int]
@@ -208,7 +209,8 @@ def lib():
         L.md_pool_destroy.restype = None
         for name in ("md_create", "md_set_surface", "md_set_particles", "md_set_model", "md_step", "md_get_state",
                      "md_set_particles_dev", "md_get_state_dev", "md_get_state_dev_noalloc",
-                     "md_pool_create", "md_pool_admit", "md_pool_run", "md_pool_poll", "md_pool_fetch",
+                     "md_pool_create", "md_pool_admit", "md_pool_run", "md_pool_launch", "md_pool_poll",
+                     "md_pool_fetch",
                      "md_pool_release", "md_pool_usage", "md_get_stats", "md_pool_get_stats", "md_tune"):
             getattr(L, name).restype = C.c_int
         _lib = L
@@ -403,6 +405,11 @@ class Pool:
 
     def run(self, steps: int):
         _check(lib().md_pool_run(self._h, int(steps)), "md_pool_run")
+
+    def launch(self, steps: int):
+        """md_pool_launch: enqueue one chunk and return without waiting (the next
+        poll, fetch, release or run completes it)."""
+        _check(lib().md_pool_launch(self._h, int(steps)), "md_pool_launch")
 
     def poll(self, cap: int = 4096):
         ids = (C.c_int * cap)()

@@ -3,10 +3,11 @@
 Jobs (independent simulations) arrive over time.  The loop admits waiting jobs
 in arrival order while the pool has device memory and a free slot
 (md_pool_admit returns MD_EAGAIN otherwise), advances every resident job
-together by one chunk of steps (md_pool_run), and fetches and releases the jobs
-that finished, so later arrivals are admitted as soon as room frees up and
-their work shares launches with the jobs already running.  Latency of a job is
-its completion time minus its arrival time.
+together by one chunk of steps (md_pool_launch, which returns while the chunk
+runs, so the next admissions overlap it; md_pool_poll collects it), and
+fetches and releases the jobs that finished, so later arrivals are admitted as
+soon as room frees up and their work shares launches with the jobs already
+running.  Latency of a job is its completion time minus its arrival time.
 
 `run_plain` is the reference point: one job at a time, one context per job,
 one launch per step (no graphs), the same kernels.
@@ -50,7 +51,11 @@ class Job:
 def serve(jobs, budget_bytes: int, max_jobs: int, chunk: int = 32, realtime: bool = True,
           keep_results: bool = False, pool_factory=None, clock=time.perf_counter, sleep=time.sleep):
     """Run `jobs` through one pool; returns (jobs, pool stats).  With
-    realtime=False every job counts as arrived at t = 0 (closed loop)."""
+    realtime=False every job counts as arrived at t = 0 (closed loop).
+
+    Each round enqueues one chunk for the resident jobs (md_pool_launch) and,
+    while it runs, admits the jobs that are waiting; then it collects the
+    chunk (md_pool_poll) and fetches and releases the jobs it finished."""
     make = pool_factory or (lambda: md.Pool(budget_bytes, max_jobs))
     if not realtime:
         for j in jobs:
@@ -59,6 +64,7 @@ def serve(jobs, budget_bytes: int, max_jobs: int, chunk: int = 32, realtime: boo
     pending = collections.deque(sorted(jobs, key=lambda j: j.arrival))
     waiting = collections.deque()
     resident = {}
+    running = False  # a chunk is in flight
     t0 = clock()
     try:
         while pending or waiting or resident:
@@ -73,21 +79,27 @@ def serve(jobs, budget_bytes: int, max_jobs: int, chunk: int = 32, realtime: boo
                 j.admitted = clock() - t0
                 resident[pid] = j
                 waiting.popleft()
-            if not resident:
-                if pending and realtime:
-                    sleep(max(0.0, pending[0].arrival - (clock() - t0)))
-                elif waiting:
-                    raise RuntimeError(f"job {waiting[0].jid} does not fit an empty pool")
-                continue
-            pool.run(chunk)
-            for pid in pool.poll():
-                j = resident.pop(pid)
-                rc, res = pool.fetch(pid)
-                j.finished = clock() - t0
-                j.status = rc
-                if keep_results:
-                    j.result = res
-                pool.release(pid)
+            freed = False
+            if running:
+                for pid in pool.poll():
+                    j = resident.pop(pid)
+                    rc, res = pool.fetch(pid)
+                    j.finished = clock() - t0
+                    j.status = rc
+                    if keep_results:
+                        j.result = res
+                    pool.release(pid)
+                    freed = True
+                running = False
+            if resident:
+                pool.launch(chunk)
+                running = True
+            elif freed:
+                continue  # room for the waiting jobs
+            elif pending and realtime:
+                sleep(max(0.0, pending[0].arrival - (clock() - t0)))
+            elif waiting:
+                raise RuntimeError(f"job {waiting[0].jid} does not fit an empty pool")
         stats = pool.stats()
     finally:
         pool.close()

@@ -31,6 +31,10 @@ class FakePool:
         for v in self.res.values():
             v["left"] = max(0, v["left"] - k)
 
+    def launch(self, k):
+        # the fake's chunk is done at once; poll reports it
+        self.run(k)
+
     def poll(self):
         out = [j for j, v in self.res.items() if v["left"] == 0 and not v["reported"]]
         for j in out:
