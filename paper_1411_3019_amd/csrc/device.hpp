@@ -566,25 +566,36 @@ __device__ __forceinline__ void pair_forces(const JobDev& J, const DevBufs& B, i
   } else {
     const float eps24 = (float)(24.0 * J.eps), sig2 = (float)J.sig2, dphic = (float)J.dphic;
     const double bias = J.grid_bias;
-    auto coef = [&](double r2) {
+    auto coef_t = [&](double r2, auto smooth_tag) {
       const float r2f = (float)r2;
       const float inv = __builtin_amdgcn_rcpf(r2f);
       const float s2 = sig2 * inv;
       const float s6 = s2 * s2 * s2;
       float c = eps24 * inv * s6 * (2.0f * s6 - 1.0f);
-      if (smooth) c += dphic * __builtin_amdgcn_rsqf(r2f);
+      if constexpr (decltype(smooth_tag)::value) c += dphic * __builtin_amdgcn_rsqf(r2f);
       return c;
     };
+    auto coef = [&](double r2) { return smooth ? coef_t(r2, std::true_type{}) : coef_t(r2, std::false_type{}); };
     GridSum s;
     s.clear();
-    for_entries(B, i, cnt, q, [&](uint32_t e) {
-      double dx, dy, dz;
-      const double r2 = sep(e, dx, dy, dz);
-      float c = coef(r2);
-      c = r2 < rc2 ? c : 0.0f;
-      s.add(c, dx, dy, dz, bias);
-    });
-    exact = s.get(cnt, J.grid_cmax, Fx, Fy, Fz);
+    int nadd = 0;  // terms added
+    // the smoothed potential's extra term only where it is used (one copy of
+    // the loop per form)
+    auto run = [&](auto smooth_tag) {
+      for_entries(B, i, cnt, q, [&](uint32_t e) {
+        double dx, dy, dz;
+        const double r2 = sep(e, dx, dy, dz);
+        float c = coef_t(r2, smooth_tag);
+        c = r2 < rc2 ? c : 0.0f;
+        s.add(c, dx, dy, dz, bias);
+      });
+    };
+    if (smooth)
+      run(std::true_type{});
+    else
+      run(std::false_type{});
+    nadd = cnt;
+    exact = s.get(nadd, J.grid_cmax, Fx, Fy, Fz);
     if (!exact) {
       // (rare: a plain loop, kept out of the unrolled code)
       double fx = 0.0, fy = 0.0, fz = 0.0;
