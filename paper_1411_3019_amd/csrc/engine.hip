@@ -562,7 +562,7 @@ struct Engine {
     MDCHK(dalloc(&B.RANK, C));
     MDCHK(dalloc(&B.INV, C));
     MDCHK(dalloc(&B.SRC, C));
-    MDCHK(dalloc(&B.PK, C + 8));  // the list build reads up to 7 records past a column
+    MDCHK(dalloc(&B.PK, C + 16));  // the list build reads up to 7 records past a column
     MDCHK(dalloc(&B.TYPE[0], C));
     MDCHK(dalloc(&B.TYPE[1], C));
     MDCHK(dalloc(&B.TACC, C / kGroup + 1));

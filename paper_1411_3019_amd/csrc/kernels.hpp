@@ -561,63 +561,73 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const JobDev* 
     const uint32_t bpm = (uint32_t)J.bpm, mstart = bpm != 0u ? (myid / bpm) * bpm : 0u;  // bpm = 0: no molecules
     const float4* __restrict__ PK = B.PK + base;
     const uint32_t loc0 = 0u - first_local;  // own-tile index of job slot 0 (mod 2^32)
-    // slots [b, e) of a column whose candidate numbers are slot + o; reads up
-    // to 7 records past e (the record array is padded for that)
-    // f0..f3: the records of slots b .. b + 3, loaded ahead
+    // four candidates r[0..3] at slots j .. j+3 (rem: candidates left from j)
+    auto test4 = [&](const float4* r, int rem, uint32_t t, uint32_t loc) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        float dx = xf - r[u].x, dy = yf - r[u].y, dz = zf - r[u].z;
+        if (anyper) min_image_f(pL, piL, dx, dy, dz);
+        const float d2 = dx * dx + dy * dy + dz * dz;
+        const uint32_t w = __float_as_uint(r[u].w);
+        bool take;
+        if (kWide) {
+          const uint32_t tj = w >> kTypeShift;
+          const float tt = tj == 0u ? tthr[0] : (tj == 1u ? tthr[1] : (tj == 2u ? tthr[2] : tthr[3]));
+          take = d2 < tt && (w & kIdMask) - mstart >= bpm;
+        } else {
+          take = d2 < thr;
+        }
+        take = take && u < rem && loc + u != (uint32_t)lane;
+        const bool own = loc + u < (uint32_t)kTile;
+        uint32_t code = own ? kOwn | (loc + u) : t + u;
+        if (kWide) code |= (w >> kTypeShift) << kTypeShift;
+        if (sorted) {
+          // insertion by particle index (the order of the FP64 sums)
+          if (take && cnt < kmax) {
+            const uint32_t qid = w & kIdMask;
+            int k = cnt;
+            while (k > 0 && kkey[(k - 1) * kNlistBlock + lane] > qid) {
+              kkey[k * kNlistBlock + lane] = kkey[(k - 1) * kNlistBlock + lane];
+              kid[k * kNlistBlock + lane] = kid[(k - 1) * kNlistBlock + lane];
+              --k;
+            }
+            kkey[k * kNlistBlock + lane] = qid;
+            kid[k * kNlistBlock + lane] = (code_t)code;
+          }
+        } else {
+          kid[min(cnt, kmax) * kNlistBlock + lane] = (code_t)code;
+        }
+        cnt += take ? 1 : 0;
+      }
+    };
+    // slots [b, e) of a column whose candidate numbers are slot + o; f0..f3:
+    // the records of slots b .. b+3, loaded ahead.  Two batches of four in
+    // flight, in alternating registers; a batch loads only after one with
+    // candidates left, so the reads stop 7 records past e (the record array
+    // is padded for that)
     auto scan = [&](uint32_t b, uint32_t e, uint32_t o, float4 f0, float4 f1, float4 f2, float4 f3) {
       if (b >= e) return;
       const float4* q = PK + b;
-      float4 nxt[4] = {f0, f1, f2, f3};
+      float4 ra[4] = {f0, f1, f2, f3}, rb4[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) rb4[u] = q[4 + u];
       int rem = (int)(e - b);
       uint32_t t = b + o;
       uint32_t loc = b + loc0;
-      while (rem > 0) {
-        float4 r[4];
-        q += 4;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          r[u] = nxt[u];
-          nxt[u] = q[u];
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          float dx = xf - r[u].x, dy = yf - r[u].y, dz = zf - r[u].z;
-          if (anyper) min_image_f(pL, piL, dx, dy, dz);
-          const float d2 = dx * dx + dy * dy + dz * dz;
-          const uint32_t w = __float_as_uint(r[u].w);
-          bool take;
-          if (kWide) {
-            const uint32_t tj = w >> kTypeShift;
-            const float tt = tj == 0u ? tthr[0] : (tj == 1u ? tthr[1] : (tj == 2u ? tthr[2] : tthr[3]));
-            take = d2 < tt && (w & kIdMask) - mstart >= bpm;
-          } else {
-            take = d2 < thr;
-          }
-          take = take && u < rem && loc + u != (uint32_t)lane;
-          const bool own = loc + u < (uint32_t)kTile;
-          uint32_t code = own ? kOwn | (loc + u) : t + u;
-          if (kWide) code |= (w >> kTypeShift) << kTypeShift;
-          if (sorted) {
-            // insertion by particle index (the order of the FP64 sums)
-            if (take && cnt < kmax) {
-              const uint32_t qid = w & kIdMask;
-              int k = cnt;
-              while (k > 0 && kkey[(k - 1) * kNlistBlock + lane] > qid) {
-                kkey[k * kNlistBlock + lane] = kkey[(k - 1) * kNlistBlock + lane];
-                kid[k * kNlistBlock + lane] = kid[(k - 1) * kNlistBlock + lane];
-                --k;
-              }
-              kkey[k * kNlistBlock + lane] = qid;
-              kid[k * kNlistBlock + lane] = (code_t)code;
-            }
-          } else {
-            kid[min(cnt, kmax) * kNlistBlock + lane] = (code_t)code;
-          }
-          cnt += take ? 1 : 0;
-        }
+      while (true) {
+        test4(ra, rem, t, loc);
         rem -= 4;
-        t += 4u;
-        loc += 4u;
+        if (rem <= 0) break;
+        q += 8;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) ra[u] = q[u];
+        test4(rb4, rem, t + 4u, loc + 4u);
+        rem -= 4;
+        if (rem <= 0) break;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) rb4[u] = q[4 + u];
+        t += 8u;
+        loc += 8u;
       }
     };
     // the 9 columns, unrolled (their runs stay in registers)
@@ -668,24 +678,25 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const JobDev* 
   }
   __syncthreads();
   const uint32_t hcap = (uint32_t)B.hcap;
-  for (uint32_t t = lane; t < M; t += kNlistBlock) {
-    const uint32_t w = bits[t >> 5];
-    if (!((w >> (t & 31)) & 1u)) continue;
-    const uint32_t rank = wpre[t >> 5] + __popc(w & ((1u << (t & 31)) - 1u));
-    if (rank >= hcap) continue;
-    uint32_t slot = span_lo + t;
-    if (!by_span) {
-      int lo = 0, hi = kColCap;
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (coff[mid] <= t)
-          lo = mid;
-        else
-          hi = mid;
+  // the halo list: each lane takes bitmap words and writes their set bits
+  for (uint32_t wi = lane; wi < (M + 31u) / 32u; wi += kNlistBlock) {
+    uint32_t w = bits[wi];
+    for (uint32_t rank = wpre[wi]; w != 0u && rank < hcap; ++rank, w &= w - 1u) {
+      const uint32_t t = wi * 32u + (uint32_t)(__ffs(w) - 1);
+      uint32_t slot = span_lo + t;
+      if (!by_span) {
+        int lo = 0, hi = kColCap;
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (coff[mid] <= t)
+            lo = mid;
+          else
+            hi = mid;
+        }
+        slot = cb[lo] + (t - coff[lo]);
       }
-      slot = cb[lo] + (t - coff[lo]);
+      B.HALO[gt * (int64_t)hcap + rank] = (uint32_t)(base + slot);
     }
-    B.HALO[gt * (int64_t)hcap + rank] = (uint32_t)(base + slot);
   }
   if (lane == 0) {
     B.HCNT[gt] = H;
