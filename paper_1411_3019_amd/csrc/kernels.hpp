@@ -660,11 +660,15 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const JobDev* 
   // 3. the halo: kept candidates outside the tile, marked in the bitmap,
   // ranked in candidate order
   const int stored = valid ? (cnt < kmax ? cnt : kmax) : 0;
-  for (int k = 0; k < stored; ++k) {
-    const uint32_t code = (uint32_t)kid[k * kNlistBlock + lane];
-    if (!(code & kOwn)) {
-      const uint32_t v = code & 0xFFFFu;
-      atomicOr(&bits[v >> 5], 1u << (v & 31));
+  for (int k = 0; k < stored; k += kRow) {
+    // eight codes read together (rows past the list read row kmax, in bounds)
+    uint32_t code[kRow];
+#pragma unroll
+    for (int u = 0; u < kRow; ++u) code[u] = (uint32_t)kid[min(k + u, kmax) * kNlistBlock + lane];
+#pragma unroll
+    for (int u = 0; u < kRow; ++u) {
+      const uint32_t v = code[u] & 0xFFFFu;
+      if (k + u < stored && !(code[u] & kOwn)) atomicOr(&bits[v >> 5], 1u << (v & 31));
     }
   }
   __syncthreads();
@@ -705,23 +709,26 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const JobDev* 
   }
   if (valid) {
     for (int k = 0; k < stored; k += kRow) {
-      uint32_t e[kRow];
+      // without branches: the eight codes, then their bitmap words and ranks
+      // (an own slot reads word loc/32 and keeps loc)
+      uint32_t code[kRow], w[kRow], pre[kRow], e[kRow];
 #pragma unroll
       for (int u = 0; u < kRow; ++u) {
-        e[u] = 0u;
-        if (k + u < stored) {
-          const uint32_t code = (uint32_t)kid[(k + u) * kNlistBlock + lane];
-          const uint32_t v = code & 0xFFFFu & ~kOwn;
-          uint32_t en;
-          if (code & kOwn) {
-            en = v;
-          } else {
-            const uint32_t w = bits[v >> 5];
-            en = (uint32_t)kTile + wpre[v >> 5] + __popc(w & ((1u << (v & 31)) - 1u));
-          }
-          if (kWide) en |= (code >> kTypeShift) << kEntryTypeShift;
-          e[u] = en & 0xFFFFu;
-        }
+        code[u] = (uint32_t)kid[min(k + u, kmax) * kNlistBlock + lane];
+        if (k + u >= stored) code[u] = kOwn;  // past the list: entry 0
+      }
+#pragma unroll
+      for (int u = 0; u < kRow; ++u) {
+        const uint32_t v = code[u] & 0xFFFFu & ~kOwn;
+        w[u] = bits[v >> 5];
+        pre[u] = wpre[v >> 5];
+      }
+#pragma unroll
+      for (int u = 0; u < kRow; ++u) {
+        const uint32_t v = code[u] & 0xFFFFu & ~kOwn;
+        uint32_t en = (code[u] & kOwn) ? v : (uint32_t)kTile + pre[u] + __popc(w[u] & ((1u << (v & 31)) - 1u));
+        if (kWide) en |= (code[u] >> kTypeShift) << kEntryTypeShift;
+        e[u] = k + u < stored ? en & 0xFFFFu : 0u;
       }
       store_row<kStream>(B.NL, C, k, i, e);
     }
