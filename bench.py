@@ -564,6 +564,7 @@ def main():
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "traffic_GBps": None if traffic is None else traffic / per_launch_s / 1e9,
+            "traffic_frac": None if traffic is None else traffic / per_launch_s / 1e9 / HBM_PEAK_GBS,
             "kernel": "k_step_f32 (instance %d)" % st1["step_variant"], "mean_launch_us": per_launch_s * 1e6,
             "alg_bytes_per_particle_step": step_kernel_bytes(st1["nl_mean"]), "nl_mean": st1["nl_mean"],
         },
