@@ -382,7 +382,7 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const JobDev* 
   using code_t = typename std::conditional<kWide, uint32_t, uint16_t>::type;
   constexpr uint32_t kOwn = kWide ? 0x10000u : 0x8000u;
   // codes [kmax + 1][256] (row kmax takes the appends beyond the capacity);
-  // wide instance: then particle indices [kmax][256]
+  // wide instance: then particle indices [kmax + 1][256]
   extern __shared__ uint32_t dyn[];
   __shared__ uint32_t ckey[kColCap], cb[kColCap], ce[kColCap], coff[kColCap + 1];
   __shared__ uint32_t bits[kCandCap / 32], wpre[kCandCap / 32];
@@ -581,22 +581,9 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const JobDev* 
         const bool own = loc + u < (uint32_t)kTile;
         uint32_t code = own ? kOwn | (loc + u) : t + u;
         if (kWide) code |= (w >> kTypeShift) << kTypeShift;
-        if (sorted) {
-          // insertion by particle index (the order of the FP64 sums)
-          if (take && cnt < kmax) {
-            const uint32_t qid = w & kIdMask;
-            int k = cnt;
-            while (k > 0 && kkey[(k - 1) * kNlistBlock + lane] > qid) {
-              kkey[k * kNlistBlock + lane] = kkey[(k - 1) * kNlistBlock + lane];
-              kid[k * kNlistBlock + lane] = kid[(k - 1) * kNlistBlock + lane];
-              --k;
-            }
-            kkey[k * kNlistBlock + lane] = qid;
-            kid[k * kNlistBlock + lane] = (code_t)code;
-          }
-        } else {
-          kid[min(cnt, kmax) * kNlistBlock + lane] = (code_t)code;
-        }
+        const int row = min(cnt, kmax);
+        kid[row * kNlistBlock + lane] = (code_t)code;
+        if (sorted) kkey[row * kNlistBlock + lane] = w & kIdMask;  // ordered after the walk
         cnt += take ? 1 : 0;
       }
     };
@@ -657,9 +644,26 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const JobDev* 
       }
     }
   }
+  const int stored = valid ? (cnt < kmax ? cnt : kmax) : 0;
+  if (sorted) {
+    // FP64 class: the lane's list by particle index (the order of the FP64
+    // sums), insertion sort in LDS over its few entries
+    for (int a = 1; a < stored; ++a) {
+      const uint32_t key = kkey[a * kNlistBlock + lane];
+      const code_t c = kid[a * kNlistBlock + lane];
+      int b = a;
+      for (; b > 0; --b) {
+        const uint32_t prev = kkey[(b - 1) * kNlistBlock + lane];
+        if (prev <= key) break;
+        kkey[b * kNlistBlock + lane] = prev;
+        kid[b * kNlistBlock + lane] = kid[(b - 1) * kNlistBlock + lane];
+      }
+      kkey[b * kNlistBlock + lane] = key;
+      kid[b * kNlistBlock + lane] = c;
+    }
+  }
   // 3. the halo: kept candidates outside the tile, marked in the bitmap,
   // ranked in candidate order
-  const int stored = valid ? (cnt < kmax ? cnt : kmax) : 0;
   for (int k = 0; k < stored; k += kRow) {
     // eight codes read together (rows past the list read row kmax, in bounds)
     uint32_t code[kRow];
@@ -751,9 +755,9 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const JobDev* 
 
 // Dynamic LDS of k_nlist for a list capacity kmax: the kept neighbours' codes
 // (16-bit, or 32-bit plus particle indices in the wide instance), with one
-// spare row of codes.
+// spare row.
 constexpr size_t nlist_lds_bytes(int kmax, bool wide) {
-  return (size_t)(kmax + 1) * kNlistBlock * (wide ? 4 : 2) + (wide ? (size_t)kmax * kNlistBlock * 4 : 0);
+  return (size_t)(kmax + 1) * kNlistBlock * (wide ? 8 : 2);
 }
 
 // Static LDS of k_nlist (column table, halo bitmap).
