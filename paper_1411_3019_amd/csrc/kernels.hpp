@@ -689,19 +689,26 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const JobDev* 
   // the halo list: each lane takes bitmap words and writes their set bits
   for (uint32_t wi = lane; wi < (M + 31u) / 32u; wi += kNlistBlock) {
     uint32_t w = bits[wi];
+    // by columns: the column holding the word's first bit, found once per
+    // word (later bits of the word step forward from it)
+    uint32_t h = 0u;
+    if (!by_span && w != 0u) {
+      uint32_t lo = 0u, hi = kColCap;
+      while (hi - lo > 1u) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (coff[mid] <= wi * 32u)
+          lo = mid;
+        else
+          hi = mid;
+      }
+      h = lo;
+    }
     for (uint32_t rank = wpre[wi]; w != 0u && rank < hcap; ++rank, w &= w - 1u) {
       const uint32_t t = wi * 32u + (uint32_t)(__ffs(w) - 1);
       uint32_t slot = span_lo + t;
       if (!by_span) {
-        int lo = 0, hi = kColCap;
-        while (hi - lo > 1) {
-          const int mid = (lo + hi) >> 1;
-          if (coff[mid] <= t)
-            lo = mid;
-          else
-            hi = mid;
-        }
-        slot = cb[lo] + (t - coff[lo]);
+        while (coff[h + 1] <= t) ++h;
+        slot = cb[h] + (t - coff[h]);
       }
       B.HALO[gt * (int64_t)hcap + rank] = (uint32_t)(base + slot);
     }
