@@ -415,6 +415,8 @@ struct Engine {
   Chunk* chunks_d = nullptr;
   uint32_t* chunk_sums = nullptr;
   double* diag_d = nullptr;  // [4 kDiagBlocks] partials, then [4] results
+  double* diag_many = nullptr;  // [4] results per job of finish_many
+  int64_t diag_many_cap = 0;
   double* scratch_d = nullptr;  // this device's `scratch` (md_get_state_dev_noalloc)
   bool no_alloc = false;        // set during md_get_state_dev_noalloc: device and pinned allocations fail
   int64_t chunk_cap = 0;
@@ -466,7 +468,8 @@ struct Engine {
                     B.NZD[0], B.NZD[1], B.NZF[0], B.NZF[1], B.FC, B.OX, B.OP, B.OF, B.OD, B.NL, B.NCNT, B.HALO, B.HCNT, B.BM, B.WOFF,
                     B.CCNT, B.CSTART, B.RASTER, B.CID, B.RANK, B.INV, B.SRC, B.PK, B.TYPE[0], B.TYPE[1],
                     (void*)B.models, B.TACC, B.NLSTAT, B.jobs, B.book, step_tiles_job, step_tiles_first,
-                    step_counts, aux_tiles_job, aux_tiles_first, chunks_d, chunk_sums, ranges_d, diag_d};
+                    step_counts, aux_tiles_job, aux_tiles_first, chunks_d, chunk_sums, ranges_d, diag_d,
+                    diag_many};
     for (void* p : ptrs)
       if (p) (void)hipFree(p);
     std::memset(&B, 0, sizeof(B));
@@ -478,6 +481,8 @@ struct Engine {
     chunk_sums = nullptr;
     ranges_d = nullptr;
     diag_d = nullptr;
+    diag_many = nullptr;
+    diag_many_cap = 0;
     if (book_h) (void)hipHostFree(book_h);
     if (stage) (void)hipHostFree(stage);
     if (arena) (void)hipHostFree(arena);
@@ -1499,6 +1504,106 @@ struct Engine {
     }
     return h.status;
   }
+
+  // finish() for several jobs into host arrays: one list build for the jobs
+  // whose lists are stale, the finish and diagnostics kernels and copies of
+  // every job enqueued back to back, and one wait.  status[q] receives job
+  // ids[q]'s own status (or MD_ENOTFOUND).
+  int finish_many(const int* ids, int n, double* const* xs, double* const* ps, md_diag* diags, int* status) {
+    std::vector<int> need;
+    for (int q = 0; q < n; ++q) {
+      const int j = ids[q];
+      if (j < 0 || j >= max_jobs || !jobs[j].used) continue;
+      const HostJob& h = jobs[j];
+      if (h.n > 0 && h.status == MD_OK && (!h.built || h.A_now > h.dev.half_skin)) need.push_back(j);
+    }
+    if (!need.empty()) MDCHK(rebuild_now(need));
+    size_t bytes = 4 * sizeof(double) * (size_t)n;
+    std::vector<size_t> at(n, 0);
+    for (int q = 0; q < n; ++q) {
+      const int j = ids[q];
+      if (j < 0 || j >= max_jobs || !jobs[j].used) continue;
+      HostJob& h = jobs[j];
+      h.dev.step0 = h.step;
+      h.dev.remaining = 0;
+      at[q] = bytes;
+      bytes += 2 * sizeof(double) * 3 * (size_t)h.n;
+    }
+    if (n > diag_many_cap) {
+      if (diag_many) (void)hipFree(diag_many);
+      diag_many = nullptr;
+      diag_many_cap = 0;
+      MDCHK(dalloc(&diag_many, 4 * (size_t)n));
+      diag_many_cap = n;
+    }
+    MDCHK(ensure_stage(bytes));  // (waits for the stream)
+    MDCHK(upload_jobs());
+    char* st = (char*)stage;
+    std::vector<int> tj;
+    std::vector<int64_t> tf;
+    for (int q = 0; q < n; ++q) {
+      const int j = ids[q];
+      if (j < 0 || j >= max_jobs || !jobs[j].used || jobs[j].n == 0) continue;
+      const HostJob& h = jobs[j];
+      tj.clear();
+      tf.clear();
+      tiles_of(h, j, tj, tf);
+      MDCHK(upload_cached(aux_tiles_job, tj.data(), sizeof(int) * tj.size()));
+      MDCHK(upload_cached(aux_tiles_first, tf.data(), sizeof(int64_t) * tf.size()));
+      if (h.dev.force_fp64)
+        hipLaunchKernelGGL(k_finish<true>, dim3((unsigned)tj.size()), dim3(kTile), 0, stream, B, aux_tiles_job,
+                           aux_tiles_first);
+      else
+        hipLaunchKernelGGL(k_finish<false>, dim3((unsigned)tj.size()), dim3(kTile), 0, stream, B, aux_tiles_job,
+                           aux_tiles_first);
+      const int nb = (int)std::min<int64_t>(kDiagBlocks, (h.n + kDiagThreads - 1) / kDiagThreads);
+      // the partials are reused job after job (stream order)
+      hipLaunchKernelGGL(k_diag_partial, dim3(nb), dim3(kDiagThreads), 0, stream, B.OD, (int64_t)C, h.off, h.n,
+                         diag_d);
+      hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(kDiagThreads), 0, stream, diag_d, nb, diag_many + 4 * q);
+      HIPCHK(hipGetLastError());
+      const size_t vb = sizeof(double) * 3 * (size_t)h.n;
+      HIPCHK(hipMemcpyAsync(st + at[q], B.OX + 3 * h.off, vb, hipMemcpyDeviceToHost, stream));
+      HIPCHK(hipMemcpyAsync(st + at[q] + vb, B.OP + 3 * h.off, vb, hipMemcpyDeviceToHost, stream));
+    }
+    HIPCHK(hipMemcpyAsync(st, diag_many, 4 * sizeof(double) * (size_t)n, hipMemcpyDeviceToHost, stream));
+    MDCHK(sync());
+    for (int q = 0; q < n; ++q) {
+      const int j = ids[q];
+      if (j < 0 || j >= max_jobs || !jobs[j].used) {
+        if (status) status[q] = MD_ENOTFOUND;
+        continue;
+      }
+      const HostJob& h = jobs[j];
+      const size_t vb = sizeof(double) * 3 * (size_t)h.n;
+      if (h.n > 0) {
+        if (xs && xs[q]) std::memcpy(xs[q], st + at[q], vb);
+        if (ps && ps[q]) std::memcpy(ps[q], st + at[q] + vb, vb);
+      }
+      if (diags) {
+        md_diag& d = diags[q];
+        std::memset(&d, 0, sizeof(d));
+        const double* red = (const double*)st + 4 * q;
+        if (h.n > 0) {
+          d.K = red[0];
+          d.U = red[1];
+          d.gdist_max = red[2];
+          d.nv_max = red[3];
+        }
+        d.ndof = h.ndof;
+        d.kT = h.ndof > 0 ? 2.0 * d.K / h.ndof : 0.0;
+        d.step = h.step;
+        d.rebuilds = h.rebuilds;
+        d.newton_iter_max = h.newton_max;
+        d.nlist_max = h.nl_max;
+        d.error_index = h.n > 0 ? h.err_id : -1;
+        d.error_step = h.n > 0 ? h.err_step : -1;
+        d.exact_sum_breaches = h.sum_breaches;
+      }
+      if (status) status[q] = h.status;
+    }
+    return MD_OK;
+  }
 };
 
 // ---------------------------------------------------------------------------
@@ -1970,6 +2075,14 @@ int md_pool_fetch(md_pool* pool, int job_id, double* x, double* p, md_diag* diag
   if (!pool->eng.jobs[job_id].used) return MD_ENOTFOUND;
   MDCHK(pool->eng.drain());
   return pool->eng.finish(job_id, x, p, nullptr, diag);
+}
+
+int md_pool_fetch_many(md_pool* pool, const int* job_ids, int n, double* const* x, double* const* p, md_diag* diag,
+                       int* status) {
+  if (!pool || n < 0 || (n > 0 && !job_ids)) return MD_EINVAL;
+  if (n == 0) return MD_OK;
+  MDCHK(pool->eng.drain());
+  return pool->eng.finish_many(job_ids, n, x, p, diag, status);
 }
 
 int md_pool_release(md_pool* pool, int job_id) {

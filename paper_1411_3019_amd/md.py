@@ -24,7 +24,7 @@ SYMBOLS = ["md_create", "md_set_surface", "md_set_particles", "md_step", "md_get
            "md_strerror", "md_job_footprint", "md_pool_create", "md_pool_admit", "md_pool_run", "md_pool_poll",
            "md_pool_fetch", "md_pool_release", "md_pool_usage", "md_pool_destroy", "md_get_stats",
            "md_pool_get_stats", "md_tune", "md_set_model", "md_set_particles_dev", "md_get_state_dev",
-           "md_get_state_dev_noalloc", "md_pool_launch"]
+           "md_get_state_dev_noalloc", "md_pool_launch", "md_pool_fetch_many"]
 MD_MAX_TYPES = 4
 
 
@@ -198,6 +198,8 @@ def lib():
         L.md_pool_admit.argtypes = [vp, C.POINTER(_JobDesc), C.POINTER(C.c_int)]
         L.md_pool_run.argtypes = [vp, C.c_int]
         L.md_pool_launch.argtypes = [vp, C.c_int]
+        L.md_pool_fetch_many.argtypes = [vp, C.POINTER(C.c_int), C.c_int, C.POINTER(dp), C.POINTER(dp),
+                                         C.POINTER(_Diag), C.POINTER(C.c_int)]
         L.md_pool_poll.argtypes = [vp, C.POINTER(C.c_int), C.c_int, C.POINTER(C.c_int)]
         L.md_pool_fetch.argtypes = [vp, C.c_int, dp, dp, C.POINTER(_Diag)]
         L.md_pool_release.argtypes = [vp, C.c_int]
@@ -210,7 +212,7 @@ def lib():
         for name in ("md_create", "md_set_surface", "md_set_particles", "md_set_model", "md_step", "md_get_state",
                      "md_set_particles_dev", "md_get_state_dev", "md_get_state_dev_noalloc",
                      "md_pool_create", "md_pool_admit", "md_pool_run", "md_pool_launch", "md_pool_poll",
-                     "md_pool_fetch",
+                     "md_pool_fetch", "md_pool_fetch_many",
                      "md_pool_release", "md_pool_usage", "md_get_stats", "md_pool_get_stats", "md_tune"):
             getattr(L, name).restype = C.c_int
         _lib = L
@@ -424,6 +426,24 @@ class Pool:
         d = _Diag()
         rc = lib().md_pool_fetch(self._h, int(job), _dp(x), _dp(p), C.byref(d))
         return rc, dict(x=x, p=p, diag=d.to_dict())
+
+    def fetch_many(self, jobs):
+        """md_pool_fetch_many: [(status, dict(x, p, diag))] for the given job ids,
+        with one wait for all of them."""
+        jobs = [int(j) for j in jobs]
+        n = len(jobs)
+        if n == 0:
+            return []
+        xs = [np.zeros((self._keep.get(j, 0), 3)) for j in jobs]
+        ps = [np.zeros((self._keep.get(j, 0), 3)) for j in jobs]
+        ids = (C.c_int * n)(*jobs)
+        DP = C.POINTER(C.c_double)
+        xa = (DP * n)(*[_dp(a) for a in xs])
+        pa = (DP * n)(*[_dp(a) for a in ps])
+        ds = (_Diag * n)()
+        st = (C.c_int * n)()
+        _check(lib().md_pool_fetch_many(self._h, ids, n, xa, pa, ds, st), "md_pool_fetch_many")
+        return [(st[q], dict(x=xs[q], p=ps[q], diag=ds[q].to_dict())) for q in range(n)]
 
     def release(self, job: int):
         _check(lib().md_pool_release(self._h, int(job)), "md_pool_release")

@@ -7,7 +7,8 @@ together by one chunk of steps (md_pool_launch, which returns while the chunk
 runs, so the next admissions overlap it; md_pool_poll collects it), and
 fetches and releases the jobs that finished, so later arrivals are admitted as
 soon as room frees up and their work shares launches with the jobs already
-running.  Latency of a job is its completion time minus its arrival time.
+running; the finished jobs of a chunk are fetched together (md_pool_fetch_many).
+Latency of a job is its completion time minus its arrival time.
 
 `run_plain` is the reference point: one job at a time, one context per job,
 one launch per step (no graphs), the same kernels.
@@ -81,9 +82,10 @@ def serve(jobs, budget_bytes: int, max_jobs: int, chunk: int = 32, realtime: boo
                 waiting.popleft()
             freed = False
             if running:
-                for pid in pool.poll():
+                done = pool.poll()
+                # the finished jobs' states, read together (one wait)
+                for pid, (rc, res) in zip(done, pool.fetch_many(done)):
                     j = resident.pop(pid)
-                    rc, res = pool.fetch(pid)
                     j.finished = clock() - t0
                     j.status = rc
                     if keep_results:

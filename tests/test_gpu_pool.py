@@ -81,6 +81,31 @@ def test_sparse_jobs_build_lists():
         assert e < 1e-6
 
 
+def test_fetch_many_matches_fetch():
+    """md_pool_fetch_many (the finished jobs read together, one wait) gives the
+    same bits as md_pool_fetch one job at a time; an unknown id reports
+    MD_ENOTFOUND in its status."""
+    from paper_1411_3019_amd import md
+    jobs = _serving_jobs([7, 8, 9, 11], lambda j: 80 + 13 * j)
+    pool = md.Pool(256 << 20, 8)
+    ids = [pool.admit(j.params, j.surface, j.surf, j.x, j.p, j.nsteps) for j in jobs]
+    print("[gpu] fetch_many", [(j.surface, j.n, j.nsteps) for j in jobs], flush=True)
+    done = set()
+    while not done >= set(ids):
+        pool.run(32)
+        done |= set(pool.poll())
+    many = pool.fetch_many(ids + [4])
+    assert many[-1][0] == md.MD_ENOTFOUND
+    for pid, (rc, res) in zip(ids, many):
+        rc1, one = pool.fetch(pid)
+        assert rc == rc1 == 0
+        assert np.array_equal(res["x"], one["x"]) and np.array_equal(res["p"], one["p"])
+        for key, v in one["diag"].items():
+            assert res["diag"][key] == v, key
+        assert res["diag"]["step"] == jobs[ids.index(pid)].nsteps
+    pool.close()
+
+
 def test_admission_backpressure_small_budget():
     """A budget that holds only a few jobs: MD_EAGAIN keeps the rest waiting;
     all of them finish, and the pool never holds more than the budget."""

@@ -44,6 +44,9 @@ class FakePool:
     def fetch(self, jid):
         return 0, {}
 
+    def fetch_many(self, jids):
+        return [self.fetch(j) for j in jids]
+
     def release(self, jid):
         del self.res[jid]
 
