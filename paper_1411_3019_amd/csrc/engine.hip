@@ -1028,9 +1028,12 @@ struct Engine {
     if ((int64_t)(cb.size() + cc.size()) > chunk_cap || (int64_t)tj.size() > tile_cap ||
         (int64_t)(rb.size() + rcnt.size() + rtacc.size()) > range_cap)
       return MD_ENOMEM;
-    bool wide = false;  // FP64-class or bead-model jobs among those built
-    for (int j : set) wide = wide || jobs[j].dev.force_fp64 || jobs[j].model;
-    const size_t lds = nlist_lds_bytes(kmax, wide);
+    bool wide = false, sorted = false;  // FP64-class or bead-model jobs among those built; FP64-class ones
+    for (int j : set) {
+      wide = wide || jobs[j].dev.force_fp64 || jobs[j].model;
+      sorted = sorted || jobs[j].dev.force_fp64;
+    }
+    const size_t lds = nlist_lds_bytes(kmax, wide, sorted);
     if ((int64_t)lds + nlist_static_lds(wide) > (int64_t)lds_max) return MD_ENOMEM;
     MDCHK(upload_jobs());
     MDCHK(upload_cached(aux_tiles_job, tj.data(), sizeof(int) * tj.size()));

@@ -382,7 +382,8 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const JobDev* 
   using code_t = typename std::conditional<kWide, uint32_t, uint16_t>::type;
   constexpr uint32_t kOwn = kWide ? 0x10000u : 0x8000u;
   // codes [kmax + 1][256] (row kmax takes the appends beyond the capacity);
-  // wide instance: then particle indices [kmax + 1][256]
+  // wide instance with FP64-class jobs in the build: then particle indices
+  // [kmax + 1][256]
   extern __shared__ uint32_t dyn[];
   __shared__ uint32_t ckey[kColCap], cb[kColCap], ce[kColCap], coff[kColCap + 1];
   __shared__ uint32_t bits[kCandCap / 32], wpre[kCandCap / 32];
@@ -761,10 +762,10 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const JobDev* 
 }
 
 // Dynamic LDS of k_nlist for a list capacity kmax: the kept neighbours' codes
-// (16-bit, or 32-bit plus particle indices in the wide instance), with one
-// spare row.
-constexpr size_t nlist_lds_bytes(int kmax, bool wide) {
-  return (size_t)(kmax + 1) * kNlistBlock * (wide ? 8 : 2);
+// (16-bit, or 32-bit in the wide instance, then the particle indices when an
+// FP64-class job is among those built), with one spare row.
+constexpr size_t nlist_lds_bytes(int kmax, bool wide, bool sorted = true) {
+  return (size_t)(kmax + 1) * kNlistBlock * (wide ? (sorted ? 8 : 4) : 2);
 }
 
 // Static LDS of k_nlist (column table, halo bitmap).
