@@ -415,6 +415,8 @@ struct Engine {
   Chunk* chunks_d = nullptr;
   uint32_t* chunk_sums = nullptr;
   double* diag_d = nullptr;  // [4 kDiagBlocks] partials, then [4] results
+  uint32_t* kkey_d = nullptr;  // list build: FP64-class particle indices that do not fit LDS
+  int64_t kkey_cap = 0;
   double* diag_many = nullptr;  // [4] results per job of finish_many
   int64_t diag_many_cap = 0;
   double* scratch_d = nullptr;  // this device's `scratch` (md_get_state_dev_noalloc)
@@ -469,7 +471,7 @@ struct Engine {
                     B.CCNT, B.CSTART, B.RASTER, B.CID, B.RANK, B.INV, B.SRC, B.PK, B.TYPE[0], B.TYPE[1],
                     (void*)B.models, B.TACC, B.NLSTAT, B.jobs, B.book, step_tiles_job, step_tiles_first,
                     step_counts, aux_tiles_job, aux_tiles_first, chunks_d, chunk_sums, ranges_d, diag_d,
-                    diag_many};
+                    diag_many, kkey_d};
     for (void* p : ptrs)
       if (p) (void)hipFree(p);
     std::memset(&B, 0, sizeof(B));
@@ -483,6 +485,8 @@ struct Engine {
     diag_d = nullptr;
     diag_many = nullptr;
     diag_many_cap = 0;
+    kkey_d = nullptr;
+    kkey_cap = 0;
     if (book_h) (void)hipHostFree(book_h);
     if (stage) (void)hipHostFree(stage);
     if (arena) (void)hipHostFree(arena);
@@ -1033,7 +1037,21 @@ struct Engine {
       wide = wide || jobs[j].dev.force_fp64 || jobs[j].model;
       sorted = sorted || jobs[j].dev.force_fp64;
     }
-    const size_t lds = nlist_lds_bytes(kmax, wide, sorted);
+    size_t lds = nlist_lds_bytes(kmax, wide, sorted);
+    B.KKEY = nullptr;
+    if (sorted && (int64_t)lds + nlist_static_lds(wide) > (int64_t)lds_max) {
+      // long FP64-class lists: their particle indices go to global memory
+      lds = nlist_lds_bytes(kmax, wide, false);
+      const int64_t need = (int64_t)tj.size() * (kmax + 1) * kNlistBlock;
+      if (need > kkey_cap) {
+        if (kkey_d) (void)hipFree(kkey_d);
+        kkey_d = nullptr;
+        kkey_cap = 0;
+        MDCHK(dalloc(&kkey_d, (size_t)need));
+        kkey_cap = need;
+      }
+      B.KKEY = kkey_d;
+    }
     if ((int64_t)lds + nlist_static_lds(wide) > (int64_t)lds_max) return MD_ENOMEM;
     MDCHK(upload_jobs());
     MDCHK(upload_cached(aux_tiles_job, tj.data(), sizeof(int) * tj.size()));

@@ -383,7 +383,7 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const JobDev* 
   constexpr uint32_t kOwn = kWide ? 0x10000u : 0x8000u;
   // codes [kmax + 1][256] (row kmax takes the appends beyond the capacity);
   // wide instance with FP64-class jobs in the build: then particle indices
-  // [kmax + 1][256]
+  // [kmax + 1][256] (in global memory, B.KKEY, when they would not fit)
   extern __shared__ uint32_t dyn[];
   __shared__ uint32_t ckey[kColCap], cb[kColCap], ce[kColCap], coff[kColCap + 1];
   __shared__ uint32_t bits[kCandCap / 32], wpre[kCandCap / 32];
@@ -392,7 +392,8 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const JobDev* 
   __shared__ int fail;
   const int kmax = B.kmax;
   code_t* kid = reinterpret_cast<code_t*>(dyn);
-  uint32_t* kkey = dyn + ((size_t)(kmax + 1) * kNlistBlock * sizeof(code_t) + 3) / 4;
+  uint32_t* kkey = B.KKEY ? B.KKEY + (size_t)blockIdx.x * (kmax + 1) * kNlistBlock
+                         : dyn + ((size_t)(kmax + 1) * kNlistBlock * sizeof(code_t) + 3) / 4;
   const int tile = (int)blockIdx.x;
   const int job = uniform_int(tile_job[tile]);
   const JobDev& J = jobs[job];

@@ -100,6 +100,24 @@ def test_free_gas_periodic_box(force_fp64):
     assert st["diag"]["ndof"] == 3.0 * n
 
 
+@pytest.mark.parametrize("force_fp64", [0, 1])
+def test_large_halos_grow_and_spill(force_fp64):
+    """A dense periodic LJ liquid (volume fraction 0.3) with a long list radius
+    (rc 2.5 + skin 1.0): each tile's halo holds well over a thousand slots, more
+    than the default halo capacity (the lists are built again with a larger
+    one) and more than any instance stages in LDS (the rest is read through the
+    halo list).  Against the oracle over 20 steps."""
+    n = 4000
+    L = (n * np.pi / 6.0 / 0.3) ** (1.0 / 3.0)
+    s = gen.box_gas(n, L, 23)
+    print(f"[gpu] large halos n={n} L={L:.2f} force_fp64={force_fp64}", flush=True)
+    kw = dict(dt=0.002, rc=2.5, seed=8, force_fp64=force_fp64, skin=1.0)
+    ref, st = _compare(s, 20, **kw)
+    e = rel_pos_err(st["x"], ref.x)
+    report(f"large halos fp64={force_fp64} 20 steps", x=e)
+    assert e < (1e-10 if force_fp64 else 1e-6)
+
+
 def test_pool_with_degenerate_jobs():
     """Empty and one-particle jobs in a pool beside ordinary ones: all finish,
     and the one-particle job's result equals the same job run alone."""
