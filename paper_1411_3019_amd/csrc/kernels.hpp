@@ -117,7 +117,8 @@ __global__ void __launch_bounds__(kTile) k_count(DevBufs B, const int* __restric
 }
 
 // Destination of every slot in the new (cell) order: SRC[new slot] = old slot,
-// and the inverse permutation by particle index.
+// and, for jobs with a bead model (the only readers: bonded terms look up the
+// beads of a molecule by index), the inverse permutation by particle index.
 __global__ void __launch_bounds__(kTile) k_perm(DevBufs B, const int* __restrict__ tile_job,
                                                 const int64_t* __restrict__ tile_first) {
   const int job = uniform_int(tile_job[blockIdx.x]);
@@ -126,10 +127,10 @@ __global__ void __launch_bounds__(kTile) k_perm(DevBufs B, const int* __restrict
   const int64_t off = J.off;
   if (i >= off + J.n) return;
   // the independent loads first, together
-  const uint32_t cid = B.CID[i], rank = B.RANK[i], id = B.ID[J.scur][i];
+  const uint32_t cid = B.CID[i], rank = B.RANK[i];
   const int64_t d = off + B.CSTART[off + cid] + rank;
   B.SRC[d] = (uint32_t)(i - off);
-  B.INV[off + id] = (uint32_t)(d - off);
+  if (J.model) B.INV[off + B.ID[J.scur][i]] = (uint32_t)(d - off);
 }
 
 // Gather the state into the new order: consecutive threads write consecutive
