@@ -132,7 +132,7 @@ struct DevBufs {
   uint32_t* RANK;      // rank within the cell per slot
   uint32_t* INV;       // slot of each particle index after the last sort, by job offset + index (bead-model jobs only)
   uint32_t* SRC;       // old slot (job-relative) of each new slot during a sort
-  uint32_t* KKEY;      // list build, FP64 class, when its particle indices do not fit LDS: [tile][kmax + 1][256], else null
+  uint32_t* KKEY;      // list build, wide instance, when the window records do not fit LDS: [tile][256 + hcap], else null
   float4* PK;          // list-build candidates in the sorted order: FP32 position, particle index
                        // (bead model: type in the top two bits)
   uint8_t* TYPE[2];    // bead type (jobs with a bead model); parity as ID

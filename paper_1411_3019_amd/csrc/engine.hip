@@ -415,8 +415,9 @@ struct Engine {
   Chunk* chunks_d = nullptr;
   uint32_t* chunk_sums = nullptr;
   double* diag_d = nullptr;  // [4 kDiagBlocks] partials, then [4] results
-  uint32_t* kkey_d = nullptr;  // list build: FP64-class particle indices that do not fit LDS
+  uint32_t* kkey_d = nullptr;  // list build: window records of FP64-class / bead-model tiles that do not fit LDS
   int64_t kkey_cap = 0;
+  bool list_table_global = false;  // MD_LIST_TABLE_GLOBAL: keep those records in global memory always
   double* diag_many = nullptr;  // [4] results per job of finish_many
   int64_t diag_many_cap = 0;
   double* scratch_d = nullptr;  // this device's `scratch` (md_get_state_dev_noalloc)
@@ -534,6 +535,7 @@ struct Engine {
     B.C = C;
     B.kmax = kmax;
     B.hcap = hcap;
+    if (const char* v = std::getenv("MD_LIST_TABLE_GLOBAL")) list_table_global = std::atoi(v) != 0;
     if (const char* v = std::getenv("MD_STEP_VARIANT")) f32_variant = std::max(0, std::min(kNumStepVariants - 1, std::atoi(v)));
     {
       int v = 0;
@@ -1032,17 +1034,15 @@ struct Engine {
     if ((int64_t)(cb.size() + cc.size()) > chunk_cap || (int64_t)tj.size() > tile_cap ||
         (int64_t)(rb.size() + rcnt.size() + rtacc.size()) > range_cap)
       return MD_ENOMEM;
-    bool wide = false, sorted = false;  // FP64-class or bead-model jobs among those built; FP64-class ones
-    for (int j : set) {
-      wide = wide || jobs[j].dev.force_fp64 || jobs[j].model;
-      sorted = sorted || jobs[j].dev.force_fp64;
-    }
-    size_t lds = nlist_lds_bytes(kmax, wide, sorted);
+    bool wide = false;  // FP64-class or bead-model jobs among those built
+    for (int j : set) wide = wide || jobs[j].dev.force_fp64 || jobs[j].model;
+    // the wide instance's table of window records: in LDS when it fits
+    const int64_t wlen = (int64_t)kTile + hcap;
+    size_t lds = nlist_lds_bytes(kmax, wide ? wlen : 0);
     B.KKEY = nullptr;
-    if (sorted && (int64_t)lds + nlist_static_lds(wide) > (int64_t)lds_max) {
-      // long FP64-class lists: their particle indices go to global memory
-      lds = nlist_lds_bytes(kmax, wide, false);
-      const int64_t need = (int64_t)tj.size() * (kmax + 1) * kNlistBlock;
+    if (wide && (list_table_global || (int64_t)lds + nlist_static_lds(wide) > (int64_t)lds_max)) {
+      lds = nlist_lds_bytes(kmax, 0);
+      const int64_t need = (int64_t)tj.size() * wlen;
       if (need > kkey_cap) {
         if (kkey_d) (void)hipFree(kkey_d);
         kkey_d = nullptr;

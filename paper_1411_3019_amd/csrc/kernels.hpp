@@ -328,6 +328,8 @@ __device__ __forceinline__ uint32_t block_scan(uint32_t v, uint32_t* sh, uint32_
 //     are written as 16-bit entries, with the halo list of the tile.
 // FP64 class: lists sorted by particle index (the order of the FP64 sums).
 // FP32 class: lists in the order found.
+// FP64-class and bead-model jobs look up the index (and type) of each window
+// entry in a table of the window's record words, made with the halo list.
 // The FP32 distance test uses the list radius widened by a bound on the FP32
 // rounding of both positions and of the separation (times eight), so it
 // accepts every pair closer than the list radius; the few extra pairs it may
@@ -379,12 +381,12 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const JobDev* 
                                                        const int* __restrict__ tile_job,
                                                        const int64_t* __restrict__ tile_first) {
   // codes of kept neighbours: own-tile slots as kOwn | local index, others as
-  // their candidate number; bead model: the partner's type in the top bits
-  using code_t = typename std::conditional<kWide, uint32_t, uint16_t>::type;
-  constexpr uint32_t kOwn = kWide ? 0x10000u : 0x8000u;
+  // their candidate number
+  using code_t = uint16_t;
+  constexpr uint32_t kOwn = 0x8000u;
   // codes [kmax + 1][256] (row kmax takes the appends beyond the capacity);
-  // wide instance with FP64-class jobs in the build: then particle indices
-  // [kmax + 1][256] (in global memory, B.KKEY, when they would not fit)
+  // wide instance: then the record words (particle index, bead type) of the
+  // window, [256 + hcap] (in global memory, B.KKEY, when they would not fit)
   extern __shared__ uint32_t dyn[];
   __shared__ uint32_t ckey[kColCap], cb[kColCap], ce[kColCap], coff[kColCap + 1];
   __shared__ uint32_t bits[kCandCap / 32], wpre[kCandCap / 32];
@@ -393,8 +395,8 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const JobDev* 
   __shared__ int fail;
   const int kmax = B.kmax;
   code_t* kid = reinterpret_cast<code_t*>(dyn);
-  uint32_t* kkey = B.KKEY ? B.KKEY + (size_t)blockIdx.x * (kmax + 1) * kNlistBlock
-                         : dyn + ((size_t)(kmax + 1) * kNlistBlock * sizeof(code_t) + 3) / 4;
+  const uint32_t wlen = (uint32_t)kTile + (uint32_t)B.hcap;  // window length
+  uint32_t* wrec = B.KKEY ? B.KKEY + (size_t)blockIdx.x * wlen : dyn + (size_t)(kmax + 1) * kNlistBlock / 2;
   const int tile = (int)blockIdx.x;
   const int job = uniform_int(tile_job[tile]);
   const JobDev& J = jobs[job];
@@ -426,6 +428,8 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const JobDev* 
   for (int w = lane; w < kCandCap / 32; w += kNlistBlock) bits[w] = 0u;
   if (lane == 0) fail = 0, span_lo = 0xFFFFFFFFu, span_hi = 0u;
   const double* __restrict__ X = B.X[J.xcur ^ 1];  // the sorted copies written by k_gather
+  const float4* __restrict__ PK = B.PK + base;
+  if (kWide) wrec[lane] = valid ? __float_as_uint(PK[first_local + lane].w) : 0u;
   double xi = 0.0, yi = 0.0, zi = 0.0;
   int cx = 0, cy = 0, cz = 0;
   if (valid) {
@@ -562,7 +566,6 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const JobDev* 
       }
     }
     const uint32_t bpm = (uint32_t)J.bpm, mstart = bpm != 0u ? (myid / bpm) * bpm : 0u;  // bpm = 0: no molecules
-    const float4* __restrict__ PK = B.PK + base;
     const uint32_t loc0 = 0u - first_local;  // own-tile index of job slot 0 (mod 2^32)
     // four candidates r[0..3] at slots j .. j+3 (rem: candidates left from j)
     auto test4 = [&](const float4* r, int rem, uint32_t t, uint32_t loc) {
@@ -582,11 +585,8 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const JobDev* 
         }
         take = take && u < rem && loc + u != (uint32_t)lane;
         const bool own = loc + u < (uint32_t)kTile;
-        uint32_t code = own ? kOwn | (loc + u) : t + u;
-        if (kWide) code |= (w >> kTypeShift) << kTypeShift;
-        const int row = min(cnt, kmax);
-        kid[row * kNlistBlock + lane] = (code_t)code;
-        if (sorted) kkey[row * kNlistBlock + lane] = w & kIdMask;  // ordered after the walk
+        const uint32_t code = own ? kOwn | (loc + u) : t + u;
+        kid[min(cnt, kmax) * kNlistBlock + lane] = (code_t)code;
         cnt += take ? 1 : 0;
       }
     };
@@ -648,23 +648,6 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const JobDev* 
     }
   }
   const int stored = valid ? (cnt < kmax ? cnt : kmax) : 0;
-  if (sorted) {
-    // FP64 class: the lane's list by particle index (the order of the FP64
-    // sums), insertion sort in LDS over its few entries
-    for (int a = 1; a < stored; ++a) {
-      const uint32_t key = kkey[a * kNlistBlock + lane];
-      const code_t c = kid[a * kNlistBlock + lane];
-      int b = a;
-      for (; b > 0; --b) {
-        const uint32_t prev = kkey[(b - 1) * kNlistBlock + lane];
-        if (prev <= key) break;
-        kkey[b * kNlistBlock + lane] = prev;
-        kid[b * kNlistBlock + lane] = kid[(b - 1) * kNlistBlock + lane];
-      }
-      kkey[b * kNlistBlock + lane] = key;
-      kid[b * kNlistBlock + lane] = c;
-    }
-  }
   // 3. the halo: kept candidates outside the tile, marked in the bitmap,
   // ranked in candidate order
   for (int k = 0; k < stored; k += kRow) {
@@ -714,6 +697,7 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const JobDev* 
         slot = cb[h] + (t - coff[h]);
       }
       B.HALO[gt * (int64_t)hcap + rank] = (uint32_t)(base + slot);
+      if (kWide) wrec[kTile + rank] = __float_as_uint(PK[slot].w);
     }
   }
   if (lane == 0) {
@@ -721,11 +705,15 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const JobDev* 
     // a halo beyond the capacity stops the job before its first step on these lists
     if (H > hcap) atomicMin(&K.stop_at, (long long)J.step0);
   }
+  if (kWide) __syncthreads();  // the window's records
+  // record word of window entry e (clamped: a halo beyond the capacity stops
+  // the job, its entries are never used)
+  auto rec = [&](uint32_t e) { return wrec[min(e, wlen - 1u)]; };
   if (valid) {
-    for (int k = 0; k < stored; k += kRow) {
-      // without branches: the eight codes, then their bitmap words and ranks
-      // (an own slot reads word loc/32 and keeps loc)
-      uint32_t code[kRow], w[kRow], pre[kRow], e[kRow];
+    // the window entries of codes k .. k+7, without branches: the codes, then
+    // their bitmap words and ranks (an own slot keeps its local index)
+    auto entries = [&](int k, uint32_t* e) {
+      uint32_t code[kRow], w[kRow], pre[kRow];
 #pragma unroll
       for (int u = 0; u < kRow; ++u) {
         code[u] = (uint32_t)kid[min(k + u, kmax) * kNlistBlock + lane];
@@ -733,15 +721,53 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const JobDev* 
       }
 #pragma unroll
       for (int u = 0; u < kRow; ++u) {
-        const uint32_t v = code[u] & 0xFFFFu & ~kOwn;
+        const uint32_t v = code[u] & ~kOwn;
         w[u] = bits[v >> 5];
         pre[u] = wpre[v >> 5];
       }
 #pragma unroll
       for (int u = 0; u < kRow; ++u) {
-        const uint32_t v = code[u] & 0xFFFFu & ~kOwn;
-        uint32_t en = (code[u] & kOwn) ? v : (uint32_t)kTile + pre[u] + __popc(w[u] & ((1u << (v & 31)) - 1u));
-        if (kWide) en |= (code[u] >> kTypeShift) << kEntryTypeShift;
+        const uint32_t v = code[u] & ~kOwn;
+        e[u] = (code[u] & kOwn) ? v : (uint32_t)kTile + pre[u] + __popc(w[u] & ((1u << (v & 31)) - 1u));
+      }
+    };
+    if (sorted) {
+      // FP64 class: the entries in place, then the lane's list by particle
+      // index (the order of the FP64 sums), insertion sort over its few entries
+      for (int k = 0; k < stored; k += kRow) {
+        uint32_t e[kRow];
+        entries(k, e);
+#pragma unroll
+        for (int u = 0; u < kRow; ++u)
+          if (k + u < stored) kid[(k + u) * kNlistBlock + lane] = (code_t)e[u];
+      }
+      const uint32_t idm = typed ? kIdMask : 0xFFFFFFFFu;
+      for (int a = 1; a < stored; ++a) {
+        const code_t c = kid[a * kNlistBlock + lane];
+        const uint32_t key = rec(c) & idm;
+        int b = a;
+        for (; b > 0; --b) {
+          const code_t prev = kid[(b - 1) * kNlistBlock + lane];
+          if ((rec(prev) & idm) <= key) break;
+          kid[b * kNlistBlock + lane] = prev;
+        }
+        kid[b * kNlistBlock + lane] = c;
+      }
+    }
+    for (int k = 0; k < stored; k += kRow) {
+      // the row's eight entries (FP64 class: already ordered)
+      uint32_t e[kRow];
+      if (sorted) {
+#pragma unroll
+        for (int u = 0; u < kRow; ++u) e[u] = (uint32_t)kid[min(k + u, kmax) * kNlistBlock + lane];
+      } else {
+        entries(k, e);
+      }
+#pragma unroll
+      for (int u = 0; u < kRow; ++u) {
+        uint32_t en = e[u];
+        // bead model: the partner's type in the top bits
+        if (typed) en |= (rec(en) >> kTypeShift) << kEntryTypeShift;
         e[u] = k + u < stored ? en & 0xFFFFu : 0u;
       }
       store_row<kStream>(B.NL, C, k, i, e);
@@ -763,11 +789,11 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const JobDev* 
   }
 }
 
-// Dynamic LDS of k_nlist for a list capacity kmax: the kept neighbours' codes
-// (16-bit, or 32-bit in the wide instance, then the particle indices when an
-// FP64-class job is among those built), with one spare row.
-constexpr size_t nlist_lds_bytes(int kmax, bool wide, bool sorted = true) {
-  return (size_t)(kmax + 1) * kNlistBlock * (wide ? (sorted ? 8 : 4) : 2);
+// Dynamic LDS of k_nlist for a list capacity kmax: the kept neighbours'
+// 16-bit codes, with one spare row, then table_words record words (the
+// window's, in the wide instance, when they are staged in LDS).
+constexpr size_t nlist_lds_bytes(int kmax, int64_t table_words) {
+  return (size_t)(kmax + 1) * kNlistBlock * 2 + 4 * (size_t)table_words;
 }
 
 // Static LDS of k_nlist (column table, halo bitmap).

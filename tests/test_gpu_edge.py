@@ -118,6 +118,30 @@ def test_large_halos_grow_and_spill(force_fp64):
     assert e < (1e-10 if force_fp64 else 1e-6)
 
 
+def test_window_records_in_global_memory(monkeypatch):
+    """FP64 class: the list build orders each list by particle index, looked up
+    in a table of the tile window's records, staged in LDS or (when it would
+    not fit, here forced) kept in global memory.  Both give the same lists, so
+    the same bits over 200 steps with several rebuilds, and the oracle's
+    trajectory."""
+    s = gen.torus(6000, 30.0, 10.0, 12)
+    print(f"[gpu] window records in global memory n={s.n}", flush=True)
+    kw = dict(dt=0.002, rc=2.5, seed=14, force_fp64=1, skin=0.3)
+    outs = []
+    for table_global in (0, 1):
+        monkeypatch.setenv("MD_LIST_TABLE_GLOBAL", str(table_global))
+        g = gpu_system(s, **kw)
+        g.step(200)
+        outs.append(g.get_state())
+        g.close()
+    assert outs[0]["diag"]["rebuilds"] >= 2
+    assert np.array_equal(outs[0]["x"], outs[1]["x"]) and np.array_equal(outs[0]["p"], outs[1]["p"])
+    ref = o.State(oracle_params(s, **kw), s.x, s.p, mass=s.mass, cons=s.cons).run(200)
+    e = rel_pos_err(outs[1]["x"], ref.x)
+    report("window records in global memory, 200 steps", x=e)
+    assert e < 1e-10
+
+
 def test_pool_with_degenerate_jobs():
     """Empty and one-particle jobs in a pool beside ordinary ones: all finish,
     and the one-particle job's result equals the same job run alone."""
