@@ -462,7 +462,7 @@ def main():
     ap.add_argument("--n", type=int, default=2_000_000)
     ap.add_argument("--skin", type=float, default=0.5, help="list skin when not tuning (and of the secondary runs)")
     ap.add_argument("--no-tune", action="store_true", help="skip md_tune (step-kernel instance and skin)")
-    ap.add_argument("--tune-steps", type=int, default=120, help="steps per md_tune candidate")
+    ap.add_argument("--tune-steps", type=int, default=300, help="steps per md_tune trial")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="launch steps one by one instead of hipGraph chunks")
     ap.add_argument("--serving-jobs", type=int, default=10000, help="0 skips the serving measurement")

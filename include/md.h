@@ -290,12 +290,14 @@ int md_get_stats(md_ctx* ctx, md_stats* stats);
  * compiled variants differ in occupancy target and in how many halo entries
  * a tile stages in LDS; FP64-class and bead-model jobs have one instance),
  * then the neighbour-list skin (skins[0..nskins), or a built-in set
- * {0.2, 0.3, 0.4, 0.5, 0.6, 0.8} sigma when skins is NULL).  Each candidate
+ * {0.2, 0.3, 0.4, 0.5, 0.6, 0.8} sigma when skins is NULL).  Each trial
  * runs one step (which takes the list build a new choice may force) and then
- * trial_steps steps scored by GPU time per step, step kernels and list builds
- * together (HIP events, so graph capture does not count); the fastest
- * instance and skin stay in effect and md_get_stats reports them.  The system
- * really advances (instances + skins) * (trial_steps + 1) steps: results
+ * trial_steps steps scored by GPU time per step (HIP events, so graph capture
+ * does not count): an instance by its step kernels alone, twice (all
+ * instances in turn, then in reverse order; the faster trial counts), a skin
+ * by step kernels and list builds together.  The fastest instance and skin
+ * stay in effect and md_get_stats reports them.  The system really advances
+ * (2 * instances + skins) * (trial_steps + 1) steps: results
  * depend on neither choice, so the trajectory is the one md_step would have
  * produced.  best_skin and best_us_per_step (GPU microseconds per step) may be
  * NULL.  Candidate skins whose cell grid does not fit the context's memory are

@@ -1936,28 +1936,38 @@ int md_tune(md_ctx* ctx, int trial_steps, const double* skins, int nskins, doubl
   Engine* e = ctx->eng;
   const int j = ctx->job;
   // GPU microseconds per step of one trial: step chunks and list builds (one
-  // step first, which takes the list build a new skin forces)
-  auto trial = [&](double* us) -> int {
+  // step first, which takes the list build a new skin forces); step_us: the
+  // step chunks alone
+  auto trial = [&](double* us, double* step_us) -> int {
     MDCHK(md_step(ctx, 1));
     const md_stats a = e->stats;
     MDCHK(md_step(ctx, trial_steps));
     const md_stats b = e->stats;
     const int64_t steps = b.steps - a.steps;
-    const double ms = (b.step_kernel_ms - a.step_kernel_ms) + (b.rebuild_ms - a.rebuild_ms);
+    const double ks = b.step_kernel_ms - a.step_kernel_ms;
+    const double ms = ks + (b.rebuild_ms - a.rebuild_ms);
     *us = steps > 0 ? 1000.0 * ms / (double)steps : 1e300;
+    if (step_us) *step_us = steps > 0 ? 1000.0 * ks / (double)steps : 1e300;
     return MD_OK;
   };
-  // 1. the step-kernel instance, at the current skin (FP32-class jobs only)
+  // 1. the step-kernel instance, at the current skin (FP32-class jobs only),
+  // by step-kernel time alone (the instance does not change the list builds,
+  // whose count per trial would only add noise); each instance is timed twice,
+  // in forward and then reverse order, and keeps its faster trial
   const HostJob& h0 = e->jobs[j];
   if (!h0.dev.force_fp64 && !h0.model && h0.n > 0) {
-    int best_v = e->f32_variant;
-    double best_v_us = 1e300;
-    for (int v = 0; v < kNumStepVariants; ++v) {
+    double v_us[kNumStepVariants];
+    for (int v = 0; v < kNumStepVariants; ++v) v_us[v] = 1e300;
+    for (int q = 0; q < 2 * kNumStepVariants; ++q) {
+      const int v = q < kNumStepVariants ? q : 2 * kNumStepVariants - 1 - q;
       e->set_variant(v);
-      double us = 0.0;
-      MDCHK(trial(&us));
-      if (us < best_v_us) best_v_us = us, best_v = v;
+      double us = 0.0, sus = 0.0;
+      MDCHK(trial(&us, &sus));
+      v_us[v] = std::min(v_us[v], sus);
     }
+    int best_v = 0;
+    for (int v = 1; v < kNumStepVariants; ++v)
+      if (v_us[v] < v_us[best_v]) best_v = v;
     e->set_variant(best_v);
   }
   // 2. the skin, with that instance
@@ -1965,7 +1975,7 @@ int md_tune(md_ctx* ctx, int trial_steps, const double* skins, int nskins, doubl
   for (int q = 0; q < nskins; ++q) {
     if (e->set_skin(j, skins[q]) != MD_OK) continue;
     double us = 0.0;
-    MDCHK(trial(&us));
+    MDCHK(trial(&us, nullptr));
     if (us < best_us) {
       best_us = us;
       best = skins[q];

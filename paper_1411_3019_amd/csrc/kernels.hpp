@@ -319,10 +319,11 @@ __device__ __forceinline__ uint32_t block_scan(uint32_t v, uint32_t* sh, uint32_
 //     into an LDS table of the tile's columns; the hulls, one after another,
 //     number the tile's candidates;
 //  2. each lane walks its 9 runs over the packed FP32 candidate records, four
-//     at a time with the next four loading, and appends the candidates inside
-//     the list radius without branching (a rejected candidate is overwritten
-//     by the next one);
-//  3. kept candidates outside the tile are marked in a bitmap over candidate
+//     at a time with the next four loading, and appends the candidate numbers
+//     of those inside the list radius without branching (a rejected candidate
+//     is overwritten by the next one); its own slot is found like any other;
+//  3. kept candidates in the tile become local indices (the lane's own slot
+//     leaves the list), the others are marked in a bitmap over candidate
 //     numbers; the halo is the marked candidates in candidate order; list
 //     entries become window indices (own slots 0..255, halo 256 + rank) and
 //     are written as 16-bit entries, with the halo list of the tile.
@@ -337,6 +338,7 @@ __device__ __forceinline__ uint32_t block_scan(uint32_t v, uint32_t* sh, uint32_
 constexpr int kColCap = 256;     // distinct stencil columns of one tile
 constexpr int kCandCap = 16384;  // candidates of one tile
 constexpr uint32_t kNoCol = 0xFFFFFFFFu;
+constexpr int kNlistRows = 5;    // list rows in LDS beyond kmax
 
 // FP32 minimum image with box lengths L and inverses iL (both 0 along a
 // non-periodic axis, where the correction vanishes).
@@ -376,7 +378,7 @@ __device__ __forceinline__ int column_slot(const uint32_t* ckey, uint32_t key) {
 // (32-bit codes, particle indices kept for the sort).
 // jobs, models: B.jobs and B.models as no-alias arguments (scalar loads).
 template <bool kWide, bool kStream>
-__global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const JobDev* __restrict__ jobs,
+__global__ void __launch_bounds__(kNlistBlock) __attribute__((amdgpu_waves_per_eu(kWide ? 1 : 6, 8))) k_nlist(DevBufs B, const JobDev* __restrict__ jobs,
                                                        const ModelDev* __restrict__ models,
                                                        const int* __restrict__ tile_job,
                                                        const int64_t* __restrict__ tile_first) {
@@ -384,19 +386,20 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const JobDev* 
   // their candidate number
   using code_t = uint16_t;
   constexpr uint32_t kOwn = 0x8000u;
-  // codes [kmax + 1][256] (row kmax takes the appends beyond the capacity);
+  // codes [kmax + kNlistRows][256] (kmax + 1 entries with the lane's own slot, then
+  // rows for the appends beyond the capacity);
   // wide instance: then the record words (particle index, bead type) of the
   // window, [256 + hcap] (in global memory, B.KKEY, when they would not fit)
   extern __shared__ uint32_t dyn[];
-  __shared__ uint32_t ckey[kColCap], cb[kColCap], ce[kColCap], coff[kColCap + 1];
+  __shared__ uint32_t ckey[kColCap], cb[kColCap], ce[kColCap], coff[kColCap], scoff[kColCap + 1];
   __shared__ uint32_t bits[kCandCap / 32], wpre[kCandCap / 32];
   __shared__ uint32_t scan_sh[kNlistBlock / 64];
-  __shared__ uint32_t span_lo, span_hi;
+  __shared__ uint32_t span_lo, span_hi, nhull;
   __shared__ int fail;
   const int kmax = B.kmax;
   code_t* kid = reinterpret_cast<code_t*>(dyn);
   const uint32_t wlen = (uint32_t)kTile + (uint32_t)B.hcap;  // window length
-  uint32_t* wrec = B.KKEY ? B.KKEY + (size_t)blockIdx.x * wlen : dyn + (size_t)(kmax + 1) * kNlistBlock / 2;
+  uint32_t* wrec = B.KKEY ? B.KKEY + (size_t)blockIdx.x * wlen : dyn + (size_t)(kmax + kNlistRows) * kNlistBlock / 2;
   const int tile = (int)blockIdx.x;
   const int job = uniform_int(tile_job[tile]);
   const JobDev& J = jobs[job];
@@ -510,17 +513,37 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const JobDev* 
     }
   }
   __syncthreads();
-  // candidate numbering: the columns' hulls one after another in table order
-  uint32_t M = 0u;
-  {
-    const uint32_t len = ckey[lane] != kNoCol ? ce[lane] - cb[lane] : 0u;
-    const uint32_t off = block_scan(len, scan_sh, M);
+  // candidate numbering by columns: the hulls (disjoint slot ranges) one after
+  // another in slot order, so that numbers grow with the slot as in the span
+  // numbering and the tile's own slots have consecutive numbers.  coff: first
+  // number of each table entry's hull; scb, scoff: first slot and first number
+  // of the hulls in slot order (scb in place of ce, the occupied entries
+  // listed in wpre meanwhile)
+  uint32_t M = span;
+  if (!by_span) {
+    const bool occ = ckey[lane] != kNoCol;
+    const uint32_t my = cb[lane], len = occ ? ce[lane] - my : 0u;
+    uint32_t nh = 0u;
+    block_scan(len, scan_sh, M);
+    const uint32_t r = block_scan(occ ? 1u : 0u, scan_sh, nh);
+    uint32_t* hidx = wpre;
+    if (occ) hidx[r] = (uint32_t)lane;
+    __syncthreads();
+    uint32_t off = 0u, rank = 0u;
+    if (occ) {
+      for (uint32_t q = 0; q < nh; ++q) {
+        const uint32_t j = hidx[q], bj = cb[j];
+        if (bj < my) off += ce[j] - bj, ++rank;
+      }
+    }
+    __syncthreads();
+    uint32_t* scb = ce;
     coff[lane] = off;
-    if (lane == 0) coff[kColCap] = M;
+    if (occ) scoff[rank] = off, scb[rank] = my;
+    if (lane == 0) scoff[nh] = M, nhull = nh;
+    M = M > (uint32_t)kCandCap || fail ? 0xFFFFFFFFu : M;
   }
   __syncthreads();
-  if (!by_span) M = M > (uint32_t)kCandCap || fail ? 0xFFFFFFFFu : M;
-  else M = span;
   if (M > (uint32_t)kCandCap) {
     // neither numbering fits: the job stops with an error
     if (lane == 0) {
@@ -566,9 +589,12 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const JobDev* 
       }
     }
     const uint32_t bpm = (uint32_t)J.bpm, mstart = bpm != 0u ? (myid / bpm) * bpm : 0u;  // bpm = 0: no molecules
-    const uint32_t loc0 = 0u - first_local;  // own-tile index of job slot 0 (mod 2^32)
-    // four candidates r[0..3] at slots j .. j+3 (rem: candidates left from j)
-    auto test4 = [&](const float4* r, int rem, uint32_t t, uint32_t loc) {
+    // four candidates r[0..3] numbered t .. t+3 (rem: candidates left from t);
+    // every one is written at the next free row, a kept one advances it
+    // (rows from kmax + 1 on take what does not fit, up to three per batch)
+    auto test4 = [&](const float4* r, int rem, uint32_t t) {
+      const int row0 = min(cnt, kmax + 1);
+      int tk = 0;
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         float dx = xf - r[u].x, dy = yf - r[u].y, dz = zf - r[u].z;
@@ -583,12 +609,11 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const JobDev* 
         } else {
           take = d2 < thr;
         }
-        take = take && u < rem && loc + u != (uint32_t)lane;
-        const bool own = loc + u < (uint32_t)kTile;
-        const uint32_t code = own ? kOwn | (loc + u) : t + u;
-        kid[min(cnt, kmax) * kNlistBlock + lane] = (code_t)code;
-        cnt += take ? 1 : 0;
+        take = take && u < rem;
+        kid[(row0 + tk) * kNlistBlock + lane] = (code_t)(t + u);
+        tk += take ? 1 : 0;
       }
+      cnt += tk;
     };
     // slots [b, e) of a column whose candidate numbers are slot + o; f0..f3:
     // the records of slots b .. b+3, loaded ahead.  Two batches of four in
@@ -603,21 +628,19 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const JobDev* 
       for (int u = 0; u < 4; ++u) rb4[u] = q[4 + u];
       int rem = (int)(e - b);
       uint32_t t = b + o;
-      uint32_t loc = b + loc0;
       while (true) {
-        test4(ra, rem, t, loc);
+        test4(ra, rem, t);
         rem -= 4;
         if (rem <= 0) break;
         q += 8;
 #pragma unroll
         for (int u = 0; u < 4; ++u) ra[u] = q[u];
-        test4(rb4, rem, t + 4u, loc + 4u);
+        test4(rb4, rem, t + 4u);
         rem -= 4;
         if (rem <= 0) break;
 #pragma unroll
         for (int u = 0; u < 4; ++u) rb4[u] = q[4 + u];
         t += 8u;
-        loc += 8u;
       }
     };
     // the 9 columns, unrolled (their runs stay in registers)
@@ -647,20 +670,41 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const JobDev* 
       }
     }
   }
-  const int stored = valid ? (cnt < kmax ? cnt : kmax) : 0;
   // 3. the halo: kept candidates outside the tile, marked in the bitmap,
-  // ranked in candidate order
-  for (int k = 0; k < stored; k += kRow) {
-    // eight codes read together (rows past the list read row kmax, in bounds)
+  // ranked in candidate order.  Codes of own-tile slots become kOwn | local
+  // index; the lane's own slot (found by the walk unless the molecule rule
+  // left it out) leaves the list, the last entry taking its place.
+  // number of the tile's first slot (its slots have consecutive numbers)
+  uint32_t t0 = first_local - span_lo;
+  if (!by_span && valid) {
+    const int h = column_slot(ckey, column_key(J, cx, cy, 4));  // the lane's own column
+    t0 = coff[h] + (first_local - cb[h]);
+  }
+  int nall = valid ? min(cnt, kmax + 1) : 0;
+  int pself = -1;
+  for (int k = 0; k < nall; k += kRow) {
+    // eight codes read together (rows past the list read the last row, in bounds)
     uint32_t code[kRow];
 #pragma unroll
-    for (int u = 0; u < kRow; ++u) code[u] = (uint32_t)kid[min(k + u, kmax) * kNlistBlock + lane];
+    for (int u = 0; u < kRow; ++u) code[u] = (uint32_t)kid[min(k + u, kmax + kNlistRows - 1) * kNlistBlock + lane];
 #pragma unroll
     for (int u = 0; u < kRow; ++u) {
-      const uint32_t v = code[u] & 0xFFFFu;
-      if (k + u < stored && !(code[u] & kOwn)) atomicOr(&bits[v >> 5], 1u << (v & 31));
+      if (k + u >= nall) continue;
+      const uint32_t loc = code[u] - t0;
+      if (loc == (uint32_t)lane)
+        pself = k + u;
+      else if (loc < (uint32_t)kTile)
+        kid[(k + u) * kNlistBlock + lane] = (code_t)(kOwn | loc);
+      else
+        atomicOr(&bits[code[u] >> 5], 1u << (code[u] & 31));
     }
   }
+  if (pself >= 0) {
+    kid[pself * kNlistBlock + lane] = kid[(nall - 1) * kNlistBlock + lane];
+    nall -= 1;
+  }
+  const int found = valid ? cnt - (pself >= 0 ? 1 : 0) : 0;  // neighbours found
+  const int stored = min(nall, kmax);
   __syncthreads();
   uint32_t H = 0u;
   {
@@ -675,14 +719,14 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const JobDev* 
   // the halo list: each lane takes bitmap words and writes their set bits
   for (uint32_t wi = lane; wi < (M + 31u) / 32u; wi += kNlistBlock) {
     uint32_t w = bits[wi];
-    // by columns: the column holding the word's first bit, found once per
-    // word (later bits of the word step forward from it)
+    // by columns: the hull holding the word's first bit, found once per word
+    // (later bits of the word step forward from it)
     uint32_t h = 0u;
     if (!by_span && w != 0u) {
-      uint32_t lo = 0u, hi = kColCap;
+      uint32_t lo = 0u, hi = nhull;
       while (hi - lo > 1u) {
         const uint32_t mid = (lo + hi) >> 1;
-        if (coff[mid] <= wi * 32u)
+        if (scoff[mid] <= wi * 32u)
           lo = mid;
         else
           hi = mid;
@@ -693,8 +737,8 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const JobDev* 
       const uint32_t t = wi * 32u + (uint32_t)(__ffs(w) - 1);
       uint32_t slot = span_lo + t;
       if (!by_span) {
-        while (coff[h + 1] <= t) ++h;
-        slot = cb[h] + (t - coff[h]);
+        while (scoff[h + 1] <= t) ++h;
+        slot = ce[h] + (t - scoff[h]);  // ce: the hulls' first slots in slot order
       }
       B.HALO[gt * (int64_t)hcap + rank] = (uint32_t)(base + slot);
       if (kWide) wrec[kTile + rank] = __float_as_uint(PK[slot].w);
@@ -776,7 +820,7 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const JobDev* 
   }
   // list statistics of these 64 slots (no atomics); an overflow stops the job
   // before its first step on these lists
-  uint32_t mx = (uint32_t)cnt, sm = (uint32_t)stored;
+  uint32_t mx = (uint32_t)found, sm = (uint32_t)stored;
   for (int o = 32; o > 0; o >>= 1) {
     mx = max(mx, (uint32_t)__shfl_xor((int)mx, o, 64));
     sm += (uint32_t)__shfl_xor((int)sm, o, 64);
@@ -790,15 +834,16 @@ __global__ void __launch_bounds__(kNlistBlock) k_nlist(DevBufs B, const JobDev* 
 }
 
 // Dynamic LDS of k_nlist for a list capacity kmax: the kept neighbours'
-// 16-bit codes, with one spare row, then table_words record words (the
-// window's, in the wide instance, when they are staged in LDS).
+// 16-bit codes (room for kmax + 1 with the lane's own slot, and four rows for
+// what does not fit), then table_words record words (the window's, in the
+// wide instance, when they are staged in LDS).
 constexpr size_t nlist_lds_bytes(int kmax, int64_t table_words) {
-  return (size_t)(kmax + 1) * kNlistBlock * 2 + 4 * (size_t)table_words;
+  return (size_t)(kmax + kNlistRows) * kNlistBlock * 2 + 4 * (size_t)table_words;
 }
 
 // Static LDS of k_nlist (column table, halo bitmap).
 constexpr int64_t nlist_static_lds(bool) {
-  return 4 * (4 * kColCap + 1) + 8 * (kCandCap / 32) + 4 * (kNlistBlock / 64) + 4;
+  return 4 * (5 * kColCap + 1) + 8 * (kCandCap / 32) + 4 * (kNlistBlock / 64) + 16;
 }
 
 // Diagnostics of one job from the finish kernel's per-particle values (Section

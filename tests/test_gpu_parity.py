@@ -338,7 +338,7 @@ def test_autotune_keeps_trajectory():
     assert best in (0.25, 0.45, 0.7) and us > 0.0
     assert st["skin"] == best and 0 <= st["step_variant"] < 4
     assert st["step_waves"] > 0 and st["step_halo_lds"] > 0 and st["list_capacity"] > 0
-    steps = 41 * (4 + 3)
+    steps = 41 * (2 * 4 + 3)  # each instance twice, then each skin
     g = gpu_system(s, **kw)
     g.step(steps)
     b = g.get_state()
