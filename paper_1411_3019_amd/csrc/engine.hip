@@ -433,8 +433,10 @@ struct Engine {
   size_t arena_used = 0;
   std::map<void*, std::vector<char>> uploaded;  // last contents of descriptor arrays that rarely change
   bool build_timing_pending = false;
-  // step graphs
+  // step graphs (by number of steps), and the stream whole-chunk graphs are
+  // captured on while the library's stream runs
   std::map<GraphKey, hipGraphExec_t> graphs;
+  hipStream_t cap_stream = nullptr;
   bool step_tiles_valid = false;
   md_stats stats{};
   static constexpr int kSubEvents = 16;
@@ -498,6 +500,7 @@ struct Engine {
     arena_used = 0;
     uploaded.clear();
     if (own_stream && stream) (void)hipStreamDestroy(stream);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream), cap_stream = nullptr;
     stream = nullptr;
     own_stream = false;
   }
@@ -526,6 +529,7 @@ struct Engine {
       HIPCHK(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
       own_stream = true;
     }
+    HIPCHK(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
     C = round_up(std::max<int64_t>(slot_cap, kTile), kTile);
     BMW = std::max<int64_t>(word_cap, 64);
     max_jobs = std::max(1, njobs);
@@ -1234,9 +1238,9 @@ struct Engine {
     return MD_OK;
   }
 
-  // One step launch of tile class c (see class_of).
-  void launch_class(int c, int t, bool stream_st) {
-    const StepLaunch L{dim3(grid[c]), stream, &B, step_tiles_job + c * tile_cap, step_tiles_first + c * tile_cap,
+  // One step launch of tile class c (see class_of) on stream s.
+  void launch_class(int c, int t, bool stream_st, hipStream_t s) {
+    const StepLaunch L{dim3(grid[c]), s, &B, step_tiles_job + c * tile_cap, step_tiles_first + c * tile_cap,
                        step_counts + c, t};
     const bool all = c >= 4;
     switch (c & 3) {
@@ -1247,13 +1251,33 @@ struct Engine {
     }
   }
 
-  void enqueue_steps_as(int t0, int k, bool stream_st) {
+  void enqueue_steps_as(int t0, int k, bool stream_st, hipStream_t s) {
     for (int t = t0; t < t0 + k; ++t)
       for (int c = 0; c < kClasses; ++c)
-        if (grid[c] > 0) launch_class(c, t, stream_st);
+        if (grid[c] > 0) launch_class(c, t, stream_st, s);
   }
 
-  void enqueue_steps(int t0, int k) { enqueue_steps_as(t0, k, stream_stores); }
+  void enqueue_steps(int t0, int k) { enqueue_steps_as(t0, k, stream_stores, stream); }
+
+  // The graph of steps t = 0 .. k-1 under the current tile grids and store
+  // policy, captured on stream s when it is not cached (capture only records
+  // the launches: s may be a stream that never runs them).
+  int step_graph(int k, hipStream_t s, hipGraphExec_t* out) {
+    auto it = graphs.find(GraphKey{k});
+    if (it == graphs.end()) {
+      hipGraph_t g = nullptr;
+      HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      enqueue_steps_as(0, k, stream_stores, s);
+      HIPCHK(hipStreamEndCapture(s, &g));
+      hipGraphExec_t ex = nullptr;
+      const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      HIPCHK(e);
+      it = graphs.emplace(GraphKey{k}, ex).first;
+    }
+    *out = it->second;
+    return MD_OK;
+  }
 
   int launch_chunk(int k, bool use_graph) {
     if (!use_graph) {
@@ -1261,19 +1285,9 @@ struct Engine {
       HIPCHK(hipGetLastError());
       return MD_OK;
     }
-    auto it = graphs.find(GraphKey{k});
-    if (it == graphs.end()) {
-      hipGraph_t g = nullptr;
-      HIPCHK(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
-      enqueue_steps(0, k);
-      HIPCHK(hipStreamEndCapture(stream, &g));
-      hipGraphExec_t ex = nullptr;
-      const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(g);
-      HIPCHK(e);
-      it = graphs.emplace(GraphKey{k}, ex).first;
-    }
-    HIPCHK(hipGraphLaunch(it->second, stream));
+    hipGraphExec_t ex = nullptr;
+    MDCHK(step_graph(k, stream, &ex));
+    HIPCHK(hipGraphLaunch(ex, stream));
     return MD_OK;
   }
 
@@ -1295,9 +1309,12 @@ struct Engine {
   // eager = true (pools): rebuild every job whose list would go stale within
   // the chunk, and run the full chunk; eager = false (one system): rebuild only
   // when the list is (nearly) stale and shorten the chunk to the prediction.
-  // A chunk of k steps is a run of cached graphs of power-of-two lengths (the
-  // binary digits of k), with the job records for each uploaded before it; the
-  // host waits once, for the job records at the end.
+  // A chunk of k steps is one graph of k steps with one upload of the job
+  // records before it, once that graph is cached; until then a run of cached
+  // graphs of power-of-two lengths (the binary digits of k), with the job
+  // records for each uploaded before it, while the graph of k steps is
+  // captured on a side stream.  The host waits once, for the job records at
+  // the end.
   int run_chunk(int kcap, bool use_graph, int64_t* advanced, bool eager = false) {
     MDCHK(enqueue_chunk(kcap, use_graph, eager));
     return complete_chunk(advanced);
@@ -1342,9 +1359,9 @@ struct Engine {
     MDCHK(prepare_step_tiles());
     set_store_policy();
     std::vector<JobDev> tab(max_jobs);
-    int t0 = 0, nsub = 0;
-    for (int len = kMaxChunk; len >= 1; len >>= 1) {
-      if (!(kk & len)) continue;
+    int nsub = 0;
+    // sub-chunk [t0, t0 + len): the job records for it, then its launches
+    auto sub_chunk = [&](int t0, int len, bool graph) -> int {
       for (int j = 0; j < max_jobs; ++j) {
         const HostJob& h = jobs[j];
         JobDev d = h.dev;
@@ -1356,10 +1373,28 @@ struct Engine {
       }
       MDCHK(upload(B.jobs, tab.data(), sizeof(JobDev) * max_jobs));
       HIPCHK(hipEventRecord(ev_sub[2 * nsub], stream));
-      MDCHK(launch_chunk(len, use_graph));
+      MDCHK(launch_chunk(len, graph));
       HIPCHK(hipEventRecord(ev_sub[2 * nsub + 1], stream));
       ++nsub;
-      t0 += len;
+      return MD_OK;
+    };
+    if (!use_graph || graphs.count(GraphKey{kk})) {
+      // one launch sequence (or the chunk's own cached graph)
+      MDCHK(sub_chunk(0, kk, use_graph));
+    } else {
+      // the cached graphs of power-of-two lengths (the binary digits of kk,
+      // each with its job records); then, while they run, the graph of the
+      // whole chunk is captured on a side stream for the next chunk of kk steps
+      int t0 = 0;
+      for (int len = kMaxChunk; len >= 1; len >>= 1) {
+        if (!(kk & len)) continue;
+        MDCHK(sub_chunk(t0, len, true));
+        t0 += len;
+      }
+      if (nsub > 1) {
+        hipGraphExec_t ex = nullptr;
+        MDCHK(step_graph(kk, cap_stream, &ex));
+      }
     }
     hipLaunchKernelGGL(k_job_stats, dim3(max_jobs), dim3(kStatsThreads), 0, stream, B, 0);
     HIPCHK(hipGetLastError());
