@@ -247,43 +247,60 @@ __device__ __forceinline__ uint32_t column_key(const JobDev& J, int cx, int cy, 
   return ok ? (uint32_t)ax * (uint32_t)J.nc[1] + (uint32_t)ay : 0xFFFFFFFFu;
 }
 
-// Slot runs [rb, re) (relative to the job) of cells z in [za, zb] of the 9
-// stencil columns of (cx, cy), looked up three columns at a time (their loads
-// in flight together); an off-grid column gives an empty run.
+// Slot runs [rb, re) (relative to the job) of cells z in [za, zb] of stencil
+// columns C0 .. C1-1 of (cx, cy), looked up together in two rounds of loads:
+// per column the bitmap word of its first cell, the word after it when the
+// run's end falls there (za..zb spans at most three cells, so the end is in
+// one of the two), and the first word's popcount prefix; then the two cell
+// starts.  An off-grid column gives an empty run.
+template <int C0, int C1>
+__device__ __forceinline__ void column_runs(const DevBufs& B, const JobDev& J, int cx, int cy, int za, int zb,
+                                            uint32_t* rb, uint32_t* re) {
+  constexpr int G = C1 - C0;
+  const uint32_t ncy = (uint32_t)J.nc[1], ncz = (uint32_t)J.nc[2];
+  // the job's bitmap, popcount prefix and cell starts (uniform bases, 32-bit
+  // per-lane offsets)
+  const uint32_t* __restrict__ bm = B.BM + J.bm_off;
+  const uint32_t* __restrict__ woff = B.WOFF + J.bm_off;
+  const uint32_t* __restrict__ cstart = B.CSTART + J.off;
+  const uint32_t dz = (uint32_t)(zb - za + 1);  // cells in the run (at most three)
+  uint32_t ra[G], bm0[G], bm1[G], wo[G];
+  uint32_t okm = 0u;  // bit u: column C0 + u is on the grid
+#pragma unroll
+  for (int u = 0; u < G; ++u) {
+    const int col = C0 + u;
+    int ax = 0, ay = 0;
+    const bool ok = stencil_coord(J, 0, cx, col / 3 - 1, ax) & stencil_coord(J, 1, cy, col % 3 - 1, ay);
+    if (!ok) ax = 0, ay = 0;  // looks up column (0, 0), dropped below
+    okm |= ok ? 1u << u : 0u;
+    ra[u] = ((uint32_t)ax * ncy + (uint32_t)ay) * ncz + (uint32_t)za;
+    const uint32_t wa = ra[u] >> 5;
+    bm0[u] = bm[wa];
+    wo[u] = woff[wa];
+    // the end's word, when it is the next one (always inside the job's words:
+    // the end of the last z-run is addressable)
+    bm1[u] = ((ra[u] + dz) >> 5) != wa ? bm[wa + 1u] : 0u;
+  }
+#pragma unroll
+  for (int u = 0; u < G; ++u) {
+    const uint32_t rz = ra[u] + dz;
+    const uint32_t ia = wo[u] + __popc(bm0[u] & ((1u << (ra[u] & 31)) - 1u));
+    const uint32_t mz = (1u << (rz & 31)) - 1u;
+    const uint32_t iz = (rz >> 5) != (ra[u] >> 5) ? wo[u] + __popc(bm0[u]) + __popc(bm1[u] & mz)
+                                                  : wo[u] + __popc(bm0[u] & mz);
+    rb[C0 + u] = cstart[ia];
+    re[C0 + u] = cstart[iz];
+  }
+#pragma unroll
+  for (int u = 0; u < G; ++u)
+    if (!((okm >> u) & 1u)) re[C0 + u] = rb[C0 + u];
+}
+
+// The runs of all 9 stencil columns, in two groups of lookups.
 __device__ __forceinline__ void column_runs9(const DevBufs& B, const JobDev& J, int cx, int cy, int za, int zb,
                                              uint32_t* rb, uint32_t* re) {
-  const int64_t base = J.off;
-  const uint32_t ncy = (uint32_t)J.nc[1], ncz = (uint32_t)J.nc[2];
-#pragma unroll
-  for (int g = 0; g < 9; g += 3) {
-    uint32_t ra[3], rz[3], bma[3], bmz[3], woa[3], woz[3];
-    bool ok[3];
-#pragma unroll
-    for (int u = 0; u < 3; ++u) {
-      const int col = g + u;
-      int ax = 0, ay = 0;
-      ok[u] = stencil_coord(J, 0, cx, col / 3 - 1, ax) & stencil_coord(J, 1, cy, col % 3 - 1, ay);
-      if (!ok[u]) ax = 0, ay = 0;  // looks up column (0, 0), dropped below
-      const uint32_t c0 = ((uint32_t)ax * ncy + (uint32_t)ay) * ncz;
-      ra[u] = c0 + (uint32_t)za;
-      rz[u] = c0 + (uint32_t)zb + 1u;
-      const int64_t wa = J.bm_off + (ra[u] >> 5), wz = J.bm_off + (rz[u] >> 5);
-      bma[u] = B.BM[wa];
-      woa[u] = B.WOFF[wa];
-      bmz[u] = B.BM[wz];
-      woz[u] = B.WOFF[wz];
-    }
-#pragma unroll
-    for (int u = 0; u < 3; ++u) {
-      const uint32_t ia = woa[u] + __popc(bma[u] & ((1u << (ra[u] & 31)) - 1u));
-      const uint32_t iz = woz[u] + __popc(bmz[u] & ((1u << (rz[u] & 31)) - 1u));
-      rb[g + u] = B.CSTART[base + ia];
-      re[g + u] = B.CSTART[base + iz];
-    }
-#pragma unroll
-    for (int u = 0; u < 3; ++u)
-      if (!ok[u]) re[g + u] = rb[g + u];
-  }
+  column_runs<0, 5>(B, J, cx, cy, za, zb, rb, re);
+  column_runs<5, 9>(B, J, cx, cy, za, zb, rb, re);
 }
 
 // Exclusive scan over the 256 threads of a workgroup (every thread calls it);
