@@ -206,6 +206,35 @@ def test_exact_sum_guard_close_pair():
     assert st2["diag"]["exact_sum_breaches"] == 0
 
 
+@pytest.mark.parametrize("force_fp64", [0, 1])
+def test_graph_replays_match_eager(force_fp64, monkeypatch):
+    """Steps run as hipGraphs against the same steps launched one by one
+    (MD_NO_GRAPH=1), compared after every md_step call: chunk lengths repeat
+    (20, 20, 7, 20, 33, 20, 7) so that a length first runs as power-of-two
+    graphs while its own graph is captured, and then replays that graph,
+    with host reads (md_get_state) and list builds between the replays."""
+    from paper_1411_3019_amd import md
+    s = gen.torus(6000, 40.0, 13.3, 41)
+    kw = dict(dt=0.002, rc=2.5, seed=17, force_fp64=force_fp64, skin=0.4)
+    print(f"[gpu] graph replays vs eager launches force_fp64={force_fp64}", flush=True)
+    systems = []
+    for flag in ("1", "0"):
+        monkeypatch.setenv("MD_NO_GRAPH", flag)
+        systems.append(gpu_system(s, **kw))
+    eager, graph = systems
+    for k in (20, 20, 7, 20, 33, 20, 7):
+        monkeypatch.setenv("MD_NO_GRAPH", "1")
+        eager.step(k)
+        monkeypatch.setenv("MD_NO_GRAPH", "0")
+        graph.step(k)
+        a, b = eager.get_state(), graph.get_state()
+        assert a["step"] == b["step"]
+        assert np.array_equal(a["x"], b["x"]) and np.array_equal(a["p"], b["p"]), k
+    assert b["diag"]["rebuilds"] >= 2
+    for g in systems:
+        g.close()
+
+
 def test_full_size_torus_2m_one_step():
     """The 2,000,000-particle torus workload at full size in the launch
     configuration the benchmark times (FP32 forces, graphs, skin 0.5): one step,
