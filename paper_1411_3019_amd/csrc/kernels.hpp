@@ -355,7 +355,7 @@ __device__ __forceinline__ uint32_t block_scan(uint32_t v, uint32_t* sh, uint32_
 constexpr int kColCap = 256;     // distinct stencil columns of one tile
 constexpr int kCandCap = 16384;  // candidates of one tile
 constexpr uint32_t kNoCol = 0xFFFFFFFFu;
-constexpr int kNlistRows = 5;    // list rows in LDS beyond kmax
+constexpr int kNlistRows = 2;    // list rows in LDS beyond kmax
 
 // FP32 minimum image with box lengths L and inverses iL (both 0 along a
 // non-periodic axis, where the correction vanishes).
@@ -404,11 +404,11 @@ __global__ void __launch_bounds__(kNlistBlock) __attribute__((amdgpu_waves_per_e
   using code_t = uint16_t;
   constexpr uint32_t kOwn = 0x8000u;
   // codes [kmax + kNlistRows][256] (kmax + 1 entries with the lane's own slot, then
-  // rows for the appends beyond the capacity);
+  // a row for the appends beyond the capacity);
   // wide instance: then the record words (particle index, bead type) of the
   // window, [256 + hcap] (in global memory, B.KKEY, when they would not fit)
   extern __shared__ uint32_t dyn[];
-  __shared__ uint32_t ckey[kColCap], cb[kColCap], ce[kColCap], coff[kColCap], scoff[kColCap + 1];
+  __shared__ uint32_t ckey[kColCap], cb[kColCap], ce[kColCap], coff[kColCap];
   __shared__ uint32_t bits[kCandCap / 32], wpre[kCandCap / 32];
   __shared__ uint32_t scan_sh[kNlistBlock / 64];
   __shared__ uint32_t span_lo, span_hi, nhull;
@@ -532,10 +532,10 @@ __global__ void __launch_bounds__(kNlistBlock) __attribute__((amdgpu_waves_per_e
   __syncthreads();
   // candidate numbering by columns: the hulls (disjoint slot ranges) one after
   // another in slot order, so that numbers grow with the slot as in the span
-  // numbering and the tile's own slots have consecutive numbers.  coff: first
-  // number of each table entry's hull; scb, scoff: first slot and first number
-  // of the hulls in slot order (scb in place of ce, the occupied entries
-  // listed in wpre meanwhile)
+  // numbering and the tile's own slots have consecutive numbers.  coff: per
+  // table entry, number minus slot in its hull; then, in slot order, the
+  // hulls' first numbers (scoff, in place of cb) and first slots (scb, in
+  // place of ce), the occupied entries listed in wpre meanwhile
   uint32_t M = span;
   if (!by_span) {
     const bool occ = ckey[lane] != kNoCol;
@@ -554,10 +554,10 @@ __global__ void __launch_bounds__(kNlistBlock) __attribute__((amdgpu_waves_per_e
       }
     }
     __syncthreads();
-    uint32_t* scb = ce;
-    coff[lane] = off;
+    uint32_t *scoff = cb, *scb = ce;
+    coff[lane] = off - my;
     if (occ) scoff[rank] = off, scb[rank] = my;
-    if (lane == 0) scoff[nh] = M, nhull = nh;
+    if (lane == 0) nhull = nh;
     M = M > (uint32_t)kCandCap || fail ? 0xFFFFFFFFu : M;
   }
   __syncthreads();
@@ -607,8 +607,8 @@ __global__ void __launch_bounds__(kNlistBlock) __attribute__((amdgpu_waves_per_e
     }
     const uint32_t bpm = (uint32_t)J.bpm, mstart = bpm != 0u ? (myid / bpm) * bpm : 0u;  // bpm = 0: no molecules
     // four candidates r[0..3] numbered t .. t+3 (rem: candidates left from t);
-    // every one is written at the next free row, a kept one advances it
-    // (rows from kmax + 1 on take what does not fit, up to three per batch)
+    // every one is written at the next free row, a kept one advances it (row
+    // kmax + 1 takes what does not fit)
     auto test4 = [&](const float4* r, int rem, uint32_t t) {
       const int row0 = min(cnt, kmax + 1);
       int tk = 0;
@@ -627,7 +627,7 @@ __global__ void __launch_bounds__(kNlistBlock) __attribute__((amdgpu_waves_per_e
           take = d2 < thr;
         }
         take = take && u < rem;
-        kid[(row0 + tk) * kNlistBlock + lane] = (code_t)(t + u);
+        kid[min(row0 + tk, kmax + 1) * kNlistBlock + lane] = (code_t)(t + u);
         tk += take ? 1 : 0;
       }
       cnt += tk;
@@ -667,7 +667,7 @@ __global__ void __launch_bounds__(kNlistBlock) __attribute__((amdgpu_waves_per_e
         uint32_t o = 0u - span_lo;  // (mod 2^32)
         if (!by_span) {
           const int h = column_slot(ckey, column_key(J, cx, cy, col));
-          o = coff[h] - cb[h];
+          o = coff[h];
         }
         scan(rb[col], re[col], o, PK[rb[col]], PK[rb[col] + 1], PK[rb[col] + 2], PK[rb[col] + 3]);
       }
@@ -681,7 +681,7 @@ __global__ void __launch_bounds__(kNlistBlock) __attribute__((amdgpu_waves_per_e
         uint32_t o = 0u - span_lo;
         if (!by_span) {
           const int h = column_slot(ckey, column_key(J, cx, cy, col));
-          o = coff[h] - cb[h];
+          o = coff[h];
         }
         scan(b1[col], e1[col], o, PK[b1[col]], PK[b1[col] + 1], PK[b1[col] + 2], PK[b1[col] + 3]);
       }
@@ -695,7 +695,7 @@ __global__ void __launch_bounds__(kNlistBlock) __attribute__((amdgpu_waves_per_e
   uint32_t t0 = first_local - span_lo;
   if (!by_span && valid) {
     const int h = column_slot(ckey, column_key(J, cx, cy, 4));  // the lane's own column
-    t0 = coff[h] + (first_local - cb[h]);
+    t0 = coff[h] + first_local;
   }
   int nall = valid ? min(cnt, kmax + 1) : 0;
   int pself = -1;
@@ -743,7 +743,7 @@ __global__ void __launch_bounds__(kNlistBlock) __attribute__((amdgpu_waves_per_e
       uint32_t lo = 0u, hi = nhull;
       while (hi - lo > 1u) {
         const uint32_t mid = (lo + hi) >> 1;
-        if (scoff[mid] <= wi * 32u)
+        if (cb[mid] <= wi * 32u)  // cb: the hulls' first numbers in slot order
           lo = mid;
         else
           hi = mid;
@@ -754,8 +754,8 @@ __global__ void __launch_bounds__(kNlistBlock) __attribute__((amdgpu_waves_per_e
       const uint32_t t = wi * 32u + (uint32_t)(__ffs(w) - 1);
       uint32_t slot = span_lo + t;
       if (!by_span) {
-        while (scoff[h + 1] <= t) ++h;
-        slot = ce[h] + (t - scoff[h]);  // ce: the hulls' first slots in slot order
+        while (h + 1 < nhull && cb[h + 1] <= t) ++h;
+        slot = ce[h] + (t - cb[h]);  // ce: the hulls' first slots in slot order
       }
       B.HALO[gt * (int64_t)hcap + rank] = (uint32_t)(base + slot);
       if (kWide) wrec[kTile + rank] = __float_as_uint(PK[slot].w);
@@ -860,7 +860,7 @@ constexpr size_t nlist_lds_bytes(int kmax, int64_t table_words) {
 
 // Static LDS of k_nlist (column table, halo bitmap).
 constexpr int64_t nlist_static_lds(bool) {
-  return 4 * (5 * kColCap + 1) + 8 * (kCandCap / 32) + 4 * (kNlistBlock / 64) + 16;
+  return 4 * (4 * kColCap) + 8 * (kCandCap / 32) + 4 * (kNlistBlock / 64) + 16;
 }
 
 // Diagnostics of one job from the finish kernel's per-particle values (Section
