@@ -1071,12 +1071,15 @@ struct Engine {
     const int ntiles = (int)tj.size();
     if (!build_timing_pending) HIPCHK(hipEventRecord(ev[2], stream));
     // zero bitmaps and cell counters
-    hipLaunchKernelGGL(k_zero_ranges, dim3(64, (unsigned)rb.size()), dim3(256), 0, stream, B.BM, ranges_d,
-                       (int)rb.size());
-    hipLaunchKernelGGL(k_zero_ranges, dim3(64, (unsigned)rcnt.size()), dim3(256), 0, stream, B.CCNT,
-                       ranges_d + rb.size(), (int)rcnt.size());
-    hipLaunchKernelGGL(k_zero_ranges, dim3(4, (unsigned)rtacc.size()), dim3(256), 0, stream, (uint32_t*)B.TACC,
-                       ranges_d + rb.size() + rcnt.size(), (int)rtacc.size());
+    {
+      // one launch for the three sets of ranges; fewer workgroups per range
+      // when there are many ranges
+      const int nr = (int)rall.size();
+      const int gx = std::max(4, std::min(256, 4096 / std::max(1, nr)));
+      for (int q0 = 0; q0 < nr; q0 += 65535)  // the grid's y extent is at most 65535
+        hipLaunchKernelGGL(k_zero_ranges, dim3(gx, (unsigned)std::min(65535, nr - q0)), dim3(256), 0, stream, B.BM,
+                           B.CCNT, (uint32_t*)B.TACC, ranges_d, (int)rb.size(), (int)rcnt.size(), q0);
+    }
     // k_mark resets the job records of jobs with particles; the others are reset here
     for (int j : set) {
       if (jobs[j].n > 0) continue;

@@ -32,8 +32,14 @@ struct Range {
   int64_t len;
 };
 
-__global__ void k_zero_ranges(uint32_t* __restrict__ base, const Range* __restrict__ ranges, int nranges) {
-  const Range r = ranges[blockIdx.y];
+// Clears words [start, start + len) of each range: ranges 0 .. n0-1 of array
+// a0, the next n1 of a1, the rest of a2 (one launch for all three; range
+// q0 + blockIdx.y per row of workgroups).
+__global__ void k_zero_ranges(uint32_t* __restrict__ a0, uint32_t* __restrict__ a1, uint32_t* __restrict__ a2,
+                              const Range* __restrict__ ranges, int n0, int n1, int q0) {
+  const int q = q0 + (int)blockIdx.y;
+  const Range r = ranges[q];
+  uint32_t* __restrict__ base = q < n0 ? a0 : (q < n0 + n1 ? a1 : a2);
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < r.len; k += (int64_t)gridDim.x * blockDim.x)
     base[r.start + k] = 0u;
 }
