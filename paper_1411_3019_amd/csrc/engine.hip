@@ -418,6 +418,7 @@ struct Engine {
   uint32_t* kkey_d = nullptr;  // list build: window records of FP64-class / bead-model tiles that do not fit LDS
   int64_t kkey_cap = 0;
   bool list_table_global = false;  // MD_LIST_TABLE_GLOBAL: keep those records in global memory always
+  bool scan_three_pass = false;    // MD_SCAN_3PASS: the three-pass scans whatever the segment lengths
   double* diag_many = nullptr;  // [4] results per job of finish_many
   int64_t diag_many_cap = 0;
   double* scratch_d = nullptr;  // this device's `scratch` (md_get_state_dev_noalloc)
@@ -540,6 +541,7 @@ struct Engine {
     B.kmax = kmax;
     B.hcap = hcap;
     if (const char* v = std::getenv("MD_LIST_TABLE_GLOBAL")) list_table_global = std::atoi(v) != 0;
+    if (const char* v = std::getenv("MD_SCAN_3PASS")) scan_three_pass = std::atoi(v) != 0;
     if (const char* v = std::getenv("MD_STEP_VARIANT")) f32_variant = std::max(0, std::min(kNumStepVariants - 1, std::atoi(v)));
     {
       int v = 0;
@@ -1010,6 +1012,7 @@ struct Engine {
     std::vector<Chunk> cb, cc;
     std::vector<Range> rb, rcnt;
     std::vector<Range> rtacc;
+    int64_t seg_chunks_max = 0;  // chunks of the longest scan segment
     for (int j : set) {
       HostJob& h = jobs[j];
       h.dev.remaining = 0;
@@ -1021,9 +1024,11 @@ struct Engine {
       int first = (int)cb.size();
       for (int64_t s = 0; s < h.bm_words; s += kScanChunk)
         cb.push_back({h.bm_off + s, (int)std::min<int64_t>(kScanChunk, h.bm_words - s), first});
+      seg_chunks_max = std::max<int64_t>(seg_chunks_max, (int64_t)cb.size() - first);
       first = (int)cc.size();
       for (int64_t s = 0; s < h.n + 1; s += kScanChunk)
         cc.push_back({h.off + s, (int)std::min<int64_t>(kScanChunk, h.n + 1 - s), first});
+      seg_chunks_max = std::max<int64_t>(seg_chunks_max, (int64_t)cc.size() - first);
     }
     if (tj.empty()) {
       // only empty jobs: nothing to sort; their records start afresh
@@ -1089,15 +1094,23 @@ struct Engine {
     hipLaunchKernelGGL(k_mark, dim3(ntiles), dim3(kTile), 0, stream, B, aux_tiles_job, aux_tiles_first);
     // bitmap popcount prefix (segmented by job)
     const int nb = (int)cb.size(), nc = (int)cc.size();
+    // segments of few chunks: passes B and C in one launch
+    const bool bc = seg_chunks_max <= kScanBcMax && !scan_three_pass;
+    auto scan_rest = [&](uint32_t* out, const Chunk* ch, uint32_t* sums, int n) {
+      if (bc) {
+        hipLaunchKernelGGL(k_scan_bc, dim3(n), dim3(kScanThreads), 0, stream, out, ch, sums);
+      } else {
+        hipLaunchKernelGGL(k_scan_b, dim3(1), dim3(kScanB), 0, stream, sums, ch, n);
+        hipLaunchKernelGGL(k_scan_c, dim3(n), dim3(kScanThreads), 0, stream, out, ch, sums);
+      }
+    };
     hipLaunchKernelGGL(k_scan_a<true>, dim3(nb), dim3(kScanThreads), 0, stream, B.BM, B.WOFF, chunks_d, chunk_sums);
-    hipLaunchKernelGGL(k_scan_b, dim3(1), dim3(kScanB), 0, stream, chunk_sums, chunks_d, nb);
-    hipLaunchKernelGGL(k_scan_c, dim3(nb), dim3(kScanThreads), 0, stream, B.WOFF, chunks_d, chunk_sums);
+    scan_rest(B.WOFF, chunks_d, chunk_sums, nb);
     hipLaunchKernelGGL(k_count, dim3(ntiles), dim3(kTile), 0, stream, B, aux_tiles_job, aux_tiles_first);
     // cell starts (segmented by job)
     hipLaunchKernelGGL(k_scan_a<false>, dim3(nc), dim3(kScanThreads), 0, stream, B.CCNT, B.CSTART, chunks_d + nb,
                        chunk_sums + nb);
-    hipLaunchKernelGGL(k_scan_b, dim3(1), dim3(kScanB), 0, stream, chunk_sums + nb, chunks_d + nb, nc);
-    hipLaunchKernelGGL(k_scan_c, dim3(nc), dim3(kScanThreads), 0, stream, B.CSTART, chunks_d + nb, chunk_sums + nb);
+    scan_rest(B.CSTART, chunks_d + nb, chunk_sums + nb, nc);
     hipLaunchKernelGGL(k_perm, dim3(ntiles), dim3(kTile), 0, stream, B, aux_tiles_job, aux_tiles_first);
     hipLaunchKernelGGL(k_gather, dim3(ntiles), dim3(kTile), 0, stream, B, aux_tiles_job, aux_tiles_first);
     set_store_policy();

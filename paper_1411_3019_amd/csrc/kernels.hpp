@@ -1086,4 +1086,25 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_c(uint32_t* __restrict__ 
   for (int idx = threadIdx.x; idx < ch.len; idx += kScanThreads) out[ch.start + idx] += add;
 }
 
+// Passes B and C in one, for segments of at most kScanBcMax chunks: each
+// workgroup sums the totals of the chunks before its own in its segment
+// (integers: the same result in any order) and adds that to its chunk.
+constexpr int kScanBcMax = 2048;
+__global__ void __launch_bounds__(kScanThreads) k_scan_bc(uint32_t* __restrict__ out, const Chunk* __restrict__ chunks,
+                                                          const uint32_t* __restrict__ sums) {
+  __shared__ uint32_t red[kScanThreads / 64];
+  const int c = (int)blockIdx.x;
+  const Chunk ch = chunks[c];
+  uint32_t a = 0u;
+  for (int q = ch.seg_first + (int)threadIdx.x; q < c; q += kScanThreads) a += sums[q];
+  for (int o = 32; o > 0; o >>= 1) a += (uint32_t)__shfl_xor((int)a, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
+  __syncthreads();
+  uint32_t add = 0u;
+#pragma unroll
+  for (int w = 0; w < kScanThreads / 64; ++w) add += red[w];
+  if (add == 0u) return;
+  for (int idx = threadIdx.x; idx < ch.len; idx += kScanThreads) out[ch.start + idx] += add;
+}
+
 }  // namespace mdk

@@ -123,19 +123,23 @@ def test_window_records_in_global_memory(monkeypatch):
     in a table of the tile window's records, staged in LDS or (when it would
     not fit, here forced) kept in global memory.  Both give the same lists, so
     the same bits over 200 steps with several rebuilds, and the oracle's
-    trajectory."""
+    trajectory.  The third run takes the sort's three-pass scans (used for
+    jobs above 4M particles or bitmap words, here forced) in place of the
+    two-pass ones: the same bits again."""
     s = gen.torus(6000, 30.0, 10.0, 12)
     print(f"[gpu] window records in global memory n={s.n}", flush=True)
     kw = dict(dt=0.002, rc=2.5, seed=14, force_fp64=1, skin=0.3)
     outs = []
-    for table_global in (0, 1):
+    for table_global, three_pass in ((0, 0), (1, 0), (0, 1)):
         monkeypatch.setenv("MD_LIST_TABLE_GLOBAL", str(table_global))
+        monkeypatch.setenv("MD_SCAN_3PASS", str(three_pass))
         g = gpu_system(s, **kw)
         g.step(200)
         outs.append(g.get_state())
         g.close()
     assert outs[0]["diag"]["rebuilds"] >= 2
-    assert np.array_equal(outs[0]["x"], outs[1]["x"]) and np.array_equal(outs[0]["p"], outs[1]["p"])
+    for k in (1, 2):
+        assert np.array_equal(outs[0]["x"], outs[k]["x"]) and np.array_equal(outs[0]["p"], outs[k]["p"])
     ref = o.State(oracle_params(s, **kw), s.x, s.p, mass=s.mass, cons=s.cons).run(200)
     e = rel_pos_err(outs[1]["x"], ref.x)
     report("window records in global memory, 200 steps", x=e)
