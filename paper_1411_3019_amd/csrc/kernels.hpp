@@ -928,10 +928,11 @@ __global__ void __launch_bounds__(kDiagThreads) k_diag_final(const double* __res
   if (tid == 0) out[0] = sk[0], out[1] = su[0], out[2] = sg[0], out[3] = sv[0];
 }
 
-// Per-job reductions read by the host after a chunk of steps: the largest
-// per-tile displacement bound and, after list builds, the list statistics
-// (largest list, sum of list lengths, largest tile halo).  One workgroup per
-// job record.
+// Per-job reductions read by the host after a chunk of steps: at the end of
+// each chunk the largest per-tile displacement bound; after list builds only
+// the list statistics (largest list, sum of list lengths, largest tile halo;
+// the bound is read after the chunk that follows every build).  One workgroup
+// per job record.
 constexpr int kStatsThreads = 1024;
 __global__ void __launch_bounds__(kStatsThreads) k_job_stats(DevBufs B, int with_lists) {
   __shared__ double ra[kStatsThreads / 64], rs[kStatsThreads / 64];
@@ -945,12 +946,13 @@ __global__ void __launch_bounds__(kStatsThreads) k_job_stats(DevBufs B, int with
   // four independent loads in flight per thread (one workgroup serves a job)
   constexpr int64_t kStride = kStatsThreads;
   int64_t g = g0 + threadIdx.x;
-  for (; g + 3 * kStride < g1; g += 4 * kStride) {
-    const double t0 = B.TACC[g], t1 = B.TACC[g + kStride], t2 = B.TACC[g + 2 * kStride], t3 = B.TACC[g + 3 * kStride];
-    a = fmax(fmax(a, fmax(t0, t1)), fmax(t2, t3));
-  }
-  for (; g < g1; g += kStride) a = fmax(a, B.TACC[g]);
-  if (with_lists) {
+  if (!with_lists) {
+    for (; g + 3 * kStride < g1; g += 4 * kStride) {
+      const double t0 = B.TACC[g], t1 = B.TACC[g + kStride], t2 = B.TACC[g + 2 * kStride], t3 = B.TACC[g + 3 * kStride];
+      a = fmax(fmax(a, fmax(t0, t1)), fmax(t2, t3));
+    }
+    for (; g < g1; g += kStride) a = fmax(a, B.TACC[g]);
+  } else {
     // list-length sums are integers: exact in FP64 in any order
     const uint2* __restrict__ st = reinterpret_cast<const uint2*>(B.NLSTAT);
     g = g0 + threadIdx.x;
@@ -979,11 +981,12 @@ __global__ void __launch_bounds__(kStatsThreads) k_job_stats(DevBufs B, int with
   if (threadIdx.x == 0) {
     for (int q = 1; q < kStatsThreads / 64; ++q) a = fmax(a, ra[q]), sm += rs[q], mx = max(mx, rm[q]), hx = max(hx, rh[q]);
     JobBook& K = B.book[job];
-    K.a_now = a;
     if (with_lists) {
       K.nl_max = (int)mx;
       K.nl_sum = sm;
       K.halo_max = (int)hx;
+    } else {
+      K.a_now = a;
     }
   }
 }
