@@ -419,8 +419,12 @@ struct Engine {
   int64_t kkey_cap = 0;
   bool list_table_global = false;  // MD_LIST_TABLE_GLOBAL: keep those records in global memory always
   bool scan_three_pass = false;    // MD_SCAN_3PASS: the three-pass scans whatever the segment lengths
-  double* diag_many = nullptr;  // [4] results per job of finish_many
+  double* diag_many = nullptr;  // finish_many: [4 kDiagBlocks] diagnostic partials per job
   int64_t diag_many_cap = 0;
+  double* pack_d = nullptr;  // finish_many: the results packed for one copy to the host
+  int64_t pack_cap = 0;
+  char* fj_d = nullptr;  // finish_many: its two job tables
+  int64_t fj_cap = 0;
   double* scratch_d = nullptr;  // this device's `scratch` (md_get_state_dev_noalloc)
   bool no_alloc = false;        // set during md_get_state_dev_noalloc: device and pinned allocations fail
   int64_t chunk_cap = 0;
@@ -475,7 +479,7 @@ struct Engine {
                     B.CCNT, B.CSTART, B.RASTER, B.CID, B.RANK, B.INV, B.SRC, B.PK, B.TYPE[0], B.TYPE[1],
                     (void*)B.models, B.TACC, B.NLSTAT, B.jobs, B.book, step_tiles_job, step_tiles_first,
                     step_counts, aux_tiles_job, aux_tiles_first, chunks_d, chunk_sums, ranges_d, diag_d,
-                    diag_many, kkey_d};
+                    diag_many, kkey_d, pack_d, fj_d};
     for (void* p : ptrs)
       if (p) (void)hipFree(p);
     std::memset(&B, 0, sizeof(B));
@@ -489,6 +493,10 @@ struct Engine {
     diag_d = nullptr;
     diag_many = nullptr;
     diag_many_cap = 0;
+    pack_d = nullptr;
+    pack_cap = 0;
+    fj_d = nullptr;
+    fj_cap = 0;
     kkey_d = nullptr;
     kkey_cap = 0;
     if (book_h) (void)hipHostFree(book_h);
@@ -1601,44 +1609,85 @@ struct Engine {
       at[q] = bytes;
       bytes += 2 * sizeof(double) * 3 * (size_t)h.n;
     }
-    if (n > diag_many_cap) {
+    // device buffers: the jobs' diagnostic partials, the packed results
+    // (diagnostics, then each job's x and p, as laid out by `at`) and the two
+    // job tables
+    if ((int64_t)n * 4 * kDiagBlocks > diag_many_cap) {
       if (diag_many) (void)hipFree(diag_many);
       diag_many = nullptr;
       diag_many_cap = 0;
-      MDCHK(dalloc(&diag_many, 4 * (size_t)n));
-      diag_many_cap = n;
+      MDCHK(dalloc(&diag_many, (size_t)n * 4 * kDiagBlocks));
+      diag_many_cap = (int64_t)n * 4 * kDiagBlocks;
+    }
+    const int64_t pack_doubles = (int64_t)(bytes / sizeof(double));
+    if (pack_doubles > pack_cap) {
+      if (pack_d) (void)hipFree(pack_d);
+      pack_d = nullptr;
+      pack_cap = 0;
+      MDCHK(dalloc(&pack_d, (size_t)pack_doubles));
+      pack_cap = pack_doubles;
+    }
+    const size_t tab_bytes = (sizeof(DiagJob) + sizeof(PackJob)) * (size_t)n;
+    if ((int64_t)tab_bytes > fj_cap) {
+      if (fj_d) (void)hipFree(fj_d);
+      fj_d = nullptr;
+      fj_cap = 0;
+      MDCHK(dalloc(&fj_d, tab_bytes));
+      fj_cap = (int64_t)tab_bytes;
     }
     MDCHK(ensure_stage(bytes));  // (waits for the stream)
     MDCHK(upload_jobs());
     char* st = (char*)stage;
-    std::vector<int> tj;
-    std::vector<int64_t> tf;
+    // all the fetched jobs at once: one finish launch per force class over
+    // their tiles (FP64 class first), one pair of diagnostic launches, one
+    // packing launch and one copy to the host
+    std::vector<int> tj, tj32;
+    std::vector<int64_t> tf, tf32;
+    std::vector<char> tabs(tab_bytes);
+    DiagJob* djs = reinterpret_cast<DiagJob*>(tabs.data());
+    PackJob* pjs = reinterpret_cast<PackJob*>(tabs.data() + sizeof(DiagJob) * (size_t)n);
+    int64_t maxn = 0;
     for (int q = 0; q < n; ++q) {
       const int j = ids[q];
-      if (j < 0 || j >= max_jobs || !jobs[j].used || jobs[j].n == 0) continue;
-      const HostJob& h = jobs[j];
-      tj.clear();
-      tf.clear();
-      tiles_of(h, j, tj, tf);
+      const bool ok = j >= 0 && j < max_jobs && jobs[j].used && jobs[j].n > 0;
+      const HostJob* h = ok ? &jobs[j] : nullptr;
+      const int64_t nq = ok ? h->n : 0;
+      djs[q] = DiagJob{ok ? h->off : 0, nq, std::min<int64_t>(kDiagBlocks, (nq + kDiagThreads - 1) / kDiagThreads)};
+      pjs[q] = PackJob{ok ? h->off : 0, nq, (int64_t)(at[q] / sizeof(double))};
+      maxn = std::max(maxn, nq);
+      if (ok) {
+        if (h->dev.force_fp64)
+          tiles_of(*h, j, tj, tf);
+        else
+          tiles_of(*h, j, tj32, tf32);
+      }
+    }
+    const int n64 = (int)tj.size(), n32 = (int)tj32.size();
+    tj.insert(tj.end(), tj32.begin(), tj32.end());
+    tf.insert(tf.end(), tf32.begin(), tf32.end());
+    if (!tj.empty()) {
       MDCHK(upload_cached(aux_tiles_job, tj.data(), sizeof(int) * tj.size()));
       MDCHK(upload_cached(aux_tiles_first, tf.data(), sizeof(int64_t) * tf.size()));
-      if (h.dev.force_fp64)
-        hipLaunchKernelGGL(k_finish<true>, dim3((unsigned)tj.size()), dim3(kTile), 0, stream, B, aux_tiles_job,
-                           aux_tiles_first);
-      else
-        hipLaunchKernelGGL(k_finish<false>, dim3((unsigned)tj.size()), dim3(kTile), 0, stream, B, aux_tiles_job,
-                           aux_tiles_first);
-      const int nb = (int)std::min<int64_t>(kDiagBlocks, (h.n + kDiagThreads - 1) / kDiagThreads);
-      // the partials are reused job after job (stream order)
-      hipLaunchKernelGGL(k_diag_partial, dim3(nb), dim3(kDiagThreads), 0, stream, B.OD, (int64_t)C, h.off, h.n,
-                         diag_d);
-      hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(kDiagThreads), 0, stream, diag_d, nb, diag_many + 4 * q);
-      HIPCHK(hipGetLastError());
-      const size_t vb = sizeof(double) * 3 * (size_t)h.n;
-      HIPCHK(hipMemcpyAsync(st + at[q], B.OX + 3 * h.off, vb, hipMemcpyDeviceToHost, stream));
-      HIPCHK(hipMemcpyAsync(st + at[q] + vb, B.OP + 3 * h.off, vb, hipMemcpyDeviceToHost, stream));
     }
-    HIPCHK(hipMemcpyAsync(st, diag_many, 4 * sizeof(double) * (size_t)n, hipMemcpyDeviceToHost, stream));
+    if (n64 > 0)
+      hipLaunchKernelGGL(k_finish<true>, dim3((unsigned)n64), dim3(kTile), 0, stream, B, aux_tiles_job,
+                         aux_tiles_first);
+    if (n32 > 0)
+      hipLaunchKernelGGL(k_finish<false>, dim3((unsigned)n32), dim3(kTile), 0, stream, B, aux_tiles_job + n64,
+                         aux_tiles_first + n64);
+    MDCHK(upload(fj_d, tabs.data(), tab_bytes));
+    const DiagJob* dj_d = reinterpret_cast<const DiagJob*>(fj_d);
+    const PackJob* pj_d = reinterpret_cast<const PackJob*>(fj_d + sizeof(DiagJob) * (size_t)n);
+    const unsigned gx = (unsigned)std::max<int64_t>(1, std::min<int64_t>(1024, (3 * maxn + 255) / 256));
+    for (int q0 = 0; q0 < n; q0 += 65535) {  // the grid's y extent is at most 65535
+      const unsigned ny = (unsigned)std::min(65535, n - q0);
+      hipLaunchKernelGGL(k_diag_partial_many, dim3(kDiagBlocks, ny), dim3(kDiagThreads), 0, stream, B.OD, (int64_t)C,
+                         dj_d, q0, diag_many);
+      hipLaunchKernelGGL(k_pack_xp, dim3(gx, ny), dim3(256), 0, stream, B.OX, B.OP, pj_d, q0, pack_d);
+    }
+    hipLaunchKernelGGL(k_diag_final_many, dim3((unsigned)n), dim3(kDiagThreads), 0, stream, diag_many, dj_d, pack_d);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(st, pack_d, bytes, hipMemcpyDeviceToHost, stream));
     MDCHK(sync());
     for (int q = 0; q < n; ++q) {
       const int j = ids[q];

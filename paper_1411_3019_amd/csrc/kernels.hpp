@@ -891,12 +891,14 @@ __device__ __forceinline__ void diag_tree(double* sk, double* su, double* sg, do
   __syncthreads();
 }
 
-__global__ void __launch_bounds__(kDiagThreads) k_diag_partial(const double* __restrict__ OD, int64_t C, int64_t off,
-                                                               int64_t n, double* __restrict__ part) {
-  __shared__ double sk[kDiagThreads], su[kDiagThreads], sg[kDiagThreads], sv[kDiagThreads];
+// One workgroup's share of the job's diagnostics: the n values from off split
+// into nb equal pieces, piece b reduced over kDiagThreads threads.
+__device__ __forceinline__ void diag_partial_block(const double* __restrict__ OD, int64_t C, int64_t off, int64_t n,
+                                                   int nb, int b, double* __restrict__ part, double* sk, double* su,
+                                                   double* sg, double* sv) {
   const int tid = threadIdx.x;
-  const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
-  const int64_t b0 = (int64_t)blockIdx.x * chunk, b1 = min(b0 + chunk, n);
+  const int64_t chunk = (n + nb - 1) / nb;
+  const int64_t b0 = (int64_t)b * chunk, b1 = min(b0 + chunk, n);
   double k = 0.0, u = 0.0, g = 0.0, v = 0.0;
   for (int64_t i = b0 + tid; i < b1; i += kDiagThreads) {
     k += OD[off + i];
@@ -907,14 +909,14 @@ __global__ void __launch_bounds__(kDiagThreads) k_diag_partial(const double* __r
   sk[tid] = k, su[tid] = u, sg[tid] = g, sv[tid] = v;
   diag_tree(sk, su, sg, sv, tid);
   if (tid == 0) {
-    double* o = part + 4 * blockIdx.x;
+    double* o = part + 4 * b;
     o[0] = sk[0], o[1] = su[0], o[2] = sg[0], o[3] = sv[0];
   }
 }
 
-__global__ void __launch_bounds__(kDiagThreads) k_diag_final(const double* __restrict__ part, int nb,
-                                                             double* __restrict__ out) {
-  __shared__ double sk[kDiagThreads], su[kDiagThreads], sg[kDiagThreads], sv[kDiagThreads];
+// The nb partials of a job reduced to its four results.
+__device__ __forceinline__ void diag_final_block(const double* __restrict__ part, int nb, double* __restrict__ out,
+                                                 double* sk, double* su, double* sg, double* sv) {
   const int tid = threadIdx.x;
   double k = 0.0, u = 0.0, g = 0.0, v = 0.0;
   for (int b = tid; b < nb; b += kDiagThreads) {
@@ -926,6 +928,60 @@ __global__ void __launch_bounds__(kDiagThreads) k_diag_final(const double* __res
   sk[tid] = k, su[tid] = u, sg[tid] = g, sv[tid] = v;
   diag_tree(sk, su, sg, sv, tid);
   if (tid == 0) out[0] = sk[0], out[1] = su[0], out[2] = sg[0], out[3] = sv[0];
+}
+
+__global__ void __launch_bounds__(kDiagThreads) k_diag_partial(const double* __restrict__ OD, int64_t C, int64_t off,
+                                                               int64_t n, double* __restrict__ part) {
+  __shared__ double sk[kDiagThreads], su[kDiagThreads], sg[kDiagThreads], sv[kDiagThreads];
+  diag_partial_block(OD, C, off, n, (int)gridDim.x, (int)blockIdx.x, part, sk, su, sg, sv);
+}
+
+__global__ void __launch_bounds__(kDiagThreads) k_diag_final(const double* __restrict__ part, int nb,
+                                                             double* __restrict__ out) {
+  __shared__ double sk[kDiagThreads], su[kDiagThreads], sg[kDiagThreads], sv[kDiagThreads];
+  diag_final_block(part, nb, out, sk, su, sg, sv);
+}
+
+// Several jobs' diagnostics in one pair of launches (the same pieces and trees
+// as one job at a time, so the same results): job q0 + blockIdx.y, its pieces
+// in part + 4 kDiagBlocks (q0 + blockIdx.y).
+struct DiagJob {
+  int64_t off, n;
+  int64_t nb;
+};
+__global__ void __launch_bounds__(kDiagThreads) k_diag_partial_many(const double* __restrict__ OD, int64_t C,
+                                                                    const DiagJob* __restrict__ dj, int q0,
+                                                                    double* __restrict__ part) {
+  __shared__ double sk[kDiagThreads], su[kDiagThreads], sg[kDiagThreads], sv[kDiagThreads];
+  const int q = q0 + (int)blockIdx.y;
+  const DiagJob d = dj[q];
+  if ((int64_t)blockIdx.x >= d.nb) return;
+  diag_partial_block(OD, C, d.off, d.n, (int)d.nb, (int)blockIdx.x, part + (size_t)4 * kDiagBlocks * q, sk, su, sg,
+                     sv);
+}
+__global__ void __launch_bounds__(kDiagThreads) k_diag_final_many(const double* __restrict__ part,
+                                                                  const DiagJob* __restrict__ dj,
+                                                                  double* __restrict__ out) {
+  __shared__ double sk[kDiagThreads], su[kDiagThreads], sg[kDiagThreads], sv[kDiagThreads];
+  const int q = (int)blockIdx.x;
+  if (dj[q].n <= 0) return;
+  diag_final_block(part + (size_t)4 * kDiagBlocks * q, (int)dj[q].nb, out + 4 * q, sk, su, sg, sv);
+}
+
+// Positions and momenta of several jobs (finish outputs, by particle index)
+// packed one after another for one copy to the host: job q0 + blockIdx.y's
+// 3n values of OX at dst + at, then its 3n values of OP.
+struct PackJob {
+  int64_t off, n, at;
+};
+__global__ void __launch_bounds__(256) k_pack_xp(const double* __restrict__ OX, const double* __restrict__ OP,
+                                                 const PackJob* __restrict__ pj, int q0, double* __restrict__ dst) {
+  const PackJob p = pj[q0 + (int)blockIdx.y];
+  const int64_t m = 3 * p.n;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < m; k += (int64_t)gridDim.x * blockDim.x) {
+    dst[p.at + k] = OX[3 * p.off + k];
+    dst[p.at + m + k] = OP[3 * p.off + k];
+  }
 }
 
 // Per-job reductions read by the host after a chunk of steps: at the end of
