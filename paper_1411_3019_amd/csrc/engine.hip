@@ -1509,11 +1509,16 @@ struct Engine {
     HostJob& h = jobs[j];
     if (!h.used) return MD_ENOTFOUND;
     if (h.n == 0) {
+      // (the counters as finish_many reports them)
       if (diag) {
         std::memset(diag, 0, sizeof(*diag));
         diag->step = h.step;
+        diag->rebuilds = h.rebuilds;
+        diag->newton_iter_max = h.newton_max;
+        diag->nlist_max = h.nl_max;
         diag->error_index = -1;
         diag->error_step = -1;
+        diag->exact_sum_breaches = h.sum_breaches;
       }
       return h.status;
     }

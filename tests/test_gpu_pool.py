@@ -82,11 +82,14 @@ def test_sparse_jobs_build_lists():
 
 
 def test_fetch_many_matches_fetch():
-    """md_pool_fetch_many (the finished jobs read together, one wait) gives the
-    same bits as md_pool_fetch one job at a time; an unknown id reports
-    MD_ENOTFOUND in its status."""
-    from paper_1411_3019_amd import md
-    jobs = _serving_jobs([7, 8, 9, 11], lambda j: 80 + 13 * j)
+    """md_pool_fetch_many (the finished jobs read together: one finish launch
+    per force class, batched diagnostics, one copy) gives the same bits as
+    md_pool_fetch one job at a time, for jobs of both force classes and an
+    empty job; an unknown id reports MD_ENOTFOUND in its status."""
+    from paper_1411_3019_amd import md, serve
+    jobs = _serving_jobs([7, 8, 9, 11], lambda j: 80 + 13 * j, lambda j: 1 if j in (8, 11) else 0)
+    e = jobs[0]
+    jobs.append(serve.Job(99, 0.0, e.params, e.surface, e.surf, np.zeros((0, 3)), np.zeros((0, 3)), 50))
     pool = md.Pool(256 << 20, 8)
     ids = [pool.admit(j.params, j.surface, j.surf, j.x, j.p, j.nsteps) for j in jobs]
     print("[gpu] fetch_many", [(j.surface, j.n, j.nsteps) for j in jobs], flush=True)
@@ -94,7 +97,8 @@ def test_fetch_many_matches_fetch():
     while not done >= set(ids):
         pool.run(32)
         done |= set(pool.poll())
-    many = pool.fetch_many(ids + [4])
+    unknown = next(k for k in range(8) if k not in ids)
+    many = pool.fetch_many(ids + [unknown])
     assert many[-1][0] == md.MD_ENOTFOUND
     for pid, (rc, res) in zip(ids, many):
         rc1, one = pool.fetch(pid)
