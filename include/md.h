@@ -369,8 +369,10 @@ int md_pool_fetch(md_pool* pool, int job_id, double* x, double* p, md_diag* diag
 /* md_pool_fetch for n jobs at once (job_ids[0..n)): x[q], p[q] receive job
  * job_ids[q]'s state (host, n_q*3 each; either array or entry may be NULL),
  * diag[q] its diagnostics and status[q] its own status (MD_ENOTFOUND for an
- * unknown id); diag and status may be NULL.  The jobs' finish work is
- * enqueued back to back and waited for once. */
+ * unknown id); diag and status may be NULL.  The jobs' finish work runs as
+ * one launch per force class over all their tiles, their diagnostics as one
+ * pair of reductions (the same pieces and trees as md_pool_fetch, so the same
+ * bits), and their results come back in one copy, waited for once. */
 int md_pool_fetch_many(md_pool* pool, const int* job_ids, int n, double* const* x, double* const* p, md_diag* diag,
                        int* status);
 
