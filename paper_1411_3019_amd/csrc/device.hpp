@@ -131,6 +131,8 @@ struct DevBufs {
   uint32_t* CID;       // compact cell index per slot
   uint32_t* RANK;      // rank within the cell per slot
   uint32_t* INV;       // slot of each particle index after the last sort, by job offset + index (bead-model jobs only)
+  uint2* BW;           // bead-model jobs: window entries of beads id-2, id-1 (x) and id+1, id+2 (y) of slot i's
+                       // molecule, 16 bits each with the type in the top two; 0xFFFF: outside the window or molecule
   uint32_t* SRC;       // old slot (job-relative) of each new slot during a sort
   uint32_t* KKEY;      // list build, wide instance, when the window records do not fit LDS: [tile][256 + hcap], else null
   float4* PK;          // list-build candidates in the sorted order: FP32 position, particle index
@@ -853,13 +855,17 @@ __device__ __forceinline__ double bonded_forces(const JobDev& J, const ModelDev&
   return u;
 }
 
-// Gather the positions and types of beads id-2 .. id+2 of id's molecule.
+// Gather the positions and types of beads id-2 .. id+2 of id's molecule:
+// from the tile's window through the entries bw (pos), else (an entry 0xFFFF
+// for a bead of the molecule) through the inverse permutation.
+template <class Pos>
 __device__ __forceinline__ void molecule_window(const JobDev& J, const ModelDev& M, const DevBufs& B,
                                                 const double* __restrict__ X, int64_t id, double xi, double yi,
-                                                double zi, int ti, double* xs, int* tid) {
+                                                double zi, int ti, uint2 bw, Pos pos, double* xs, int* tid) {
   const int64_t bpm = M.bpm;
   const int64_t m0 = bpm > 0 ? (id / bpm) * bpm : id, m1 = bpm > 0 ? min(m0 + bpm, (int64_t)J.n) : id + 1;
   const uint8_t* __restrict__ T = B.TYPE[J.scur];
+  const uint32_t ent[5] = {bw.x & 0xFFFFu, bw.x >> 16, 0u, bw.y & 0xFFFFu, bw.y >> 16};
   for (int q = 0; q < 5; ++q) {
     const int64_t g = id - 2 + q;
     tid[q] = 0;
@@ -868,8 +874,13 @@ __device__ __forceinline__ void molecule_window(const JobDev& J, const ModelDev&
       xs[6] = xi, xs[7] = yi, xs[8] = zi;
       tid[2] = ti;
     } else if (g >= m0 && g < m1) {
-      pos_of(J, B, X, g, xs + 3 * q);
-      tid[q] = T[J.off + B.INV[J.off + g]];
+      if (ent[q] != 0xFFFFu) {
+        pos(ent[q] & kEntryMask, xs[3 * q], xs[3 * q + 1], xs[3 * q + 2]);
+        tid[q] = (int)(ent[q] >> kEntryTypeShift);
+      } else {
+        pos_of(J, B, X, g, xs + 3 * q);
+        tid[q] = T[J.off + B.INV[J.off + g]];
+      }
     }
   }
 }

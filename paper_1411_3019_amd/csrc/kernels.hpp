@@ -583,6 +583,10 @@ __global__ void __launch_bounds__(kNlistBlock) __attribute__((amdgpu_waves_per_e
   }
   // 2. this lane's stencil walk
   int cnt = 0;
+  // the lane's particle index and its molecule [mstart, mstart + bpm) (bpm = 0:
+  // no molecules)
+  const uint32_t myid = kWide && valid ? B.ID[J.scur ^ 1][i] : 0u;
+  const uint32_t bpm = (uint32_t)J.bpm, mstart = bpm != 0u ? (myid / bpm) * bpm : 0u;
   if (valid) {
     const bool anyper = uniform_int(J.periodic[0] | J.periodic[1] | J.periodic[2]) != 0;
     double lper = 0.0;
@@ -600,7 +604,6 @@ __global__ void __launch_bounds__(kNlistBlock) __attribute__((amdgpu_waves_per_e
     // bound above covers the shorter radii too); partners of the same
     // molecule are left out
     float tthr[kMaxTypes];
-    const uint32_t myid = kWide ? B.ID[J.scur ^ 1][i] : 0u;
     if (kWide) {
       const int ti = typed ? (int)B.TYPE[J.scur ^ 1][i] : 0;
       const double skin = 2.0 * J.half_skin;
@@ -611,7 +614,6 @@ __global__ void __launch_bounds__(kNlistBlock) __attribute__((amdgpu_waves_per_e
         tthr[b] = (float)((r + delta) * (r + delta) * (1.0 + 0x1p-20));
       }
     }
-    const uint32_t bpm = (uint32_t)J.bpm, mstart = bpm != 0u ? (myid / bpm) * bpm : 0u;  // bpm = 0: no molecules
     // four candidates r[0..3] numbered t .. t+3 (rem: candidates left from t);
     // every one is written at the next free row, a kept one advances it (row
     // kmax + 1 takes what does not fit)
@@ -728,6 +730,45 @@ __global__ void __launch_bounds__(kNlistBlock) __attribute__((amdgpu_waves_per_e
   }
   const int found = valid ? cnt - (pself >= 0 ? 1 : 0) : 0;  // neighbours found
   const int stored = min(nall, kmax);
+  // bead model: the molecule's beads id-2, id-1, id+1, id+2 (the bonded
+  // terms' partners, which the lists leave out) found through the inverse
+  // permutation, numbered like candidates (none when outside the tile's
+  // candidates) and marked for the halo like list entries
+  constexpr uint32_t kNoCode = 0xFFFFFFFFu;
+  uint32_t pcode[4] = {kNoCode, kNoCode, kNoCode, kNoCode};
+  if (typed && valid && bpm > 1u) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint32_t g = myid - 2u + (uint32_t)(q < 2 ? q : q + 1);  // (wraps below 0: then outside)
+      if (g - mstart >= bpm || g >= (uint32_t)J.n) continue;
+      const uint32_t sl = B.INV[base + g];  // job-local slot
+      uint32_t t = kNoCode;
+      if (by_span) {
+        if (sl >= span_lo && sl < span_hi) t = sl - span_lo;
+      } else {
+        // the hull holding the slot: ce, cb hold the hulls' first slots and
+        // first numbers in slot order
+        uint32_t lo = 0u, hi = nhull;
+        while (hi - lo > 1u) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if (ce[mid] <= sl)
+            lo = mid;
+          else
+            hi = mid;
+        }
+        const uint32_t len = (lo + 1u < nhull ? cb[lo + 1u] : M) - cb[lo];
+        if (nhull > 0u && sl >= ce[lo] && sl - ce[lo] < len) t = cb[lo] + (sl - ce[lo]);
+      }
+      if (t == kNoCode) continue;
+      const uint32_t loc = t - t0;
+      if (loc < (uint32_t)kTile) {
+        pcode[q] = kOwn | loc;
+      } else {
+        atomicOr(&bits[t >> 5], 1u << (t & 31));
+        pcode[q] = t;
+      }
+    }
+  }
   __syncthreads();
   uint32_t H = 0u;
   {
@@ -840,6 +881,19 @@ __global__ void __launch_bounds__(kNlistBlock) __attribute__((amdgpu_waves_per_e
       store_row<kStream>(B.NL, C, k, i, e);
     }
     B.NCNT[i] = (uint32_t)stored;
+    if (typed) {
+      // the bonded partners' window entries, with their types
+      uint32_t pe[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint32_t v = pcode[q] & ~kOwn;
+        uint32_t en = (pcode[q] & kOwn) ? v
+                                        : (uint32_t)kTile + wpre[v >> 5] + __popc(bits[v >> 5] & ((1u << (v & 31)) - 1u));
+        en |= (rec(en) >> kTypeShift) << kEntryTypeShift;
+        pe[q] = pcode[q] == kNoCode ? 0xFFFFu : en & 0xFFFFu;
+      }
+      B.BW[i] = make_uint2(pe[0] | (pe[1] << 16), pe[2] | (pe[3] << 16));
+    }
   }
   // list statistics of these 64 slots (no atomics); an overflow stops the job
   // before its first step on these lists

@@ -115,7 +115,10 @@ __device__ __forceinline__ double model_forces(const JobDev& J, const ModelDev& 
   double u = kEnergy ? pair_energy_model(J, M, B, X, first, i, ti, xi, yi, zi) : 0.0;
   double xs[15];
   int tid[5];
-  molecule_window(J, M, B, X, id, xi, yi, zi, ti, xs, tid);
+  // the step kernel finds the molecule's beads in its window; the finish
+  // kernel (kEnergy) through the inverse permutation
+  const uint2 bw = kEnergy ? make_uint2(0xFFFFFFFFu, 0xFFFFFFFFu) : B.BW[i];
+  molecule_window(J, M, B, X, id, xi, yi, zi, ti, bw, pos, xs, tid);
   u += bonded_forces(J, M, B, X, id, tid, xs, Fx, Fy, Fz, tab);
   return u;
 }
