@@ -354,6 +354,9 @@ __device__ __forceinline__ uint32_t block_scan(uint32_t v, uint32_t* sh, uint32_
 // FP32 class: lists in the order found.
 // FP64-class and bead-model jobs look up the index (and type) of each window
 // entry in a table of the window's record words, made with the halo list.
+// Bead model: each bead's bonded partners (beads id-2 .. id+2 of its
+// molecule, found through the inverse permutation) join the halo like list
+// entries, and their window entries are stored in BW for the step kernel.
 // The FP32 distance test uses the list radius widened by a bound on the FP32
 // rounding of both positions and of the separation (times eight), so it
 // accepts every pair closer than the list radius; the few extra pairs it may
