@@ -146,6 +146,7 @@ struct DevBufs {
   int64_t C;           // slot capacity (SoA stride)
   int kmax;
   int hcap;            // halo capacity per tile
+  int no_bw;           // 1: the list build leaves BW empty (bonded partners through the inverse permutation)
 };
 
 // ---------------------------------------------------------------------------

@@ -550,6 +550,8 @@ struct Engine {
     B.hcap = hcap;
     if (const char* v = std::getenv("MD_LIST_TABLE_GLOBAL")) list_table_global = std::atoi(v) != 0;
     if (const char* v = std::getenv("MD_SCAN_3PASS")) scan_three_pass = std::atoi(v) != 0;
+    // MD_NO_BONDED_WINDOW: bonded partners through the inverse permutation only
+    if (const char* v = std::getenv("MD_NO_BONDED_WINDOW")) B.no_bw = std::atoi(v) != 0 ? 1 : 0;
     if (const char* v = std::getenv("MD_STEP_VARIANT")) f32_variant = std::max(0, std::min(kNumStepVariants - 1, std::atoi(v)));
     {
       int v = 0;

@@ -739,7 +739,7 @@ __global__ void __launch_bounds__(kNlistBlock) __attribute__((amdgpu_waves_per_e
   // candidates) and marked for the halo like list entries
   constexpr uint32_t kNoCode = 0xFFFFFFFFu;
   uint32_t pcode[4] = {kNoCode, kNoCode, kNoCode, kNoCode};
-  if (typed && valid && bpm > 1u) {
+  if (typed && valid && bpm > 1u && !B.no_bw) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const uint32_t g = myid - 2u + (uint32_t)(q < 2 ? q : q + 1);  // (wraps below 0: then outside)

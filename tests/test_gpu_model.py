@@ -84,6 +84,34 @@ def test_model_one_step_map(case):
     assert ef < 1e-9
 
 
+@pytest.mark.parametrize("force_fp64", [1, 0])
+def test_model_far_bonded_partner(force_fp64, monkeypatch):
+    """A molecule whose tip bead sits 12 sigma_0 out along the normal (a bond
+    stretched far beyond the list radius, the partners far outside each
+    other's stencils): the one-step map still matches the oracle (the
+    stretched bond's force is large but finite), with the bonded partners
+    read from the tile's window and, forced, through the inverse permutation."""
+    s, rw = _capsid()
+    x = s.x.copy()
+    base = x[0]
+    nrm = base / np.linalg.norm(base)
+    x[3] = x[2] + 12.0 * nrm  # bead 3 of molecule 0
+    s = gen.System(x, s.p.copy(), s.surface, s.surf, box_lo=s.box_lo, box_hi=s.box_hi, periodic=s.periodic,
+                   mass=s.mass, cons=s.cons, types=s.types)
+    print(f"[gpu] bead model far bonded partner force_fp64={force_fp64} n={s.n}", flush=True)
+    for no_bw in (0, 1):
+        monkeypatch.setenv("MD_NO_BONDED_WINDOW", str(no_bw))
+        ref, g = _pair(s, rw, force_fp64=force_fp64)
+        ref.run(1)
+        g.step(1)
+        st = g.get_state()
+        g.close()
+        ex, ef = rel_pos_err(st["x"], ref.x), rel_err(st["f"], ref.f)
+        report(f"model far partner fp64={force_fp64} no_bw={no_bw} 1-step", x=ex, f=ef)
+        assert ex < (1e-12 if force_fp64 else 1e-6)
+        assert ef < (1e-9 if force_fp64 else 1e-4)
+
+
 @pytest.mark.parametrize("case", list(CASES))
 def test_model_short_trajectory(case):
     s, rw = CASES[case]()
@@ -134,20 +162,23 @@ def test_model_fp32_class(case):
 def test_model_deterministic_across_list_schedules(force_fp64, monkeypatch):
     """Different skins rebuild at different steps with different slot orders;
     FP64 class: lists in particle-index order; FP32 class: pair terms summed
-    exactly; so the bits agree.  The last run keeps the list build's table of
-    window records (bead types, particle indices) in global memory instead of
-    LDS: the same lists, so the same bits."""
+    exactly; so the bits agree.  The fourth run keeps the list build's table
+    of window records (bead types, particle indices) in global memory instead
+    of LDS: the same lists, so the same bits.  The fifth reads the bonded
+    partners through the inverse permutation instead of the tile's window:
+    the same positions, so the same bits."""
     s, rw = _capsid(400, 13.5, 8)
     print(f"[gpu] bead model determinism n={s.n} force_fp64={force_fp64}", flush=True)
     outs = []
-    for skin, table_global in ((0.3, 0), (0.3, 0), (0.8, 0), (0.3, 1)):
+    for skin, table_global, no_bw in ((0.3, 0, 0), (0.3, 0, 0), (0.8, 0, 0), (0.3, 1, 0), (0.3, 0, 1)):
         monkeypatch.setenv("MD_LIST_TABLE_GLOBAL", str(table_global))
+        monkeypatch.setenv("MD_NO_BONDED_WINDOW", str(no_bw))
         _, g = _pair(s, rw, skin=skin, seed=11, force_fp64=force_fp64)
         g.step(300)
         outs.append(g.get_state())
         g.close()
     assert outs[2]["diag"]["rebuilds"] != outs[0]["diag"]["rebuilds"]
-    for k in (1, 2, 3):
+    for k in (1, 2, 3, 4):
         assert np.array_equal(outs[0]["x"], outs[k]["x"]) and np.array_equal(outs[0]["p"], outs[k]["p"])
 
 
