@@ -737,14 +737,24 @@ struct Engine {
     }
   }
 
+  // Job records in use: indices below this (the device copies of the job and
+  // bookkeeping records are moved for these only; no kernel reads the others)
+  int live_jobs() const {
+    int n = 1;
+    for (int j = 0; j < max_jobs; ++j)
+      if (jobs[j].used) n = j + 1;
+    return n;
+  }
+
   int upload_jobs() {
-    std::vector<JobDev> tab(max_jobs);
-    for (int j = 0; j < max_jobs; ++j) tab[j] = jobs[j].dev;
-    return upload(B.jobs, tab.data(), sizeof(JobDev) * max_jobs);
+    const int nj = live_jobs();
+    std::vector<JobDev> tab(nj);
+    for (int j = 0; j < nj; ++j) tab[j] = jobs[j].dev;
+    return upload(B.jobs, tab.data(), sizeof(JobDev) * nj);
   }
 
   int read_book() {
-    HIPCHK(hipMemcpyAsync(book_h, B.book, sizeof(JobBook) * max_jobs, hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipMemcpyAsync(book_h, B.book, sizeof(JobBook) * live_jobs(), hipMemcpyDeviceToHost, stream));
     return sync();
   }
 
@@ -1134,7 +1144,7 @@ struct Engine {
       hipLaunchKernelGGL((k_nlist<false, true>), ng, nb_, lds, stream, B, B.jobs, B.models, aux_tiles_job, aux_tiles_first);
     else
       hipLaunchKernelGGL((k_nlist<false, false>), ng, nb_, lds, stream, B, B.jobs, B.models, aux_tiles_job, aux_tiles_first);
-    hipLaunchKernelGGL(k_job_stats, dim3(max_jobs), dim3(kStatsThreads), 0, stream, B, 1);
+    hipLaunchKernelGGL(k_job_stats, dim3(live_jobs()), dim3(kStatsThreads), 0, stream, B, 1);
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(ev[3], stream));
     build_timing_pending = true;
@@ -1385,11 +1395,12 @@ struct Engine {
     }
     MDCHK(prepare_step_tiles());
     set_store_policy();
-    std::vector<JobDev> tab(max_jobs);
+    const int nj = live_jobs();
+    std::vector<JobDev> tab(nj);
     int nsub = 0;
     // sub-chunk [t0, t0 + len): the job records for it, then its launches
     auto sub_chunk = [&](int t0, int len, bool graph) -> int {
-      for (int j = 0; j < max_jobs; ++j) {
+      for (int j = 0; j < nj; ++j) {
         const HostJob& h = jobs[j];
         JobDev d = h.dev;
         d.step0 = h.step + t0;
@@ -1398,7 +1409,7 @@ struct Engine {
         if (t0 > 0) d.mode = kModeSteady;
         tab[j] = d;
       }
-      MDCHK(upload(B.jobs, tab.data(), sizeof(JobDev) * max_jobs));
+      MDCHK(upload(B.jobs, tab.data(), sizeof(JobDev) * nj));
       HIPCHK(hipEventRecord(ev_sub[2 * nsub], stream));
       MDCHK(launch_chunk(len, graph));
       HIPCHK(hipEventRecord(ev_sub[2 * nsub + 1], stream));
@@ -1423,9 +1434,9 @@ struct Engine {
         MDCHK(step_graph(kk, cap_stream, &ex));
       }
     }
-    hipLaunchKernelGGL(k_job_stats, dim3(max_jobs), dim3(kStatsThreads), 0, stream, B, 0);
+    hipLaunchKernelGGL(k_job_stats, dim3(nj), dim3(kStatsThreads), 0, stream, B, 0);
     HIPCHK(hipGetLastError());
-    HIPCHK(hipMemcpyAsync(book_h, B.book, sizeof(JobBook) * max_jobs, hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipMemcpyAsync(book_h, B.book, sizeof(JobBook) * nj, hipMemcpyDeviceToHost, stream));
     HIPCHK(hipEventRecord(ev_book, stream));
     int classes = 0;
     for (int c = 0; c < kClasses; ++c) classes += grid[c] > 0;
