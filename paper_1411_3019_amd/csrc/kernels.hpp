@@ -401,13 +401,14 @@ __device__ __forceinline__ int column_slot(const uint32_t* ckey, uint32_t key) {
 }
 
 // kWide: the instance for builds that include FP64-class or bead-model jobs
-// (32-bit codes, particle indices kept for the sort).
+// (typed radii, the window-record table, the ordering by particle index).
+// The FP32-class instance is held to 80 registers (6 wavefronts per SIMD);
+// the wide one keeps the compiler's allocation.
 // jobs, models: B.jobs and B.models as no-alias arguments (scalar loads).
 template <bool kWide, bool kStream>
-__global__ void __launch_bounds__(kNlistBlock) __attribute__((amdgpu_waves_per_eu(kWide ? 1 : 6, 8))) k_nlist(DevBufs B, const JobDev* __restrict__ jobs,
-                                                       const ModelDev* __restrict__ models,
-                                                       const int* __restrict__ tile_job,
-                                                       const int64_t* __restrict__ tile_first) {
+__global__ void __launch_bounds__(kNlistBlock) __attribute__((amdgpu_waves_per_eu(kWide ? 1 : 6, 8)))
+k_nlist(DevBufs B, const JobDev* __restrict__ jobs, const ModelDev* __restrict__ models,
+        const int* __restrict__ tile_job, const int64_t* __restrict__ tile_first) {
   // codes of kept neighbours: own-tile slots as kOwn | local index, others as
   // their candidate number
   using code_t = uint16_t;
