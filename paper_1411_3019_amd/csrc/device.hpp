@@ -133,7 +133,6 @@ struct DevBufs {
   uint32_t* INV;       // slot of each particle index after the last sort, by job offset + index (bead-model jobs only)
   uint2* BW;           // bead-model jobs: window entries of beads id-2, id-1 (x) and id+1, id+2 (y) of slot i's
                        // molecule, 16 bits each with the type in the top two; 0xFFFF: outside the window or molecule
-  uint32_t* SRC;       // old slot (job-relative) of each new slot during a sort
   uint32_t* KKEY;      // list build, wide instance, when the window records do not fit LDS: [tile][256 + hcap], else null
   float4* PK;          // list-build candidates in the sorted order: FP32 position, particle index
                        // (bead model: type in the top two bits)

@@ -217,7 +217,7 @@ constexpr double kInfinityCacheBytes = 256.0 * 1024.0 * 1024.0;  // MI355X last-
 
 constexpr int64_t kSlotBytes = 2 * 24 /*X*/ + 2 * 24 /*P*/ + 2 * 36 /*NZD, NZF*/ + 2 * 4 /*ID*/ + 2 * 1 /*FLG*/ +
                                2 * 8 /*MASS*/ + 24 /*FC*/ + 3 * 24 /*OX,OP,OF*/ + 32 /*OD*/ + 4 /*NCNT*/ +
-                               4 * 7 /*rebuild*/ + 16 /*PK*/ + 2 * 1 /*TYPE*/ + 8 /*BW*/;
+                               4 * 6 /*rebuild*/ + 16 /*PK*/ + 2 * 1 /*TYPE*/ + 8 /*BW*/;
 
 // Device bytes per slot with list capacity kmax (16-bit entries) and halo
 // capacity hcap (per tile of kTile slots).
@@ -476,7 +476,7 @@ struct Engine {
     if (ev_book) (void)hipEventDestroy(ev_book), ev_book = nullptr;
     void* ptrs[] = {B.X[0], B.X[1], B.P[0], B.P[1], B.ID[0], B.ID[1], B.FLG[0], B.FLG[1], B.MASS[0], B.MASS[1],
                     B.NZD[0], B.NZD[1], B.NZF[0], B.NZF[1], B.FC, B.OX, B.OP, B.OF, B.OD, B.NL, B.NCNT, B.HALO, B.HCNT, B.BM, B.WOFF,
-                    B.CCNT, B.CSTART, B.RASTER, B.CID, B.RANK, B.INV, B.BW, B.SRC, B.PK, B.TYPE[0], B.TYPE[1],
+                    B.CCNT, B.CSTART, B.RASTER, B.CID, B.RANK, B.INV, B.BW, B.PK, B.TYPE[0], B.TYPE[1],
                     (void*)B.models, B.TACC, B.NLSTAT, B.jobs, B.book, step_tiles_job, step_tiles_first,
                     step_counts, aux_tiles_job, aux_tiles_first, chunks_d, chunk_sums, ranges_d, diag_d,
                     diag_many, kkey_d, pack_d, fj_d};
@@ -589,7 +589,6 @@ struct Engine {
     MDCHK(dalloc(&B.RANK, C));
     MDCHK(dalloc(&B.INV, C));
     MDCHK(dalloc(&B.BW, C));
-    MDCHK(dalloc(&B.SRC, C));
     MDCHK(dalloc(&B.PK, C + 16));  // the list build reads up to 7 records past a column
     MDCHK(dalloc(&B.TYPE[0], C));
     MDCHK(dalloc(&B.TYPE[1], C));
@@ -1132,8 +1131,7 @@ struct Engine {
     hipLaunchKernelGGL(k_scan_a<false>, dim3(nc), dim3(kScanThreads), 0, stream, B.CCNT, B.CSTART, chunks_d + nb,
                        chunk_sums + nb);
     scan_rest(B.CSTART, chunks_d + nb, chunk_sums + nb, nc);
-    hipLaunchKernelGGL(k_perm, dim3(ntiles), dim3(kTile), 0, stream, B, aux_tiles_job, aux_tiles_first);
-    hipLaunchKernelGGL(k_gather, dim3(ntiles), dim3(kTile), 0, stream, B, aux_tiles_job, aux_tiles_first);
+    hipLaunchKernelGGL(k_move, dim3(ntiles), dim3(kTile), 0, stream, B, aux_tiles_job, aux_tiles_first);
     set_store_policy();
     const dim3 ng(ntiles), nb_(kNlistBlock);
     if (wide && stream_stores)

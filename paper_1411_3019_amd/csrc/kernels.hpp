@@ -122,40 +122,28 @@ __global__ void __launch_bounds__(kTile) k_count(DevBufs B, const int* __restric
   if (valid) B.RANK[i] = base + (uint32_t)(lane - start);
 }
 
-// Destination of every slot in the new (cell) order: SRC[new slot] = old slot,
-// and, for jobs with a bead model (the only readers: bonded terms look up the
-// beads of a molecule by index), the inverse permutation by particle index.
-__global__ void __launch_bounds__(kTile) k_perm(DevBufs B, const int* __restrict__ tile_job,
+// Move every slot's state to its place in the new (cell) order: slot i goes
+// to d = the start of its cell + its rank in the cell.  Consecutive threads
+// read consecutive slots (whole cache lines); the writes follow the
+// permutation, which moves most slots only a few places since the last sort,
+// so they land in the same cache lines.  Jobs with a bead model also get the
+// inverse permutation by particle index (the bonded terms find the beads of a
+// molecule through it).  The noise cache (the last step's normals) moves with
+// the momenta.
+__global__ void __launch_bounds__(kTile) k_move(DevBufs B, const int* __restrict__ tile_job,
                                                 const int64_t* __restrict__ tile_first) {
   const int job = uniform_int(tile_job[blockIdx.x]);
   const JobDev& J = B.jobs[job];
   const int64_t i = uniform_i64(tile_first[blockIdx.x]) + threadIdx.x;
   const int64_t off = J.off;
   if (i >= off + J.n) return;
-  // the independent loads first, together
-  const uint32_t cid = B.CID[i], rank = B.RANK[i];
-  const int64_t d = off + B.CSTART[off + cid] + rank;
-  B.SRC[d] = (uint32_t)(i - off);
-  if (J.model) B.INV[off + B.ID[J.scur][i]] = (uint32_t)(d - off);
-}
-
-// Gather the state into the new order: consecutive threads write consecutive
-// slots (whole cache lines), the reads follow the permutation.  The noise
-// cache (the last step's normals) moves with the momenta.
-__global__ void __launch_bounds__(kTile) k_gather(DevBufs B, const int* __restrict__ tile_job,
-                                                  const int64_t* __restrict__ tile_first) {
-  const int job = uniform_int(tile_job[blockIdx.x]);
-  const JobDev& J = B.jobs[job];
-  const int64_t d = uniform_i64(tile_first[blockIdx.x]) + threadIdx.x;
-  if (d >= J.off + J.n) return;
-  const int64_t i = J.off + B.SRC[d];
   const double* __restrict__ Xs = B.X[J.xcur];
   double* __restrict__ Xd = B.X[J.xcur ^ 1];
   const double* __restrict__ Ps = B.P[J.pcur];
   double* __restrict__ Pd = B.P[J.pcur ^ 1];
   // every load before the first store: source and destination are different
-  // buffers, and this way the loads are in flight together instead of each
-  // waiting for the store before it
+  // buffers, and this way the loads are in flight together
+  const uint32_t cid = B.CID[i], rank = B.RANK[i];
   double x[3], p[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
@@ -178,6 +166,7 @@ __global__ void __launch_bounds__(kTile) k_gather(DevBufs B, const int* __restri
 #pragma unroll
     for (int k = 0; k < 3; ++k) nz[k] = (double)zs[3 * i + k];
   }
+  const int64_t d = off + B.CSTART[off + cid] + rank;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     Xd[3 * d + k] = x[k];
@@ -200,6 +189,7 @@ __global__ void __launch_bounds__(kTile) k_gather(DevBufs B, const int* __restri
     // bead model: the type rides in the top two bits of the record's index
     B.TYPE[sc ^ 1][d] = type;
     w |= (uint32_t)type << kTypeShift;
+    B.INV[off + id] = (uint32_t)(d - off);
   }
   B.PK[d] = make_float4((float)x[0], (float)x[1], (float)x[2], __uint_as_float(w));
 }
@@ -457,7 +447,7 @@ k_nlist(DevBufs B, const JobDev* __restrict__ jobs, const ModelDev* __restrict__
   ce[lane] = 0u;
   for (int w = lane; w < kCandCap / 32; w += kNlistBlock) bits[w] = 0u;
   if (lane == 0) fail = 0, span_lo = 0xFFFFFFFFu, span_hi = 0u;
-  const double* __restrict__ X = B.X[J.xcur ^ 1];  // the sorted copies written by k_gather
+  const double* __restrict__ X = B.X[J.xcur ^ 1];  // the sorted copies written by k_move
   const float4* __restrict__ PK = B.PK + base;
   if (kWide) wrec[lane] = valid ? __float_as_uint(PK[first_local + lane].w) : 0u;
   double xi = 0.0, yi = 0.0, zi = 0.0;
