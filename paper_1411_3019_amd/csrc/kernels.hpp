@@ -1096,10 +1096,12 @@ __global__ void __launch_bounds__(kStatsThreads) k_job_stats(DevBufs B, int with
 }
 
 // ---------------------------------------------------------------------------
-// Segmented exclusive scan, three passes, staged in LDS.
+// Segmented exclusive scan, three passes.
 // A chunk is a piece of one segment; chunks of a segment are consecutive in
-// the chunk list.  Pass A scans each chunk in LDS and writes its total; pass B
-// scans the totals within each segment (one workgroup); pass C adds them.
+// the chunk list.  Pass A scans each chunk (eight elements per thread, the
+// thread totals by wavefront shuffles, the four wavefront totals through LDS)
+// and writes its total; pass B scans the totals within each segment (one
+// workgroup); pass C adds them.
 // ---------------------------------------------------------------------------
 struct Chunk {
   int64_t start;   // element index of the chunk's first element
@@ -1114,34 +1116,55 @@ constexpr int kScanChunk = kScanThreads * kScanPer;
 template <bool kPopc>
 __global__ void __launch_bounds__(kScanThreads) k_scan_a(const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
                                                          const Chunk* __restrict__ chunks, uint32_t* __restrict__ sums) {
-  __shared__ uint32_t tot[kScanThreads];
+  __shared__ uint32_t wtot[kScanThreads / 64];
   const Chunk ch = chunks[blockIdx.x];
+  const int t = (int)threadIdx.x, wl = t & 63, w = t >> 6;
+  // this thread's eight consecutive elements: two 16-byte loads when the
+  // chunk starts on a 16-byte boundary (input and output share the offset)
+  // and all eight are in the chunk, else one at a time
+  const int i0 = t * kScanPer;
+  const bool whole = i0 + kScanPer <= ch.len && (ch.start & 3) == 0;
   uint32_t v[kScanPer];
+  if (whole) {
+    const uint4 q0 = *reinterpret_cast<const uint4*>(in + ch.start + i0);
+    const uint4 q1 = *reinterpret_cast<const uint4*>(in + ch.start + i0 + 4);
+    v[0] = q0.x, v[1] = q0.y, v[2] = q0.z, v[3] = q0.w;
+    v[4] = q1.x, v[5] = q1.y, v[6] = q1.z, v[7] = q1.w;
+  } else {
+#pragma unroll
+    for (int e = 0; e < kScanPer; ++e) v[e] = i0 + e < ch.len ? in[ch.start + i0 + e] : 0u;
+  }
   uint32_t run = 0;
 #pragma unroll
   for (int e = 0; e < kScanPer; ++e) {
-    const int idx = threadIdx.x * kScanPer + e;
-    uint32_t a = idx < ch.len ? in[ch.start + idx] : 0u;
-    if (kPopc) a = __popc(a);
+    const uint32_t a = kPopc ? (uint32_t)__popc(v[e]) : v[e];
     v[e] = run;
     run += a;
   }
-  tot[threadIdx.x] = run;
+  // inclusive scan of the thread totals within the wavefront, then across
+  // the four wavefronts
+  uint32_t incl = run;
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t u = (uint32_t)__shfl_up((int)incl, o, 64);
+    if (wl >= o) incl += u;
+  }
+  if (wl == 63) wtot[w] = incl;
   __syncthreads();
-  // Hillis-Steele inclusive scan of the per-thread totals
-  for (int o = 1; o < kScanThreads; o <<= 1) {
-    const uint32_t add = threadIdx.x >= o ? tot[threadIdx.x - o] : 0u;
-    __syncthreads();
-    tot[threadIdx.x] += add;
-    __syncthreads();
-  }
-  const uint32_t base = threadIdx.x > 0 ? tot[threadIdx.x - 1] : 0u;
+  uint32_t base = incl - run, total = 0u;
 #pragma unroll
-  for (int e = 0; e < kScanPer; ++e) {
-    const int idx = threadIdx.x * kScanPer + e;
-    if (idx < ch.len) out[ch.start + idx] = base + v[e];
+  for (int q = 0; q < kScanThreads / 64; ++q) {
+    if (q < w) base += wtot[q];
+    total += wtot[q];
   }
-  if (threadIdx.x == kScanThreads - 1) sums[blockIdx.x] = tot[kScanThreads - 1];
+  if (whole) {
+    *reinterpret_cast<uint4*>(out + ch.start + i0) = make_uint4(base + v[0], base + v[1], base + v[2], base + v[3]);
+    *reinterpret_cast<uint4*>(out + ch.start + i0 + 4) = make_uint4(base + v[4], base + v[5], base + v[6], base + v[7]);
+  } else {
+#pragma unroll
+    for (int e = 0; e < kScanPer; ++e)
+      if (i0 + e < ch.len) out[ch.start + i0 + e] = base + v[e];
+  }
+  if (t == 0) sums[blockIdx.x] = total;
 }
 
 constexpr int kScanB = 1024;
