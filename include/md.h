@@ -250,7 +250,10 @@ int md_set_particles(md_ctx* ctx, int64_t n, const double* x, const double* p,
 
 /* Advance nsteps time steps (Algorithm S1 around Algorithm 1).  Returns after
  * the work is done; MD_ENEWTON / MD_ENAN report a failure, and md_get_state's
- * diagnostics then name the failing step (error_step) and particle. */
+ * diagnostics then name the failing step (error_step) and particle.
+ * MD_ENOMEM when the neighbour lists need more entries than the list build can
+ * hold (its rows live in LDS: a cut-off far beyond the particle spacing), or
+ * when device memory for larger lists or halos cannot be allocated. */
 int md_step(md_ctx* ctx, int64_t nsteps);
 
 /* md_set_particles with device pointers (e.g. PyTorch tensors on the same

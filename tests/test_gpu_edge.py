@@ -2,7 +2,8 @@
 sizes that leave ragged tiles and wavefronts, non-uniform masses, free
 particles with no surface in a periodic box, pools holding empty and
 one-particle jobs beside ordinary ones, lists outgrowing their capacity
-mid-run, and the device-pointer entry points."""
+mid-run, the device-pointer entry points, and the reported errors for a
+non-finite state and for lists longer than a workgroup's LDS holds."""
 import numpy as np
 import pytest
 
@@ -284,3 +285,44 @@ def test_device_pointer_variants_match_host_variants():
     b = g.get_state()
     g.close()
     assert np.array_equal(a["x"], b["x"]) and np.array_equal(a["p"], b["p"])
+
+
+def test_nonfinite_state_reported():
+    """A free particle given a momentum of 1e301 (finite, accepted on input)
+    drifts to about 1e298 in its first step: the step reports MD_ENAN with
+    that step and particle, and the other particles stay finite."""
+    from paper_1411_3019_amd import md
+    s = gen.height_membrane(200, 300, 20.0, 20.0, 16.0, 2.0, 20.0, 6)
+    k = 250
+    assert s.cons[k] == 0
+    p = s.p.copy()
+    p[k] = (1e301, 0.0, 0.0)
+    print("[gpu] non-finite state", flush=True)
+    g = md.System(gpu_params(s, force_fp64=1), s.surface, s.surf)
+    g.set_particles(s.x, p, mass=s.mass, cons=s.cons)
+    with pytest.raises(md.MDError) as e:
+        g.step(5)
+    assert e.value.code == md.MD_ENAN
+    st = g.get_state()
+    g.close()
+    assert st["status"] == md.MD_ENAN
+    d = st["diag"]
+    assert d["error_index"] == k
+    assert d["error_step"] == 0 and st["step"] == 1
+    others = np.ones(s.n, bool)
+    others[k] = False
+    assert np.isfinite(st["x"][others]).all() and np.isfinite(st["p"][others]).all()
+
+
+def test_list_capacity_beyond_lds_reported():
+    """A cut-off of 16 sigma at area fraction 0.5 needs lists of about 420
+    entries; their rows would take more LDS than a workgroup has, so after the
+    first (overflowing) build md_step returns MD_ENOMEM instead of launching."""
+    from paper_1411_3019_amd import md
+    s = gen.plane(1250, 50.0, 3)
+    print("[gpu] list capacity beyond LDS", flush=True)
+    g = gpu_system(s, rc=16.0, force_fp64=0)
+    with pytest.raises(md.MDError) as e:
+        g.step(3)
+    assert e.value.code == md.MD_ENOMEM
+    g.close()
