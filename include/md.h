@@ -189,7 +189,8 @@ typedef struct md_diag {
   int64_t rebuilds;       /* neighbour-list builds so far                       */
   int newton_iter_max;    /* largest Newton iteration count seen                */
   int nlist_max;          /* largest neighbour count at the last build          */
-  int error_index;        /* particle index of the last device error, or -1     */
+  int error_index;        /* smallest particle index among those that failed at
+                             error_step (the same in any schedule), or -1      */
   int exact_sum_breaches; /* FP32 class: particle-steps whose pair terms left the
                              exact-sum range (a pair closer than about sigma/2);
                              those forces were summed in FP64 in list order, so

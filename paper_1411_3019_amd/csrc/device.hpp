@@ -68,8 +68,8 @@ constexpr long long kNever = 0x7FFFFFFFFFFFFFFFLL;
 struct JobBook {
   long long stop_at;                // first step that must not run: stale list, list overflow or error (kNever if none)
   long long err_step;               // step whose launch found the error (-1 if none)
-  int err_code;
-  int err_id;
+  unsigned long long err_key;       // smallest (particle index << 2 | error code) among the particles that
+                                    // failed at err_step (kNoError if none): the same report in any schedule
   int newton_max;
   int nl_max;                       // largest neighbour count of the last list build (above kmax: overflow)
   double nl_sum;                    // sum of the stored neighbour counts of the last list build
@@ -77,10 +77,10 @@ struct JobBook {
   int halo_max;                     // largest tile halo of the last build (above the capacity: overflow)
   int build_fail;                   // the last build could not stage a tile's candidates (see k_nlist)
   int sum_breaches;                 // particles whose FP32-class force terms left the exact-sum range
-  int sum_breach_id;                // particle index of the first such particle
 };
+constexpr unsigned long long kNoError = ~0ull;
 __host__ __device__ constexpr JobBook fresh_book() {
-  return JobBook{kNever, -1, 0, 0, 0, 0, 0.0, 0.0, 0, 0, 0, -1};
+  return JobBook{kNever, -1, kNoError, 0, 0, 0.0, 0.0, 0, 0, 0};
 }
 
 // Bead model of one job (SI, Virus capsid self-assembly), tables by type pair

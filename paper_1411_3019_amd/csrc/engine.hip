@@ -1468,11 +1468,11 @@ struct Engine {
       if (K.stop_at < h.step + done) done = std::max<int64_t>(0, K.stop_at - h.step);
       h.newton_max = std::max(h.newton_max, K.newton_max);
       h.sum_breaches = h.breach_base + K.sum_breaches;
-      if (K.err_code != 0) {
+      if (K.err_key != kNoError) {
         // the launch of step err_step failed: the state is that after it (its
-        // position stage ran), undefined for the failing particle
-        h.status = K.err_code == kErrNewton ? MD_ENEWTON : MD_ENAN;
-        h.err_id = K.err_id;
+        // position stage ran), undefined for the failing particles
+        h.status = (int)(K.err_key & 3u) == kErrNewton ? MD_ENEWTON : MD_ENAN;
+        h.err_id = (int)(K.err_key >> 2);
         h.err_step = K.err_step;
         if (done & 1) h.dev.xcur ^= 1;
         h.step += done;

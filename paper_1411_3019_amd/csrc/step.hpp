@@ -25,19 +25,18 @@
 
 namespace mdk {
 
-// An error at step s stops the job from step s + 1 on.
+// An error at step s stops the job from step s + 1 on (only that launch can
+// record one, so every recording lane stores the same step).  Each failing
+// particle offers (particle index << 2 | code) and the smallest is kept: the
+// report names the same particle whatever the order of the workgroups.
 __device__ __forceinline__ void record_error(JobBook& K, int code, uint32_t id, long long s) {
-  if (atomicCAS(&K.err_code, 0, code) == 0) {
-    K.err_id = (int)id;
-    K.err_step = s;
-  }
+  atomicMin(&K.err_key, ((unsigned long long)id << 2) | (unsigned long long)code);
+  K.err_step = s;
   atomicMin(&K.stop_at, s + 1);
 }
 
 // An FP32-class particle whose force terms left the exact-sum range.
-__device__ __forceinline__ void record_breach(JobBook& K, uint32_t id) {
-  if (atomicAdd(&K.sum_breaches, 1) == 0) K.sum_breach_id = (int)id;
-}
+__device__ __forceinline__ void record_breach(JobBook& K) { atomicAdd(&K.sum_breaches, 1); }
 
 __device__ __forceinline__ double nn3(double x, double y, double z) { return x * x + y * y + z * z; }
 __device__ __forceinline__ double dot3(double ax, double ay, double az, double bx, double by, double bz) {
@@ -300,7 +299,7 @@ __device__ __forceinline__ void step_body(const DevBufs& B, const JobDev* __rest
         else
           pair_forces<kF64>(J, B, i, cnt, rows, xi, yi, zi, mixed_pos, Fx, Fy, Fz, exact);
       }
-      if (!exact) record_breach(K, id);
+      if (!exact) record_breach(K);
     }
     // the particle's own momentum and flag are loaded after the force loop,
     // which keeps them out of the loop's live registers

@@ -246,3 +246,58 @@ def test_bead_model_jobs_in_a_pool():
     g.close()
     assert np.array_equal(mix["x"], alone["x"])
     pool.close()
+
+
+def test_failing_jobs_leave_the_pool_intact():
+    """Two jobs that fail on the device (a free particle with a momentum of
+    1e301: MD_ENAN; a Newton cap of one iteration: MD_ENEWTON) resident beside
+    three ordinary ones: each failing job reports the status, step and
+    particle it reports alone, and the others finish bit for bit as alone."""
+    from paper_1411_3019_amd import md
+    from _common import WCA, gpu_params
+    mem = gen.height_membrane(200, 300, 20.0, 20.0, 16.0, 2.0, 20.0, 6)
+    pbad = mem.p.copy()
+    pbad[250] = (1e301, 0.0, 0.0)
+    cases = [
+        (gen.sphere(300, 8.0, 1), None, dict(rc=2.5, force_fp64=0), md.MD_OK),
+        (mem, pbad, dict(rc=WCA, force_fp64=1), md.MD_ENAN),
+        (gen.torus(400, 12.0, 4.0, 3), None, dict(rc=2.5, force_fp64=0), md.MD_OK),
+        (gen.sphere(300, 8.0, 1), None, dict(newton_max_iter=1), md.MD_ENEWTON),
+        (gen.box_gas(300, 12.0, 8), None, dict(rc=2.5, force_fp64=1), md.MD_OK),
+    ]
+    nsteps = 100
+    print("[gpu] pool with failing jobs:", [(s.surface, want) for s, _, _, want in cases], flush=True)
+    pool = md.Pool(256 << 20, 16)
+    ids = []
+    for s, p, kw, _ in cases:
+        jid = pool.admit(gpu_params(s, **kw), s.surface, s.surf, s.x, s.p if p is None else p, nsteps,
+                         mass=s.mass, cons=s.cons)
+        assert jid is not None
+        ids.append(jid)
+    done = set()
+    for _ in range(50):
+        pool.run(32)
+        done |= set(pool.poll())
+        if done >= set(ids):
+            break
+    assert done >= set(ids)
+    for (s, p, kw, want), jid in zip(cases, ids):
+        rc, mix = pool.fetch(jid)
+        assert rc == want, (s.surface, rc, want)
+        g = md.System(gpu_params(s, **kw), s.surface, s.surf)
+        g.set_particles(s.x, s.p if p is None else p, mass=s.mass, cons=s.cons)
+        try:
+            g.step(nsteps)
+        except md.MDError as e:
+            assert e.code == want, (s.surface, e.code)
+        alone = g.get_state()
+        g.close()
+        assert alone["status"] == want
+        if want == md.MD_OK:
+            assert np.array_equal(mix["x"], alone["x"]) and np.array_equal(mix["p"], alone["p"]), s.surface
+            assert mix["diag"]["step"] == nsteps
+        else:
+            for key in ("error_step", "error_index", "step"):
+                assert mix["diag"][key] == alone["diag"][key], (s.surface, key)
+            assert 0 <= mix["diag"]["error_index"] < s.n
+    pool.close()
